@@ -1,0 +1,190 @@
+/*
+ * se2conv — convolutional finite Fourier series on Z^2\SE(2) for AMD gfx950.
+ *
+ * Computes, on the sampling grid Omega_L (paper Sec. 3.2, eq. (OmL)):
+ *   x_i = -1/2 + i/Nx, y_j = -1/2 + j/Ny, theta_l = 2 pi l / M   (0-based),
+ * the convolutional finite Fourier series (Sec. 5.2, eq. (SKfg); matrix form of
+ * Sec. 6.1 with N = L):
+ *   S_K[f, rho_1 .. rho_q](w) = sum_k f^[k; L] * prod_j rho_j^[k; L] * phi_k(w),
+ * i.e. the real field f convolved on the right with a chain of kernels that are
+ * radial in translations (Thm. f*gP: then every convolution is a product of
+ * finite Fourier coefficients; Sec. 6.3 for chains and powers).
+ *
+ * Memory layout of every field: real samples F[b][theta][y][x], x fastest
+ * (the order of the paper's F(i, j, l) with i fastest).  All pointers marked
+ * "device" are HIP device pointers of the plan's device; the caller owns them.
+ * All calls are asynchronous on the given stream; argument errors are detected
+ * on the host before anything is enqueued and leave no partial state.
+ * Supported sizes: Nx, Ny even, 8 <= Nx, Ny <= 512; 2 <= M <= 512; every size
+ * of the form 2^a 3^b.
+ */
+#ifndef SE2CONV_H
+#define SE2CONV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SE2CONV_ABI_VERSION 1
+
+typedef struct se2conv_plan_s* se2conv_plan_t;
+
+typedef enum {
+    SE2CONV_OK = 0,
+    SE2CONV_ERR_INVALID_ARG = 1,      /* null/misaligned pointer, bad index, foreign table, bad flag */
+    SE2CONV_ERR_UNSUPPORTED_SIZE = 2, /* grid size outside the supported set */
+    SE2CONV_ERR_OUT_OF_MEMORY = 3,    /* device allocation failed inside the plan */
+    SE2CONV_ERR_DEVICE = 4,           /* HIP runtime error (launch, no device, host-only plan) */
+    SE2CONV_ERR_INTERNAL = 5
+} se2conv_status;
+
+typedef enum { SE2CONV_F32 = 0, SE2CONV_F64 = 1 } se2conv_dtype;
+
+/* Omega_L sizes (eq. (OmL)): Nx x Ny spatial points, M angular points. */
+typedef struct {
+    int32_t nx, ny, m;
+} se2conv_shape;
+
+/* ---- plan flags */
+#define SE2CONV_PLAN_HOST_ONLY 0x1u /* validation-only plan: no device resources; every
+                                       call that would enqueue work returns ERR_DEVICE
+                                       after validating its arguments */
+
+/*
+ * se2conv_plan: create a plan for a list of grid shapes and a compute dtype.
+ *   shapes[n_shapes]  host array, copied.
+ *   dtype             SE2CONV_F32: FP32 butterflies and products with FP64-generated
+ *                     twiddles; SE2CONV_F64: FP64 throughout.
+ *   out               receives the plan handle (owned by the caller, released with
+ *                     se2conv_plan_destroy).
+ * The plan allocates twiddle tables (generated in FP64 on the device, eq. (3DFT)
+ * roots e^{-2 pi i j/L}) and a workspace of one real plane of the largest shape,
+ * on the current HIP device.  Returns ERR_UNSUPPORTED_SIZE for a bad shape,
+ * ERR_DEVICE when no device is usable.
+ */
+se2conv_status se2conv_plan(const se2conv_shape* shapes, int32_t n_shapes, se2conv_dtype dtype, uint32_t flags,
+                            se2conv_plan_t* out);
+
+/* Release a plan and its device resources (synchronises the plan's device). */
+se2conv_status se2conv_plan_destroy(se2conv_plan_t plan);
+
+/* ---- kernels rho (radial in translations, Sec. 5.1 footnote to Thm. f*gP) */
+typedef enum {
+    /* rho(x, theta) = exp(-|x|^2 / (2 sigma^2)) * exp(kappa cos(theta - theta0)),
+       periodized over the lattice (eq. (TH)).  Separable: its table is the outer
+       product of three 1-D coefficient vectors. */
+    SE2CONV_K_GAUSS_VM = 0,
+    /* arbitrary kernel samples P[theta][y][x] on Omega_L: device FP64 array `data`.
+       The operator is S_K with these coefficients whether or not the kernel is
+       radial; only for radial kernels is it the SE(2) convolution. */
+    SE2CONV_K_SAMPLES = 1,
+    /* radial profile: P[l][j][i] = sum_images sum_q prof[q][l] hat_q(|x_ij + image|),
+       hat_q piecewise-linear with knots r_q = q r_max/(n_knots-1); `data` is the
+       device FP64 array prof[n_knots][M]; 0 < r_max <= 1. */
+    SE2CONV_K_RADIAL_PROFILE = 2
+} se2conv_kernel_kind;
+
+/* normalisation (kernel flags, bits 0..1) */
+#define SE2CONV_KNORM_DISCRETE 0u   /* samples scaled so that rho^[0; L] = mean(P) = 1 (default) */
+#define SE2CONV_KNORM_CONTINUOUS 1u /* GAUSS_VM only: unit Haar mass (1/2pi) int int rho = 1, eq. (dg) */
+#define SE2CONV_KNORM_NONE 2u       /* raw samples */
+
+typedef struct {
+    int32_t kind;      /* se2conv_kernel_kind */
+    uint32_t flags;    /* SE2CONV_KNORM_* */
+    double sigma;      /* GAUSS_VM: translational width (> 0) */
+    double kappa;      /* GAUSS_VM: von Mises concentration (>= 0) */
+    double theta0;     /* GAUSS_VM: angular centre */
+    const void* data;  /* SAMPLES / RADIAL_PROFILE: device FP64 array (see kind) */
+    int32_t n_knots;   /* RADIAL_PROFILE: >= 2 */
+    double r_max;      /* RADIAL_PROFILE */
+} se2conv_kernel_desc;
+
+/* Table kinds reported by se2conv_table_info. */
+#define SE2CONV_TABLE_SEPARABLE 0 /* layout: Tx[Nx] | Ty[Ny] | Tt[M], complex (re, im) of the plan dtype;
+                                     rho^[k; L] = Tx[k1] Ty[k2] Tt[k3] */
+#define SE2CONV_TABLE_FULL 1      /* layout: T[M][Ny][Nx] complex of the plan dtype, T[k3][k2][k1] = rho^[k; L] */
+
+/*
+ * se2conv_coeffs: finite Fourier coefficients of a kernel chain (eq. (FkLv)),
+ *   rho^[k; L] = prod_j (-1)^{k1+k2} P_j^[k] / norm_j, stored at array index tau(k)
+ *   (tau_L(k) = k mod L).
+ * Computed in FP64 on the device (samples, DFT, sign, normalisation, chain product)
+ * and rounded once to the plan dtype.  All GAUSS_VM chains give a SEPARABLE table;
+ * a chain containing SAMPLES or RADIAL_PROFILE gives a FULL table.
+ *   kernels[n_kernels]  host array of descriptors (1 <= n_kernels <= 64).
+ *   d_table             device buffer of *table_bytes bytes, 16-byte aligned, or NULL to
+ *                       query the size into *table_bytes.
+ * The plan records the table (its address, shape and kind); se2conv_apply rejects
+ * tables it did not produce.  Uses the plan's FP64 scratch (allocated on first use).
+ */
+se2conv_status se2conv_coeffs(se2conv_plan_t plan, int32_t shape_idx, const se2conv_kernel_desc* kernels,
+                              int32_t n_kernels, void* d_table, size_t* table_bytes, hipStream_t stream);
+
+/* Kind (SE2CONV_TABLE_*) and byte size of a table produced by this plan. */
+se2conv_status se2conv_table_info(se2conv_plan_t plan, const void* d_table, int32_t* kind, int32_t* shape_idx,
+                                  size_t* bytes);
+
+/* ---- apply flags */
+#define SE2CONV_ADJOINT 0x1u /* apply the transpose (conjugate coefficients: correlation with the kernels) */
+#define SE2CONV_GRAPH 0x2u   /* se2conv_chain only: capture the submission once in a HIP graph and replay it */
+#define SE2CONV_TIMING 0x4u  /* record a HIP event on the stream before the first and after every pass
+                                launch; read the per-pass durations with se2conv_pass_times */
+
+/*
+ * se2conv_apply: out[b] = Re S_K[f[b], chain] for b = 0 .. batch-1.
+ *   d_f, d_out  device arrays [batch][M][Ny][Nx] of the plan dtype, 16-byte aligned;
+ *               d_out == d_f (in place) is allowed, other overlaps are not.
+ *   d_table     a table produced by se2conv_coeffs for this plan and shape.
+ * Separable tables run two passes (x-theta slabs, then y pencils) when a slab fits
+ * in LDS, three otherwise; full tables run forward / product / inverse passes on
+ * pairs of fields.  Uses the plan workspace when batch is odd and the table is
+ * FULL: calls on one plan must not overlap on different streams.
+ */
+se2conv_status se2conv_apply(se2conv_plan_t plan, int32_t shape_idx, const void* d_f, const void* d_table,
+                             void* d_out, int32_t batch, uint32_t flags, hipStream_t stream);
+
+/* One problem of a heterogeneous submission: out = Re S_K[f, tables[0] * ... ]. */
+typedef struct {
+    int32_t shape_idx;
+    int32_t batch;
+    const void* f;              /* device [batch][M][Ny][Nx] */
+    void* out;                  /* device, same shape (may equal f) */
+    const void* const* tables;  /* host array of n_tables device tables of this plan/shape */
+    int32_t n_tables;           /* 1 .. 8; coefficients multiplied in the plan dtype */
+} se2conv_problem;
+
+/*
+ * se2conv_chain: run n_probs problems (different shapes and kernel chains allowed)
+ * on one stream.  With SE2CONV_GRAPH the submission is captured into a HIP graph on
+ * first use and replayed on later calls with the same problem list (same pointers
+ * and sizes).  SE2CONV_ADJOINT applies to every problem.
+ */
+se2conv_status se2conv_chain(se2conv_plan_t plan, const se2conv_problem* probs, int32_t n_probs, uint32_t flags,
+                             hipStream_t stream);
+
+/*
+ * se2conv_pass_times: durations of the passes enqueued with SE2CONV_TIMING since the
+ * last read, in launch order.  Synchronises on the last recorded event.
+ *   ms[cap], kinds[cap]   host arrays; kinds: 0 = x-theta slab pass, 1 = y pencil,
+ *                         2 = theta pencil, 3 = x-row pass.
+ *   n                     receives the number of passes recorded (may exceed cap;
+ *                         only the first cap are written).  The record is cleared.
+ */
+se2conv_status se2conv_pass_times(se2conv_plan_t plan, float* ms, int32_t* kinds, int32_t cap, int32_t* n);
+
+/* Static description of a status code. */
+const char* se2conv_status_string(se2conv_status s);
+/* Message of the last error on the calling thread ("" if none). */
+const char* se2conv_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SE2CONV_H */

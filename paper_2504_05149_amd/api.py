@@ -1,0 +1,172 @@
+"""Python binding of the se2conv C ABI (argument marshalling only).
+
+PyTorch provides device memory and streams; every step of the convolution runs
+in the HIP kernels of libse2conv.so.  Names follow the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+
+import torch
+
+from . import _lib as L
+
+
+@dataclasses.dataclass
+class GaussVM:
+    """exp(-|x|^2 / 2 sigma^2) * exp(kappa cos(theta - theta0)), radial in translations."""
+    sigma: float
+    kappa: float
+    theta0: float = 0.0
+    norm: int = L.KNORM_DISCRETE
+
+
+@dataclasses.dataclass
+class Samples:
+    """Kernel samples P[theta][y][x] on the grid (device float64 tensor)."""
+    data: torch.Tensor
+    norm: int = L.KNORM_DISCRETE
+
+
+@dataclasses.dataclass
+class RadialProfile:
+    """Piecewise-linear radial profile prof[n_knots][M] (device float64), knots up to r_max."""
+    prof: torch.Tensor
+    r_max: float
+    norm: int = L.KNORM_NONE
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _desc(k) -> L.KernelDesc:
+    d = L.KernelDesc()
+    if isinstance(k, GaussVM):
+        d.kind, d.flags = L.K_GAUSS_VM, k.norm
+        d.sigma, d.kappa, d.theta0 = k.sigma, k.kappa, k.theta0
+    elif isinstance(k, Samples):
+        _require(k.data, torch.float64)
+        d.kind, d.flags, d.data = L.K_SAMPLES, k.norm, k.data.data_ptr()
+    elif isinstance(k, RadialProfile):
+        _require(k.prof, torch.float64)
+        d.kind, d.flags, d.data = L.K_RADIAL_PROFILE, k.norm, k.prof.data_ptr()
+        d.n_knots, d.r_max = int(k.prof.shape[0]), float(k.r_max)
+    else:
+        raise TypeError(f"unknown kernel descriptor {k!r}")
+    return d
+
+
+def _require(t: torch.Tensor, dtype) -> None:
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {dtype} device tensor")
+
+
+class Table:
+    """A coefficient table produced by Plan.coeffs (device buffer + its plan)."""
+
+    def __init__(self, plan: "Plan", shape_idx: int, buf: torch.Tensor, kind: int):
+        self.plan = plan
+        self.shape_idx = shape_idx
+        self.buf = buf
+        self.kind = kind
+
+    @property
+    def ptr(self) -> int:
+        return self.buf.data_ptr()
+
+    def complex_view(self) -> torch.Tensor:
+        """The table as a complex tensor (SEPARABLE: [Nx+Ny+M]; FULL: [M][Ny][Nx])."""
+        nx, ny, m = self.plan.shapes[self.shape_idx]
+        cdt = torch.complex64 if self.plan.dtype == L.F32 else torch.complex128
+        v = self.buf.view(cdt)
+        return v if self.kind == L.TABLE_SEPARABLE else v.view(m, ny, nx)
+
+
+class Plan:
+    def __init__(self, shapes, dtype: str = "f32", host_only: bool = False):
+        self._lib = L.load()
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.dtype = {"f32": L.F32, "f64": L.F64}[dtype]
+        self.tdtype = torch.float32 if self.dtype == L.F32 else torch.float64
+        arr = (L.Shape * len(self.shapes))(*[L.Shape(*s) for s in self.shapes])
+        h = ctypes.c_void_p()
+        L.check(self._lib.se2conv_plan(arr, len(self.shapes), self.dtype,
+                                       L.PLAN_HOST_ONLY if host_only else 0, ctypes.byref(h)))
+        self.handle = h
+        self._tables = []
+
+    def close(self) -> None:
+        if self.handle:
+            L.check(self._lib.se2conv_plan_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def table_bytes(self, shape_idx: int, kernels) -> int:
+        descs = (L.KernelDesc * len(kernels))(*[_desc(k) for k in kernels])
+        nbytes = ctypes.c_size_t(0)
+        L.check(self._lib.se2conv_coeffs(self.handle, shape_idx, descs, len(kernels), None,
+                                         ctypes.byref(nbytes), None))
+        return int(nbytes.value)
+
+    def coeffs(self, shape_idx: int, kernels, stream=None) -> Table:
+        descs = (L.KernelDesc * len(kernels))(*[_desc(k) for k in kernels])
+        nbytes = ctypes.c_size_t(0)
+        L.check(self._lib.se2conv_coeffs(self.handle, shape_idx, descs, len(kernels), None,
+                                         ctypes.byref(nbytes), None))
+        buf = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        L.check(self._lib.se2conv_coeffs(self.handle, shape_idx, descs, len(kernels), buf.data_ptr(),
+                                         ctypes.byref(nbytes), _stream_handle(stream)))
+        kind = ctypes.c_int32()
+        L.check(self._lib.se2conv_table_info(self.handle, buf.data_ptr(), ctypes.byref(kind), None, None))
+        t = Table(self, shape_idx, buf, kind.value)
+        return t
+
+    def apply(self, shape_idx: int, f: torch.Tensor, table: Table, out: torch.Tensor | None = None,
+              adjoint: bool = False, stream=None, timing: bool = False) -> torch.Tensor:
+        _require(f, self.tdtype)
+        nx, ny, m = self.shapes[shape_idx]
+        if f.shape[-3:] != (m, ny, nx):
+            raise ValueError(f"field shape {tuple(f.shape)} does not end in {(m, ny, nx)}")
+        batch = f.numel() // (nx * ny * m)
+        if out is None:
+            out = torch.empty_like(f)
+        _require(out, self.tdtype)
+        L.check(self._lib.se2conv_apply(self.handle, shape_idx, f.data_ptr(), table.ptr, out.data_ptr(),
+                                        batch, (L.ADJOINT if adjoint else 0) | (L.TIMING if timing else 0),
+                                        _stream_handle(stream)))
+        return out
+
+    def pass_times(self, cap: int = 4096):
+        """[(pass kind name, milliseconds)] of passes enqueued with timing=True since the last read."""
+        ms = (ctypes.c_float * cap)()
+        kinds = (ctypes.c_int32 * cap)()
+        n = ctypes.c_int32(0)
+        L.check(self._lib.se2conv_pass_times(self.handle, ms, kinds, cap, ctypes.byref(n)))
+        return [(L.PASS_KINDS.get(kinds[i], str(kinds[i])), float(ms[i])) for i in range(min(n.value, cap))]
+
+    def chain(self, problems, adjoint: bool = False, graph: bool = False, stream=None,
+              timing: bool = False) -> None:
+        """problems: list of (shape_idx, f, out, [tables])."""
+        keep = []
+        arr = (L.Problem * len(problems))()
+        for i, (sidx, f, out, tabs) in enumerate(problems):
+            nx, ny, m = self.shapes[sidx]
+            tp = (ctypes.c_void_p * len(tabs))(*[t.ptr for t in tabs])
+            keep.append(tp)
+            arr[i].shape_idx = sidx
+            arr[i].batch = f.numel() // (nx * ny * m)
+            arr[i].f = f.data_ptr()
+            arr[i].out = out.data_ptr()
+            arr[i].tables = ctypes.cast(tp, ctypes.POINTER(ctypes.c_void_p))
+            arr[i].n_tables = len(tabs)
+        flags = (L.ADJOINT if adjoint else 0) | (L.GRAPH if graph else 0) | (L.TIMING if timing else 0)
+        L.check(self._lib.se2conv_chain(self.handle, arr, len(problems), flags, _stream_handle(stream)))

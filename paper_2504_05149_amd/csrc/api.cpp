@@ -1,0 +1,887 @@
+// Host side of the se2conv C ABI: plans, argument validation, table registry,
+// pass scheduling and HIP-graph capture.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <set>
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/se2conv.h"
+#include "coeffs.hpp"
+#include "passes.hpp"
+
+using namespace se2c;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+se2conv_status fail(se2conv_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+se2conv_status ok() {
+    g_last_error.clear();
+    return SE2CONV_OK;
+}
+
+#define HIPCHK(expr)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(SE2CONV_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+bool is_2a3b(int n) {
+    if (n <= 0) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+bool shape_supported(const se2conv_shape& s, std::string* why) {
+    if (s.nx < 8 || s.nx > 512 || s.ny < 8 || s.ny > 512) {
+        *why = "Nx and Ny must lie in [8, 512]";
+        return false;
+    }
+    if ((s.nx & 1) || (s.ny & 1)) {
+        *why = "Nx and Ny must be even";
+        return false;
+    }
+    if (s.m < 2 || s.m > 512) {
+        *why = "M must lie in [2, 512]";
+        return false;
+    }
+    if (!is_2a3b(s.nx) || !is_2a3b(s.ny) || !is_2a3b(s.m)) {
+        *why = "every size must be of the form 2^a 3^b";
+        return false;
+    }
+    return true;
+}
+
+RadixPlan make_radix_plan(int L) {
+    RadixPlan p{};
+    p.L = L;
+    p.nst = 0;
+    int n = L;
+    while (n % 3 == 0) {
+        p.r[p.nst++] = 3;
+        n /= 3;
+    }
+    while (n >= 16 && n % 16 == 0) {
+        p.r[p.nst++] = 16;
+        n /= 16;
+    }
+    if (n == 8) p.r[p.nst++] = 8, n = 1;
+    if (n == 4) p.r[p.nst++] = 4, n = 1;
+    if (n == 2) p.r[p.nst++] = 2, n = 1;
+    // put the largest radices first (the first stage needs no twiddles)
+    std::sort(p.r, p.r + p.nst, [](int a, int b) { return a > b; });
+    return p;
+}
+
+constexpr size_t kMaxLds = 160 * 1024;
+
+int max_threads(bool d) { return d ? 512 : 1024; }
+
+int threads_for(long long P, bool d) {
+    long long t = (P + SE2C_MAXV - 1) / SE2C_MAXV;
+    t = ((t + 63) / 64) * 64;
+    if (t < 64) t = 64;
+    if (t > max_threads(d)) t = max_threads(d);
+    return (int)t;
+}
+
+struct TableRec {
+    int32_t shape_idx;
+    int32_t kind;
+    size_t bytes;
+};
+
+struct GraphRec {
+    std::vector<uint64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+}  // namespace
+
+struct se2conv_plan_s {
+    int device = -1;
+    se2conv_dtype dtype = SE2CONV_F32;
+    uint32_t flags = 0;
+    bool host_only = false;
+    std::vector<se2conv_shape> shapes;
+    std::map<int, void*> tw32, tw64;   // length -> device twiddle table
+    void* ws = nullptr;                // one real plane of the largest shape (plan dtype)
+    size_t ws_bytes = 0;
+    void* scratch64 = nullptr;         // FP64 scratch for se2conv_coeffs
+    size_t scratch64_bytes = 0;
+    std::unordered_map<uintptr_t, TableRec> tables;
+    std::vector<GraphRec> graphs;
+    std::mutex mu;
+    // pass timing (SE2CONV_TIMING)
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<hipEvent_t> ev_rec;   // recorded events in order
+    std::vector<int> ev_kind;         // kind of each timed pass, in order
+    std::set<size_t> ev_sub_start;    // indices in ev_rec that open a new submission
+};
+
+namespace {
+
+bool dbl(const se2conv_plan_s* p) { return p->dtype == SE2CONV_F64; }
+size_t real_bytes(const se2conv_plan_s* p) { return dbl(p) ? 8 : 4; }
+size_t cplx_bytes(const se2conv_plan_s* p) { return dbl(p) ? 16 : 8; }
+
+const void* tw_of(se2conv_plan_s* p, int L, bool use64) { return use64 ? p->tw64.at(L) : p->tw32.at(L); }
+
+bool aligned16(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15u) == 0; }
+
+// Current plan for pass timing (set by the entry points while they enqueue).
+thread_local se2conv_plan_s* g_timing_plan = nullptr;
+
+hipError_t record_event(se2conv_plan_s* p, hipStream_t st, bool submission_start = false) {
+    hipEvent_t ev;
+    if (submission_start && !p->ev_rec.empty()) p->ev_sub_start.insert(p->ev_rec.size());
+    if (!p->ev_pool.empty()) {
+        ev = p->ev_pool.back();
+        p->ev_pool.pop_back();
+    } else {
+        hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) return e;
+    }
+    p->ev_rec.push_back(ev);
+    return hipEventRecord(ev, st);
+}
+
+hipError_t after_pass(int kind, hipStream_t st) {
+    se2conv_plan_s* p = g_timing_plan;
+    if (!p) return hipSuccess;
+    if (p->ev_rec.empty()) return hipErrorInvalidValue;
+    p->ev_kind.push_back(kind);
+    return record_event(p, st);
+}
+
+// ------------------------------------------------------------ pass schedules
+struct Chain {
+    int ntab = 0;
+    int kind[SE2C_MAX_TABLES];
+    const void* ptr[SE2C_MAX_TABLES];
+};
+
+bool slab_fits(const se2conv_shape& s, bool d) {
+    SlabArgs a{};
+    a.nx = s.nx;
+    a.m = s.m;
+    a.rows_per_tile = s.m;
+    a.pad = 0;
+    const long long P = (long long)s.nx * s.m;
+    return P <= (long long)SE2C_MAXV * max_threads(d) && slab_lds_bytes(a, d) <= kMaxLds;
+}
+
+int rows_for_xpass(const se2conv_shape& s) {
+    int best = 1;
+    for (int r = 1; r <= s.m; ++r)
+        if (s.m % r == 0 && (long long)r * s.nx <= 4096) best = r;
+    return best;
+}
+
+int pencil_width(int ncols, int L, bool d) {
+    int W = 16;
+    while (W > 1 && (long long)W * L > (long long)SE2C_MAXV * max_threads(d)) W /= 2;
+    if (ncols < W) W = ncols;
+    return W;
+}
+
+hipError_t run_slab(SlabArgs a, bool d, hipStream_t st) {
+    const long long P = (long long)a.rows_per_tile * a.nx;
+    const int nthr = threads_for(P, d);
+    const long long ntiles = (long long)a.nslab * a.ntile_t * a.nitems;
+    const int nb = (int)std::min<long long>(ntiles, 1 << 20);
+    hipError_t e = launch_slab(a, d, nthr, nb, st);
+    if (e != hipSuccess) return e;
+    return after_pass(a.do_t ? 0 : 3, st);
+}
+
+hipError_t run_pencil(PencilArgs a, bool d, hipStream_t st) {
+    const long long P = (long long)a.p.L * a.W;
+    const int nthr = threads_for(P, d);
+    const int ncol_tiles = (a.ncols + a.W - 1) / a.W;
+    const int nother = a.axis == 1 ? a.m : a.ny;
+    const long long ntiles = (long long)ncol_tiles * nother * a.nitems;
+    const int nb = (int)std::min<long long>(ntiles, 1 << 20);
+    hipError_t e = launch_pencil(a, d, nthr, nb, st);
+    if (e != hipSuccess) return e;
+    return after_pass(a.axis == 1 ? 1 : 2, st);
+}
+
+// Separable chain: every table SEPARABLE.  f, out: [batch][m][ny][nx] real.
+se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void* f, void* out, int batch,
+                           const Chain& ch, bool conj, hipStream_t st) {
+    const bool d = dbl(p);
+    const long long n = (long long)s.nx * s.ny * s.m;
+    const RadixPlan px = make_radix_plan(s.nx), py = make_radix_plan(s.ny), pt = make_radix_plan(s.m);
+    const size_t cb = cplx_bytes(p);
+    auto fx = [&](int j) { return ch.ptr[j]; };
+    auto fy = [&](int j) { return (const void*)((const char*)ch.ptr[j] + cb * s.nx); };
+    auto ftt = [&](int j) { return (const void*)((const char*)ch.ptr[j] + cb * (s.nx + s.ny)); };
+
+    // pass 1: x (and theta) on y-pair slabs, real -> real
+    SlabArgs a{};
+    a.in0 = f;
+    a.out0 = out;
+    a.item_stride_in = n;
+    a.item_stride_out = n;
+    a.nitems = batch;
+    a.in_mode = 0;
+    a.out_mode = 0;
+    a.nx = s.nx;
+    a.ny = s.ny;
+    a.m = s.m;
+    a.nslab = s.ny / 2;
+    a.pad = 0;
+    a.fwd = 1;
+    a.inv = 1;
+    a.mul = 1;
+    a.ntab = ch.ntab;
+    a.conj_tab = conj ? 1 : 0;
+    a.px = px;
+    a.pt = pt;
+    a.twx = tw_of(p, s.nx, d);
+    a.twt = tw_of(p, s.m, d);
+    for (int j = 0; j < ch.ntab; ++j) {
+        a.tx[j] = fx(j);
+        a.tt[j] = ftt(j);
+    }
+    const bool two_pass = slab_fits(s, d);
+    if (two_pass) {
+        a.rows_per_tile = s.m;
+        a.ntile_t = 1;
+        a.do_t = 1;
+        a.scale = 1.0 / ((double)s.nx * s.m);
+    } else {
+        a.rows_per_tile = rows_for_xpass(s);
+        a.ntile_t = s.m / a.rows_per_tile;
+        a.do_t = 0;
+        a.scale = 1.0 / (double)s.nx;
+    }
+    HIPCHK(run_slab(a, d, st));
+
+    // pass 2 (and 3): y pencils (and theta pencils) on x-pairs, in place on out
+    auto pencil = [&](int axis) -> se2conv_status {
+        PencilArgs b{};
+        b.in0 = out;
+        b.out0 = out;
+        b.item_stride_in = n;
+        b.item_stride_out = n;
+        b.nitems = batch;
+        b.mode = 0;
+        b.axis = axis;
+        b.nx = s.nx;
+        b.ny = s.ny;
+        b.m = s.m;
+        b.ncols = s.nx / 2;
+        const int L = axis == 1 ? s.ny : s.m;
+        b.W = pencil_width(b.ncols, L, d);
+        b.pad = 0;
+        b.fwd = 1;
+        b.inv = 1;
+        b.mul = 1;
+        b.ntab = ch.ntab;
+        for (int j = 0; j < ch.ntab; ++j) b.tab1[j] = axis == 1 ? fy(j) : ftt(j);
+        b.conj_tab = conj ? 1 : 0;
+        b.scale = 1.0 / (double)L;
+        b.p = axis == 1 ? py : pt;
+        b.tw = tw_of(p, L, d);
+        HIPCHK(run_pencil(b, d, st));
+        return SE2CONV_OK;
+    };
+    se2conv_status r = pencil(1);
+    if (r != SE2CONV_OK) return r;
+    if (!two_pass) {
+        r = pencil(2);
+        if (r != SE2CONV_OK) return r;
+    }
+    return SE2CONV_OK;
+}
+
+// Forward (dir = 0) or inverse (dir = 1) transform along x and theta of complex
+// plane pairs.  in/out planes per item: (in0 + it*stride, in1 + it*stride).
+hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int dir, const void* in0,
+                        const void* in1, void* out0, void* out1, const void* lone_in1, void* lone_out1,
+                        long long stride_in, long long stride_out, int nitems, hipStream_t st) {
+    const RadixPlan px = make_radix_plan(s.nx), pt = make_radix_plan(s.m);
+    SlabArgs a{};
+    a.in0 = in0;
+    a.in1 = in1;
+    a.out0 = out0;
+    a.out1 = out1;
+    a.lone_in1 = lone_in1;
+    a.lone_out1 = lone_out1;
+    a.item_stride_in = stride_in;
+    a.item_stride_out = stride_out;
+    a.nitems = nitems;
+    a.in_mode = 1;
+    a.out_mode = 1;
+    a.nx = s.nx;
+    a.ny = s.ny;
+    a.m = s.m;
+    a.nslab = s.ny;
+    a.pad = 0;
+    a.fwd = dir == 0;
+    a.inv = dir == 1;
+    a.mul = 0;
+    a.px = px;
+    a.pt = pt;
+    a.twx = tw_of(p, s.nx, d);
+    a.twt = tw_of(p, s.m, d);
+    if (slab_fits(s, d)) {
+        a.rows_per_tile = s.m;
+        a.ntile_t = 1;
+        a.do_t = 1;
+        return run_slab(a, d, st);
+    }
+    // split: x rows and theta pencils (planes mode), in the right order
+    a.rows_per_tile = rows_for_xpass(s);
+    a.ntile_t = s.m / a.rows_per_tile;
+    a.do_t = 0;
+    PencilArgs b{};
+    b.mode = 1;
+    b.axis = 2;
+    b.nx = s.nx;
+    b.ny = s.ny;
+    b.m = s.m;
+    b.ncols = s.nx;
+    b.W = pencil_width(b.ncols, s.m, d);
+    b.pad = 0;
+    b.fwd = dir == 0;
+    b.inv = dir == 1;
+    b.mul = 0;
+    b.p = pt;
+    b.tw = tw_of(p, s.m, d);
+    b.nitems = nitems;
+    hipError_t e;
+    if (dir == 0) {
+        e = run_slab(a, d, st);  // in -> out
+        if (e != hipSuccess) return e;
+        b.in0 = out0;
+        b.in1 = out1;
+        b.out0 = out0;
+        b.out1 = out1;
+        b.lone_in1 = lone_out1;
+        b.lone_out1 = lone_out1;
+        b.item_stride_in = stride_out;
+        b.item_stride_out = stride_out;
+        return run_pencil(b, d, st);
+    }
+    b.in0 = in0;
+    b.in1 = in1;
+    b.out0 = const_cast<void*>(in0);
+    b.out1 = const_cast<void*>(in1);
+    b.lone_in1 = lone_in1;
+    b.lone_out1 = const_cast<void*>(lone_in1);
+    b.item_stride_in = stride_in;
+    b.item_stride_out = stride_in;
+    e = run_pencil(b, d, st);  // in place on the input planes
+    if (e != hipSuccess) return e;
+    return run_slab(a, d, st);
+}
+
+// y pencils on complex plane pairs: forward, optional product, inverse.
+hipError_t y_pass(se2conv_plan_s* p, const se2conv_shape& s, bool d, void* re, void* im, void* lone_im,
+                  long long stride, int nitems, int fwd, int inv, int mul, const Chain* ch, bool conj,
+                  double scale, hipStream_t st) {
+    PencilArgs b{};
+    b.in0 = re;
+    b.in1 = im;
+    b.out0 = re;
+    b.out1 = im;
+    b.lone_in1 = lone_im;
+    b.lone_out1 = lone_im;
+    b.item_stride_in = stride;
+    b.item_stride_out = stride;
+    b.nitems = nitems;
+    b.mode = 1;
+    b.axis = 1;
+    b.nx = s.nx;
+    b.ny = s.ny;
+    b.m = s.m;
+    b.ncols = s.nx;
+    b.W = pencil_width(b.ncols, s.ny, d);
+    b.pad = 0;
+    b.fwd = fwd;
+    b.inv = inv;
+    b.mul = mul;
+    b.p = make_radix_plan(s.ny);
+    b.tw = tw_of(p, s.ny, d);
+    b.conj_tab = conj ? 1 : 0;
+    b.scale = scale;
+    if (mul && ch) {
+        const size_t cb = cplx_bytes(p);
+        b.ntab = ch->ntab;
+        for (int j = 0; j < ch->ntab; ++j) {
+            if (ch->kind[j] == SE2CONV_TABLE_FULL) {
+                b.tab3[j] = ch->ptr[j];
+            } else {
+                b.tab3[j] = nullptr;
+                b.sepx[j] = ch->ptr[j];
+                b.sepy[j] = (const char*)ch->ptr[j] + cb * s.nx;
+                b.sept[j] = (const char*)ch->ptr[j] + cb * (s.nx + s.ny);
+            }
+        }
+    }
+    return run_pencil(b, d, st);
+}
+
+// Full (non-separable) chain on pairs of fields.
+se2conv_status enqueue_full(se2conv_plan_s* p, const se2conv_shape& s, const void* f, void* out, int batch,
+                            const Chain& ch, bool conj, hipStream_t st) {
+    const bool d = dbl(p);
+    const long long n = (long long)s.nx * s.ny * s.m;
+    const size_t rb = real_bytes(p);
+    const int pairs = (batch + 1) / 2;
+    const bool odd = (batch & 1) != 0;
+    const void* f1 = (const char*)f + rb * n;
+    void* o1 = (char*)out + rb * n;
+    // the odd item's imaginary plane: zero on input, plan workspace in between
+    void* lone = odd ? p->ws : nullptr;
+    if (batch == 1) {
+        f1 = nullptr;
+        o1 = nullptr;
+    }
+    HIPCHK(xt_transform(p, s, d, 0, f, batch == 1 ? nullptr : f1, out, batch == 1 ? nullptr : o1,
+                        nullptr, odd ? lone : nullptr, 2 * n, 2 * n, pairs, st));
+    // With batch == 1 the only item is "lone": xt_transform wrote its imaginary
+    // part to lone (because lone_out1 is used for the last odd item).
+    HIPCHK(y_pass(p, s, d, out, o1, lone, 2 * n, pairs, 1, 1, 2, &ch, conj, 1.0 / (double)n, st));
+    HIPCHK(xt_transform(p, s, d, 1, out, o1, out, o1, lone, nullptr, 2 * n, 2 * n, pairs, st));
+    return SE2CONV_OK;
+}
+
+se2conv_status lookup_chain(se2conv_plan_s* p, int shape_idx, const void* const* tables, int ntab, Chain* ch,
+                            bool* all_sep) {
+    if (ntab < 1 || ntab > SE2C_MAX_TABLES)
+        return fail(SE2CONV_ERR_INVALID_ARG, "n_tables must lie in [1, %d]", SE2C_MAX_TABLES);
+    ch->ntab = ntab;
+    *all_sep = true;
+    std::lock_guard<std::mutex> g(p->mu);
+    for (int j = 0; j < ntab; ++j) {
+        auto it = p->tables.find(reinterpret_cast<uintptr_t>(tables[j]));
+        if (tables[j] == nullptr || it == p->tables.end())
+            return fail(SE2CONV_ERR_INVALID_ARG, "table %d was not produced by this plan", j);
+        if (it->second.shape_idx != shape_idx)
+            return fail(SE2CONV_ERR_INVALID_ARG, "table %d belongs to shape %d, not %d", j, it->second.shape_idx,
+                        shape_idx);
+        ch->kind[j] = it->second.kind;
+        ch->ptr[j] = tables[j];
+        if (it->second.kind != SE2CONV_TABLE_SEPARABLE) *all_sep = false;
+    }
+    return SE2CONV_OK;
+}
+
+se2conv_status validate_io(se2conv_plan_s* p, int32_t shape_idx, const void* f, void* out, int32_t batch) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (shape_idx < 0 || shape_idx >= (int)p->shapes.size())
+        return fail(SE2CONV_ERR_INVALID_ARG, "shape_idx %d out of range", shape_idx);
+    if (batch < 1) return fail(SE2CONV_ERR_INVALID_ARG, "batch must be >= 1 (got %d)", batch);
+    if (!f || !out) return fail(SE2CONV_ERR_INVALID_ARG, "f and out must be non-null");
+    if (!aligned16(f) || !aligned16(out)) return fail(SE2CONV_ERR_INVALID_ARG, "f and out must be 16-byte aligned");
+    const se2conv_shape& s = p->shapes[shape_idx];
+    const long long bytes = (long long)batch * s.nx * s.ny * s.m * (long long)real_bytes(p);
+    const char* a = (const char*)f;
+    const char* b = (const char*)out;
+    if (a != b && a < b + bytes && b < a + bytes)
+        return fail(SE2CONV_ERR_INVALID_ARG, "f and out overlap without being equal");
+    return SE2CONV_OK;
+}
+
+se2conv_status enqueue_problem(se2conv_plan_s* p, int shape_idx, const void* f, void* out, int batch,
+                               const Chain& ch, bool all_sep, bool conj, hipStream_t st) {
+    const se2conv_shape& s = p->shapes[shape_idx];
+    if (all_sep) return enqueue_sep(p, s, f, out, batch, ch, conj, st);
+    return enqueue_full(p, s, f, out, batch, ch, conj, st);
+}
+
+se2conv_status ensure_scratch64(se2conv_plan_s* p, size_t bytes) {
+    if (p->scratch64_bytes >= bytes) return SE2CONV_OK;
+    if (p->scratch64) {
+        hipError_t e = hipFree(p->scratch64);
+        p->scratch64 = nullptr;
+        p->scratch64_bytes = 0;
+        if (e != hipSuccess) return fail(SE2CONV_ERR_DEVICE, "hipFree: %s", hipGetErrorString(e));
+    }
+    if (hipMalloc(&p->scratch64, bytes) != hipSuccess)
+        return fail(SE2CONV_ERR_OUT_OF_MEMORY, "could not allocate %zu bytes of FP64 scratch", bytes);
+    p->scratch64_bytes = bytes;
+    return SE2CONV_OK;
+}
+
+}  // namespace
+
+// ===================================================================== C ABI
+extern "C" {
+
+se2conv_status se2conv_pass_times(se2conv_plan_t p, float* ms, int32_t* kinds, int32_t cap, int32_t* n) {
+    if (!p || !n || cap < 0 || (cap > 0 && (!ms || !kinds))) return fail(SE2CONV_ERR_INVALID_ARG, "bad arguments");
+    std::lock_guard<std::mutex> g(p->mu);
+    *n = (int32_t)p->ev_kind.size();
+    if (!p->ev_rec.empty()) {
+        HIPCHK(hipEventSynchronize(p->ev_rec.back()));
+        // events are grouped per submission: each submission starts with an extra
+        // event, so walk the records and pair every pass with the event before it.
+        size_t k = 0;
+        for (size_t i = 1; i < p->ev_rec.size() && k < p->ev_kind.size(); ++i) {
+            float t = 0.f;
+            HIPCHK(hipEventElapsedTime(&t, p->ev_rec[i - 1], p->ev_rec[i]));
+            if (p->ev_sub_start.count(i)) continue;
+            if ((int32_t)k < cap) {
+                ms[k] = t;
+                kinds[k] = p->ev_kind[k];
+            }
+            ++k;
+        }
+    }
+    for (auto ev : p->ev_rec) p->ev_pool.push_back(ev);
+    p->ev_rec.clear();
+    p->ev_kind.clear();
+    p->ev_sub_start.clear();
+    return ok();
+}
+
+const char* se2conv_status_string(se2conv_status s) {
+    switch (s) {
+        case SE2CONV_OK: return "ok";
+        case SE2CONV_ERR_INVALID_ARG: return "invalid argument";
+        case SE2CONV_ERR_UNSUPPORTED_SIZE: return "unsupported size";
+        case SE2CONV_ERR_OUT_OF_MEMORY: return "out of device memory";
+        case SE2CONV_ERR_DEVICE: return "device error";
+        case SE2CONV_ERR_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+const char* se2conv_last_error(void) { return g_last_error.c_str(); }
+
+se2conv_status se2conv_plan(const se2conv_shape* shapes, int32_t n_shapes, se2conv_dtype dtype, uint32_t flags,
+                            se2conv_plan_t* out) {
+    if (!out) return fail(SE2CONV_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    if (!shapes || n_shapes < 1 || n_shapes > 4096)
+        return fail(SE2CONV_ERR_INVALID_ARG, "need 1..4096 shapes");
+    if (dtype != SE2CONV_F32 && dtype != SE2CONV_F64) return fail(SE2CONV_ERR_INVALID_ARG, "bad dtype %d", (int)dtype);
+    if (flags & ~SE2CONV_PLAN_HOST_ONLY) return fail(SE2CONV_ERR_INVALID_ARG, "unknown plan flags 0x%x", flags);
+    for (int i = 0; i < n_shapes; ++i) {
+        std::string why;
+        if (!shape_supported(shapes[i], &why))
+            return fail(SE2CONV_ERR_UNSUPPORTED_SIZE, "shape %d (%d x %d x %d): %s", i, shapes[i].nx, shapes[i].ny,
+                        shapes[i].m, why.c_str());
+    }
+    auto* p = new se2conv_plan_s();
+    p->dtype = dtype;
+    p->flags = flags;
+    p->shapes.assign(shapes, shapes + n_shapes);
+    if (flags & SE2CONV_PLAN_HOST_ONLY) {
+        p->host_only = true;
+        *out = p;
+        return ok();
+    }
+    auto cleanup = [&](se2conv_status st) {
+        se2conv_plan_destroy(p);
+        return st;
+    };
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+        return cleanup(fail(SE2CONV_ERR_DEVICE, "no HIP device available"));
+    if (hipGetDevice(&p->device) != hipSuccess) return cleanup(fail(SE2CONV_ERR_DEVICE, "hipGetDevice failed"));
+    // twiddles for every distinct length, generated in FP64
+    std::vector<int> lens;
+    size_t maxn = 0;
+    for (auto& s : p->shapes) {
+        lens.push_back(s.nx);
+        lens.push_back(s.ny);
+        lens.push_back(s.m);
+        maxn = std::max(maxn, (size_t)s.nx * s.ny * s.m);
+    }
+    std::sort(lens.begin(), lens.end());
+    lens.erase(std::unique(lens.begin(), lens.end()), lens.end());
+    for (int L : lens) {
+        void* t64 = nullptr;
+        void* t32 = nullptr;
+        if (hipMalloc(&t64, sizeof(double2) * L) != hipSuccess)
+            return cleanup(fail(SE2CONV_ERR_OUT_OF_MEMORY, "twiddle allocation"));
+        p->tw64[L] = t64;
+        if (hipMalloc(&t32, sizeof(float2) * L) != hipSuccess)
+            return cleanup(fail(SE2CONV_ERR_OUT_OF_MEMORY, "twiddle allocation"));
+        p->tw32[L] = t32;
+        if (launch_twiddles((double2*)t64, (float2*)t32, L, nullptr) != hipSuccess)
+            return cleanup(fail(SE2CONV_ERR_DEVICE, "twiddle generation launch failed"));
+    }
+    if (prepare_kernels() != hipSuccess) return cleanup(fail(SE2CONV_ERR_DEVICE, "kernel attribute setup failed"));
+    p->ws_bytes = maxn * real_bytes(p);
+    if (hipMalloc(&p->ws, p->ws_bytes) != hipSuccess)
+        return cleanup(fail(SE2CONV_ERR_OUT_OF_MEMORY, "workspace allocation (%zu bytes)", p->ws_bytes));
+    if (hipDeviceSynchronize() != hipSuccess) return cleanup(fail(SE2CONV_ERR_DEVICE, "plan synchronisation failed"));
+    *out = p;
+    return ok();
+}
+
+se2conv_status se2conv_plan_destroy(se2conv_plan_t p) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (!p->host_only) {
+        int cur = -1;
+        (void)hipGetDevice(&cur);
+        if (p->device >= 0) (void)hipSetDevice(p->device);
+        (void)hipDeviceSynchronize();
+        for (auto& g : p->graphs) {
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+        }
+        for (auto ev : p->ev_pool) (void)hipEventDestroy(ev);
+        for (auto ev : p->ev_rec) (void)hipEventDestroy(ev);
+        for (auto& kv : p->tw32) (void)hipFree(kv.second);
+        for (auto& kv : p->tw64) (void)hipFree(kv.second);
+        if (p->ws) (void)hipFree(p->ws);
+        if (p->scratch64) (void)hipFree(p->scratch64);
+        if (cur >= 0) (void)hipSetDevice(cur);
+    }
+    delete p;
+    return SE2CONV_OK;  // keeps the thread's last error (plan creation cleans up through here)
+}
+
+se2conv_status se2conv_coeffs(se2conv_plan_t p, int32_t shape_idx, const se2conv_kernel_desc* kernels,
+                              int32_t n_kernels, void* d_table, size_t* table_bytes, hipStream_t stream) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (shape_idx < 0 || shape_idx >= (int)p->shapes.size())
+        return fail(SE2CONV_ERR_INVALID_ARG, "shape_idx %d out of range", shape_idx);
+    if (!kernels || n_kernels < 1 || n_kernels > 64) return fail(SE2CONV_ERR_INVALID_ARG, "need 1..64 kernels");
+    if (!table_bytes) return fail(SE2CONV_ERR_INVALID_ARG, "table_bytes is null");
+    const se2conv_shape& s = p->shapes[shape_idx];
+    bool sep = true;
+    for (int j = 0; j < n_kernels; ++j) {
+        const se2conv_kernel_desc& k = kernels[j];
+        const uint32_t norm = k.flags & 3u;
+        if (k.flags & ~3u) return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: unknown flags 0x%x", j, k.flags);
+        if (norm == 3u) return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: bad normalisation", j);
+        switch (k.kind) {
+            case SE2CONV_K_GAUSS_VM:
+                if (!(k.sigma > 0.0) || !std::isfinite(k.sigma) || !(k.kappa >= 0.0) || !std::isfinite(k.kappa) ||
+                    k.kappa > 700.0 || !std::isfinite(k.theta0))
+                    return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: need sigma > 0, 0 <= kappa <= 700", j);
+                break;
+            case SE2CONV_K_SAMPLES:
+                sep = false;
+                if (!k.data) return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: samples pointer is null", j);
+                if (norm == SE2CONV_KNORM_CONTINUOUS)
+                    return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: continuous normalisation needs GAUSS_VM", j);
+                break;
+            case SE2CONV_K_RADIAL_PROFILE:
+                sep = false;
+                if (!k.data) return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: profile pointer is null", j);
+                if (k.n_knots < 2 || k.n_knots > 4096)
+                    return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: n_knots must lie in [2, 4096]", j);
+                if (!(k.r_max > 0.0) || !(k.r_max <= 1.0))
+                    return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: r_max must lie in (0, 1]", j);
+                if (norm == SE2CONV_KNORM_CONTINUOUS)
+                    return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: continuous normalisation needs GAUSS_VM", j);
+                break;
+            default:
+                return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: unknown kind %d", j, k.kind);
+        }
+    }
+    const long long n = (long long)s.nx * s.ny * s.m;
+    const size_t cb = cplx_bytes(p);
+    const size_t bytes = sep ? cb * (size_t)(s.nx + s.ny + s.m) : cb * (size_t)n;
+    if (!d_table) {
+        *table_bytes = bytes;
+        return ok();
+    }
+    if (*table_bytes < bytes) return fail(SE2CONV_ERR_INVALID_ARG, "table buffer too small (%zu < %zu)", *table_bytes, bytes);
+    if (!aligned16(d_table)) return fail(SE2CONV_ERR_INVALID_ARG, "table must be 16-byte aligned");
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+
+    std::lock_guard<std::mutex> g(p->mu);
+    const int nsep = s.nx + s.ny + s.m;
+    // FP64 scratch: sep accumulator | (full) accumulator n | spectrum re n | im n | samples n
+    const size_t need = sizeof(double2) * nsep + (sep ? 0 : (sizeof(double2) * n + 3 * sizeof(double) * n));
+    se2conv_status r = ensure_scratch64(p, need);
+    if (r != SE2CONV_OK) return r;
+    auto* sepacc = reinterpret_cast<double2*>(p->scratch64);
+    auto* full = reinterpret_cast<double2*>(sepacc + nsep);
+    auto* re = reinterpret_cast<double*>(full + n);
+    double* im = re + n;
+    double* samp = im + n;
+    bool first_full = true;
+    for (int j = 0; j < n_kernels; ++j) {
+        const se2conv_kernel_desc& k = kernels[j];
+        const int norm = (int)(k.flags & 3u);
+        if (k.kind == SE2CONV_K_GAUSS_VM) {
+            SepKernelParams kp;
+            kp.sigma = k.sigma;
+            kp.kappa = k.kappa;
+            kp.theta0 = k.theta0;
+            kp.ive0 = std::cyl_bessel_i(0.0, k.kappa) * std::exp(-k.kappa);
+            kp.norm = norm;
+            if (sep) {
+                HIPCHK(launch_sep_factor(kp, s.nx, s.ny, s.m, sepacc, j == 0, stream));
+            } else {
+                HIPCHK(launch_sep_factor(kp, s.nx, s.ny, s.m, sepacc, 1, stream));
+                HIPCHK(launch_full_fold_sep(sepacc, full, n, s.nx, s.ny, first_full, stream));
+                first_full = false;
+            }
+        } else {
+            const double* src = reinterpret_cast<const double*>(k.data);
+            if (k.kind == SE2CONV_K_RADIAL_PROFILE) {
+                HIPCHK(launch_profile_samples(src, k.n_knots, k.r_max, s.nx, s.ny, s.m, samp, stream));
+                src = samp;
+            }
+            // FP64 forward 3-D DFT of the real samples into (re, im) planes
+            HIPCHK(xt_transform(p, s, true, 0, src, nullptr, re, im, nullptr, nullptr, n, n, 1, stream));
+            HIPCHK(y_pass(p, s, true, re, im, nullptr, n, 1, 1, 0, 0, nullptr, false, 1.0, stream));
+            HIPCHK(launch_full_fold(re, im, full, n, s.nx, s.ny, norm == 0 ? 0 : 1, first_full, stream));
+            first_full = false;
+        }
+    }
+    HIPCHK(launch_round(sep ? sepacc : full, d_table, sep ? nsep : n, dbl(p) ? 1 : 0, stream));
+    TableRec rec;
+    rec.shape_idx = shape_idx;
+    rec.kind = sep ? SE2CONV_TABLE_SEPARABLE : SE2CONV_TABLE_FULL;
+    rec.bytes = bytes;
+    p->tables[reinterpret_cast<uintptr_t>(d_table)] = rec;
+    return ok();
+}
+
+se2conv_status se2conv_table_info(se2conv_plan_t p, const void* d_table, int32_t* kind, int32_t* shape_idx,
+                                  size_t* bytes) {
+    if (!p || !d_table) return fail(SE2CONV_ERR_INVALID_ARG, "null argument");
+    std::lock_guard<std::mutex> g(p->mu);
+    auto it = p->tables.find(reinterpret_cast<uintptr_t>(d_table));
+    if (it == p->tables.end()) return fail(SE2CONV_ERR_INVALID_ARG, "table was not produced by this plan");
+    if (kind) *kind = it->second.kind;
+    if (shape_idx) *shape_idx = it->second.shape_idx;
+    if (bytes) *bytes = it->second.bytes;
+    return ok();
+}
+
+se2conv_status se2conv_apply(se2conv_plan_t p, int32_t shape_idx, const void* d_f, const void* d_table, void* d_out,
+                             int32_t batch, uint32_t flags, hipStream_t stream) {
+    se2conv_status r = validate_io(p, shape_idx, d_f, d_out, batch);
+    if (r != SE2CONV_OK) return r;
+    if (flags & ~(SE2CONV_ADJOINT | SE2CONV_TIMING))
+        return fail(SE2CONV_ERR_INVALID_ARG, "unknown apply flags 0x%x", flags);
+    Chain ch;
+    bool all_sep = true;
+    const void* tabs[1] = {d_table};
+    r = lookup_chain(p, shape_idx, tabs, 1, &ch, &all_sep);
+    if (r != SE2CONV_OK) return r;
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    if (flags & SE2CONV_TIMING) {
+        std::lock_guard<std::mutex> g(p->mu);
+        HIPCHK(record_event(p, stream, true));
+        g_timing_plan = p;
+    }
+    r = enqueue_problem(p, shape_idx, d_f, d_out, batch, ch, all_sep, (flags & SE2CONV_ADJOINT) != 0, stream);
+    g_timing_plan = nullptr;
+    if (r != SE2CONV_OK) return r;
+    return ok();
+}
+
+se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int32_t n_probs, uint32_t flags,
+                             hipStream_t stream) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (!probs || n_probs < 1) return fail(SE2CONV_ERR_INVALID_ARG, "need at least one problem");
+    if (flags & ~(SE2CONV_ADJOINT | SE2CONV_GRAPH | SE2CONV_TIMING))
+        return fail(SE2CONV_ERR_INVALID_ARG, "unknown chain flags 0x%x", flags);
+    if ((flags & SE2CONV_GRAPH) && (flags & SE2CONV_TIMING))
+        return fail(SE2CONV_ERR_INVALID_ARG, "SE2CONV_TIMING cannot be combined with SE2CONV_GRAPH");
+    if ((flags & SE2CONV_GRAPH) && stream == nullptr)
+        return fail(SE2CONV_ERR_INVALID_ARG, "SE2CONV_GRAPH needs a created stream (the null stream cannot be captured)");
+    std::vector<Chain> chains(n_probs);
+    std::vector<char> seps(n_probs);
+    std::vector<uint64_t> key;
+    key.push_back(flags);
+    for (int i = 0; i < n_probs; ++i) {
+        const se2conv_problem& q = probs[i];
+        se2conv_status r = validate_io(p, q.shape_idx, q.f, q.out, q.batch);
+        if (r != SE2CONV_OK) return fail(r, "problem %d: %s", i, g_last_error.c_str());
+        if (!q.tables) return fail(SE2CONV_ERR_INVALID_ARG, "problem %d: tables is null", i);
+        bool all_sep = true;
+        r = lookup_chain(p, q.shape_idx, q.tables, q.n_tables, &chains[i], &all_sep);
+        if (r != SE2CONV_OK) return fail(r, "problem %d: %s", i, g_last_error.c_str());
+        seps[i] = all_sep;
+        key.push_back((uint64_t)q.shape_idx);
+        key.push_back((uint64_t)q.batch);
+        key.push_back((uint64_t)(uintptr_t)q.f);
+        key.push_back((uint64_t)(uintptr_t)q.out);
+        for (int j = 0; j < q.n_tables; ++j) key.push_back((uint64_t)(uintptr_t)q.tables[j]);
+    }
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    const bool conj = (flags & SE2CONV_ADJOINT) != 0;
+    auto submit = [&]() -> se2conv_status {
+        for (int i = 0; i < n_probs; ++i) {
+            se2conv_status r = enqueue_problem(p, probs[i].shape_idx, probs[i].f, probs[i].out, probs[i].batch,
+                                               chains[i], seps[i], conj, stream);
+            if (r != SE2CONV_OK) return r;
+        }
+        return SE2CONV_OK;
+    };
+    if (!(flags & SE2CONV_GRAPH)) {
+        if (flags & SE2CONV_TIMING) {
+            HIPCHK(record_event(p, stream, true));
+            g_timing_plan = p;
+        }
+        se2conv_status r = submit();
+        g_timing_plan = nullptr;
+        return r == SE2CONV_OK ? ok() : r;
+    }
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        for (auto& gr : p->graphs) {
+            if (gr.key == key) {
+                HIPCHK(hipGraphLaunch(gr.exec, stream));
+                return ok();
+            }
+        }
+    }
+    HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
+    se2conv_status r = submit();
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(stream, &graph);
+    if (r != SE2CONV_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return r;
+    }
+    if (e != hipSuccess) return fail(SE2CONV_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(SE2CONV_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        GraphRec gr;
+        gr.key = key;
+        gr.graph = graph;
+        gr.exec = exec;
+        p->graphs.push_back(gr);
+    }
+    HIPCHK(hipGraphLaunch(exec, stream));
+    return ok();
+}
+
+}  // extern "C"

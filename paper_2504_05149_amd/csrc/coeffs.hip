@@ -1,0 +1,256 @@
+// FP64 generation of twiddle tables and kernel coefficient tables on the GPU.
+//
+// Kernel coefficients are the finite Fourier coefficients of the sampled kernel
+// (paper Sec. 4.1, eq. (FkLv)): rho^[k; L] = (-1)^{k1+k2} P^[k] / (Lx Ly Lr),
+// where P^ is the DFT (Sec. 2.3, eq. (3DFT)) of the periodized kernel samples on
+// Omega_L (eq. (OmL)).  A chain rho_1 * ... * rho_q uses the product of the
+// tables (Thm. f*gP(2); Sec. 6.3); the product is formed here in FP64 and
+// rounded once.
+//
+// A Gaussian x von Mises kernel exp(-|x|^2/2s^2) exp(k cos(theta - theta0)) is a
+// product of 1-D factors in x, y and theta, and so is its lattice periodization;
+// its table is the outer product Tx (x) Ty (x) Tt of three 1-D FFC vectors, each
+// computed by a direct FP64 DFT with exactly reduced arguments ((k i) mod L).
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "coeffs.hpp"
+#include "fft_device.hpp"
+
+namespace se2c {
+
+// ------------------------------------------------------------------ twiddles
+__global__ void twiddle_kernel(double2* out64, float2* out32, int L) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < L; j += gridDim.x * blockDim.x) {
+        // exp(-2 pi i j / L): use the symmetric quarter-turn reduction so that the
+        // table is exactly symmetric, and sincospi for the reduced angle.
+        double s, c;
+        sincospi(2.0 * (double)j / (double)L, &s, &c);
+        // Snap the exact quarter-turn points.
+        if ((4LL * j) % L == 0) {
+            const int q = (int)((4LL * j) / L) & 3;
+            c = (q == 0) ? 1.0 : (q == 2 ? -1.0 : 0.0);
+            s = (q == 1) ? 1.0 : (q == 3 ? -1.0 : 0.0);
+        }
+        double2 w;
+        w.x = c;
+        w.y = -s;
+        if (out64) out64[j] = w;
+        if (out32) out32[j] = make_float2((float)c, (float)(-s));
+    }
+}
+
+hipError_t launch_twiddles(double2* out64, float2* out32, int L, hipStream_t s) {
+    const int nthr = 256;
+    const int nb = (L + nthr - 1) / nthr;
+    hipLaunchKernelGGL(twiddle_kernel, dim3(nb), dim3(nthr), 0, s, out64, out32, L);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- separable (Gauss x vM) tables
+// One block per axis (blockIdx.x: 0 = x, 1 = y, 2 = theta).  acc64 holds the
+// running FP64 product for the chain: [nx + ny + m] double2.
+__device__ double periodized_gauss(double x, double sigma) {
+    double acc = 0.0;
+    for (int l = -SE2C_GAUSS_IMAGES; l <= SE2C_GAUSS_IMAGES; ++l) {
+        const double d = x + (double)l;
+        acc += exp(-(d * d) / (2.0 * sigma * sigma));
+    }
+    return acc;
+}
+
+__global__ void sep_factor_kernel(SepKernelParams kp, int nx, int ny, int m, double2* acc64, int first) {
+    extern __shared__ double g[];  // samples (L doubles) then partial sums
+    const int axis = blockIdx.x;
+    const int L = axis == 0 ? nx : (axis == 1 ? ny : m);
+    const int off = axis == 0 ? 0 : (axis == 1 ? nx : nx + ny);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    double* red = g + L;
+
+    // 1) samples of the 1-D factor on Omega_L
+    for (int i = tid; i < L; i += nthr) {
+        if (axis < 2) {
+            const double x = -0.5 + (double)i / (double)L;
+            g[i] = periodized_gauss(x, kp.sigma);
+        } else {
+            const double t = 2.0 * M_PI * (double)i / (double)L;
+            g[i] = exp(kp.kappa * (cos(t - kp.theta0) - 1.0));
+        }
+    }
+    __syncthreads();
+    // 2) sum of samples (for the discrete-mass normalisation)
+    double part = 0.0;
+    for (int i = tid; i < L; i += nthr) part += g[i];
+    red[tid] = part;
+    __syncthreads();
+    for (int w = nthr / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    const double sum = red[0];
+
+    // normalisation of this 1-D factor
+    double norm;
+    if (kp.norm == 0) {
+        norm = 1.0 / sum;  // factor value 1 at k = 0: grid mean of the product is 1
+    } else if (kp.norm == 1) {
+        // continuous Haar mass: spatial factor 1/(sqrt(2 pi) sigma) per axis, angular
+        // factor 1/I0(kappa) (the samples carry e^{-kappa}, matched by kp.ive0).
+        norm = (axis < 2) ? 1.0 / ((double)L * sqrt(2.0 * M_PI) * kp.sigma)
+                          : 1.0 / ((double)L * kp.ive0);
+    } else {
+        norm = (axis < 2) ? 1.0 / (double)L : exp(kp.kappa) / (double)L;
+    }
+
+    // 3) direct DFT with reduced arguments, sign (-1)^k on spatial axes, product
+    for (int k = tid; k < L; k += nthr) {
+        double re = 0.0, im = 0.0;
+        for (int i = 0; i < L; ++i) {
+            const long long r = ((long long)k * i) % L;
+            double s, c;
+            sincospi(2.0 * (double)r / (double)L, &s, &c);
+            re += g[i] * c;
+            im -= g[i] * s;
+        }
+        double sg = 1.0;
+        if (axis < 2 && (k & 1)) sg = -1.0;  // (-1)^k; L even so index parity = signed parity
+        re *= sg * norm;
+        im *= sg * norm;
+        double2 v;
+        if (first) {
+            v.x = re;
+            v.y = im;
+        } else {
+            const double2 a = acc64[off + k];
+            v.x = a.x * re - a.y * im;
+            v.y = a.x * im + a.y * re;
+        }
+        acc64[off + k] = v;
+    }
+}
+
+hipError_t launch_sep_factor(const SepKernelParams& kp, int nx, int ny, int m, double2* acc64, int first,
+                             hipStream_t s) {
+    const int nthr = 256;
+    const int Lmax = nx > ny ? (nx > m ? nx : m) : (ny > m ? ny : m);
+    const size_t lds = sizeof(double) * (size_t)(Lmax + nthr);
+    hipLaunchKernelGGL(sep_factor_kernel, dim3(3), dim3(nthr), lds, s, kp, nx, ny, m, acc64, first);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------- full 3-D tables
+// spec = (re, im) planes of the FP64 DFT of the samples.  Multiplies the FFC
+// (-1)^{k1+k2} P^[k] / norm into acc (complex FP64 [m][ny][nx]).  norm is the
+// sample sum (discrete normalisation, = P^[0]) or n.
+__global__ void full_fold_kernel(const double* re, const double* im, double2* acc, long long n, int nx, int ny,
+                                 int norm_mode, int first) {
+    const double norm = norm_mode == 0 ? re[0] : (double)n;
+    const double inv = 1.0 / norm;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int kx = (int)(i % nx);
+        const int ky = (int)((i / nx) % ny);
+        const double sg = ((kx + ky) & 1) ? -inv : inv;
+        double2 v;
+        v.x = re[i] * sg;
+        v.y = im[i] * sg;
+        if (!first) {
+            const double2 a = acc[i];
+            double2 w;
+            w.x = a.x * v.x - a.y * v.y;
+            w.y = a.x * v.y + a.y * v.x;
+            v = w;
+        }
+        acc[i] = v;
+    }
+}
+
+// Multiply a separable FP64 factor triple (acc64 layout [nx | ny | m]) into a full table.
+__global__ void full_fold_sep_kernel(const double2* sep, double2* acc, long long n, int nx, int ny, int first) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int kx = (int)(i % nx);
+        const int ky = (int)((i / nx) % ny);
+        const int kt = (int)(i / ((long long)nx * ny));
+        double2 ab;
+        const double2 fx = sep[kx];
+        const double2 fy = sep[nx + ky];
+        const double2 ft = sep[nx + ny + kt];
+        ab.x = fx.x * fy.x - fx.y * fy.y;
+        ab.y = fx.x * fy.y + fx.y * fy.x;
+        double2 v;
+        v.x = ab.x * ft.x - ab.y * ft.y;
+        v.y = ab.x * ft.y + ab.y * ft.x;
+        if (!first) {
+            const double2 p = acc[i];
+            double2 w;
+            w.x = p.x * v.x - p.y * v.y;
+            w.y = p.x * v.y + p.y * v.x;
+            v = w;
+        }
+        acc[i] = v;
+    }
+}
+
+hipError_t launch_full_fold(const double* re, const double* im, double2* acc, long long n, int nx, int ny,
+                            int norm_mode, int first, hipStream_t s) {
+    hipLaunchKernelGGL(full_fold_kernel, dim3(1024), dim3(256), 0, s, re, im, acc, n, nx, ny, norm_mode, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_full_fold_sep(const double2* sep, double2* acc, long long n, int nx, int ny, int first,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(full_fold_sep_kernel, dim3(1024), dim3(256), 0, s, sep, acc, n, nx, ny, first);
+    return hipGetLastError();
+}
+
+// Round an FP64 complex array into the table dtype.
+__global__ void round_kernel(const double2* src, void* dst, long long n, int dbl) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        if (dbl) {
+            reinterpret_cast<double2*>(dst)[i] = src[i];
+        } else {
+            reinterpret_cast<float2*>(dst)[i] = make_float2((float)src[i].x, (float)src[i].y);
+        }
+    }
+}
+
+hipError_t launch_round(const double2* src, void* dst, long long n, int dbl, hipStream_t s) {
+    long long nb = (n + 255) / 256;
+    if (nb > 4096) nb = 4096;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(round_kernel, dim3((unsigned)nb), dim3(256), 0, s, src, dst, n, dbl);
+    return hipGetLastError();
+}
+
+// Radial-profile kernel samples (FP64):
+// P[l][j][i] = sum_images sum_q prof[q][l] * hat_q(|x_ij + image|),
+// hat_q(r) = max(0, 1 - |r/h - q|), h = r_max/(n_knots-1).
+__global__ void profile_samples_kernel(const double* prof, int n_knots, double r_max, int nx, int ny, int m,
+                                       double* out) {
+    const long long n = (long long)nx * ny * m;
+    const double h = r_max / (double)(n_knots - 1);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < n; idx += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(idx % nx);
+        const int j = (int)((idx / nx) % ny);
+        const int l = (int)(idx / ((long long)nx * ny));
+        const double x = -0.5 + (double)i / nx, y = -0.5 + (double)j / ny;
+        double acc = 0.0;
+        for (int a = -SE2C_PROFILE_IMAGES; a <= SE2C_PROFILE_IMAGES; ++a) {
+            for (int b = -SE2C_PROFILE_IMAGES; b <= SE2C_PROFILE_IMAGES; ++b) {
+                const double dx = x + a, dy = y + b;
+                const double u = sqrt(dx * dx + dy * dy) / h;
+                const int q0 = (int)floor(u);
+                if (q0 >= 0 && q0 < n_knots) acc += (1.0 - (u - q0)) * prof[(long long)q0 * m + l];
+                if (q0 + 1 >= 0 && q0 + 1 < n_knots) acc += (u - q0) * prof[(long long)(q0 + 1) * m + l];
+            }
+        }
+        out[idx] = acc;
+    }
+}
+
+hipError_t launch_profile_samples(const double* prof, int n_knots, double r_max, int nx, int ny, int m, double* out,
+                                  hipStream_t s) {
+    hipLaunchKernelGGL(profile_samples_kernel, dim3(2048), dim3(256), 0, s, prof, n_knots, r_max, nx, ny, m, out);
+    return hipGetLastError();
+}
+
+}  // namespace se2c

@@ -1,0 +1,248 @@
+// Device-side FFT building blocks for gfx950 (CDNA4, wave64).
+//
+// Stockham auto-sort radix-R stages over an LDS-resident tile of complex lines.
+// A stage reads R points per butterfly at stride L/R, applies the twiddles
+// w_L^{r*k*L/(Ns*R)} (k = j mod Ns, Ns = product of earlier radices), does an
+// in-register radix-R DFT and writes the R results at stride Ns; after the last
+// stage the line is in natural frequency order.  Every thread first reads all of
+// its butterflies into registers, the workgroup synchronises, then writes, so a
+// single LDS buffer serves as both source and destination.
+//
+// The forward transform uses e^{-2 pi i jk/L} as in the paper's DFT (Sec. 2.3,
+// eq. (3DFT)); the inverse uses the conjugate roots and no 1/L (the scale is
+// folded into the spectral product).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace se2c {
+
+template <typename T> struct cx;
+template <> struct cx<float> { using t = float2; };
+template <> struct cx<double> { using t = double2; };
+template <typename T> using C = typename cx<T>::t;
+
+template <typename T> __device__ __forceinline__ C<T> mk(T a, T b) { C<T> r; r.x = a; r.y = b; return r; }
+template <typename T> __device__ __forceinline__ C<T> add(C<T> a, C<T> b) { return mk<T>(a.x + b.x, a.y + b.y); }
+template <typename T> __device__ __forceinline__ C<T> sub(C<T> a, C<T> b) { return mk<T>(a.x - b.x, a.y - b.y); }
+template <typename T> __device__ __forceinline__ C<T> mul(C<T> a, C<T> b) {
+    return mk<T>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// a * conj(b)
+template <typename T> __device__ __forceinline__ C<T> mulc(C<T> a, C<T> b) {
+    return mk<T>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
+}
+template <typename T> __device__ __forceinline__ C<T> scl(C<T> a, T s) { return mk<T>(a.x * s, a.y * s); }
+
+// Multiply by -i (forward) or +i (inverse).
+template <typename T, bool INV> __device__ __forceinline__ C<T> rot(C<T> a) {
+    return INV ? mk<T>(-a.y, a.x) : mk<T>(a.y, -a.x);
+}
+// Multiply by w = (c, -s) forward or (c, +s) inverse, i.e. e^{-+i phi} with c=cos, s=sin.
+template <typename T, bool INV> __device__ __forceinline__ C<T> rotw(C<T> a, T c, T s) {
+    return INV ? mk<T>(a.x * c - a.y * s, a.x * s + a.y * c)
+               : mk<T>(a.x * c + a.y * s, a.y * c - a.x * s);
+}
+
+// Constants written in double and rounded to T.
+#define SE2C_SQRT1_2 0.70710678118654752440084436210484903928
+#define SE2C_COS_PI8 0.92387953251128675612818318939678828682
+#define SE2C_SIN_PI8 0.38268343236508977172845998403039886676
+#define SE2C_SQRT3_2 0.86602540378443864676372317075293618347
+
+template <typename T, bool INV> __device__ __forceinline__ void dft2(C<T>* a) {
+    C<T> t = a[0];
+    a[0] = add<T>(t, a[1]);
+    a[1] = sub<T>(t, a[1]);
+}
+
+template <typename T, bool INV> __device__ __forceinline__ void dft3(C<T>* a) {
+    const T h = (T)SE2C_SQRT3_2;
+    C<T> s = add<T>(a[1], a[2]);
+    C<T> d = sub<T>(a[1], a[2]);
+    C<T> m = mk<T>(a[0].x - (T)0.5 * s.x, a[0].y - (T)0.5 * s.y);
+    // -i*h*d (forward) / +i*h*d (inverse)
+    C<T> r = rot<T, INV>(scl<T>(d, h));
+    a[0] = add<T>(a[0], s);
+    a[1] = add<T>(m, r);
+    a[2] = sub<T>(m, r);
+}
+
+template <typename T, bool INV> __device__ __forceinline__ void dft4(C<T>* a) {
+    C<T> t0 = add<T>(a[0], a[2]);
+    C<T> t1 = sub<T>(a[0], a[2]);
+    C<T> t2 = add<T>(a[1], a[3]);
+    C<T> t3 = rot<T, INV>(sub<T>(a[1], a[3]));
+    a[0] = add<T>(t0, t2);
+    a[2] = sub<T>(t0, t2);
+    a[1] = add<T>(t1, t3);
+    a[3] = sub<T>(t1, t3);
+}
+
+template <typename T, bool INV> __device__ __forceinline__ void dft8(C<T>* a) {
+    C<T> e[4] = {a[0], a[2], a[4], a[6]};
+    C<T> o[4] = {a[1], a[3], a[5], a[7]};
+    dft4<T, INV>(e);
+    dft4<T, INV>(o);
+    const T r = (T)SE2C_SQRT1_2;
+    o[1] = rotw<T, INV>(o[1], r, r);        // w8^1
+    o[2] = rot<T, INV>(o[2]);               // w8^2 = -i
+    o[3] = rotw<T, INV>(o[3], -r, r);       // w8^3
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        a[k] = add<T>(e[k], o[k]);
+        a[k + 4] = sub<T>(e[k], o[k]);
+    }
+}
+
+template <typename T, bool INV> __device__ __forceinline__ void dft16(C<T>* a) {
+    // 16 = 4 x 4: column DFTs over n1, twiddle w16^{n2 k1}, row DFTs over n2.
+    C<T> y[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+        C<T> t[4] = {a[n2], a[4 + n2], a[8 + n2], a[12 + n2]};
+        dft4<T, INV>(t);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = t[k1];
+    }
+    const T c1 = (T)SE2C_COS_PI8, s1 = (T)SE2C_SIN_PI8, r = (T)SE2C_SQRT1_2;
+    // n2 = 1: w^1, w^2, w^3 ; n2 = 2: w^2, w^4, w^6 ; n2 = 3: w^3, w^6, w^9
+    y[1][1] = rotw<T, INV>(y[1][1], c1, s1);
+    y[1][2] = rotw<T, INV>(y[1][2], r, r);
+    y[1][3] = rotw<T, INV>(y[1][3], s1, c1);
+    y[2][1] = rotw<T, INV>(y[2][1], r, r);
+    y[2][2] = rot<T, INV>(y[2][2]);
+    y[2][3] = rotw<T, INV>(y[2][3], -r, r);
+    y[3][1] = rotw<T, INV>(y[3][1], s1, c1);
+    y[3][2] = rotw<T, INV>(y[3][2], -r, r);
+    y[3][3] = rotw<T, INV>(y[3][3], -c1, -s1);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        C<T> t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+        dft4<T, INV>(t);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) a[k1 + 4 * k2] = t[k2];
+    }
+}
+
+template <int R, typename T, bool INV> __device__ __forceinline__ void dftR(C<T>* a) {
+    if constexpr (R == 2) dft2<T, INV>(a);
+    else if constexpr (R == 3) dft3<T, INV>(a);
+    else if constexpr (R == 4) dft4<T, INV>(a);
+    else if constexpr (R == 8) dft8<T, INV>(a);
+    else dft16<T, INV>(a);
+}
+
+// Division by a small runtime divisor d (1 <= d, n < 2^21) via a 32x32->64
+// multiply by ceil(2^42/d): exact for all n < 2^21 because n*d < 2^42.
+struct FastDiv {
+    uint32_t d;
+    uint64_t m;
+};
+__host__ __device__ inline FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f;
+    f.d = d;
+    f.m = ((uint64_t(1) << 42) + d - 1) / d;
+    return f;
+}
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
+    return (uint32_t)((uint64_t(n) * f.m) >> 42);
+}
+
+// One radix-R stage over 'nlines' lines of length L in LDS.
+// Element (line, e) lives at buf[line*ls + e*es].  'line_fast' selects whether
+// consecutive threads walk consecutive lines (use when ls == 1) or consecutive
+// butterflies within a line (use when es == 1).
+struct StageGeom {
+    int L, Ns, es, ls, nlines;
+    FastDiv div_nbl;  // L/R (butterflies per line)
+    FastDiv div_ns;   // Ns
+    FastDiv div_nl;   // nlines
+    int tw_step;      // L/(Ns*R)
+};
+
+template <typename T, int R, int MAXV, bool INV>
+__device__ __forceinline__ void stockham_stage(C<T>* buf, const C<T>* tw, const StageGeom g,
+                                               bool line_fast, int tid, int nthr) {
+    constexpr int U = (MAXV + R - 1) / R;
+    const int nbl = g.L / R;
+    const int nb = nbl * g.nlines;
+    C<T> v[U][R];
+    int dst[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int b = tid + u * nthr;
+        dst[u] = -1;
+        if (b < nb) {
+            int line, j;
+            if (line_fast) {
+                j = (int)fdiv((uint32_t)b, g.div_nl);
+                line = b - j * g.nlines;
+            } else {
+                line = (int)fdiv((uint32_t)b, g.div_nbl);
+                j = b - line * nbl;
+            }
+            const int jq = (int)fdiv((uint32_t)j, g.div_ns);
+            const int k = j - jq * g.Ns;
+            const C<T>* src = buf + line * g.ls + j * g.es;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[u][r] = src[r * nbl * g.es];
+            if (g.Ns > 1) {
+                const int step = k * g.tw_step;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C<T> w = tw[r * step];
+                    v[u][r] = INV ? mulc<T>(v[u][r], w) : mul<T>(v[u][r], w);
+                }
+            }
+            dftR<R, T, INV>(v[u]);
+            dst[u] = line * g.ls + (jq * g.Ns * R + k) * g.es;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (dst[u] >= 0) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[dst[u] + r * g.Ns * g.es] = v[u][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Radix plan for one transform length: up to 6 stages.
+struct RadixPlan {
+    int L;
+    int nst;
+    int r[6];
+};
+
+// Transform 'nlines' lines of length p.L (forward or inverse) in LDS.
+template <typename T, int MAXV, bool INV>
+__device__ void line_fft(C<T>* buf, const C<T>* tw, const RadixPlan& p, int es, int ls, int nlines,
+                         bool line_fast, int tid, int nthr) {
+    int Ns = 1;
+    for (int s = 0; s < p.nst; ++s) {
+        const int R = p.r[s];
+        StageGeom g;
+        g.L = p.L;
+        g.Ns = Ns;
+        g.es = es;
+        g.ls = ls;
+        g.nlines = nlines;
+        g.div_nbl = make_fastdiv((uint32_t)(p.L / R));
+        g.div_ns = make_fastdiv((uint32_t)Ns);
+        g.div_nl = make_fastdiv((uint32_t)nlines);
+        g.tw_step = p.L / (Ns * R);
+        switch (R) {
+            case 16: stockham_stage<T, 16, MAXV, INV>(buf, tw, g, line_fast, tid, nthr); break;
+            case 8: stockham_stage<T, 8, MAXV, INV>(buf, tw, g, line_fast, tid, nthr); break;
+            case 4: stockham_stage<T, 4, MAXV, INV>(buf, tw, g, line_fast, tid, nthr); break;
+            case 3: stockham_stage<T, 3, MAXV, INV>(buf, tw, g, line_fast, tid, nthr); break;
+            default: stockham_stage<T, 2, MAXV, INV>(buf, tw, g, line_fast, tid, nthr); break;
+        }
+        Ns *= R;
+    }
+}
+
+}  // namespace se2c

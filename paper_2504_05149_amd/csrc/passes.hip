@@ -1,0 +1,332 @@
+// Pass kernels of the convolutional finite Fourier series on an Nx x Ny x M grid.
+//
+// Data layout in HBM: real samples F[item][theta][y][x], x fastest (the memory
+// order of the paper's F(i, j, l), Sec. 3.2 eq. (OmL)).
+//
+// Real fields are complexified two at a time (z = a + i b) so that every
+// transform is a full-length complex FFT:
+//   * y-pair  : rows y = 2s and 2s+1 of one field (used when y is not transformed
+//               in this pass and the kernel table is separable);
+//   * x-pair  : columns x = 2c and 2c+1 (a float2 / double2 load);
+//   * planes  : two separate real planes, e.g. two fields of a batch, or the
+//               real/imaginary planes of an intermediate spectrum.
+// Because the convolution kernel is real in space, conv(a + i b) = conv(a) +
+// i conv(b), so the pair is separated again just by taking Re and Im.
+//
+// slab_kernel   : tile = one (theta, x) plane: FFT along x and (optionally)
+//                 theta, optional separable spectral product, inverse.
+// pencil_kernel : tile = W adjacent columns x one line along y or theta: FFT
+//                 along that axis, optional spectral product (1-D factor of a
+//                 separable table, or full 3-D table), inverse.
+#include "fft_device.hpp"
+#include "passes.hpp"
+
+namespace se2c {
+
+template <typename T>
+__device__ __forceinline__ void load_tw(C<T>* dst, const void* src, int L, int tid, int nthr) {
+    const C<T>* s = reinterpret_cast<const C<T>*>(src);
+    for (int i = tid; i < L; i += nthr) dst[i] = s[i];
+}
+
+// ---------------------------------------------------------------- slab pass
+template <typename T, int MAXV>
+__global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) slab_kernel(SlabArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C<T>* tile = reinterpret_cast<C<T>*>(smem_raw);
+    const int pitch = a.nx + a.pad;                 // row pitch (complex) in LDS
+    const int rows = a.rows_per_tile;
+    C<T>* twx = tile + rows * pitch;
+    C<T>* twt = twx + a.nx;
+    C<T>* fx = twt + a.m;                           // separable factors (scaled)
+    C<T>* ft = fx + a.nx;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+
+    load_tw<T>(twx, a.twx, a.nx, tid, nthr);
+    if (a.do_t) load_tw<T>(twt, a.twt, a.m, tid, nthr);
+    if (a.mul) {
+        const T sc = (T)a.scale;
+        for (int i = tid; i < a.nx; i += nthr) {
+            C<T> v = mk<T>(sc, (T)0);
+            for (int j = 0; j < a.ntab; ++j) v = mul<T>(v, reinterpret_cast<const C<T>*>(a.tx[j])[i]);
+            if (a.conj_tab) v.y = -v.y;
+            fx[i] = v;
+        }
+        if (a.do_t) {
+            for (int i = tid; i < a.m; i += nthr) {
+                C<T> v = mk<T>((T)1, (T)0);
+                for (int j = 0; j < a.ntab; ++j) v = mul<T>(v, reinterpret_cast<const C<T>*>(a.tt[j])[i]);
+                if (a.conj_tab) v.y = -v.y;
+                ft[i] = v;
+            }
+        }
+    }
+    // (twiddles become visible at the first barrier inside the tile loop)
+
+    const long long plane = (long long)a.nx * a.ny;
+    const int tiles_per_item = a.nslab * a.ntile_t;
+    const int ntiles = tiles_per_item * a.nitems;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int item = t / tiles_per_item;
+        const int rem = t - item * tiles_per_item;
+        const int slab = rem / a.ntile_t;
+        const int t0 = (rem - slab * a.ntile_t) * rows;
+        const bool last_odd = (a.lone_in1 != nullptr || a.lone_out1 != nullptr) && item == a.nitems - 1;
+
+        // ---- load: tile[r][x] for theta = t0 + r
+        const T* in0 = reinterpret_cast<const T*>(a.in0) + (long long)item * a.item_stride_in;
+        const T* in1;
+        if (a.in_mode == 0) {
+            in0 += (long long)(2 * slab) * a.nx;
+            in1 = in0 + a.nx;
+        } else {
+            in0 += (long long)slab * a.nx;
+            in1 = last_odd ? reinterpret_cast<const T*>(a.lone_in1)
+                           : (a.in1 ? reinterpret_cast<const T*>(a.in1) + (long long)item * a.item_stride_in : nullptr);
+            if (in1) in1 += (long long)slab * a.nx;
+        }
+        __syncthreads();
+        const int P = rows * a.nx;
+        for (int i = tid; i < P; i += nthr) {
+            const int r = i / a.nx;
+            const int x = i - r * a.nx;
+            const long long off = (long long)(t0 + r) * plane + x;
+            C<T> v;
+            v.x = in0[off];
+            v.y = in1 ? in1[off] : (T)0;
+            tile[r * pitch + x] = v;
+        }
+        __syncthreads();
+
+        // ---- forward
+        if (a.fwd) {
+            line_fft<T, MAXV, false>(tile, twx, a.px, 1, pitch, rows, false, tid, nthr);
+            if (a.do_t) line_fft<T, MAXV, false>(tile, twt, a.pt, pitch, 1, a.nx, true, tid, nthr);
+        }
+        // ---- separable spectral product: z[kt][kx] *= Tx[kx] * Tt[kt] / (nx*m)
+        if (a.mul) {
+            for (int i = tid; i < P; i += nthr) {
+                const int r = i / a.nx;
+                const int x = i - r * a.nx;
+                const C<T> f = a.do_t ? mul<T>(fx[x], ft[t0 + r]) : fx[x];
+                tile[r * pitch + x] = mul<T>(tile[r * pitch + x], f);
+            }
+            __syncthreads();
+        }
+        // ---- inverse
+        if (a.inv) {
+            if (a.do_t) line_fft<T, MAXV, true>(tile, twt, a.pt, pitch, 1, a.nx, true, tid, nthr);
+            line_fft<T, MAXV, true>(tile, twx, a.px, 1, pitch, rows, false, tid, nthr);
+        }
+
+        // ---- store
+        T* out0 = reinterpret_cast<T*>(a.out0) + (long long)item * a.item_stride_out;
+        T* out1;
+        if (a.out_mode == 0) {
+            out0 += (long long)(2 * slab) * a.nx;
+            out1 = out0 + a.nx;
+        } else {
+            out0 += (long long)slab * a.nx;
+            out1 = last_odd ? reinterpret_cast<T*>(a.lone_out1)
+                            : (a.out1 ? reinterpret_cast<T*>(a.out1) + (long long)item * a.item_stride_out : nullptr);
+            if (out1) out1 += (long long)slab * a.nx;
+        }
+        for (int i = tid; i < P; i += nthr) {
+            const int r = i / a.nx;
+            const int x = i - r * a.nx;
+            const long long off = (long long)(t0 + r) * plane + x;
+            const C<T> v = tile[r * pitch + x];
+            out0[off] = v.x;
+            if (out1) out1[off] = v.y;
+        }
+    }
+}
+
+// -------------------------------------------------------------- pencil pass
+template <typename T, int MAXV>
+__global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) pencil_kernel(PencilArgs a) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C<T>* tile = reinterpret_cast<C<T>*>(smem_raw);
+    const int L = a.p.L;
+    const int pitch = a.W + a.pad;                  // LDS pitch between consecutive axis points
+    C<T>* tw = tile + L * pitch;
+    C<T>* f1 = tw + L;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+
+    load_tw<T>(tw, a.tw, L, tid, nthr);
+    if (a.mul == 1) {
+        const T sc = (T)a.scale;
+        for (int i = tid; i < L; i += nthr) {
+            C<T> v = mk<T>(sc, (T)0);
+            for (int j = 0; j < a.ntab; ++j) v = mul<T>(v, reinterpret_cast<const C<T>*>(a.tab1[j])[i]);
+            if (a.conj_tab) v.y = -v.y;
+            f1[i] = v;
+        }
+    }
+
+    const long long plane = (long long)a.nx * a.ny;
+    // element stride along the transform axis (in real elements)
+    const long long astride = (a.axis == 1) ? (long long)a.nx : plane;
+    const int nother = (a.axis == 1) ? a.m : a.ny;
+    const int ncol_tiles = (a.ncols + a.W - 1) / a.W;
+    const int tiles_per_item = ncol_tiles * nother;
+    const int ntiles = tiles_per_item * a.nitems;
+    const int P = L * a.W;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int item = t / tiles_per_item;
+        const int rem = t - item * tiles_per_item;
+        const int other = rem / ncol_tiles;
+        const int c0 = (rem - other * ncol_tiles) * a.W;
+        const bool last_odd = (a.lone_in1 != nullptr || a.lone_out1 != nullptr) && item == a.nitems - 1;
+        const long long obase = (a.axis == 1) ? (long long)other * plane : (long long)other * a.nx;
+
+        __syncthreads();
+        if (a.mode == 0) {
+            // x-pair view: complex column c = (x = 2c, x = 2c + 1)
+            const C<T>* in = reinterpret_cast<const C<T>*>(
+                reinterpret_cast<const T*>(a.in0) + (long long)item * a.item_stride_in + obase);
+            for (int i = tid; i < P; i += nthr) {
+                const int e = i / a.W;
+                const int c = i - e * a.W;
+                C<T> v = mk<T>((T)0, (T)0);
+                if (c0 + c < a.ncols) v = in[(e * astride) / 2 + c0 + c];
+                tile[e * pitch + c] = v;
+            }
+        } else {
+            const T* in0 = reinterpret_cast<const T*>(a.in0) + (long long)item * a.item_stride_in + obase;
+            const T* in1 = last_odd ? reinterpret_cast<const T*>(a.lone_in1)
+                                    : (a.in1 ? reinterpret_cast<const T*>(a.in1) + (long long)item * a.item_stride_in : nullptr);
+            if (in1) in1 += obase;
+            for (int i = tid; i < P; i += nthr) {
+                const int e = i / a.W;
+                const int c = i - e * a.W;
+                C<T> v = mk<T>((T)0, (T)0);
+                if (c0 + c < a.ncols) {
+                    const long long off = e * astride + c0 + c;
+                    v.x = in0[off];
+                    v.y = in1 ? in1[off] : (T)0;
+                }
+                tile[e * pitch + c] = v;
+            }
+        }
+        __syncthreads();
+
+        if (a.fwd) line_fft<T, MAXV, false>(tile, tw, a.p, pitch, 1, a.W, true, tid, nthr);
+        if (a.mul == 1) {
+            for (int i = tid; i < P; i += nthr) {
+                const int e = i / a.W;
+                const int c = i - e * a.W;
+                tile[e * pitch + c] = mul<T>(tile[e * pitch + c], f1[e]);
+            }
+            __syncthreads();
+        } else if (a.mul == 2) {
+            // full-table product (axis == y): element (kx = c0 + c, ky = e, kt = other);
+            // a separable table contributes Tx[kx] Ty[ky] Tt[kt].
+            const T sc = (T)a.scale;
+            for (int i = tid; i < P; i += nthr) {
+                const int e = i / a.W;
+                const int c = i - e * a.W;
+                if (c0 + c < a.ncols) {
+                    const int kx = c0 + c;
+                    C<T> w = mk<T>(sc, (T)0);
+                    for (int j = 0; j < a.ntab; ++j) {
+                        if (a.tab3[j]) {
+                            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.tab3[j])[(long long)other * plane + (long long)e * a.nx + kx]);
+                        } else {
+                            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.sepx[j])[kx]);
+                            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.sepy[j])[e]);
+                            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.sept[j])[other]);
+                        }
+                    }
+                    if (a.conj_tab) w.y = -w.y;
+                    tile[e * pitch + c] = mul<T>(tile[e * pitch + c], w);
+                }
+            }
+            __syncthreads();
+        }
+        if (a.inv) line_fft<T, MAXV, true>(tile, tw, a.p, pitch, 1, a.W, true, tid, nthr);
+
+        if (a.mode == 0) {
+            C<T>* out = reinterpret_cast<C<T>*>(
+                reinterpret_cast<T*>(a.out0) + (long long)item * a.item_stride_out + obase);
+            for (int i = tid; i < P; i += nthr) {
+                const int e = i / a.W;
+                const int c = i - e * a.W;
+                if (c0 + c < a.ncols) out[(e * astride) / 2 + c0 + c] = tile[e * pitch + c];
+            }
+        } else {
+            T* out0 = reinterpret_cast<T*>(a.out0) + (long long)item * a.item_stride_out + obase;
+            T* out1 = last_odd ? reinterpret_cast<T*>(a.lone_out1)
+                               : (a.out1 ? reinterpret_cast<T*>(a.out1) + (long long)item * a.item_stride_out : nullptr);
+            if (out1) out1 += obase;
+            for (int i = tid; i < P; i += nthr) {
+                const int e = i / a.W;
+                const int c = i - e * a.W;
+                if (c0 + c < a.ncols) {
+                    const long long off = e * astride + c0 + c;
+                    const C<T> v = tile[e * pitch + c];
+                    out0[off] = v.x;
+                    if (out1) out1[off] = v.y;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ host launchers
+template <typename T, int MAXV>
+static hipError_t launch_slab_t(const SlabArgs& a, int nthr, int nblocks, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((slab_kernel<T, MAXV>), dim3(nblocks), dim3(nthr), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int MAXV>
+static hipError_t launch_pencil_t(const PencilArgs& a, int nthr, int nblocks, size_t lds, hipStream_t s) {
+    hipLaunchKernelGGL((pencil_kernel<T, MAXV>), dim3(nblocks), dim3(nthr), lds, s, a);
+    return hipGetLastError();
+}
+
+// Allow every pass kernel the full 160 KB of LDS (done once, outside any capture).
+hipError_t prepare_generic_kernels() {
+    const int lds = 160 * 1024;
+    const void* fns[] = {reinterpret_cast<const void*>(slab_kernel<float, SE2C_MAXV>),
+                         reinterpret_cast<const void*>(slab_kernel<double, SE2C_MAXV>),
+                         reinterpret_cast<const void*>(pencil_kernel<float, SE2C_MAXV>),
+                         reinterpret_cast<const void*>(pencil_kernel<double, SE2C_MAXV>)};
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+size_t slab_lds_bytes(const SlabArgs& a, bool dbl) {
+    const size_t cb = dbl ? 16 : 8;
+    return cb * ((size_t)a.rows_per_tile * (a.nx + a.pad) + 2 * (size_t)a.nx + 2 * (size_t)a.m);
+}
+
+size_t pencil_lds_bytes(const PencilArgs& a, bool dbl) {
+    const size_t cb = dbl ? 16 : 8;
+    return cb * ((size_t)a.p.L * (a.W + a.pad) + 2 * (size_t)a.p.L);
+}
+
+hipError_t launch_slab(const SlabArgs& a, bool dbl, int nthr, int nblocks, hipStream_t s) {
+    const size_t lds = slab_lds_bytes(a, dbl);
+    if (dbl) return launch_slab_t<double, SE2C_MAXV>(a, nthr, nblocks, lds, s);
+    return launch_slab_t<float, SE2C_MAXV>(a, nthr, nblocks, lds, s);
+}
+
+hipError_t launch_pencil(const PencilArgs& a, bool dbl, int nthr, int nblocks, hipStream_t s) {
+    const size_t lds = pencil_lds_bytes(a, dbl);
+    if (dbl) return launch_pencil_t<double, SE2C_MAXV>(a, nthr, nblocks, lds, s);
+    return launch_pencil_t<float, SE2C_MAXV>(a, nthr, nblocks, lds, s);
+}
+
+}  // namespace se2c
+
+namespace se2c {
+hipError_t prepare_kernels() {
+    static hipError_t once = prepare_generic_kernels();
+    return once;
+}
+}  // namespace se2c

@@ -1,0 +1,91 @@
+// Host-visible argument blocks and launchers of the pass kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+
+#include "fft_device.hpp"
+
+#define SE2C_MAXV 16          // complex values held per thread during a stage
+#define SE2C_MAX_TABLES 8     // kernels multiplied at run time in one pass
+// Threads per workgroup: FP32 tiles use up to 1024 (128 VGPRs each), FP64 tiles
+// up to 512 so that the doubled register footprint does not spill.
+#define SE2C_MAX_THREADS(T) (sizeof(T) == 8 ? 512 : 1024)
+
+namespace se2c {
+
+// Tile = rows_per_tile theta-rows x nx of one y-slab.  in_mode/out_mode:
+// 0 = y-pair of one real field (rows 2s, 2s+1), 1 = two real planes (in0, in1).
+struct SlabArgs {
+    const void* in0;
+    const void* in1;
+    void* out0;
+    void* out1;
+    const void* lone_in1;   // plane mode: imaginary input of the last item when the count is odd
+    void* lone_out1;        // plane mode: imaginary output of the last item (nullptr = drop)
+    long long item_stride_in;
+    long long item_stride_out;
+    int nitems;
+    int in_mode, out_mode;
+    int nx, ny, m;
+    int rows_per_tile;
+    int ntile_t;            // theta chunks per slab
+    int nslab;              // slabs per item
+    int pad;                // LDS row padding (complex)
+    int do_t;               // also transform along theta (requires rows_per_tile == m)
+    int fwd, inv;
+    int mul;                // 1: separable product with ntab tables (factors x [and theta])
+    int ntab;
+    const void* tx[SE2C_MAX_TABLES];
+    const void* tt[SE2C_MAX_TABLES];
+    int conj_tab;
+    double scale;
+    RadixPlan px, pt;
+    const void* twx;
+    const void* twt;
+};
+
+// Tile = W adjacent columns x L points along axis (1 = y, 2 = theta) at a fixed
+// other coordinate.  mode 0 = x-pair view of one real field, 1 = two real planes.
+struct PencilArgs {
+    const void* in0;
+    const void* in1;
+    void* out0;
+    void* out1;
+    const void* lone_in1;
+    void* lone_out1;
+    long long item_stride_in;
+    long long item_stride_out;
+    int nitems;
+    int mode;
+    int axis;
+    int nx, ny, m;
+    int ncols;
+    int W;
+    int pad;
+    int fwd, inv;
+    int mul;                // 1: 1-D factors (sep tables), 2: full tables / mixed
+    int ntab;
+    const void* tab1[SE2C_MAX_TABLES];    // 1-D factor along this axis (mul == 1)
+    const void* tab3[SE2C_MAX_TABLES];    // full [m][ny][nx] table, or nullptr if separable
+    const void* sepx[SE2C_MAX_TABLES];    // separable factors for mul == 2 with sep tables
+    const void* sepy[SE2C_MAX_TABLES];
+    const void* sept[SE2C_MAX_TABLES];
+    int conj_tab;
+    double scale;
+    RadixPlan p;
+    const void* tw;
+};
+
+size_t slab_lds_bytes(const SlabArgs& a, bool dbl);
+size_t pencil_lds_bytes(const PencilArgs& a, bool dbl);
+hipError_t launch_slab(const SlabArgs& a, bool dbl, int nthr, int nblocks, hipStream_t s);
+hipError_t launch_pencil(const PencilArgs& a, bool dbl, int nthr, int nblocks, hipStream_t s);
+
+// Raise the dynamic-LDS limit of the pass kernels (call once before any capture).
+hipError_t prepare_generic_kernels();
+hipError_t prepare_kernels();
+
+// FP64 twiddles w_L^j = exp(-2 pi i j / L), j in [0, L), written as double2 and float2.
+hipError_t launch_twiddles(double2* out64, float2* out32, int L, hipStream_t s);
+
+}  // namespace se2c

@@ -1,0 +1,128 @@
+"""C ABI checks that need no GPU: symbols, status strings, host-side validation."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2504_05149_amd as se2
+from paper_2504_05149_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    with open(os.path.join(ROOT, "include", "se2conv.h")) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(se2conv_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    names = _declared_functions()
+    assert "se2conv_apply" in names and "se2conv_chain" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(L.EXPORTED)
+
+
+def test_status_strings():
+    lib = L.load()
+    for code in range(6):
+        assert lib.se2conv_status_string(code)
+    assert lib.se2conv_status_string(99) == b"unknown status"
+
+
+@pytest.mark.parametrize("shape", [(50, 32, 32), (7, 8, 8), (8, 8, 1), (1024, 8, 8), (10, 8, 8), (8, 8, 5)])
+def test_unsupported_sizes(shape):
+    with pytest.raises(se2.Se2convError) as e:
+        se2.Plan([shape], host_only=True)
+    assert e.value.status == L.ERR_UNSUPPORTED_SIZE
+
+
+def test_bad_plan_arguments():
+    lib = L.load()
+    h = ctypes.c_void_p()
+    shp = (L.Shape * 1)(L.Shape(32, 32, 32))
+    assert lib.se2conv_plan(shp, 0, 0, L.PLAN_HOST_ONLY, ctypes.byref(h)) == L.ERR_INVALID_ARG
+    assert lib.se2conv_plan(shp, 1, 7, L.PLAN_HOST_ONLY, ctypes.byref(h)) == L.ERR_INVALID_ARG
+    assert lib.se2conv_plan(shp, 1, 0, 0x80, ctypes.byref(h)) == L.ERR_INVALID_ARG
+    assert lib.se2conv_plan(shp, 1, 0, L.PLAN_HOST_ONLY, None) == L.ERR_INVALID_ARG
+
+
+def test_table_sizes_and_kernel_validation():
+    p = se2.Plan([(32, 48, 16)], dtype="f32", host_only=True)
+    assert p.table_bytes(0, [se2.GaussVM(0.05, 4.0)]) == 8 * (32 + 48 + 16)
+    p64 = se2.Plan([(32, 48, 16)], dtype="f64", host_only=True)
+    assert p64.table_bytes(0, [se2.GaussVM(0.05, 4.0), se2.GaussVM(0.1, 2.0)]) == 16 * (32 + 48 + 16)
+    for bad in [se2.GaussVM(0.0, 4.0), se2.GaussVM(0.05, -1.0), se2.GaussVM(float("nan"), 1.0),
+                se2.GaussVM(0.05, 4.0, norm=3)]:
+        with pytest.raises(se2.Se2convError) as e:
+            p.table_bytes(0, [bad])
+        assert e.value.status == L.ERR_INVALID_ARG
+    lib = L.load()
+    d = L.KernelDesc()
+    d.kind = L.K_SAMPLES  # null data pointer
+    n = ctypes.c_size_t(0)
+    assert lib.se2conv_coeffs(p.handle, 0, ctypes.byref(d), 1, None, ctypes.byref(n), None) == L.ERR_INVALID_ARG
+    d.kind = L.K_RADIAL_PROFILE
+    d.data = 16
+    d.n_knots = 1
+    d.r_max = 0.5
+    assert lib.se2conv_coeffs(p.handle, 0, ctypes.byref(d), 1, None, ctypes.byref(n), None) == L.ERR_INVALID_ARG
+    d.n_knots = 8
+    d.r_max = 1.5
+    assert lib.se2conv_coeffs(p.handle, 0, ctypes.byref(d), 1, None, ctypes.byref(n), None) == L.ERR_INVALID_ARG
+    d.r_max = 0.5
+    assert lib.se2conv_coeffs(p.handle, 0, ctypes.byref(d), 1, None, ctypes.byref(n), None) == L.OK
+    assert n.value == 8 * 32 * 48 * 16
+    d.kind = 9
+    assert lib.se2conv_coeffs(p.handle, 0, ctypes.byref(d), 1, None, ctypes.byref(n), None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_coeffs(p.handle, 3, ctypes.byref(d), 1, None, ctypes.byref(n), None) == L.ERR_INVALID_ARG
+
+
+def test_apply_validation_on_host_only_plan():
+    lib = L.load()
+    p = se2.Plan([(32, 32, 16)], dtype="f32", host_only=True)
+    h = p.handle
+    fake_table = 4096
+    # bad shape index, batch, null and misaligned pointers, overlap, flags
+    assert lib.se2conv_apply(h, 1, 256, fake_table, 512, 1, 0, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_apply(h, 0, 256, fake_table, 512, 0, 0, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_apply(h, 0, None, fake_table, 512, 1, 0, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_apply(h, 0, 260, fake_table, 1 << 30, 1, 0, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_apply(h, 0, 1 << 20, fake_table, (1 << 20) + 64, 1, 0, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_apply(h, 0, 1 << 20, fake_table, 1 << 30, 1, 0x80, None) == L.ERR_INVALID_ARG
+    # a table this plan did not produce
+    assert lib.se2conv_apply(h, 0, 1 << 20, fake_table, 1 << 30, 1, 0, None) == L.ERR_INVALID_ARG
+    assert b"not produced by this plan" in lib.se2conv_last_error()
+    # in place is allowed (fails only on the table)
+    assert lib.se2conv_apply(h, 0, 1 << 20, fake_table, 1 << 20, 1, 0, None) == L.ERR_INVALID_ARG
+    # coefficient generation on a host-only plan: validated, then refused as device work
+    d = L.KernelDesc()
+    d.kind, d.sigma, d.kappa = L.K_GAUSS_VM, 0.05, 4.0
+    n = ctypes.c_size_t(1 << 20)
+    assert lib.se2conv_coeffs(h, 0, ctypes.byref(d), 1, 1 << 16, ctypes.byref(n), None) == L.ERR_DEVICE
+
+
+def test_chain_validation_on_host_only_plan():
+    lib = L.load()
+    p = se2.Plan([(32, 32, 16)], dtype="f32", host_only=True)
+    arr = (L.Problem * 1)()
+    tabs = (ctypes.c_void_p * 1)(4096)
+    arr[0].shape_idx, arr[0].batch, arr[0].f, arr[0].out = 0, 1, 1 << 20, 1 << 30
+    arr[0].tables = ctypes.cast(tabs, ctypes.POINTER(ctypes.c_void_p))
+    arr[0].n_tables = 0
+    assert lib.se2conv_chain(p.handle, arr, 1, 0, None) == L.ERR_INVALID_ARG
+    arr[0].n_tables = 9
+    assert lib.se2conv_chain(p.handle, arr, 1, 0, None) == L.ERR_INVALID_ARG
+    arr[0].n_tables = 1
+    assert lib.se2conv_chain(p.handle, arr, 1, 0, None) == L.ERR_INVALID_ARG  # foreign table
+    assert lib.se2conv_chain(p.handle, arr, 0, 0, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_chain(p.handle, arr, 1, L.GRAPH | L.TIMING, None) == L.ERR_INVALID_ARG
+
+
+def test_pass_times_empty_on_fresh_plan():
+    p = se2.Plan([(32, 32, 16)], dtype="f32", host_only=True)
+    assert p.pass_times() == []
