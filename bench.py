@@ -85,10 +85,34 @@ def run_gpu(name, steps, warmup):
     for kind, ms in times:
         per_kind.setdefault(kind, []).append(ms)
     avg = {k: float(np.mean(v)) for k, v in per_kind.items()}
+    launches = {k: len(v) / steps for k, v in per_kind.items()}
     out_host = out.cpu().numpy()
     plan.close()
-    return dict(elapsed=elapsed, avg_ms=avg, f_host=f_host, out_host=out_host, ks=ks, shape=(nx, ny, m),
-                batch=batch, dtype=dt)
+    return dict(elapsed=elapsed, avg_ms=avg, launches=launches, f_host=f_host, out_host=out_host, ks=ks,
+                shape=(nx, ny, m), batch=batch, dtype=dt)
+
+
+def copy_calibration(name, steps, warmup):
+    """A plain copy of the batch (one read + one write of every sample), timed with events."""
+    import torch
+
+    nx, ny, m, batch, nb, lc, dt, cfg = WORKLOADS[name]
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    f = torch.rand(batch, m, ny, nx, device="cuda", dtype=tdt)
+    out = torch.empty_like(f)
+    for _ in range(warmup):
+        out.copy_(f)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        out.copy_(f)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / steps
+    nbytes = 2 * f.numel() * f.element_size()
+    return {"copy_calibration": name, "bytes_per_copy": nbytes, "ms_per_copy": round(ms, 5),
+            "GBps": round(nbytes / (ms * 1e-3) / 1e9, 1)}
 
 
 def traffic_for(kernel: str, workload: str, src_hash: str):
@@ -141,12 +165,18 @@ def main():
     ap.add_argument("--workload", default="headline", choices=sorted(WORKLOADS))
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="time a plain device copy of the workload's input instead (calibrates HBM "
+                         "byte counters and gives the achievable streaming bandwidth)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
                                    "(the batch shards across GPUs with no communication, see DESIGN.md)"}))
         sys.exit(2)
 
+    if args.copy_calibration:
+        print(json.dumps(copy_calibration(args.workload, args.steps, args.warmup)), flush=True)
+        return
     res = run_gpu(args.workload, args.steps, args.warmup)
     nx, ny, m = res["shape"]
     n = nx * ny * m
@@ -155,9 +185,12 @@ def main():
     value = batch * args.steps / res["elapsed"]
     rb = 4 if res["dtype"] == "f32" else 8
     alg_bytes_step = 2 * rb * n * batch              # read f, write out (algorithmic)
-    dom = max(res["avg_ms"], key=lambda k: res["avg_ms"][k])
+    # dominant pass = largest total time per step; each launch of a pass streams its
+    # share of the batch once in and once out
+    dom = max(res["avg_ms"], key=lambda k: res["avg_ms"][k] * res["launches"][k])
     dom_ms = res["avg_ms"][dom]
-    achieved = alg_bytes_step / (dom_ms * 1e-3) / 1e9    # each pass streams the batch once in, once out
+    alg_bytes_launch = alg_bytes_step / res["launches"][dom]
+    achieved = alg_bytes_launch / (dom_ms * 1e-3) / 1e9
     src = lib_source_hash()
     traffic = traffic_for(dom, args.workload, src)
     line = {
@@ -178,7 +211,8 @@ def main():
         "pass_ms": {k: round(v, 4) for k, v in res["avg_ms"].items()},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "alg_bytes_per_launch": alg_bytes_step},
+                     "traffic": traffic, "alg_bytes_per_launch": alg_bytes_launch,
+                     "launches_per_step": res["launches"][dom]},
         "source_hash": src,
     }
     if not args.no_cpu:

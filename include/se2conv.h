@@ -54,6 +54,8 @@ typedef struct {
 #define SE2CONV_PLAN_HOST_ONLY 0x1u /* validation-only plan: no device resources; every
                                        call that would enqueue work returns ERR_DEVICE
                                        after validating its arguments */
+#define SE2CONV_PLAN_GENERIC 0x2u   /* use only the general LDS-Stockham pass kernels (no
+                                       shape-specialised register kernels); for testing and tuning */
 
 /*
  * se2conv_plan: create a plan for a list of grid shapes and a compute dtype.

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libse2conv.so")
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED_SIZE, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_INTERNAL = range(6)
 F32, F64 = 0, 1
 PLAN_HOST_ONLY = 0x1
+PLAN_GENERIC = 0x2
 K_GAUSS_VM, K_SAMPLES, K_RADIAL_PROFILE = 0, 1, 2
 KNORM_DISCRETE, KNORM_CONTINUOUS, KNORM_NONE = 0, 1, 2
 TABLE_SEPARABLE, TABLE_FULL = 0, 1

@@ -87,15 +87,15 @@ class Table:
 
 
 class Plan:
-    def __init__(self, shapes, dtype: str = "f32", host_only: bool = False):
+    def __init__(self, shapes, dtype: str = "f32", host_only: bool = False, generic: bool = False):
         self._lib = L.load()
         self.shapes = [tuple(int(v) for v in s) for s in shapes]
         self.dtype = {"f32": L.F32, "f64": L.F64}[dtype]
         self.tdtype = torch.float32 if self.dtype == L.F32 else torch.float64
         arr = (L.Shape * len(self.shapes))(*[L.Shape(*s) for s in self.shapes])
         h = ctypes.c_void_p()
-        L.check(self._lib.se2conv_plan(arr, len(self.shapes), self.dtype,
-                                       L.PLAN_HOST_ONLY if host_only else 0, ctypes.byref(h)))
+        flags = (L.PLAN_HOST_ONLY if host_only else 0) | (L.PLAN_GENERIC if generic else 0)
+        L.check(self._lib.se2conv_plan(arr, len(self.shapes), self.dtype, flags, ctypes.byref(h)))
         self.handle = h
         self._tables = []
 

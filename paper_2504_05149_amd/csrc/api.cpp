@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <set>
@@ -17,6 +18,7 @@
 #include "../../include/se2conv.h"
 #include "coeffs.hpp"
 #include "passes.hpp"
+#include "sep_fast.hpp"
 
 using namespace se2c;
 
@@ -60,6 +62,10 @@ bool shape_supported(const se2conv_shape& s, std::string* why) {
     }
     if ((s.nx & 1) || (s.ny & 1)) {
         *why = "Nx and Ny must be even";
+        return false;
+    }
+    if ((long long)s.nx * s.ny * s.m >= (1LL << 30)) {
+        *why = "Nx * Ny * M must be below 2^30 points per field";
         return false;
     }
     if (s.m < 2 || s.m > 512) {
@@ -122,6 +128,7 @@ struct GraphRec {
 
 struct se2conv_plan_s {
     int device = -1;
+    int num_cus = 256;
     se2conv_dtype dtype = SE2CONV_F32;
     uint32_t flags = 0;
     bool host_only = false;
@@ -192,6 +199,21 @@ bool slab_fits(const se2conv_shape& s, bool d) {
     a.pad = 0;
     const long long P = (long long)s.nx * s.m;
     return P <= (long long)SE2C_MAXV * max_threads(d) && slab_lds_bytes(a, d) <= kMaxLds;
+}
+
+// Fields per launch of the separable two-pass schedule.  Measured on MI355X at
+// 256x256x64: chunks small enough to keep the intermediate in the memory-side
+// cache (8, 4, 2 fields) were not faster than one launch over the whole batch,
+// so the default is the whole batch.  SE2CONV_SEP_CHUNK overrides (tuning only).
+int sep_chunk_fields(const se2conv_plan_s* p, const se2conv_shape& s, int batch) {
+    (void)p;
+    (void)s;
+    static const int env_chunk = [] {
+        const char* e = std::getenv("SE2CONV_SEP_CHUNK");
+        return e ? std::atoi(e) : 0;
+    }();
+    if (env_chunk > 0) return std::min(env_chunk, batch);
+    return batch;
 }
 
 int rows_for_xpass(const se2conv_shape& s) {
@@ -269,6 +291,52 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
         a.tt[j] = ftt(j);
     }
     const bool two_pass = slab_fits(s, d);
+    const bool generic_only = (p->flags & SE2CONV_PLAN_GENERIC) != 0;
+    FastSepArgs fa{};
+    fa.in = reinterpret_cast<const float*>(f);
+    fa.out = reinterpret_cast<float*>(out);
+    fa.n = n;
+    fa.nitems = batch;
+    fa.nx = s.nx;
+    fa.ny = s.ny;
+    fa.m = s.m;
+    fa.ntab = ch.ntab;
+    fa.conj_tab = conj ? 1 : 0;
+    fa.grid_blocks = p->num_cus * 4;
+    for (int j = 0; j < ch.ntab; ++j) {
+        fa.tx[j] = fx(j);
+        fa.ty[j] = fy(j);
+        fa.tt[j] = ftt(j);
+    }
+    const bool fast_slab = !d && !generic_only && two_pass && slab_fast_supported(s.nx, s.m);
+    const bool fast_pencil = !d && !generic_only && two_pass && pencil_fast_supported(s.nx, s.ny);
+    if (fast_slab && fast_pencil) {
+        // Fields are processed in chunks whose intermediate (one real plane set per
+        // field) stays resident in the memory-side cache between the two passes.
+        const int chunk = sep_chunk_fields(p, s, batch);
+        for (int c0 = 0; c0 < batch; c0 += chunk) {
+            FastSepArgs ca = fa;
+            ca.in = reinterpret_cast<const float*>(f) + (long long)c0 * n;
+            ca.out = reinterpret_cast<float*>(out) + (long long)c0 * n;
+            ca.nitems = std::min(chunk, batch - c0);
+            ca.tw = reinterpret_cast<const float2*>(tw_of(p, s.nx, false));
+            ca.twt = reinterpret_cast<const float2*>(tw_of(p, s.m, false));
+            HIPCHK(launch_slab_fast(ca, st));
+            HIPCHK(after_pass(0, st));
+            FastSepArgs cb = ca;
+            cb.in = ca.out;
+            cb.tw = reinterpret_cast<const float2*>(tw_of(p, s.ny, false));
+            HIPCHK(launch_pencil_fast(cb, st));
+            HIPCHK(after_pass(1, st));
+        }
+        return SE2CONV_OK;
+    }
+    if (fast_slab) {
+        fa.tw = reinterpret_cast<const float2*>(tw_of(p, s.nx, false));
+        fa.twt = reinterpret_cast<const float2*>(tw_of(p, s.m, false));
+        HIPCHK(launch_slab_fast(fa, st));
+        HIPCHK(after_pass(0, st));
+    }
     if (two_pass) {
         a.rows_per_tile = s.m;
         a.ntile_t = 1;
@@ -280,7 +348,7 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
         a.do_t = 0;
         a.scale = 1.0 / (double)s.nx;
     }
-    HIPCHK(run_slab(a, d, st));
+    if (!fast_slab) HIPCHK(run_slab(a, d, st));
 
     // pass 2 (and 3): y pencils (and theta pencils) on x-pairs, in place on out
     auto pencil = [&](int axis) -> se2conv_status {
@@ -311,8 +379,17 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
         HIPCHK(run_pencil(b, d, st));
         return SE2CONV_OK;
     };
-    se2conv_status r = pencil(1);
-    if (r != SE2CONV_OK) return r;
+    se2conv_status r = SE2CONV_OK;
+    if (fast_pencil) {
+        FastSepArgs fb = fa;
+        fb.in = reinterpret_cast<const float*>(out);
+        fb.tw = reinterpret_cast<const float2*>(tw_of(p, s.ny, false));
+        HIPCHK(launch_pencil_fast(fb, st));
+        HIPCHK(after_pass(1, st));
+    } else {
+        r = pencil(1);
+        if (r != SE2CONV_OK) return r;
+    }
     if (!two_pass) {
         r = pencil(2);
         if (r != SE2CONV_OK) return r;
@@ -584,7 +661,8 @@ se2conv_status se2conv_plan(const se2conv_shape* shapes, int32_t n_shapes, se2co
     if (!shapes || n_shapes < 1 || n_shapes > 4096)
         return fail(SE2CONV_ERR_INVALID_ARG, "need 1..4096 shapes");
     if (dtype != SE2CONV_F32 && dtype != SE2CONV_F64) return fail(SE2CONV_ERR_INVALID_ARG, "bad dtype %d", (int)dtype);
-    if (flags & ~SE2CONV_PLAN_HOST_ONLY) return fail(SE2CONV_ERR_INVALID_ARG, "unknown plan flags 0x%x", flags);
+    if (flags & ~(SE2CONV_PLAN_HOST_ONLY | SE2CONV_PLAN_GENERIC))
+        return fail(SE2CONV_ERR_INVALID_ARG, "unknown plan flags 0x%x", flags);
     for (int i = 0; i < n_shapes; ++i) {
         std::string why;
         if (!shape_supported(shapes[i], &why))
@@ -608,6 +686,9 @@ se2conv_status se2conv_plan(const se2conv_shape* shapes, int32_t n_shapes, se2co
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
         return cleanup(fail(SE2CONV_ERR_DEVICE, "no HIP device available"));
     if (hipGetDevice(&p->device) != hipSuccess) return cleanup(fail(SE2CONV_ERR_DEVICE, "hipGetDevice failed"));
+    if (hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
+        p->num_cus < 1)
+        return cleanup(fail(SE2CONV_ERR_DEVICE, "could not query the compute-unit count"));
     // twiddles for every distinct length, generated in FP64
     std::vector<int> lens;
     size_t maxn = 0;

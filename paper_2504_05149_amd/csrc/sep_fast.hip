@@ -1,0 +1,372 @@
+// Register-resident FP32 pass kernels for separable kernel tables
+// (rho^[k; L] = Tx[k1] Ty[k2] Tt[k3], e.g. Gaussian x von Mises chains).
+//
+// The separable product commutes with transforms along the other axes, so the
+// convolution factorises into 1-D circular convolutions along x, y and theta
+// (each: DFT, product with the 1-D factor, inverse DFT; the 3-D DFT of eq.
+// (3DFT) is the composition of the three 1-D DFTs).  Two passes over HBM:
+//
+// xt_slab_fast<NX, M>  one block per y-pair (rows 2s, 2s+1 packed as re/im):
+//   1. load the pair in row layout: thread (g, t) holds x = t + R2 r (r < 16) of
+//      rows theta = g + 16 i;
+//   2. x convolution as a 16 x R2 decomposition: radix-16 DFT in registers,
+//      twiddles w_NX^{t k1}, one LDS exchange (XOR-swizzled, bank-conflict
+//      free), radix-R2 DFT, product with Tx/NX, and the mirror-image inverse;
+//   3. transpose rows -> columns through LDS in chunks of 32 rows;
+//   4. theta convolution of a whole column in registers (one column per thread);
+//   5. store columns (each wave writes 1 KB contiguous per theta row).
+// y_pencil_fast<NY>    one block per 16 adjacent x-pairs (float2 columns) at one theta:
+//   the same 16 x R2 scheme along y, product with Ty/NY.
+#include "regfft.hpp"
+#include "sep_fast.hpp"
+
+namespace se2c {
+
+// Position of element (k1, t) of one 16 x R2 exchange line: the XOR swizzle makes
+// both the write (fixed k1, lanes over t) and the read (fixed t, lanes over the
+// k1 groups) hit distinct 8-byte bank slots.
+template <int R2>
+__device__ __forceinline__ int xpos(int k1, int t) {
+    constexpr int CC = 16 / R2;
+    return k1 * R2 + (t ^ (k1 / CC));
+}
+
+__device__ __forceinline__ float2 chain_factor(const void* const* tabs, int ntab, int i, float scale, int conj) {
+    float2 v = make_float2(scale, 0.f);
+    for (int j = 0; j < ntab; ++j) v = mul<float>(v, reinterpret_cast<const float2*>(tabs[j])[i]);
+    if (conj) v.y = -v.y;
+    return v;
+}
+
+// Swap a value with the neighbouring lane (lane ^ 1) through DPP quad_perm [1,0,3,2].
+__device__ __forceinline__ float swap_lane1(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float2 swap_lane1(float2 v) { return make_float2(swap_lane1(v.x), swap_lane1(v.y)); }
+
+// TPC = threads per theta column in the column phase (1: the whole column in one
+// thread; 2: even/odd theta split over neighbouring lanes, radix-2 step via DPP).
+// Two workgroups share a CU (LDS); the register cap keeps both resident.
+template <int NX, int M, int TPC>
+__global__ void __launch_bounds__(NX * TPC)
+__attribute__((amdgpu_waves_per_eu(NX * TPC >= 512 ? 4 : (NX * TPC >= 256 ? 2 : 1))))
+xt_slab_fast(FastSepArgs a) {
+    constexpr int NT = NX * TPC;
+    constexpr int R2 = NX / 16;          // second-stage radix along x
+    constexpr int CC = 16 / R2;          // first-stage frequencies owned per thread after the exchange
+    constexpr int G = NT / R2;           // row groups in row layout
+    constexpr int RPT = M / G;           // theta rows per thread in row layout
+    constexpr int RC = M < 32 ? M : 32;  // rows per transpose chunk
+    constexpr int H = M / RC;
+    constexpr int P = NX + (R2 % 16);    // LDS row pitch (complex)
+    constexpr int MV = M / TPC;          // theta values per thread in column layout
+    static_assert(G <= RC && RPT >= 1 && M % G == 0, "tile geometry");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float2* buf = reinterpret_cast<float2*>(smem_raw);  // RC x P
+    float2* tw_f = buf + RC * P;                         // [k1][t] = w_NX^{t k1}
+    float2* tw_i = tw_f + 16 * R2;                       // [t][k1]
+    float2* fx = tw_i + 16 * R2;                         // Tx / NX
+    float2* ft = fx + NX;                                // Tt / M
+    float2* twm = ft + M;                                // w_M^j (TPC == 2)
+    const int tid = threadIdx.x;
+
+    for (int i = tid; i < 16 * R2; i += NT) {
+        const int k1 = i / R2, t = i - k1 * R2;
+        const float2 w = a.tw[t * k1];
+        tw_f[k1 * R2 + t] = w;
+        tw_i[t * 16 + k1] = w;
+    }
+    for (int i = tid; i < NX; i += NT) fx[i] = chain_factor(a.tx, a.ntab, i, 1.0f / NX, a.conj_tab);
+    for (int i = tid; i < M; i += NT) ft[i] = chain_factor(a.tt, a.ntab, i, 1.0f / M, a.conj_tab);
+    if (TPC == 2)
+        for (int i = tid; i < M; i += NT) twm[i] = a.twt[i];
+    __syncthreads();
+
+    const int t = tid % R2, g = tid / R2;
+    const long long plane = (long long)NX * a.ny;
+    const int pl = (int)plane;
+    const int nslab = a.ny / 2;
+    const int tile = blockIdx.x;  // one y-pair slab per block
+    const int item = tile / nslab;
+    const int s = tile - item * nslab;
+    // uniform tile base; per-lane offsets stay 32-bit (Nx Ny M < 2^30 is checked on the host)
+    const float* __restrict__ in0 = a.in + (long long)item * a.n + (long long)(2 * s) * NX;
+    const float* __restrict__ in1 = in0 + NX;
+
+    // 1. row-layout loads: rows theta = g + G i, columns x = t + R2 r
+    float2 w[RPT][16];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int off = (g + G * i) * pl + t + R2 * r;
+            w[i][r] = make_float2(in0[off], in1[off]);
+        }
+    }
+    // 2. x convolution (16 x R2 decomposition)
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        dft16<float, false>(w[i]);
+#pragma unroll
+        for (int k1 = 1; k1 < 16; ++k1) w[i][k1] = mul<float>(w[i][k1], tw_f[k1 * R2 + t]);
+    }
+    float2* row = buf + g * P;
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+        if (i > 0) __syncthreads();
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) row[xpos<R2>(k1, t)] = w[i][k1];
+        __syncthreads();
+        float2 u[CC][R2];
+#pragma unroll
+        for (int j = 0; j < CC; ++j) {
+            const int k1 = CC * t + j;
+#pragma unroll
+            for (int tt = 0; tt < R2; ++tt) u[j][tt] = row[xpos<R2>(k1, tt)];
+            RegDFT<R2, false, float>::run(u[j]);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = mul<float>(u[j][k2], fx[k1 + 16 * k2]);
+            RegDFT<R2, true, float>::run(u[j]);
+#pragma unroll
+            for (int tt = 1; tt < R2; ++tt) u[j][tt] = mulc<float>(u[j][tt], tw_i[tt * 16 + k1]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CC; ++j) {
+#pragma unroll
+            for (int tt = 0; tt < R2; ++tt) row[xpos<R2>(CC * t + j, tt)] = u[j][tt];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) w[i][k1] = row[xpos<R2>(k1, t)];
+        dft16<float, true>(w[i]);
+    }
+    // 3. rows -> columns through LDS, RC rows at a time
+    const int xc = TPC == 1 ? tid : (tid >> 1);   // column owned in column layout
+    const int hh = TPC == 1 ? 0 : (tid & 1);      // theta parity (TPC == 2)
+    float2 v[MV];
+#pragma unroll
+    for (int h = 0; h < H; ++h) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            if (G * i >= h * RC && G * i < (h + 1) * RC) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) buf[(g + G * i - h * RC) * P + t + R2 * r] = w[i][r];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = h * RC / TPC; l < (h + 1) * RC / TPC; ++l) v[l] = buf[(TPC * l + hh - h * RC) * P + xc];
+    }
+    // 4. theta convolution in registers
+    if constexpr (TPC == 1) {
+        RegDFT<M, false, float>::run(v);
+#pragma unroll
+        for (int k = 0; k < M; ++k) v[k] = mul<float>(v[k], ft[k]);
+        RegDFT<M, true, float>::run(v);
+    } else {
+        // theta = hh + 2 s: DFT over s, twiddle w_M^{hh k1}, radix-2 across the lane pair
+        RegDFT<MV, false, float>::run(v);
+        if (hh) {
+#pragma unroll
+            for (int k1 = 1; k1 < MV; ++k1) v[k1] = mul<float>(v[k1], twm[k1]);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < MV; ++k1) {
+            const float2 o = swap_lane1(v[k1]);
+            // lane hh = 0 keeps X[k1] = Y0 + Y1', lane hh = 1 keeps X[k1 + M/2] = Y0 - Y1'
+            v[k1] = hh ? sub<float>(o, v[k1]) : add<float>(v[k1], o);
+            v[k1] = mul<float>(v[k1], ft[k1 + MV * hh]);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < MV; ++k1) {
+            const float2 o = swap_lane1(v[k1]);
+            // U_hh[k1] = X'[k1] + (-1)^hh X'[k1 + M/2]
+            v[k1] = hh ? sub<float>(o, v[k1]) : add<float>(v[k1], o);
+        }
+        if (hh) {
+#pragma unroll
+            for (int k1 = 1; k1 < MV; ++k1) v[k1] = mulc<float>(v[k1], twm[k1]);
+        }
+        RegDFT<MV, true, float>::run(v);
+    }
+    // 5. store columns
+    float* __restrict__ out0 = a.out + (long long)item * a.n + (long long)(2 * s) * NX;
+    float* __restrict__ out1 = out0 + NX;
+#pragma unroll
+    for (int l = 0; l < MV; ++l) {
+        const int off = (TPC * l + hh) * pl + xc;
+        out0[off] = v[l].x;
+        out1[off] = v[l].y;
+    }
+}
+
+template <int NY>
+__global__ void __launch_bounds__(NY) y_pencil_fast(FastSepArgs a) {
+    constexpr int R2 = NY / 16;
+    constexpr int CC = 16 / R2;
+    constexpr int W = 16;             // complex columns (x-pairs) per tile
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float2* buf = reinterpret_cast<float2*>(smem_raw);  // [k1*R2 + t][W]
+    float2* tw_f = buf + NY * W;
+    float2* tw_i = tw_f + 16 * R2;
+    float2* fy = tw_i + 16 * R2;
+    const int tid = threadIdx.x;
+    constexpr int NT = W * R2;
+    for (int i = tid; i < 16 * R2; i += NT) {
+        const int k1 = i / R2, t = i - k1 * R2;
+        const float2 w = a.tw[t * k1];
+        tw_f[k1 * R2 + t] = w;
+        tw_i[t * 16 + k1] = w;
+    }
+    for (int i = tid; i < NY; i += NT) fy[i] = chain_factor(a.ty, a.ntab, i, 1.0f / NY, a.conj_tab);
+    __syncthreads();
+
+    const int q = tid % W, t = tid / W;
+    const int ncols = a.nx / 2;
+    const int ctiles = ncols / W;
+    const long long plane = (long long)a.nx * NY;
+    const int per_item = ctiles * a.m;
+    const int ntiles = per_item * a.nitems;
+    // complex (float2) offset of a tile's first column; per-lane offsets are 32-bit
+    auto tile_base = [&](int tile) -> long long {
+        const int item = tile / per_item;
+        const int rem = tile - item * per_item;
+        const int th = rem / ctiles;
+        const int ct = rem - th * ctiles;
+        return ((long long)item * a.n + (long long)th * plane) / 2 + ct * W;
+    };
+    const float2* __restrict__ gin = reinterpret_cast<const float2*>(a.in);
+    float2* __restrict__ gout = reinterpret_cast<float2*>(a.out);
+    // persistent blocks: the next tile's loads are issued before this tile's arithmetic
+    float2 nxt[16];
+    int tile = blockIdx.x;
+    const int lane_off = q + t * ncols;
+    const int rstride = R2 * ncols;
+    if (tile < ntiles) {
+        const float2* src = gin + tile_base(tile);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) nxt[r] = (src + r * rstride)[lane_off];
+    }
+    for (; tile < ntiles; tile += gridDim.x) {
+        float2 w[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) w[r] = nxt[r];
+        const int next = tile + gridDim.x;
+        if (next < ntiles) {
+            const float2* src = gin + tile_base(next);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) nxt[r] = (src + r * rstride)[lane_off];
+        }
+        dft16<float, false>(w);
+#pragma unroll
+        for (int k1 = 1; k1 < 16; ++k1) w[k1] = mul<float>(w[k1], tw_f[k1 * R2 + t]);
+        __syncthreads();
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) buf[(k1 * R2 + t) * W + q] = w[k1];
+        __syncthreads();
+        float2 u[CC][R2];
+#pragma unroll
+        for (int j = 0; j < CC; ++j) {
+            const int k1 = CC * t + j;
+#pragma unroll
+            for (int tt = 0; tt < R2; ++tt) u[j][tt] = buf[(k1 * R2 + tt) * W + q];
+            RegDFT<R2, false, float>::run(u[j]);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = mul<float>(u[j][k2], fy[k1 + 16 * k2]);
+            RegDFT<R2, true, float>::run(u[j]);
+#pragma unroll
+            for (int tt = 1; tt < R2; ++tt) u[j][tt] = mulc<float>(u[j][tt], tw_i[tt * 16 + k1]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CC; ++j) {
+#pragma unroll
+            for (int tt = 0; tt < R2; ++tt) buf[((CC * t + j) * R2 + tt) * W + q] = u[j][tt];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k1 = 0; k1 < 16; ++k1) w[k1] = buf[(k1 * R2 + t) * W + q];
+        dft16<float, true>(w);
+        float2* dst = gout + tile_base(tile);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) (dst + r * rstride)[lane_off] = w[r];
+    }
+}
+
+// ------------------------------------------------------------------ dispatch
+template <int M> constexpr int slab_tpc() { return M == 64 ? 2 : 1; }
+
+template <int NX, int M>
+static size_t slab_fast_lds() {
+    constexpr int R2 = NX / 16;
+    constexpr int RC = M < 32 ? M : 32;
+    constexpr int P = NX + (R2 % 16);
+    return sizeof(float2) * ((size_t)RC * P + 32 * R2 + NX + 2 * M);
+}
+
+template <int NY>
+static size_t pencil_fast_lds() {
+    constexpr int R2 = NY / 16;
+    return sizeof(float2) * ((size_t)NY * 16 + 32 * R2 + NY);
+}
+
+template <int NX, int M>
+static hipError_t launch_slab_fast_t(const FastSepArgs& a, int nblocks, hipStream_t s) {
+    const size_t lds = slab_fast_lds<NX, M>();
+    constexpr int TPC = slab_tpc<M>();
+    hipLaunchKernelGGL((xt_slab_fast<NX, M, TPC>), dim3(nblocks), dim3(NX * TPC), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int NY>
+static hipError_t launch_pencil_fast_t(const FastSepArgs& a, int nblocks, hipStream_t s) {
+    const size_t lds = pencil_fast_lds<NY>();
+    hipLaunchKernelGGL((y_pencil_fast<NY>), dim3(nblocks), dim3(NY), lds, s, a);
+    return hipGetLastError();
+}
+
+bool slab_fast_supported(int nx, int m) {
+    return (nx == 64 || nx == 128 || nx == 256) && (m == 16 || m == 32 || m == 64);
+}
+
+bool pencil_fast_supported(int nx, int ny) {
+    return (ny == 64 || ny == 128 || ny == 256) && nx % 32 == 0;
+}
+
+#define SE2C_SLAB_CASE(NX_, M_) \
+    if (a.nx == NX_ && a.m == M_) return launch_slab_fast_t<NX_, M_>(a, nblocks, s);
+
+hipError_t launch_slab_fast(const FastSepArgs& a, hipStream_t s) {
+    const int nblocks = (a.ny / 2) * a.nitems;  // one block per y-pair slab
+    SE2C_SLAB_CASE(64, 16) SE2C_SLAB_CASE(64, 32) SE2C_SLAB_CASE(64, 64)
+    SE2C_SLAB_CASE(128, 16) SE2C_SLAB_CASE(128, 32) SE2C_SLAB_CASE(128, 64)
+    SE2C_SLAB_CASE(256, 16) SE2C_SLAB_CASE(256, 32) SE2C_SLAB_CASE(256, 64)
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_pencil_fast(const FastSepArgs& a, hipStream_t s) {
+    const int ntiles = (a.nx / 2 / 16) * a.m * a.nitems;
+    // persistent grid: a few blocks per CU, each walks its share of tiles
+    const int nblocks = ntiles < a.grid_blocks ? ntiles : a.grid_blocks;
+    if (a.ny == 64) return launch_pencil_fast_t<64>(a, nblocks, s);
+    if (a.ny == 128) return launch_pencil_fast_t<128>(a, nblocks, s);
+    if (a.ny == 256) return launch_pencil_fast_t<256>(a, nblocks, s);
+    return hipErrorInvalidValue;
+}
+
+#define SE2C_SLAB_ATTR(NX_, M_)                                                                        \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(xt_slab_fast<NX_, M_, slab_tpc<M_>()>),        \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)slab_fast_lds<NX_, M_>()); \
+    if (e != hipSuccess) return e;
+
+hipError_t prepare_fast_kernels() {
+    hipError_t e;
+    SE2C_SLAB_ATTR(64, 16) SE2C_SLAB_ATTR(64, 32) SE2C_SLAB_ATTR(64, 64)
+    SE2C_SLAB_ATTR(128, 16) SE2C_SLAB_ATTR(128, 32) SE2C_SLAB_ATTR(128, 64)
+    SE2C_SLAB_ATTR(256, 16) SE2C_SLAB_ATTR(256, 32) SE2C_SLAB_ATTR(256, 64)
+    return hipSuccess;
+}
+
+}  // namespace se2c

@@ -164,6 +164,31 @@ def test_headline_256x256x64_batch16_chain8_sampled():
         assert abs(out[b].mean() - f[b].mean()) <= 1e-5 * abs(f[b].mean())
 
 
+@pytest.mark.parametrize("nx,ny,m", [(64, 64, 16), (128, 64, 32), (256, 128, 64), (64, 256, 64), (128, 96, 16)])
+def test_register_kernels_match_generic_and_oracle(nx, ny, m):
+    case(f"register vs generic kernels {nx}x{ny}x{m} fp32 batch 3, chain of 3, adjoint too")
+    ks = chain_kernel_params(9, 3)
+    chain = [(k.sigma, k.kappa, 0.4 * j) for j, k in enumerate(ks)]
+    f = _fields(9, 3, 16, nx, ny, m)
+    ref_t = oracle_table_gauss(nx, ny, m, chain)
+    outs = {}
+    for generic in (False, True):
+        plan = se2.Plan([(nx, ny, m)], dtype="f32", generic=generic)
+        table = plan.coeffs(0, [se2.GaussVM(s, k, th) for s, k, th in chain])
+        fd = _dev(f, torch.float32)
+        outs[generic] = (plan.apply(0, fd, table).cpu().numpy().astype(np.float64),
+                         plan.apply(0, fd, table, adjoint=True).cpu().numpy().astype(np.float64))
+    tol = tol32(nx * ny * m)
+    for b in range(3):
+        ref = oracle_conv(f[b], ref_t)
+        ref_adj = oc.conv_with_coeffs(f[b], np.conj(ref_t))
+        for generic in (False, True):
+            e1 = rel_l2(outs[generic][0][b], ref)
+            e2 = rel_l2(outs[generic][1][b], ref_adj)
+            print(f"  field {b} generic={generic}: {e1:.2e} adj {e2:.2e}", flush=True)
+            assert e1 <= tol and e2 <= tol
+
+
 # ---------------------------------------------------------------- full path
 @pytest.mark.parametrize("dt,batch", [("f32", 1), ("f32", 2), ("f32", 3), ("f64", 3), ("f64", 2)])
 def test_full_path_parity(dt, batch, rng):
