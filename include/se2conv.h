@@ -132,6 +132,33 @@ se2conv_status se2conv_coeffs(se2conv_plan_t plan, int32_t shape_idx, const se2c
 se2conv_status se2conv_table_info(se2conv_plan_t plan, const void* d_table, int32_t* kind, int32_t* shape_idx,
                                   size_t* bytes);
 
+/*
+ * se2conv_field_coeffs: finite Fourier coefficient tables f^[k; L] = (-1)^{k1+k2} F^[k] / n
+ * (eq. (FkLv)) of real fields, in the plan dtype, one FULL table per field.  They serve as
+ * the checkpointed forward spectra of a field: the gradient of a loss with respect to the
+ * kernel samples is the adjoint apply of dL/dout with this table (dL/dP = Re S_K[g, conj f^]).
+ *   d_f         device [batch][M][Ny][Nx] real samples (plan dtype).
+ *   d_tables    device buffer; table b starts at d_tables + b * table_stride (bytes), each
+ *               M*Ny*Nx complex values; table_stride >= that size and a multiple of 16.
+ * Every table is recorded by the plan (usable with se2conv_apply / se2conv_chain).
+ * Uses two workspace planes of the largest shape (allocated on first use).
+ */
+se2conv_status se2conv_field_coeffs(se2conv_plan_t plan, int32_t shape_idx, const void* d_f, int32_t batch,
+                                    void* d_tables, size_t table_stride, hipStream_t stream);
+
+/*
+ * se2conv_profile_grad: transpose of the RADIAL_PROFILE sample expansion, summed over a
+ * batch: grad_prof[q][l] = sum_b sum_{j,i} H_q(x_ij) dP_b[l][j][i], where
+ * H_q(x) = sum_images max(0, 1 - | |x + image| / h - q |), h = r_max / (n_knots - 1).
+ *   d_grad_samples  device [batch][M][Ny][Nx] gradients w.r.t. kernel samples (plan dtype).
+ *   d_grad_prof     device FP64 [n_knots][M], overwritten.
+ * Computed in FP64 with fixed-order reductions (bitwise reproducible).  Uses the plan's
+ * FP64 scratch.
+ */
+se2conv_status se2conv_profile_grad(se2conv_plan_t plan, int32_t shape_idx, const void* d_grad_samples,
+                                    int32_t batch, int32_t n_knots, double r_max, double* d_grad_prof,
+                                    hipStream_t stream);
+
 /* ---- apply flags */
 #define SE2CONV_ADJOINT 0x1u /* apply the transpose (conjugate coefficients: correlation with the kernels) */
 #define SE2CONV_GRAPH 0x2u   /* se2conv_chain only: capture the submission once in a HIP graph and replay it */

@@ -145,6 +145,30 @@ class Plan:
                                         _stream_handle(stream)))
         return out
 
+    def field_coeffs(self, shape_idx: int, f: torch.Tensor, stream=None) -> list:
+        """FFC tables of each field of f (FULL tables in the plan dtype), one Table per field."""
+        _require(f, self.tdtype)
+        nx, ny, m = self.shapes[shape_idx]
+        batch = f.numel() // (nx * ny * m)
+        cdt = torch.complex64 if self.dtype == L.F32 else torch.complex128
+        buf = torch.empty(batch, m, ny, nx, dtype=cdt, device=f.device)
+        stride = buf[0].numel() * buf.element_size()
+        L.check(self._lib.se2conv_field_coeffs(self.handle, shape_idx, f.data_ptr(), batch, buf.data_ptr(), stride,
+                                               _stream_handle(stream)))
+        raw = buf.view(torch.uint8).view(batch, -1)
+        return [Table(self, shape_idx, raw[b], L.TABLE_FULL) for b in range(batch)]
+
+    def profile_grad(self, shape_idx: int, grad_samples: torch.Tensor, n_knots: int, r_max: float,
+                     stream=None) -> torch.Tensor:
+        """sum over the batch of the hat-basis transpose of dL/dP: a float64 [n_knots, M] tensor."""
+        _require(grad_samples, self.tdtype)
+        nx, ny, m = self.shapes[shape_idx]
+        batch = grad_samples.numel() // (nx * ny * m)
+        out = torch.empty(n_knots, m, dtype=torch.float64, device=grad_samples.device)
+        L.check(self._lib.se2conv_profile_grad(self.handle, shape_idx, grad_samples.data_ptr(), batch, n_knots,
+                                               float(r_max), out.data_ptr(), _stream_handle(stream)))
+        return out
+
     def pass_times(self, cap: int = 4096):
         """[(pass kind name, milliseconds)] of passes enqueued with timing=True since the last read."""
         ms = (ctypes.c_float * cap)()

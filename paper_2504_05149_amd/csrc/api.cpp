@@ -19,6 +19,7 @@
 #include "coeffs.hpp"
 #include "passes.hpp"
 #include "sep_fast.hpp"
+#include "grad.hpp"
 
 using namespace se2c;
 
@@ -136,6 +137,7 @@ struct se2conv_plan_s {
     std::map<int, void*> tw32, tw64;   // length -> device twiddle table
     void* ws = nullptr;                // one real plane of the largest shape (plan dtype)
     size_t ws_bytes = 0;
+    void* ws2 = nullptr;               // two more planes (field tables), allocated on first use
     void* scratch64 = nullptr;         // FP64 scratch for se2conv_coeffs
     size_t scratch64_bytes = 0;
     std::unordered_map<uintptr_t, TableRec> tables;
@@ -737,6 +739,7 @@ se2conv_status se2conv_plan_destroy(se2conv_plan_t p) {
         for (auto& kv : p->tw32) (void)hipFree(kv.second);
         for (auto& kv : p->tw64) (void)hipFree(kv.second);
         if (p->ws) (void)hipFree(p->ws);
+        if (p->ws2) (void)hipFree(p->ws2);
         if (p->scratch64) (void)hipFree(p->scratch64);
         if (cur >= 0) (void)hipSetDevice(cur);
     }
@@ -843,6 +846,74 @@ se2conv_status se2conv_coeffs(se2conv_plan_t p, int32_t shape_idx, const se2conv
     rec.kind = sep ? SE2CONV_TABLE_SEPARABLE : SE2CONV_TABLE_FULL;
     rec.bytes = bytes;
     p->tables[reinterpret_cast<uintptr_t>(d_table)] = rec;
+    return ok();
+}
+
+se2conv_status se2conv_field_coeffs(se2conv_plan_t p, int32_t shape_idx, const void* d_f, int32_t batch,
+                                    void* d_tables, size_t table_stride, hipStream_t stream) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (shape_idx < 0 || shape_idx >= (int)p->shapes.size())
+        return fail(SE2CONV_ERR_INVALID_ARG, "shape_idx %d out of range", shape_idx);
+    if (batch < 1) return fail(SE2CONV_ERR_INVALID_ARG, "batch must be >= 1");
+    if (!d_f || !d_tables || !aligned16(d_f) || !aligned16(d_tables))
+        return fail(SE2CONV_ERR_INVALID_ARG, "d_f and d_tables must be non-null and 16-byte aligned");
+    const se2conv_shape& s = p->shapes[shape_idx];
+    const long long n = (long long)s.nx * s.ny * s.m;
+    const size_t tbytes = cplx_bytes(p) * (size_t)n;
+    if (table_stride < tbytes || (table_stride & 15u))
+        return fail(SE2CONV_ERR_INVALID_ARG, "table_stride must be >= %zu and a multiple of 16", tbytes);
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    const bool d = dbl(p);
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        if (!p->ws2) {
+            if (hipMalloc(&p->ws2, 2 * p->ws_bytes) != hipSuccess)
+                return fail(SE2CONV_ERR_OUT_OF_MEMORY, "field-table workspace (%zu bytes)", 2 * p->ws_bytes);
+        }
+    }
+    void* zre = p->ws2;
+    void* zim = (char*)p->ws2 + p->ws_bytes;
+    const size_t rb = real_bytes(p);
+    for (int b = 0; b < batch; b += 2) {
+        const void* fa = (const char*)d_f + rb * n * b;
+        const void* fb = (b + 1 < batch) ? (const char*)d_f + rb * n * (b + 1) : nullptr;
+        // complex 3-D DFT of z = f_a + i f_b into the (re, im) workspace planes
+        HIPCHK(xt_transform(p, s, d, 0, fa, fb, zre, zim, nullptr, nullptr, n, n, 1, stream));
+        HIPCHK(y_pass(p, s, d, zre, zim, nullptr, n, 1, 1, 0, 0, nullptr, false, 1.0, stream));
+        void* ta = (char*)d_tables + table_stride * b;
+        void* tb = fb ? (char*)d_tables + table_stride * (b + 1) : nullptr;
+        HIPCHK(launch_unpack_tables(zre, zim, ta, tb, s.nx, s.ny, s.m, d, stream));
+    }
+    std::lock_guard<std::mutex> g(p->mu);
+    for (int b = 0; b < batch; ++b) {
+        TableRec rec;
+        rec.shape_idx = shape_idx;
+        rec.kind = SE2CONV_TABLE_FULL;
+        rec.bytes = tbytes;
+        p->tables[reinterpret_cast<uintptr_t>((char*)d_tables + table_stride * b)] = rec;
+    }
+    return ok();
+}
+
+se2conv_status se2conv_profile_grad(se2conv_plan_t p, int32_t shape_idx, const void* d_grad_samples, int32_t batch,
+                                    int32_t n_knots, double r_max, double* d_grad_prof, hipStream_t stream) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (shape_idx < 0 || shape_idx >= (int)p->shapes.size())
+        return fail(SE2CONV_ERR_INVALID_ARG, "shape_idx %d out of range", shape_idx);
+    if (batch < 1 || !d_grad_samples || !d_grad_prof)
+        return fail(SE2CONV_ERR_INVALID_ARG, "need batch >= 1 and non-null device pointers");
+    if (n_knots < 2 || n_knots > 4096 || !(r_max > 0.0) || !(r_max <= 1.0))
+        return fail(SE2CONV_ERR_INVALID_ARG, "need 2 <= n_knots <= 4096 and 0 < r_max <= 1");
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    const se2conv_shape& s = p->shapes[shape_idx];
+    const long long npts = (long long)s.nx * s.ny;
+    std::lock_guard<std::mutex> g(p->mu);
+    se2conv_status r = ensure_scratch64(p, sizeof(double) * (size_t)(npts * n_knots + npts * s.m));
+    if (r != SE2CONV_OK) return r;
+    double* basis = reinterpret_cast<double*>(p->scratch64);
+    double* G = basis + npts * n_knots;
+    HIPCHK(launch_profile_grad(d_grad_samples, batch, dbl(p), n_knots, r_max, s.nx, s.ny, s.m, basis, G, d_grad_prof,
+                               stream));
     return ok();
 }
 

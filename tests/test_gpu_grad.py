@@ -1,0 +1,141 @@
+"""GPU gradients (field tables, profile gradient, autograd) against the FP64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2504_05149_amd as se2
+from gpu_common import TOL64, case, rel_l2, tol32
+from inputs import sample_fields
+from oracle import adjoint as OA
+from oracle import conv as oc
+from oracle import kernels as ok
+from oracle.ffc import ffc
+from paper_2504_05149_amd.autograd import radial_profile_conv
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype)
+
+
+@pytest.mark.parametrize("dt,batch", [("f64", 3), ("f32", 2)])
+def test_field_tables_match_oracle_ffc(dt, batch):
+    case(f"field FFC tables 32x24x16 {dt} batch={batch}")
+    nx, ny, m = 32, 24, 16
+    f = sample_fields(20, batch, 8, nx, ny, m)
+    plan = se2.Plan([(nx, ny, m)], dtype=dt)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    tabs = plan.field_coeffs(0, _dev(f, tdt))
+    torch.cuda.synchronize()
+    for b in range(batch):
+        gpu = tabs[b].complex_view().cpu().numpy()
+        ref = ffc(f[b])
+        err = np.max(np.abs(gpu - ref)) / np.max(np.abs(ref))
+        print(f"  field {b}: max rel err {err:.2e}", flush=True)
+        assert err < (1e-13 if dt == "f64" else 1e-6)
+
+
+def test_profile_grad_matches_oracle(rng):
+    case("profile gradient 32x32x16 fp64 batch 3")
+    nx = ny = 32
+    m, nk, rmax = 16, 12, 0.45
+    gp = rng.standard_normal((3, m, ny, nx))
+    plan = se2.Plan([(nx, ny, m)], dtype="f64")
+    out = plan.profile_grad(0, _dev(gp, torch.float64), nk, rmax).cpu().numpy()
+    ref = OA.grad_profile(gp, nk, rmax)
+    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+def _loss_parts(nx, ny, m, batch, nk, rmax, seed, rng):
+    f = sample_fields(seed, batch, 8, nx, ny, m)
+    prof = np.exp(-((np.arange(nk)[:, None] * rmax / (nk - 1)) ** 2) / (2 * 0.06 ** 2)) * \
+        np.exp(3.0 * np.cos(2 * np.pi * np.arange(m) / m))[None, :] * 0.01
+    prof = prof + 0.001 * rng.standard_normal(prof.shape)
+    target = rng.standard_normal((batch, m, ny, nx))
+    return f, prof, target
+
+
+def _oracle_grads(f, prof, target, nk, rmax):
+    m, ny, nx = f.shape[1:]
+    p = ok.radial_profile(nx, ny, m, prof, rmax)
+    table = ffc(p)
+    out = np.stack([oc.conv_with_coeffs(f[b], table) for b in range(f.shape[0])])
+    g = 2.0 * (out - target)
+    gf = np.stack([oc.conv_with_coeffs(g[b], np.conj(table)) for b in range(f.shape[0])])
+    gP = np.stack([OA.grad_kernel_samples(f[b], g[b]) for b in range(f.shape[0])])
+    gprof = OA.grad_profile(gP, nk, rmax)
+    return float(np.sum((out - target) ** 2)), gf, gprof
+
+
+@pytest.mark.parametrize("dt,checkpoint", [("f64", True), ("f64", False), ("f32", True)])
+def test_autograd_matches_oracle_gradients(dt, checkpoint, rng):
+    case(f"autograd radial-profile conv 32x32x16 {dt} checkpoint={checkpoint}")
+    nx = ny = 32
+    m, batch, nk, rmax = 16, 3, 10, 0.4
+    f, prof, target = _loss_parts(nx, ny, m, batch, nk, rmax, 21, rng)
+    plan = se2.Plan([(nx, ny, m)], dtype=dt)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    fd = _dev(f, tdt).requires_grad_(True)
+    pd = _dev(prof, torch.float64).requires_grad_(True)
+    out = radial_profile_conv(fd, pd, plan, 0, rmax, checkpoint)
+    loss = ((out.double() - _dev(target, torch.float64)) ** 2).sum()
+    loss.backward()
+    ref_loss, ref_gf, ref_gprof = _oracle_grads(f, prof, target, nk, rmax)
+    tol = TOL64 * 10 if dt == "f64" else 1e-4
+    e_loss = abs(loss.item() - ref_loss) / abs(ref_loss)
+    e_gf = rel_l2(fd.grad.cpu().numpy(), ref_gf)
+    e_gp = rel_l2(pd.grad.cpu().numpy(), ref_gprof)
+    print(f"  loss {e_loss:.2e} grad_f {e_gf:.2e} grad_prof {e_gp:.2e}", flush=True)
+    assert e_loss <= tol and e_gf <= tol and e_gp <= tol
+
+
+def test_checkpoint_and_recompute_give_identical_gradients(rng):
+    case("checkpoint vs recompute: bitwise identical gradients, 32x32x16 fp32")
+    nx = ny = 32
+    m, batch, nk, rmax = 16, 2, 8, 0.4
+    f, prof, target = _loss_parts(nx, ny, m, batch, nk, rmax, 22, rng)
+    plan = se2.Plan([(nx, ny, m)], dtype="f32")
+    grads = []
+    for ck in (True, False):
+        fd = _dev(f, torch.float32).requires_grad_(True)
+        pd = _dev(prof, torch.float64).requires_grad_(True)
+        out = radial_profile_conv(fd, pd, plan, 0, rmax, ck)
+        ((out.double() - _dev(target, torch.float64)) ** 2).sum().backward()
+        grads.append((fd.grad.clone(), pd.grad.clone()))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+
+
+def test_fp64_finite_differences_on_gpu(rng):
+    case("central finite differences h=1e-3 on 16 coordinates, GPU FP64 path 32x32x16")
+    nx = ny = 32
+    m, batch, nk, rmax = 16, 2, 10, 0.4
+    f, prof, target = _loss_parts(nx, ny, m, batch, nk, rmax, 23, rng)
+    plan = se2.Plan([(nx, ny, m)], dtype="f64")
+    tgt = _dev(target, torch.float64)
+
+    def loss_of(fa, pa):
+        out = radial_profile_conv(fa, pa, plan, 0, rmax, True)
+        return float(((out - tgt) ** 2).sum().item())
+    fd = _dev(f, torch.float64).requires_grad_(True)
+    pd = _dev(prof, torch.float64).requires_grad_(True)
+    out = radial_profile_conv(fd, pd, plan, 0, rmax, True)
+    ((out - tgt) ** 2).sum().backward()
+    h = 1e-3
+    fcoords = [tuple(int(rng.integers(0, s)) for s in f.shape) for _ in range(8)]
+    pcoords = [(int(rng.integers(0, nk)), int(rng.integers(0, m))) for _ in range(8)]
+    for idx in fcoords:
+        e = np.zeros_like(f)
+        e[idx] = h
+        num = (loss_of(_dev(f + e, torch.float64), _dev(prof, torch.float64)) -
+               loss_of(_dev(f - e, torch.float64), _dev(prof, torch.float64))) / (2 * h)
+        ana = fd.grad[idx].item()
+        assert abs(num - ana) <= 1e-5 * max(1.0, abs(ana)), (idx, num, ana)
+    for idx in pcoords:
+        e = np.zeros_like(prof)
+        e[idx] = h
+        num = (loss_of(_dev(f, torch.float64), _dev(prof + e, torch.float64)) -
+               loss_of(_dev(f, torch.float64), _dev(prof - e, torch.float64))) / (2 * h)
+        ana = pd.grad[idx].item()
+        assert abs(num - ana) <= 1e-5 * max(1.0, abs(ana)), (idx, num, ana)
