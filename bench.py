@@ -32,7 +32,11 @@ WORKLOADS = {
     "headline": (256, 256, 64, 16, 32, 8, "f32", 2),
     "headline_plain": (256, 256, 64, 16, 32, 1, "f32", 2),
     "c1": (128, 128, 64, 16, 32, 8, "f32", 1),
+    "c3": (512, 512, 128, 4, 128, 4, "f32", 3),
+    "c3_f64": (512, 512, 128, 4, 128, 4, "f64", 3),
+    "c0": (32, 32, 32, 1, 8, 1, "f64", 0),
 }
+SPECIAL = ("c2", "c4")
 
 
 def lib_source_hash() -> str:
@@ -90,6 +94,99 @@ def run_gpu(name, steps, warmup):
     plan.close()
     return dict(elapsed=elapsed, avg_ms=avg, launches=launches, f_host=f_host, out_host=out_host, ks=ks,
                 shape=(nx, ny, m), batch=batch, dtype=dt)
+
+
+def run_c2(steps, warmup):
+    """256 independent problems (mixed N, M, chain lengths) replayed as one HIP graph."""
+    import torch
+
+    import paper_2504_05149_amd as se2
+    from inputs import sample_field, uneven_problem_list
+
+    probs = uneven_problem_list(2, 256)
+    shapes = sorted({(p["n"], p["n"], p["m"]) for p in probs})
+    sidx = {s: i for i, s in enumerate(shapes)}
+    plan = se2.Plan(shapes, dtype="f32")
+    items, npts = [], 0
+    for p in probs:
+        sh = (p["n"], p["n"], p["m"])
+        table = plan.coeffs(sidx[sh], [se2.GaussVM(k.sigma, k.kappa, k.theta0) for k in p["chain"]])
+        f = torch.from_numpy(sample_field(p["field"], *sh, dtype=np.float32)[None]).to("cuda")
+        items.append((sidx[sh], f, torch.empty_like(f), [table]))
+        npts += f.numel()
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(max(1, warmup)):
+        plan.chain(items, graph=True, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.chain(items, graph=True, stream=stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = el * 1e3 / steps
+    return {"metric": "SE(2) convolutions/sec, 256 uneven problems in one graph", "value": round(256 / (ms * 1e-3), 1),
+            "unit": "conv/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "256 problems, N in {32,48,64,96,128}, M in {16,32,64}, chains of 1..4 "
+                                   "Gauss-vM kernels, 8 bumps per field", "shape_classes": len(shapes),
+                       "points": npts},
+            "path_alg_GBps": round(8 * npts / (ms * 1e-3) / 1e9, 1)}
+
+
+def run_c4(steps, warmup):
+    """Loss + gradients w.r.t. the field and a 64 x 64 radial profile, 256x256x64 FP32 batch 8."""
+    import torch
+
+    import paper_2504_05149_amd as se2
+    from inputs import sample_fields
+    from paper_2504_05149_amd.autograd import radial_profile_conv
+
+    nx = ny = 256
+    m, batch, nk, rmax = 64, 8, 64, 0.5
+    plan = se2.Plan([(nx, ny, m)], dtype="f32")
+    f = torch.from_numpy(sample_fields(4, batch, 32, nx, ny, m, dtype=np.float32)).to("cuda")
+    # target: sigma* = 0.04, kappa* = 8 convolution (on the GPU) plus 1% noise
+    tt = plan.coeffs(0, [se2.GaussVM(0.04, 8.0, 0.0)])
+    clean = plan.apply(0, f, tt)
+    gen = torch.Generator(device="cuda").manual_seed(2504_05149)
+    target = clean + 0.01 * clean.pow(2).mean().sqrt() * torch.randn(clean.shape, device="cuda", generator=gen)
+    r = torch.arange(nk, dtype=torch.float64) * rmax / (nk - 1)
+    th = 2 * np.pi * torch.arange(m, dtype=torch.float64) / m
+    prof = (torch.exp(-r[:, None] ** 2 / (2 * 0.06 ** 2)) * torch.exp(4.0 * (torch.cos(th)[None, :] - 1.0))).cuda()
+    res = {}
+    for ck in (True, False):
+        def step():
+            fd = f.detach().requires_grad_(True)
+            pd = prof.detach().requires_grad_(True)
+            out = radial_profile_conv(fd, pd, plan, 0, rmax, checkpoint=ck)
+            loss = ((out - target) ** 2).sum()
+            loss.backward()
+            return loss
+        for _ in range(warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        res["checkpoint" if ck else "recompute"] = (time.perf_counter() - t0) * 1e3 / steps
+    # forward alone, for reference
+    table = plan.coeffs(0, [se2.RadialProfile(prof.contiguous(), rmax, norm=2)])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.apply(0, f, table)
+    torch.cuda.synchronize()
+    fwd_ms = (time.perf_counter() - t0) * 1e3 / steps
+    best = min(res.values())
+    return {"metric": "differentiated SE(2) convolutions/sec (forward + gradients w.r.t. f and profile)",
+            "value": round(batch / (best * 1e-3), 1), "unit": "conv/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": round(best, 4), "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "256x256x64 f32 batch 8, radial profile 64 knots x 64 angles, "
+                                   "target sigma*=0.04 kappa*=8 + 1% noise"},
+            "ms_fwd_bwd": {k: round(v, 4) for k, v in res.items()}, "ms_forward_full_table": round(fwd_ms, 4)}
 
 
 def copy_calibration(name, steps, warmup):
@@ -162,7 +259,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="headline", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="headline", choices=sorted(WORKLOADS) + list(SPECIAL))
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -176,6 +273,12 @@ def main():
 
     if args.copy_calibration:
         print(json.dumps(copy_calibration(args.workload, args.steps, args.warmup)), flush=True)
+        return
+    if args.workload == "c2":
+        print(json.dumps(run_c2(args.steps, args.warmup)), flush=True)
+        return
+    if args.workload == "c4":
+        print(json.dumps(run_c4(args.steps, args.warmup)), flush=True)
         return
     res = run_gpu(args.workload, args.steps, args.warmup)
     nx, ny, m = res["shape"]

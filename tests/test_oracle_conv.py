@@ -223,3 +223,12 @@ def test_real_input_gives_real_output():
     p = K.gauss_vm(8, 8, 8, 0.06, 2.0, 0.9)
     z = C.conv_chain(f, [p], return_complex=True)
     assert np.max(np.abs(z.imag)) < 1e-15 * np.max(np.abs(z.real))
+
+
+def test_closed_form_at_the_gradient_benchmark_kernel():
+    # sigma* = 0.04, kappa* = 8 (the target kernel of the differentiation workload)
+    bf = bump_field(4, 0, 32)
+    f = sample_field(bf, 64, 64, 64)
+    p = K.gauss_vm(64, 64, 64, 0.04, 8.0, 0.0, normalize="continuous")
+    ref = CF.conv_closed_form(bf, [KernelParams(0.04, 8.0)], 64, 64, 64)
+    assert rel_l2(C.conv_chain(f, [p]), ref) < 1e-8
