@@ -119,8 +119,13 @@ struct TableRec {
     size_t bytes;
 };
 
-struct GraphRec {
+// A problem list seen by se2conv_chain: its device item arrays (one group of
+// fields per shape with separable chains) and, with SE2CONV_GRAPH, its graph.
+struct SubmissionRec {
     std::vector<uint64_t> key;
+    void* d_items = nullptr;                       // all groups' SepItem arrays
+    std::vector<std::pair<int, int>> groups;       // (shape_idx, first item) per group
+    std::vector<int> group_counts;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -141,7 +146,7 @@ struct se2conv_plan_s {
     void* scratch64 = nullptr;         // FP64 scratch for se2conv_coeffs
     size_t scratch64_bytes = 0;
     std::unordered_map<uintptr_t, TableRec> tables;
-    std::vector<GraphRec> graphs;
+    std::vector<SubmissionRec> subs;
     std::mutex mu;
     // pass timing (SE2CONV_TIMING)
     bool timing = false;
@@ -396,6 +401,93 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
         r = pencil(2);
         if (r != SE2CONV_OK) return r;
     }
+    return SE2CONV_OK;
+}
+
+// Separable chains given as a device item list (one SepItem per field, all of shape s).
+se2conv_status enqueue_sep_items(se2conv_plan_s* p, const se2conv_shape& s, const SepItem* d_items, int nitems,
+                                 bool conj, hipStream_t st) {
+    const bool d = dbl(p);
+    const bool generic_only = (p->flags & SE2CONV_PLAN_GENERIC) != 0;
+    const bool two_pass = slab_fits(s, d);
+    const bool fast_slab = !d && !generic_only && two_pass && slab_fast_supported(s.nx, s.m);
+    const bool fast_pencil = !d && !generic_only && two_pass && pencil_fast_supported(s.nx, s.ny);
+    FastSepArgs fa{};
+    fa.nitems = nitems;
+    fa.nx = s.nx;
+    fa.ny = s.ny;
+    fa.m = s.m;
+    fa.conj_tab = conj ? 1 : 0;
+    fa.grid_blocks = p->num_cus * 4;
+    fa.items = d_items;
+    if (fast_slab) {
+        fa.tw = reinterpret_cast<const float2*>(tw_of(p, s.nx, false));
+        fa.twt = reinterpret_cast<const float2*>(tw_of(p, s.m, false));
+        HIPCHK(launch_slab_fast(fa, st));
+        HIPCHK(after_pass(0, st));
+    } else {
+        SlabArgs a{};
+        a.items = d_items;
+        a.nitems = nitems;
+        a.in_mode = 0;
+        a.out_mode = 0;
+        a.nx = s.nx;
+        a.ny = s.ny;
+        a.m = s.m;
+        a.nslab = s.ny / 2;
+        a.fwd = 1;
+        a.inv = 1;
+        a.mul = 1;
+        a.ntab = 0;  // factors come from the items
+        a.conj_tab = conj ? 1 : 0;
+        a.px = make_radix_plan(s.nx);
+        a.pt = make_radix_plan(s.m);
+        a.twx = tw_of(p, s.nx, d);
+        a.twt = tw_of(p, s.m, d);
+        if (two_pass) {
+            a.rows_per_tile = s.m;
+            a.ntile_t = 1;
+            a.do_t = 1;
+            a.scale = 1.0 / ((double)s.nx * s.m);
+        } else {
+            a.rows_per_tile = rows_for_xpass(s);
+            a.ntile_t = s.m / a.rows_per_tile;
+            a.do_t = 0;
+            a.scale = 1.0 / (double)s.nx;
+        }
+        HIPCHK(run_slab(a, d, st));
+    }
+    auto pencil = [&](int axis) -> hipError_t {
+        PencilArgs b{};
+        b.items = d_items;
+        b.nitems = nitems;
+        b.mode = 0;
+        b.axis = axis;
+        b.nx = s.nx;
+        b.ny = s.ny;
+        b.m = s.m;
+        b.ncols = s.nx / 2;
+        const int L = axis == 1 ? s.ny : s.m;
+        b.W = pencil_width(b.ncols, L, d);
+        b.fwd = 1;
+        b.inv = 1;
+        b.mul = 1;
+        b.ntab = 0;
+        b.conj_tab = conj ? 1 : 0;
+        b.scale = 1.0 / (double)L;
+        b.p = make_radix_plan(L);
+        b.tw = tw_of(p, L, d);
+        return run_pencil(b, d, st);
+    };
+    if (fast_pencil) {
+        FastSepArgs fb = fa;
+        fb.tw = reinterpret_cast<const float2*>(tw_of(p, s.ny, false));
+        HIPCHK(launch_pencil_fast(fb, st));
+        HIPCHK(after_pass(1, st));
+    } else {
+        HIPCHK(pencil(1));
+    }
+    if (!two_pass) HIPCHK(pencil(2));
     return SE2CONV_OK;
 }
 
@@ -730,9 +822,10 @@ se2conv_status se2conv_plan_destroy(se2conv_plan_t p) {
         (void)hipGetDevice(&cur);
         if (p->device >= 0) (void)hipSetDevice(p->device);
         (void)hipDeviceSynchronize();
-        for (auto& g : p->graphs) {
+        for (auto& g : p->subs) {
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
             if (g.graph) (void)hipGraphDestroy(g.graph);
+            if (g.d_items) (void)hipFree(g.d_items);
         }
         for (auto ev : p->ev_pool) (void)hipEventDestroy(ev);
         for (auto ev : p->ev_rec) (void)hipEventDestroy(ev);
@@ -983,10 +1076,74 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
     }
     if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
     const bool conj = (flags & SE2CONV_ADJOINT) != 0;
-    auto submit = [&]() -> se2conv_status {
+
+    // find or build the submission record (device item arrays grouped by shape)
+    SubmissionRec* rec = nullptr;
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        for (auto& r : p->subs)
+            if (r.key == key) rec = &r;
+    }
+    if (!rec) {
+        std::map<int, std::vector<SepItem>> by_shape;
         for (int i = 0; i < n_probs; ++i) {
+            if (!seps[i]) continue;
+            const se2conv_problem& q = probs[i];
+            const se2conv_shape& s = p->shapes[q.shape_idx];
+            const long long n = (long long)s.nx * s.ny * s.m;
+            for (int b = 0; b < q.batch; ++b) {
+                SepItem it{};
+                it.in = (const char*)q.f + real_bytes(p) * n * b;
+                it.out = (char*)q.out + real_bytes(p) * n * b;
+                it.ntab = q.n_tables;
+                for (int j = 0; j < q.n_tables; ++j) it.tab[j] = q.tables[j];
+                by_shape[q.shape_idx].push_back(it);
+            }
+        }
+        SubmissionRec nr;
+        nr.key = key;
+        std::vector<SepItem> all;
+        for (auto& kv : by_shape) {
+            nr.groups.push_back({kv.first, (int)all.size()});
+            nr.group_counts.push_back((int)kv.second.size());
+            all.insert(all.end(), kv.second.begin(), kv.second.end());
+        }
+        if (!all.empty()) {
+            if (hipMalloc(&nr.d_items, sizeof(SepItem) * all.size()) != hipSuccess)
+                return fail(SE2CONV_ERR_OUT_OF_MEMORY, "item list (%zu items)", all.size());
+            hipError_t e = hipMemcpyAsync(nr.d_items, all.data(), sizeof(SepItem) * all.size(),
+                                          hipMemcpyHostToDevice, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) {
+                (void)hipFree(nr.d_items);
+                return fail(SE2CONV_ERR_DEVICE, "item upload failed: %s", hipGetErrorString(e));
+            }
+        }
+        std::lock_guard<std::mutex> g(p->mu);
+        if (p->subs.size() >= 64) {  // bounded cache: drop the oldest record
+            SubmissionRec& old = p->subs.front();
+            (void)hipStreamSynchronize(stream);
+            if (old.exec) (void)hipGraphExecDestroy(old.exec);
+            if (old.graph) (void)hipGraphDestroy(old.graph);
+            if (old.d_items) (void)hipFree(old.d_items);
+            p->subs.erase(p->subs.begin());
+        }
+        p->subs.push_back(nr);
+        rec = &p->subs.back();
+    }
+    auto submit = [&]() -> se2conv_status {
+        // every separable problem: one launch per pass per shape group
+        for (size_t gi = 0; gi < rec->groups.size(); ++gi) {
+            const int sidx = rec->groups[gi].first;
+            const SepItem* items = reinterpret_cast<const SepItem*>(rec->d_items) + rec->groups[gi].second;
+            se2conv_status r = enqueue_sep_items(p, p->shapes[sidx], items, rec->group_counts[gi], conj, stream);
+            if (r != SE2CONV_OK) return r;
+        }
+        // problems with full tables: one submission each
+        for (int i = 0; i < n_probs; ++i) {
+            if (seps[i]) continue;
             se2conv_status r = enqueue_problem(p, probs[i].shape_idx, probs[i].f, probs[i].out, probs[i].batch,
-                                               chains[i], seps[i], conj, stream);
+                                               chains[i], false, conj, stream);
             if (r != SE2CONV_OK) return r;
         }
         return SE2CONV_OK;
@@ -1000,14 +1157,9 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
         g_timing_plan = nullptr;
         return r == SE2CONV_OK ? ok() : r;
     }
-    {
-        std::lock_guard<std::mutex> g(p->mu);
-        for (auto& gr : p->graphs) {
-            if (gr.key == key) {
-                HIPCHK(hipGraphLaunch(gr.exec, stream));
-                return ok();
-            }
-        }
+    if (rec->exec) {
+        HIPCHK(hipGraphLaunch(rec->exec, stream));
+        return ok();
     }
     HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     se2conv_status r = submit();
@@ -1024,14 +1176,8 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
         (void)hipGraphDestroy(graph);
         return fail(SE2CONV_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
     }
-    {
-        std::lock_guard<std::mutex> g(p->mu);
-        GraphRec gr;
-        gr.key = key;
-        gr.graph = graph;
-        gr.exec = exec;
-        p->graphs.push_back(gr);
-    }
+    rec->graph = graph;
+    rec->exec = exec;
     HIPCHK(hipGraphLaunch(exec, stream));
     return ok();
 }

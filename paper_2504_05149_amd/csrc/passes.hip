@@ -66,15 +66,38 @@ __global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) slab_kernel(SlabArgs a) {
     const long long plane = (long long)a.nx * a.ny;
     const int tiles_per_item = a.nslab * a.ntile_t;
     const int ntiles = tiles_per_item * a.nitems;
+    int cur_item = -1;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int item = t / tiles_per_item;
         const int rem = t - item * tiles_per_item;
         const int slab = rem / a.ntile_t;
         const int t0 = (rem - slab * a.ntile_t) * rows;
         const bool last_odd = (a.lone_in1 != nullptr || a.lone_out1 != nullptr) && item == a.nitems - 1;
+        if (a.items && a.mul && item != cur_item) {  // per-item chain factors (uniform branch)
+            __syncthreads();
+            const SepItem& it = a.items[item];
+            const T sc = (T)a.scale;
+            for (int i = tid; i < a.nx; i += nthr) {
+                C<T> v = mk<T>(sc, (T)0);
+                for (int j = 0; j < it.ntab; ++j) v = mul<T>(v, reinterpret_cast<const C<T>*>(it.tab[j])[i]);
+                if (a.conj_tab) v.y = -v.y;
+                fx[i] = v;
+            }
+            if (a.do_t) {
+                for (int i = tid; i < a.m; i += nthr) {
+                    C<T> v = mk<T>((T)1, (T)0);
+                    for (int j = 0; j < it.ntab; ++j)
+                        v = mul<T>(v, reinterpret_cast<const C<T>*>(it.tab[j])[a.nx + a.ny + i]);
+                    if (a.conj_tab) v.y = -v.y;
+                    ft[i] = v;
+                }
+            }
+            cur_item = item;
+        }
 
         // ---- load: tile[r][x] for theta = t0 + r
-        const T* in0 = reinterpret_cast<const T*>(a.in0) + (long long)item * a.item_stride_in;
+        const T* in0 = a.items ? reinterpret_cast<const T*>(a.items[item].in)
+                               : reinterpret_cast<const T*>(a.in0) + (long long)item * a.item_stride_in;
         const T* in1;
         if (a.in_mode == 0) {
             in0 += (long long)(2 * slab) * a.nx;
@@ -120,7 +143,8 @@ __global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) slab_kernel(SlabArgs a) {
         }
 
         // ---- store
-        T* out0 = reinterpret_cast<T*>(a.out0) + (long long)item * a.item_stride_out;
+        T* out0 = a.items ? reinterpret_cast<T*>(a.items[item].out)
+                          : reinterpret_cast<T*>(a.out0) + (long long)item * a.item_stride_out;
         T* out1;
         if (a.out_mode == 0) {
             out0 += (long long)(2 * slab) * a.nx;
@@ -172,6 +196,7 @@ __global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) pencil_kernel(PencilArgs 
     const int tiles_per_item = ncol_tiles * nother;
     const int ntiles = tiles_per_item * a.nitems;
     const int P = L * a.W;
+    int cur_item = -1;
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const int item = t / tiles_per_item;
         const int rem = t - item * tiles_per_item;
@@ -181,10 +206,25 @@ __global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) pencil_kernel(PencilArgs 
         const long long obase = (a.axis == 1) ? (long long)other * plane : (long long)other * a.nx;
 
         __syncthreads();
+        if (a.items && a.mul == 1 && item != cur_item) {  // per-item 1-D factor (uniform branch)
+            const SepItem& it = a.items[item];
+            const long long off = a.axis == 1 ? a.nx : (long long)a.nx + a.ny;
+            const T sc = (T)a.scale;
+            for (int i = tid; i < L; i += nthr) {
+                C<T> v = mk<T>(sc, (T)0);
+                for (int j = 0; j < it.ntab; ++j) v = mul<T>(v, reinterpret_cast<const C<T>*>(it.tab[j])[off + i]);
+                if (a.conj_tab) v.y = -v.y;
+                f1[i] = v;
+            }
+            cur_item = item;
+            __syncthreads();
+        }
         if (a.mode == 0) {
             // x-pair view: complex column c = (x = 2c, x = 2c + 1)
-            const C<T>* in = reinterpret_cast<const C<T>*>(
-                reinterpret_cast<const T*>(a.in0) + (long long)item * a.item_stride_in + obase);
+            // with items the pencil runs in place on each field's output (written by the slab pass)
+            const T* ibase = a.items ? reinterpret_cast<const T*>(a.items[item].out)
+                                     : reinterpret_cast<const T*>(a.in0) + (long long)item * a.item_stride_in;
+            const C<T>* in = reinterpret_cast<const C<T>*>(ibase + obase);
             for (int i = tid; i < P; i += nthr) {
                 const int e = i / a.W;
                 const int c = i - e * a.W;
@@ -247,8 +287,9 @@ __global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) pencil_kernel(PencilArgs 
         if (a.inv) line_fft<T, MAXV, true>(tile, tw, a.p, pitch, 1, a.W, true, tid, nthr);
 
         if (a.mode == 0) {
-            C<T>* out = reinterpret_cast<C<T>*>(
-                reinterpret_cast<T*>(a.out0) + (long long)item * a.item_stride_out + obase);
+            T* obase_ptr = a.items ? reinterpret_cast<T*>(a.items[item].out)
+                                   : reinterpret_cast<T*>(a.out0) + (long long)item * a.item_stride_out;
+            C<T>* out = reinterpret_cast<C<T>*>(obase_ptr + obase);
             for (int i = tid; i < P; i += nthr) {
                 const int e = i / a.W;
                 const int c = i - e * a.W;

@@ -13,6 +13,16 @@
 
 namespace se2c {
 
+// One field of a heterogeneous launch (separable tables only): its input, output
+// and the SEPARABLE tables of its chain (Tx at 0, Ty at Nx, Tt at Nx + Ny complex).
+// Slab passes read `in` and write `out`; pencil passes run in place on `out`.
+struct SepItem {
+    const void* in;
+    void* out;
+    const void* tab[SE2C_MAX_TABLES];
+    int ntab;
+};
+
 // Tile = rows_per_tile theta-rows x nx of one y-slab.  in_mode/out_mode:
 // 0 = y-pair of one real field (rows 2s, 2s+1), 1 = two real planes (in0, in1).
 struct SlabArgs {
@@ -42,6 +52,7 @@ struct SlabArgs {
     RadixPlan px, pt;
     const void* twx;
     const void* twt;
+    const SepItem* items;   // device; non-null: item i reads items[i] (y-pair modes, separable product)
 };
 
 // Tile = W adjacent columns x L points along axis (1 = y, 2 = theta) at a fixed
@@ -74,6 +85,7 @@ struct PencilArgs {
     double scale;
     RadixPlan p;
     const void* tw;
+    const SepItem* items;   // device; non-null: item i reads items[i] (x-pair mode, 1-D factor product)
 };
 
 size_t slab_lds_bytes(const SlabArgs& a, bool dbl);

@@ -70,27 +70,51 @@ xt_slab_fast(FastSepArgs a) {
     float2* twm = ft + M;                                // w_M^j (TPC == 2)
     const int tid = threadIdx.x;
 
+    const int nslab = a.ny / 2;
+    const int tile = blockIdx.x;  // one y-pair slab per block
+    const int item = tile / nslab;
+    const int s = tile - item * nslab;
+    const long long plane = (long long)NX * a.ny;
+    const int pl = (int)plane;
+    // the field's input, output and table chain (shared by the launch, or per item)
+    const float* fin;
+    float* fout;
+    const void* tx[SE2C_MAX_TABLES];
+    const void* tt[SE2C_MAX_TABLES];
+    int ntab;
+    if (a.items) {
+        const SepItem& it = a.items[item];
+        fin = reinterpret_cast<const float*>(it.in);
+        fout = reinterpret_cast<float*>(it.out);
+        ntab = it.ntab;
+        for (int j = 0; j < ntab; ++j) {
+            tx[j] = it.tab[j];
+            tt[j] = reinterpret_cast<const float2*>(it.tab[j]) + NX + a.ny;
+        }
+    } else {
+        fin = a.in + (long long)item * a.n;
+        fout = a.out + (long long)item * a.n;
+        ntab = a.ntab;
+        for (int j = 0; j < ntab; ++j) {
+            tx[j] = a.tx[j];
+            tt[j] = a.tt[j];
+        }
+    }
     for (int i = tid; i < 16 * R2; i += NT) {
         const int k1 = i / R2, t = i - k1 * R2;
         const float2 w = a.tw[t * k1];
         tw_f[k1 * R2 + t] = w;
         tw_i[t * 16 + k1] = w;
     }
-    for (int i = tid; i < NX; i += NT) fx[i] = chain_factor(a.tx, a.ntab, i, 1.0f / NX, a.conj_tab);
-    for (int i = tid; i < M; i += NT) ft[i] = chain_factor(a.tt, a.ntab, i, 1.0f / M, a.conj_tab);
+    for (int i = tid; i < NX; i += NT) fx[i] = chain_factor(tx, ntab, i, 1.0f / NX, a.conj_tab);
+    for (int i = tid; i < M; i += NT) ft[i] = chain_factor(tt, ntab, i, 1.0f / M, a.conj_tab);
     if (TPC == 2)
         for (int i = tid; i < M; i += NT) twm[i] = a.twt[i];
     __syncthreads();
 
     const int t = tid % R2, g = tid / R2;
-    const long long plane = (long long)NX * a.ny;
-    const int pl = (int)plane;
-    const int nslab = a.ny / 2;
-    const int tile = blockIdx.x;  // one y-pair slab per block
-    const int item = tile / nslab;
-    const int s = tile - item * nslab;
     // uniform tile base; per-lane offsets stay 32-bit (Nx Ny M < 2^30 is checked on the host)
-    const float* __restrict__ in0 = a.in + (long long)item * a.n + (long long)(2 * s) * NX;
+    const float* __restrict__ in0 = fin + (long long)(2 * s) * NX;
     const float* __restrict__ in1 = in0 + NX;
 
     // 1. row-layout loads: rows theta = g + G i, columns x = t + R2 r
@@ -192,7 +216,7 @@ xt_slab_fast(FastSepArgs a) {
         RegDFT<MV, true, float>::run(v);
     }
     // 5. store columns
-    float* __restrict__ out0 = a.out + (long long)item * a.n + (long long)(2 * s) * NX;
+    float* __restrict__ out0 = fout + (long long)(2 * s) * NX;
     float* __restrict__ out1 = out0 + NX;
 #pragma unroll
     for (int l = 0; l < MV; ++l) {
@@ -220,7 +244,8 @@ __global__ void __launch_bounds__(NY) y_pencil_fast(FastSepArgs a) {
         tw_f[k1 * R2 + t] = w;
         tw_i[t * 16 + k1] = w;
     }
-    for (int i = tid; i < NY; i += NT) fy[i] = chain_factor(a.ty, a.ntab, i, 1.0f / NY, a.conj_tab);
+    if (!a.items)
+        for (int i = tid; i < NY; i += NT) fy[i] = chain_factor(a.ty, a.ntab, i, 1.0f / NY, a.conj_tab);
     __syncthreads();
 
     const int q = tid % W, t = tid / W;
@@ -229,35 +254,56 @@ __global__ void __launch_bounds__(NY) y_pencil_fast(FastSepArgs a) {
     const long long plane = (long long)a.nx * NY;
     const int per_item = ctiles * a.m;
     const int ntiles = per_item * a.nitems;
-    // complex (float2) offset of a tile's first column; per-lane offsets are 32-bit
-    auto tile_base = [&](int tile) -> long long {
+    // complex (float2) pointer to a tile's first column; per-lane offsets are 32-bit
+    auto tile_src = [&](int tile) -> const float2* {
         const int item = tile / per_item;
         const int rem = tile - item * per_item;
         const int th = rem / ctiles;
         const int ct = rem - th * ctiles;
-        return ((long long)item * a.n + (long long)th * plane) / 2 + ct * W;
+        // with items the pencil runs in place on each field's output (written by the slab pass)
+        const float* base = a.items ? reinterpret_cast<const float*>(a.items[item].out) : a.in + (long long)item * a.n;
+        return reinterpret_cast<const float2*>(base + (long long)th * plane) + ct * W;
     };
-    const float2* __restrict__ gin = reinterpret_cast<const float2*>(a.in);
-    float2* __restrict__ gout = reinterpret_cast<float2*>(a.out);
+    auto tile_dst = [&](int tile) -> float2* {
+        const int item = tile / per_item;
+        const int rem = tile - item * per_item;
+        const int th = rem / ctiles;
+        const int ct = rem - th * ctiles;
+        float* base = a.items ? reinterpret_cast<float*>(a.items[item].out) : a.out + (long long)item * a.n;
+        return reinterpret_cast<float2*>(base + (long long)th * plane) + ct * W;
+    };
     // persistent blocks: the next tile's loads are issued before this tile's arithmetic
-    float2 nxt[16];
-    int tile = blockIdx.x;
     const int lane_off = q + t * ncols;
     const int rstride = R2 * ncols;
+    float2 nxt[16];
+    int tile = blockIdx.x;
     if (tile < ntiles) {
-        const float2* src = gin + tile_base(tile);
+        const float2* src = tile_src(tile);
 #pragma unroll
         for (int r = 0; r < 16; ++r) nxt[r] = (src + r * rstride)[lane_off];
     }
+    int cur_item = -1;
     for (; tile < ntiles; tile += gridDim.x) {
         float2 w[16];
 #pragma unroll
         for (int r = 0; r < 16; ++r) w[r] = nxt[r];
         const int next = tile + gridDim.x;
         if (next < ntiles) {
-            const float2* src = gin + tile_base(next);
+            const float2* src = tile_src(next);
 #pragma unroll
             for (int r = 0; r < 16; ++r) nxt[r] = (src + r * rstride)[lane_off];
+        }
+        if (a.items) {
+            const int item = tile / per_item;  // uniform across the block
+            if (item != cur_item) {
+                __syncthreads();
+                const SepItem& it = a.items[item];
+                const void* ty[SE2C_MAX_TABLES];
+                for (int j = 0; j < it.ntab; ++j) ty[j] = reinterpret_cast<const float2*>(it.tab[j]) + a.nx;
+                for (int i = tid; i < NY; i += NT) fy[i] = chain_factor(ty, it.ntab, i, 1.0f / NY, a.conj_tab);
+                __syncthreads();
+                cur_item = item;
+            }
         }
         dft16<float, false>(w);
 #pragma unroll
@@ -289,7 +335,7 @@ __global__ void __launch_bounds__(NY) y_pencil_fast(FastSepArgs a) {
 #pragma unroll
         for (int k1 = 0; k1 < 16; ++k1) w[k1] = buf[(k1 * R2 + t) * W + q];
         dft16<float, true>(w);
-        float2* dst = gout + tile_base(tile);
+        float2* dst = tile_dst(tile);
 #pragma unroll
         for (int r = 0; r < 16; ++r) (dst + r * rstride)[lane_off] = w[r];
     }

@@ -20,6 +20,7 @@ struct FastSepArgs {
     const float2* tw;  // FP64-generated twiddles w_L^j of the transform length (rounded)
     const float2* twt; // FP64-generated twiddles w_M^j (theta), used by the split-column slab
     int grid_blocks;   // persistent-grid size for the pencil kernel
+    const SepItem* items;  // device; non-null: field i is items[i] (own input, output and tables)
 };
 
 bool slab_fast_supported(int nx, int m);
