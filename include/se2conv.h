@@ -207,6 +207,21 @@ se2conv_status se2conv_chain(se2conv_plan_t plan, const se2conv_problem* probs, 
  */
 se2conv_status se2conv_pass_times(se2conv_plan_t plan, float* ms, int32_t* kinds, int32_t cap, int32_t* n);
 
+/*
+ * se2conv_powers: every intermediate convolution of Algorithm 7 (Sec. 6.3),
+ *   out[p-1][b] = Re S_K[f_b, rho^(p)],  p = 1 .. q,
+ * with rho^(p) the p-fold self-convolution of the kernel chain in d_table (coefficients
+ * rho^[k]^p; Thm. f*gP(2) and eq. (SqKfg)).  One forward 3-D transform of f, then for each p
+ * a running Hadamard product H_p = H_{p-1} . rho^ and one inverse transform, as the paper's
+ * fast loop does.
+ *   d_out   device [q][batch][M][Ny][Nx] of the plan dtype (must not overlap d_f); the last
+ *           slot holds the running spectrum until the final step.
+ *   q       1 .. 4096.  flags: SE2CONV_ADJOINT conjugates the table.
+ * Uses the plan workspace (and two more planes for odd batches).
+ */
+se2conv_status se2conv_powers(se2conv_plan_t plan, int32_t shape_idx, const void* d_f, const void* d_table,
+                              int32_t q, void* d_out, int32_t batch, uint32_t flags, hipStream_t stream);
+
 /* Static description of a status code. */
 const char* se2conv_status_string(se2conv_status s);
 /* Message of the last error on the calling thread ("" if none). */

@@ -169,6 +169,17 @@ class Plan:
                                                float(r_max), out.data_ptr(), _stream_handle(stream)))
         return out
 
+    def powers(self, shape_idx: int, f: torch.Tensor, table: Table, q: int, adjoint: bool = False,
+               stream=None) -> torch.Tensor:
+        """All S_K[f, rho^(p)], p = 1..q (the paper's fast loop): a [q, *f.shape] tensor."""
+        _require(f, self.tdtype)
+        nx, ny, m = self.shapes[shape_idx]
+        batch = f.numel() // (nx * ny * m)
+        out = torch.empty((q,) + tuple(f.shape), dtype=f.dtype, device=f.device)
+        L.check(self._lib.se2conv_powers(self.handle, shape_idx, f.data_ptr(), table.ptr, q, out.data_ptr(), batch,
+                                         L.ADJOINT if adjoint else 0, _stream_handle(stream)))
+        return out
+
     def pass_times(self, cap: int = 4096):
         """[(pass kind name, milliseconds)] of passes enqueued with timing=True since the last read."""
         ms = (ctypes.c_float * cap)()

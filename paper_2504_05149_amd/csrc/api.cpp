@@ -619,6 +619,51 @@ hipError_t y_pass(se2conv_plan_s* p, const se2conv_shape& s, bool d, void* re, v
     return run_pencil(b, d, st);
 }
 
+// y pencils on complex plane pairs, input planes -> output planes (may coincide).
+hipError_t y_pass_io(se2conv_plan_s* p, const se2conv_shape& s, bool d, const void* in_re, const void* in_im,
+                     void* out_re, void* out_im, const void* lone_in, void* lone_out, long long stride, int nitems,
+                     int fwd, int inv, int mul, const Chain* ch, bool conj, double scale, hipStream_t st) {
+    PencilArgs b{};
+    b.in0 = in_re;
+    b.in1 = in_im;
+    b.out0 = out_re;
+    b.out1 = out_im;
+    b.lone_in1 = lone_in;
+    b.lone_out1 = lone_out;
+    b.item_stride_in = stride;
+    b.item_stride_out = stride;
+    b.nitems = nitems;
+    b.mode = 1;
+    b.axis = 1;
+    b.nx = s.nx;
+    b.ny = s.ny;
+    b.m = s.m;
+    b.ncols = s.nx;
+    b.W = pencil_width(b.ncols, s.ny, d);
+    b.fwd = fwd;
+    b.inv = inv;
+    b.mul = mul;
+    b.p = make_radix_plan(s.ny);
+    b.tw = tw_of(p, s.ny, d);
+    b.conj_tab = conj ? 1 : 0;
+    b.scale = scale;
+    if (mul && ch) {
+        const size_t cb = cplx_bytes(p);
+        b.ntab = ch->ntab;
+        for (int j = 0; j < ch->ntab; ++j) {
+            if (ch->kind[j] == SE2CONV_TABLE_FULL) {
+                b.tab3[j] = ch->ptr[j];
+            } else {
+                b.tab3[j] = nullptr;
+                b.sepx[j] = ch->ptr[j];
+                b.sepy[j] = (const char*)ch->ptr[j] + cb * s.nx;
+                b.sept[j] = (const char*)ch->ptr[j] + cb * (s.nx + s.ny);
+            }
+        }
+    }
+    return run_pencil(b, d, st);
+}
+
 // Full (non-separable) chain on pairs of fields.
 se2conv_status enqueue_full(se2conv_plan_s* p, const se2conv_shape& s, const void* f, void* out, int batch,
                             const Chain& ch, bool conj, hipStream_t st) {
@@ -1007,6 +1052,63 @@ se2conv_status se2conv_profile_grad(se2conv_plan_t p, int32_t shape_idx, const v
     double* G = basis + npts * n_knots;
     HIPCHK(launch_profile_grad(d_grad_samples, batch, dbl(p), n_knots, r_max, s.nx, s.ny, s.m, basis, G, d_grad_prof,
                                stream));
+    return ok();
+}
+
+se2conv_status se2conv_powers(se2conv_plan_t p, int32_t shape_idx, const void* d_f, const void* d_table, int32_t q,
+                              void* d_out, int32_t batch, uint32_t flags, hipStream_t stream) {
+    if (q < 1 || q > 4096) return fail(SE2CONV_ERR_INVALID_ARG, "q must lie in [1, 4096]");
+    se2conv_status r = validate_io(p, shape_idx, d_f, d_out, batch);
+    if (r != SE2CONV_OK) return r;
+    if (flags & ~SE2CONV_ADJOINT) return fail(SE2CONV_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    const se2conv_shape& s = p->shapes[shape_idx];
+    const long long n = (long long)s.nx * s.ny * s.m;
+    const size_t rb = real_bytes(p);
+    {
+        const char* a = (const char*)d_f;
+        const char* b = (const char*)d_out;
+        const long long fb = (long long)batch * n * (long long)rb, ob = fb * q;
+        if (a < b + ob && b < a + fb) return fail(SE2CONV_ERR_INVALID_ARG, "d_out must not overlap d_f");
+    }
+    Chain ch;
+    bool all_sep = true;
+    const void* tabs[1] = {d_table};
+    r = lookup_chain(p, shape_idx, tabs, 1, &ch, &all_sep);
+    if (r != SE2CONV_OK) return r;
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    const bool d = dbl(p);
+    const bool conj = (flags & SE2CONV_ADJOINT) != 0;
+    const bool odd = (batch & 1) != 0;
+    const int pairs = (batch + 1) / 2;
+    if (odd) {
+        std::lock_guard<std::mutex> g(p->mu);
+        if (!p->ws2 && hipMalloc(&p->ws2, 2 * p->ws_bytes) != hipSuccess)
+            return fail(SE2CONV_ERR_OUT_OF_MEMORY, "workspace (%zu bytes)", 2 * p->ws_bytes);
+    }
+    const long long slot = (long long)batch * n;  // elements per output slot
+    auto slot_re = [&](int k) { return (char*)d_out + rb * (slot * k); };
+    auto slot_im = [&](int k) { return batch == 1 ? nullptr : (char*)d_out + rb * (slot * k + n); };
+    const void* f_im = batch == 1 ? nullptr : (const char*)d_f + rb * n;
+    void* spec_lone = odd ? p->ws : nullptr;    // imaginary plane of the lone field's spectrum
+    void* step_lone = odd ? p->ws2 : nullptr;   // imaginary plane of its per-step inverse
+    char* S_re = slot_re(q - 1);
+    char* S_im = slot_im(q - 1);
+    // forward: H_0 = F^ (pairs of fields packed as re/im), stored in the last slot
+    HIPCHK(xt_transform(p, s, d, 0, d_f, f_im, S_re, S_im, nullptr, spec_lone, 2 * n, 2 * n, pairs, stream));
+    HIPCHK(y_pass_io(p, s, d, S_re, S_im, S_re, S_im, spec_lone, spec_lone, 2 * n, pairs, 1, 0, 0, nullptr, false,
+                     1.0, stream));
+    for (int k = 1; k <= q; ++k) {
+        // running product H_k = H_{k-1} . rho^  (the iDFT's 1/n is folded in once, at k = 1)
+        HIPCHK(y_pass_io(p, s, d, S_re, S_im, S_re, S_im, spec_lone, spec_lone, 2 * n, pairs, 0, 0, 2, &ch, conj,
+                         k == 1 ? 1.0 / (double)n : 1.0, stream));
+        // inverse into slot k-1 (the last step inverts the running spectrum in place)
+        char* O_re = slot_re(k - 1);
+        char* O_im = slot_im(k - 1);
+        void* o_lone = k == q ? spec_lone : step_lone;
+        HIPCHK(y_pass_io(p, s, d, S_re, S_im, O_re, O_im, spec_lone, o_lone, 2 * n, pairs, 0, 1, 0, nullptr, false,
+                         1.0, stream));
+        HIPCHK(xt_transform(p, s, d, 1, O_re, O_im, O_re, O_im, o_lone, nullptr, 2 * n, 2 * n, pairs, stream));
+    }
     return ok();
 }
 

@@ -330,3 +330,33 @@ def test_foreign_table_is_rejected():
     with pytest.raises(se2.Se2convError) as e:
         p2.apply(0, f, t1)
     assert e.value.status == 1
+
+
+# ------------------------------------------------------- Algorithm 7 (powers)
+@pytest.mark.parametrize("nx,ny,m,batch,q,dt,kind", [
+    (32, 24, 16, 3, 4, "f64", "sep"),
+    (32, 32, 16, 2, 3, "f32", "full"),
+    (64, 64, 32, 1, 5, "f32", "sep"),
+    (48, 32, 24, 2, 2, "f64", "full"),
+])
+def test_all_powers_match_oracle_alg7(nx, ny, m, batch, q, dt, kind, rng):
+    case(f"Algorithm 7 powers {nx}x{ny}x{m} {dt} batch={batch} q={q} {kind} table")
+    plan = se2.Plan([(nx, ny, m)], dtype=dt)
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    if kind == "sep":
+        p = ok.gauss_vm(nx, ny, m, 0.06, 3.0, 0.5)
+        table = plan.coeffs(0, [se2.GaussVM(0.06, 3.0, 0.5)])
+    else:
+        prof = rng.uniform(0, 1, size=(10, m))
+        p = ok.radial_profile(nx, ny, m, prof, 0.4)
+        p = p / p.mean()
+        table = plan.coeffs(0, [se2.RadialProfile(_dev(prof, torch.float64), 0.4, norm=0)])
+    f = _fields(11, batch, 8, nx, ny, m)
+    out = plan.powers(0, _dev(f, tdt), table, q).cpu().numpy().astype(np.float64)
+    tol = tol32(nx * ny * m) if dt == "f32" else TOL64
+    for b in range(batch):
+        refs = oc.alg7_all_powers(f[b], p, q)
+        for k in range(q):
+            err = rel_l2(out[k, b], refs[k])
+            print(f"  field {b} power {k + 1}: {err:.2e}", flush=True)
+            assert err <= tol
