@@ -208,6 +208,30 @@ se2conv_status se2conv_chain(se2conv_plan_t plan, const se2conv_problem* probs, 
 se2conv_status se2conv_pass_times(se2conv_plan_t plan, float* ms, int32_t* kinds, int32_t cap, int32_t* n);
 
 /*
+ * se2conv_autotune: choose the launch schedule of one shape by timing candidates on
+ * synthetic data (batch fields, one Gaussian x von Mises kernel): generic pencil tile width
+ * (4..32 columns), blocks per CU of the persistent fast pencil (2, 4, 8) and x-row tile size
+ * of the three-pass schedule.  The fastest schedule is kept in the plan and, when the
+ * environment variable SE2CONV_TUNE_CACHE names a file, appended to it as a JSON line; plans
+ * created later load that file (malformed lines are ignored).  Allocates and frees its own
+ * buffers; synchronises the stream.
+ */
+se2conv_status se2conv_autotune(se2conv_plan_t plan, int32_t shape_idx, int32_t batch, hipStream_t stream);
+
+/*
+ * se2conv_sample_bumps: samples on Omega_L (eq. (OmL)) of a field made of Gaussian x von
+ * Mises bumps periodized over the lattice (eq. (TH)):
+ *   f(x, y, theta) = sum_b w_b G(x - cx_b) G(y - cy_b) exp(kappa cos(theta - theta0_b)),
+ *   G(u) = sum_{l=-3..3} exp(-(u + l)^2 / (2 s^2)),
+ * evaluated in FP64 and rounded to the plan dtype.
+ *   d_params  device FP64 [n_bumps][4] = (cx, cy, theta0, w).
+ *   d_out     device [M][Ny][Nx] (one field).
+ * For s <= 0.1 the omitted images are below 1e-21 of the peak.  Uses the plan's FP64 scratch.
+ */
+se2conv_status se2conv_sample_bumps(se2conv_plan_t plan, int32_t shape_idx, const double* d_params,
+                                    int32_t n_bumps, double s, double kappa, void* d_out, hipStream_t stream);
+
+/*
  * se2conv_powers: every intermediate convolution of Algorithm 7 (Sec. 6.3),
  *   out[p-1][b] = Re S_K[f_b, rho^(p)],  p = 1 .. q,
  * with rho^(p) the p-fold self-convolution of the kernel chain in d_table (coefficients

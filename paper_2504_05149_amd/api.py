@@ -180,6 +180,27 @@ class Plan:
                                          L.ADJOINT if adjoint else 0, _stream_handle(stream)))
         return out
 
+    def sample_bumps(self, shape_idx: int, centres, theta0, weights, s: float, kappa: float,
+                     out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """Samples of a periodized Gaussian x von Mises bump field on the grid (one field)."""
+        nx, ny, m = self.shapes[shape_idx]
+        import numpy as np
+        params = np.stack([np.asarray(centres)[:, 0], np.asarray(centres)[:, 1], np.asarray(theta0),
+                           np.asarray(weights)], axis=1).astype(np.float64)
+        dparams = torch.from_numpy(np.ascontiguousarray(params)).to("cuda")
+        if out is None:
+            out = torch.empty(m, ny, nx, dtype=self.tdtype, device="cuda")
+        _require(out, self.tdtype)
+        L.check(self._lib.se2conv_sample_bumps(self.handle, shape_idx, dparams.data_ptr(), params.shape[0],
+                                               float(s), float(kappa), out.data_ptr(), _stream_handle(stream)))
+        # keep the parameter buffer alive until the kernel has read it
+        (torch.cuda.current_stream() if stream is None else stream).synchronize()
+        return out
+
+    def autotune(self, shape_idx: int, batch: int = 4, stream=None) -> None:
+        """Time candidate launch schedules for one shape and keep the fastest in the plan."""
+        L.check(self._lib.se2conv_autotune(self.handle, shape_idx, batch, _stream_handle(stream)))
+
     def pass_times(self, cap: int = 4096):
         """[(pass kind name, milliseconds)] of passes enqueued with timing=True since the last read."""
         ms = (ctypes.c_float * cap)()

@@ -20,6 +20,7 @@
 #include "passes.hpp"
 #include "sep_fast.hpp"
 #include "grad.hpp"
+#include "sample.hpp"
 
 using namespace se2c;
 
@@ -113,6 +114,14 @@ int threads_for(long long P, bool d) {
     return (int)t;
 }
 
+// Tunable launch parameters of one shape (se2conv_autotune picks them by timing).
+struct Schedule {
+    int pencil_w = 16;          // generic pencils: columns per tile (clamped to the LDS/thread limits)
+    int fast_blocks_per_cu = 4; // persistent fast y pencil
+    int xrow_points = 4096;     // three-pass schedule: points per x-row tile
+    bool tuned = false;
+};
+
 struct TableRec {
     int32_t shape_idx;
     int32_t kind;
@@ -139,6 +148,7 @@ struct se2conv_plan_s {
     uint32_t flags = 0;
     bool host_only = false;
     std::vector<se2conv_shape> shapes;
+    std::vector<Schedule> sched;       // one per shape
     std::map<int, void*> tw32, tw64;   // length -> device twiddle table
     void* ws = nullptr;                // one real plane of the largest shape (plan dtype)
     size_t ws_bytes = 0;
@@ -223,15 +233,23 @@ int sep_chunk_fields(const se2conv_plan_s* p, const se2conv_shape& s, int batch)
     return batch;
 }
 
-int rows_for_xpass(const se2conv_shape& s) {
+int rows_for_xpass(const se2conv_shape& s, int points = 4096) {
     int best = 1;
     for (int r = 1; r <= s.m; ++r)
-        if (s.m % r == 0 && (long long)r * s.nx <= 4096) best = r;
+        if (s.m % r == 0 && (long long)r * s.nx <= points) best = r;
     return best;
 }
 
-int pencil_width(int ncols, int L, bool d) {
-    int W = 16;
+// The schedule of a shape (shapes are looked up by value: passes receive the shape).
+const Schedule& sched_of(const se2conv_plan_s* p, const se2conv_shape& s) {
+    static const Schedule dflt;
+    for (size_t i = 0; i < p->shapes.size(); ++i)
+        if (p->shapes[i].nx == s.nx && p->shapes[i].ny == s.ny && p->shapes[i].m == s.m) return p->sched[i];
+    return dflt;
+}
+
+int pencil_width(int ncols, int L, bool d, int want = 16) {
+    int W = want;
     while (W > 1 && (long long)W * L > (long long)SE2C_MAXV * max_threads(d)) W /= 2;
     if (ncols < W) W = ncols;
     return W;
@@ -309,7 +327,7 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
     fa.m = s.m;
     fa.ntab = ch.ntab;
     fa.conj_tab = conj ? 1 : 0;
-    fa.grid_blocks = p->num_cus * 4;
+    fa.grid_blocks = p->num_cus * sched_of(p, s).fast_blocks_per_cu;
     for (int j = 0; j < ch.ntab; ++j) {
         fa.tx[j] = fx(j);
         fa.ty[j] = fy(j);
@@ -350,7 +368,7 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
         a.do_t = 1;
         a.scale = 1.0 / ((double)s.nx * s.m);
     } else {
-        a.rows_per_tile = rows_for_xpass(s);
+        a.rows_per_tile = rows_for_xpass(s, sched_of(p, s).xrow_points);
         a.ntile_t = s.m / a.rows_per_tile;
         a.do_t = 0;
         a.scale = 1.0 / (double)s.nx;
@@ -372,7 +390,7 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
         b.m = s.m;
         b.ncols = s.nx / 2;
         const int L = axis == 1 ? s.ny : s.m;
-        b.W = pencil_width(b.ncols, L, d);
+        b.W = pencil_width(b.ncols, L, d, sched_of(p, s).pencil_w);
         b.pad = 0;
         b.fwd = 1;
         b.inv = 1;
@@ -418,7 +436,7 @@ se2conv_status enqueue_sep_items(se2conv_plan_s* p, const se2conv_shape& s, cons
     fa.ny = s.ny;
     fa.m = s.m;
     fa.conj_tab = conj ? 1 : 0;
-    fa.grid_blocks = p->num_cus * 4;
+    fa.grid_blocks = p->num_cus * sched_of(p, s).fast_blocks_per_cu;
     fa.items = d_items;
     if (fast_slab) {
         fa.tw = reinterpret_cast<const float2*>(tw_of(p, s.nx, false));
@@ -450,7 +468,7 @@ se2conv_status enqueue_sep_items(se2conv_plan_s* p, const se2conv_shape& s, cons
             a.do_t = 1;
             a.scale = 1.0 / ((double)s.nx * s.m);
         } else {
-            a.rows_per_tile = rows_for_xpass(s);
+            a.rows_per_tile = rows_for_xpass(s, sched_of(p, s).xrow_points);
             a.ntile_t = s.m / a.rows_per_tile;
             a.do_t = 0;
             a.scale = 1.0 / (double)s.nx;
@@ -468,7 +486,7 @@ se2conv_status enqueue_sep_items(se2conv_plan_s* p, const se2conv_shape& s, cons
         b.m = s.m;
         b.ncols = s.nx / 2;
         const int L = axis == 1 ? s.ny : s.m;
-        b.W = pencil_width(b.ncols, L, d);
+        b.W = pencil_width(b.ncols, L, d, sched_of(p, s).pencil_w);
         b.fwd = 1;
         b.inv = 1;
         b.mul = 1;
@@ -528,7 +546,7 @@ hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int d
         return run_slab(a, d, st);
     }
     // split: x rows and theta pencils (planes mode), in the right order
-    a.rows_per_tile = rows_for_xpass(s);
+    a.rows_per_tile = rows_for_xpass(s, sched_of(p, s).xrow_points);
     a.ntile_t = s.m / a.rows_per_tile;
     a.do_t = 0;
     PencilArgs b{};
@@ -538,7 +556,7 @@ hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int d
     b.ny = s.ny;
     b.m = s.m;
     b.ncols = s.nx;
-    b.W = pencil_width(b.ncols, s.m, d);
+    b.W = pencil_width(b.ncols, s.m, d, sched_of(p, s).pencil_w);
     b.pad = 0;
     b.fwd = dir == 0;
     b.inv = dir == 1;
@@ -593,7 +611,7 @@ hipError_t y_pass(se2conv_plan_s* p, const se2conv_shape& s, bool d, void* re, v
     b.ny = s.ny;
     b.m = s.m;
     b.ncols = s.nx;
-    b.W = pencil_width(b.ncols, s.ny, d);
+    b.W = pencil_width(b.ncols, s.ny, d, sched_of(p, s).pencil_w);
     b.pad = 0;
     b.fwd = fwd;
     b.inv = inv;
@@ -639,7 +657,7 @@ hipError_t y_pass_io(se2conv_plan_s* p, const se2conv_shape& s, bool d, const vo
     b.ny = s.ny;
     b.m = s.m;
     b.ncols = s.nx;
-    b.W = pencil_width(b.ncols, s.ny, d);
+    b.W = pencil_width(b.ncols, s.ny, d, sched_of(p, s).pencil_w);
     b.fwd = fwd;
     b.inv = inv;
     b.mul = mul;
@@ -733,6 +751,59 @@ se2conv_status enqueue_problem(se2conv_plan_s* p, int shape_idx, const void* f, 
     return enqueue_full(p, s, f, out, batch, ch, conj, st);
 }
 
+// ---- tuning cache: JSON lines {"nx":..,"ny":..,"m":..,"dtype":..,"w":..,"b":..,"x":..}
+const char* tune_cache_path() { return std::getenv("SE2CONV_TUNE_CACHE"); }
+
+bool parse_int_field(const std::string& line, const char* key, int* out) {
+    const std::string k = std::string("\"") + key + "\":";
+    const size_t pos = line.find(k);
+    if (pos == std::string::npos) return false;
+    char* end = nullptr;
+    const long v = std::strtol(line.c_str() + pos + k.size(), &end, 10);
+    if (end == line.c_str() + pos + k.size()) return false;
+    *out = (int)v;
+    return true;
+}
+
+// Malformed lines are ignored: a corrupt cache only means default schedules.
+void load_tune_cache(se2conv_plan_s* p) {
+    const char* path = tune_cache_path();
+    if (!path) return;
+    FILE* fh = std::fopen(path, "r");
+    if (!fh) return;
+    char buf[512];
+    while (std::fgets(buf, sizeof(buf), fh)) {
+        const std::string line(buf);
+        int nx, ny, m, dt, w, b, x;
+        if (!parse_int_field(line, "nx", &nx) || !parse_int_field(line, "ny", &ny) ||
+            !parse_int_field(line, "m", &m) || !parse_int_field(line, "dtype", &dt) ||
+            !parse_int_field(line, "w", &w) || !parse_int_field(line, "b", &b) || !parse_int_field(line, "x", &x))
+            continue;
+        if (dt != (int)p->dtype || w < 1 || w > 64 || b < 1 || b > 32 || x < 64 || x > 65536) continue;
+        for (size_t i = 0; i < p->shapes.size(); ++i) {
+            if (p->shapes[i].nx == nx && p->shapes[i].ny == ny && p->shapes[i].m == m) {
+                p->sched[i].pencil_w = w;
+                p->sched[i].fast_blocks_per_cu = b;
+                p->sched[i].xrow_points = x;
+                p->sched[i].tuned = true;
+            }
+        }
+    }
+    std::fclose(fh);
+}
+
+void append_tune_cache(const se2conv_plan_s* p, int i) {
+    const char* path = tune_cache_path();
+    if (!path) return;
+    FILE* fh = std::fopen(path, "a");
+    if (!fh) return;
+    const se2conv_shape& s = p->shapes[i];
+    const Schedule& sc = p->sched[i];
+    std::fprintf(fh, "{\"nx\":%d,\"ny\":%d,\"m\":%d,\"dtype\":%d,\"w\":%d,\"b\":%d,\"x\":%d}\n", s.nx, s.ny, s.m,
+                 (int)p->dtype, sc.pencil_w, sc.fast_blocks_per_cu, sc.xrow_points);
+    std::fclose(fh);
+}
+
 se2conv_status ensure_scratch64(se2conv_plan_s* p, size_t bytes) {
     if (p->scratch64_bytes >= bytes) return SE2CONV_OK;
     if (p->scratch64) {
@@ -812,6 +883,8 @@ se2conv_status se2conv_plan(const se2conv_shape* shapes, int32_t n_shapes, se2co
     p->dtype = dtype;
     p->flags = flags;
     p->shapes.assign(shapes, shapes + n_shapes);
+    p->sched.assign(n_shapes, Schedule());
+    load_tune_cache(p);
     if (flags & SE2CONV_PLAN_HOST_ONLY) {
         p->host_only = true;
         *out = p;
@@ -1052,6 +1125,111 @@ se2conv_status se2conv_profile_grad(se2conv_plan_t p, int32_t shape_idx, const v
     double* G = basis + npts * n_knots;
     HIPCHK(launch_profile_grad(d_grad_samples, batch, dbl(p), n_knots, r_max, s.nx, s.ny, s.m, basis, G, d_grad_prof,
                                stream));
+    return ok();
+}
+
+se2conv_status se2conv_autotune(se2conv_plan_t p, int32_t shape_idx, int32_t batch, hipStream_t stream) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (shape_idx < 0 || shape_idx >= (int)p->shapes.size())
+        return fail(SE2CONV_ERR_INVALID_ARG, "shape_idx %d out of range", shape_idx);
+    if (batch < 1 || batch > 4096) return fail(SE2CONV_ERR_INVALID_ARG, "batch must lie in [1, 4096]");
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    const se2conv_shape s = p->shapes[shape_idx];
+    const size_t bytes = real_bytes(p) * (size_t)batch * s.nx * s.ny * s.m;
+    void* f = nullptr;
+    void* out = nullptr;
+    void* tab = nullptr;
+    if (hipMalloc(&f, bytes) != hipSuccess) return fail(SE2CONV_ERR_OUT_OF_MEMORY, "autotune buffers");
+    auto release = [&]() {
+        (void)hipStreamSynchronize(stream);
+        if (f) (void)hipFree(f);
+        if (out) (void)hipFree(out);
+        if (tab) (void)hipFree(tab);
+    };
+    if (hipMalloc(&out, bytes) != hipSuccess) {
+        release();
+        return fail(SE2CONV_ERR_OUT_OF_MEMORY, "autotune buffers");
+    }
+    se2conv_kernel_desc k{};
+    k.kind = SE2CONV_K_GAUSS_VM;
+    k.sigma = 0.05;
+    k.kappa = 4.0;
+    size_t tb = 0;
+    se2conv_status r = se2conv_coeffs(p, shape_idx, &k, 1, nullptr, &tb, stream);
+    if (r == SE2CONV_OK && hipMalloc(&tab, tb) != hipSuccess) r = fail(SE2CONV_ERR_OUT_OF_MEMORY, "autotune table");
+    if (r == SE2CONV_OK) r = se2conv_coeffs(p, shape_idx, &k, 1, tab, &tb, stream);
+    if (r == SE2CONV_OK && hipMemsetAsync(f, 0, bytes, stream) != hipSuccess)
+        r = fail(SE2CONV_ERR_DEVICE, "autotune fill");
+    if (r != SE2CONV_OK) {
+        release();
+        return r;
+    }
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        release();
+        return fail(SE2CONV_ERR_DEVICE, "event creation");
+    }
+    // only the knobs this shape's schedule uses are varied
+    const bool d = dbl(p);
+    const bool two_pass = slab_fits(s, d);
+    const bool fast_pencil = !d && !(p->flags & SE2CONV_PLAN_GENERIC) && two_pass &&
+                             slab_fast_supported(s.nx, s.m) && pencil_fast_supported(s.nx, s.ny);
+    const Schedule dflt;
+    std::vector<int> widths = {dflt.pencil_w}, blocks = {dflt.fast_blocks_per_cu}, xrows = {dflt.xrow_points};
+    if (!fast_pencil || !two_pass) widths = {4, 8, 16, 32};
+    if (fast_pencil) blocks = {2, 4, 8};
+    if (!two_pass) xrows = {1024, 2048, 4096, 8192};
+    Schedule best = p->sched[shape_idx];
+    float best_ms = 1e30f;
+    for (int w : widths)
+        for (int b : blocks)
+            for (int x : xrows) {
+                Schedule c;
+                c.pencil_w = w;
+                c.fast_blocks_per_cu = b;
+                c.xrow_points = x;
+                p->sched[shape_idx] = c;
+                float ms = 0.f;
+                bool okrun = true;
+                for (int rep = 0; rep < 2 && okrun; ++rep) okrun = se2conv_apply(p, shape_idx, f, tab, out, batch, 0, stream) == SE2CONV_OK;
+                okrun = okrun && hipEventRecord(e0, stream) == hipSuccess;
+                for (int rep = 0; rep < 5 && okrun; ++rep) okrun = se2conv_apply(p, shape_idx, f, tab, out, batch, 0, stream) == SE2CONV_OK;
+                okrun = okrun && hipEventRecord(e1, stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                        hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+                if (okrun && ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        p->tables.erase(reinterpret_cast<uintptr_t>(tab));
+    }
+    release();
+    best.tuned = true;
+    p->sched[shape_idx] = best;
+    append_tune_cache(p, shape_idx);
+    return ok();
+}
+
+se2conv_status se2conv_sample_bumps(se2conv_plan_t p, int32_t shape_idx, const double* d_params, int32_t n_bumps,
+                                    double s, double kappa, void* d_out, hipStream_t stream) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (shape_idx < 0 || shape_idx >= (int)p->shapes.size())
+        return fail(SE2CONV_ERR_INVALID_ARG, "shape_idx %d out of range", shape_idx);
+    if (!d_params || !d_out || n_bumps < 1 || n_bumps > (1 << 20))
+        return fail(SE2CONV_ERR_INVALID_ARG, "need device pointers and 1 <= n_bumps <= 2^20");
+    if (!(s > 0.0) || !std::isfinite(s) || !(kappa >= 0.0) || kappa > 700.0)
+        return fail(SE2CONV_ERR_INVALID_ARG, "need s > 0 and 0 <= kappa <= 700");
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    const se2conv_shape& sh = p->shapes[shape_idx];
+    std::lock_guard<std::mutex> g(p->mu);
+    se2conv_status r = ensure_scratch64(p, sizeof(double) * (size_t)n_bumps * (sh.nx + sh.ny + sh.m));
+    if (r != SE2CONV_OK) return r;
+    HIPCHK(launch_sample_bumps(d_params, n_bumps, s, kappa, sh.nx, sh.ny, sh.m,
+                               reinterpret_cast<double*>(p->scratch64), d_out, dbl(p), stream));
     return ok();
 }
 

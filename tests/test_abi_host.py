@@ -126,3 +126,18 @@ def test_chain_validation_on_host_only_plan():
 def test_pass_times_empty_on_fresh_plan():
     p = se2.Plan([(32, 32, 16)], dtype="f32", host_only=True)
     assert p.pass_times() == []
+
+
+def test_corrupt_tuning_cache_falls_back_to_defaults(tmp_path, monkeypatch):
+    # A tuning cache with malformed lines must not break plan creation.
+    import subprocess
+    import sys
+    cache = tmp_path / "tune.jsonl"
+    cache.write_text('{"nx":32,"ny":32,"m":16,"dtype":0,"w":8,"b":2,"x":2048}\n'
+                     'garbage line\n{"nx":32,"ny":\n{"nx":32,"ny":32,"m":16,"dtype":0,"w":999,"b":2,"x":2048}\n')
+    code = ("import paper_2504_05149_amd as se2; p = se2.Plan([(32, 32, 16)], host_only=True); "
+            "print(p.table_bytes(0, [se2.GaussVM(0.05, 4.0)]))")
+    env = dict(__import__("os").environ, SE2CONV_TUNE_CACHE=str(cache))
+    res = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
+    assert res.stdout.strip() == str(8 * (32 + 32 + 16))

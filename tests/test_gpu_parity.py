@@ -360,3 +360,36 @@ def test_all_powers_match_oracle_alg7(nx, ny, m, batch, q, dt, kind, rng):
             err = rel_l2(out[k, b], refs[k])
             print(f"  field {b} power {k + 1}: {err:.2e}", flush=True)
             assert err <= tol
+
+
+# ------------------------------------------------------------ field sampling
+@pytest.mark.parametrize("dt,shape,nb", [("f64", (32, 48, 16), 8), ("f32", (256, 256, 64), 32), ("f64", (96, 64, 24), 5)])
+def test_gpu_sampler_matches_generator(dt, shape, nb):
+    from inputs import bump_field
+    case(f"GPU bump sampler {shape} {dt} {nb} bumps")
+    nx, ny, m = shape
+    bf = bump_field(12, 3, nb)
+    plan = se2.Plan([shape], dtype=dt)
+    out = plan.sample_bumps(0, bf.centres, bf.theta0, bf.weights, bf.s, bf.kappa).cpu().numpy()
+    ref = sample_field(bf, nx, ny, m)
+    err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
+    assert err <= (1e-14 if dt == "f64" else 1e-6), err
+
+
+def test_autotuned_schedules_stay_correct(tmp_path, monkeypatch):
+    case("autotune: 48x48x32 (generic), 64x64x16 (register kernels), 512x16x64 (three-pass); results vs oracle")
+    monkeypatch.setenv("SE2CONV_TUNE_CACHE", str(tmp_path / "tune.jsonl"))
+    shapes = [(48, 48, 32), (64, 64, 16), (512, 16, 64)]
+    plan = se2.Plan(shapes, dtype="f32")
+    for i in range(len(shapes)):
+        plan.autotune(i, batch=2)
+    lines = (tmp_path / "tune.jsonl").read_text().strip().splitlines()
+    assert len(lines) == 3
+    for i, (nx, ny, m) in enumerate(shapes):
+        chain = [(0.05, 3.0, 0.2), (0.03, 9.0, 0.0)]
+        table = plan.coeffs(i, [se2.GaussVM(*k) for k in chain])
+        f = _fields(13, 2, 8, nx, ny, m)
+        out = plan.apply(i, _dev(f, torch.float32), table).cpu().numpy().astype(np.float64)
+        ref_t = oracle_table_gauss(nx, ny, m, chain)
+        for b in range(2):
+            assert rel_l2(out[b], oracle_conv(f[b], ref_t)) <= tol32(nx * ny * m)
