@@ -147,6 +147,22 @@ se2conv_status se2conv_field_coeffs(se2conv_plan_t plan, int32_t shape_idx, cons
                                     void* d_tables, size_t table_stride, hipStream_t stream);
 
 /*
+ * se2conv_kernel_grad: gradient of a loss with respect to the samples P of one kernel,
+ * summed over a batch: for out_b = Re S_K[f_b, rho] and g_b = dL/dout_b,
+ *   dP = sum_b Re S_K[g_b, conj f_b^] = Re iDFT( sum_b G_b^ . conj(f_b^) ),
+ * accumulated in the spectral domain (two g fields per complex FFT, separated by Hermitian
+ * symmetry) and inverted once.
+ *   d_g           device [batch][M][Ny][Nx] (plan dtype).
+ *   d_ftables     the fields' FFC tables from se2conv_field_coeffs (table b at
+ *                 d_ftables + b * table_stride); for a kernel chain pass tables that already
+ *                 include the other kernels' coefficients.
+ *   d_grad        device [M][Ny][Nx] (plan dtype), overwritten.
+ * Uses four workspace planes of the largest shape (allocated on first use).
+ */
+se2conv_status se2conv_kernel_grad(se2conv_plan_t plan, int32_t shape_idx, const void* d_g, const void* d_ftables,
+                                   size_t table_stride, int32_t batch, void* d_grad, hipStream_t stream);
+
+/*
  * se2conv_profile_grad: transpose of the RADIAL_PROFILE sample expansion, summed over a
  * batch: grad_prof[q][l] = sum_b sum_{j,i} H_q(x_ij) dP_b[l][j][i], where
  * H_q(x) = sum_images max(0, 1 - | |x + image| / h - q |), h = r_max / (n_knots - 1).

@@ -24,7 +24,7 @@ PASS_KINDS = {0: "xt_slab", 1: "y_pencil", 2: "t_pencil", 3: "x_rows"}
 EXPORTED = [
     "se2conv_plan", "se2conv_plan_destroy", "se2conv_coeffs", "se2conv_table_info",
     "se2conv_apply", "se2conv_chain", "se2conv_pass_times", "se2conv_field_coeffs", "se2conv_profile_grad",
-    "se2conv_powers", "se2conv_sample_bumps", "se2conv_autotune",
+    "se2conv_powers", "se2conv_sample_bumps", "se2conv_autotune", "se2conv_kernel_grad",
     "se2conv_status_string",
     "se2conv_last_error",
 ]
@@ -88,13 +88,15 @@ def load() -> ctypes.CDLL:
     lib.se2conv_powers.argtypes = [vp, i32, vp, vp, i32, vp, i32, u32, vp]
     lib.se2conv_sample_bumps.argtypes = [vp, i32, vp, i32, ctypes.c_double, ctypes.c_double, vp, vp]
     lib.se2conv_autotune.argtypes = [vp, i32, i32, vp]
+    lib.se2conv_kernel_grad.argtypes = [vp, i32, vp, vp, sz, i32, vp, vp]
     lib.se2conv_status_string.argtypes = [i32]
     lib.se2conv_status_string.restype = ctypes.c_char_p
     lib.se2conv_last_error.argtypes = []
     lib.se2conv_last_error.restype = ctypes.c_char_p
     for name in ["se2conv_plan", "se2conv_plan_destroy", "se2conv_coeffs", "se2conv_table_info",
                  "se2conv_apply", "se2conv_chain", "se2conv_pass_times", "se2conv_field_coeffs",
-                 "se2conv_profile_grad", "se2conv_powers", "se2conv_sample_bumps", "se2conv_autotune"]:
+                 "se2conv_profile_grad", "se2conv_powers", "se2conv_sample_bumps", "se2conv_autotune",
+                 "se2conv_kernel_grad"]:
         getattr(lib, name).restype = i32
     _lib = lib
     return lib

@@ -158,6 +158,22 @@ class Plan:
         raw = buf.view(torch.uint8).view(batch, -1)
         return [Table(self, shape_idx, raw[b], L.TABLE_FULL) for b in range(batch)]
 
+    def kernel_grad(self, shape_idx: int, g: torch.Tensor, ftables: list, stream=None) -> torch.Tensor:
+        """sum_b dL/dP_b for dL/dout_b = g_b, given the fields' FFC tables (one [M, Ny, Nx] tensor)."""
+        _require(g, self.tdtype)
+        nx, ny, m = self.shapes[shape_idx]
+        batch = g.numel() // (nx * ny * m)
+        if len(ftables) != batch:
+            raise ValueError("need one field table per field")
+        base = ftables[0].ptr
+        stride = ftables[1].ptr - base if batch > 1 else ftables[0].buf.numel()
+        if any(t.ptr != base + b * stride for b, t in enumerate(ftables)):
+            raise ValueError("field tables must come from one se2conv_field_coeffs call")
+        out = torch.empty(m, ny, nx, dtype=self.tdtype, device=g.device)
+        L.check(self._lib.se2conv_kernel_grad(self.handle, shape_idx, g.data_ptr(), base, stride, batch,
+                                              out.data_ptr(), _stream_handle(stream)))
+        return out
+
     def profile_grad(self, shape_idx: int, grad_samples: torch.Tensor, n_knots: int, r_max: float,
                      stream=None) -> torch.Tensor:
         """sum over the batch of the hat-basis transpose of dL/dP: a float64 [n_knots, M] tensor."""

@@ -5,8 +5,8 @@ P[l][j][i] = sum_q prof[q][l] H_q(x_ij) (raw samples, no renormalisation, so the
 map prof -> P is linear).  Gradients (all computed by the HIP library):
 
 * dL/df    = adjoint apply of dL/dout with the kernel table (correlation);
-* dL/dP_b  = adjoint apply of dL/dout_b with the field's own FFC table
-             (se2conv_field_coeffs), i.e. Re S_K[g_b, conj f_b^];
+* sum_b dL/dP_b = Re iDFT(sum_b G_b^ . conj f_b^) with the fields' own FFC tables
+             (se2conv_field_coeffs), accumulated spectrally (se2conv_kernel_grad);
 * dL/dprof = hat-basis transpose of sum_b dL/dP_b (se2conv_profile_grad).
 
 checkpoint=True computes the field tables in the forward pass and keeps them for
@@ -44,9 +44,8 @@ class RadialProfileConv(torch.autograd.Function):
             grad_f = plan.apply(sidx, g, ctx.table, adjoint=True)
         if ctx.needs_input_grad[1]:
             ftabs = ctx.ftabs if ctx.ftabs is not None else plan.field_coeffs(sidx, f)
-            grad_p = torch.empty_like(g)
-            batch = g.shape[0]
-            plan.chain([(sidx, g[b:b + 1], grad_p[b:b + 1], [ftabs[b]]) for b in range(batch)], adjoint=True)
+            # sum_b dL/dP_b, accumulated in the spectral domain and inverted once
+            grad_p = plan.kernel_grad(sidx, g, ftabs)
             grad_prof = plan.profile_grad(sidx, grad_p, ctx.n_knots, ctx.r_max)
         return grad_f, grad_prof, None, None, None, None
 

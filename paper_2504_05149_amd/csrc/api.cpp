@@ -153,6 +153,7 @@ struct se2conv_plan_s {
     void* ws = nullptr;                // one real plane of the largest shape (plan dtype)
     size_t ws_bytes = 0;
     void* ws2 = nullptr;               // two more planes (field tables), allocated on first use
+    void* ws4 = nullptr;               // four more planes (kernel gradient), allocated on first use
     void* scratch64 = nullptr;         // FP64 scratch for se2conv_coeffs
     size_t scratch64_bytes = 0;
     std::unordered_map<uintptr_t, TableRec> tables;
@@ -951,6 +952,7 @@ se2conv_status se2conv_plan_destroy(se2conv_plan_t p) {
         for (auto& kv : p->tw64) (void)hipFree(kv.second);
         if (p->ws) (void)hipFree(p->ws);
         if (p->ws2) (void)hipFree(p->ws2);
+        if (p->ws4) (void)hipFree(p->ws4);
         if (p->scratch64) (void)hipFree(p->scratch64);
         if (cur >= 0) (void)hipSetDevice(cur);
     }
@@ -1103,6 +1105,53 @@ se2conv_status se2conv_field_coeffs(se2conv_plan_t p, int32_t shape_idx, const v
         rec.bytes = tbytes;
         p->tables[reinterpret_cast<uintptr_t>((char*)d_tables + table_stride * b)] = rec;
     }
+    return ok();
+}
+
+se2conv_status se2conv_kernel_grad(se2conv_plan_t p, int32_t shape_idx, const void* d_g, const void* d_ftables,
+                                   size_t table_stride, int32_t batch, void* d_grad, hipStream_t stream) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (shape_idx < 0 || shape_idx >= (int)p->shapes.size())
+        return fail(SE2CONV_ERR_INVALID_ARG, "shape_idx %d out of range", shape_idx);
+    if (batch < 1 || !d_g || !d_ftables || !d_grad || !aligned16(d_g) || !aligned16(d_grad))
+        return fail(SE2CONV_ERR_INVALID_ARG, "need batch >= 1 and aligned device pointers");
+    const se2conv_shape& s = p->shapes[shape_idx];
+    const long long n = (long long)s.nx * s.ny * s.m;
+    const size_t tbytes = cplx_bytes(p) * (size_t)n;
+    if (table_stride < tbytes || (table_stride & 15u))
+        return fail(SE2CONV_ERR_INVALID_ARG, "table_stride must be >= %zu and a multiple of 16", tbytes);
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        for (int b = 0; b < batch; ++b) {
+            auto it = p->tables.find(reinterpret_cast<uintptr_t>((const char*)d_ftables + table_stride * b));
+            if (it == p->tables.end() || it->second.shape_idx != shape_idx || it->second.kind != SE2CONV_TABLE_FULL)
+                return fail(SE2CONV_ERR_INVALID_ARG, "field table %d was not produced by this plan for this shape", b);
+        }
+    }
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    const bool d = dbl(p);
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        if (!p->ws4 && hipMalloc(&p->ws4, 4 * p->ws_bytes) != hipSuccess)
+            return fail(SE2CONV_ERR_OUT_OF_MEMORY, "kernel-gradient workspace (%zu bytes)", 4 * p->ws_bytes);
+    }
+    const size_t rb = real_bytes(p);
+    void* zre = p->ws4;
+    void* zim = (char*)p->ws4 + p->ws_bytes;
+    void* are = (char*)p->ws4 + 2 * p->ws_bytes;
+    void* aim = (char*)p->ws4 + 3 * p->ws_bytes;
+    for (int b = 0; b < batch; b += 2) {
+        const void* ga = (const char*)d_g + rb * n * b;
+        const void* gb = (b + 1 < batch) ? (const char*)d_g + rb * n * (b + 1) : nullptr;
+        HIPCHK(xt_transform(p, s, d, 0, ga, gb, zre, zim, nullptr, nullptr, n, n, 1, stream));
+        HIPCHK(y_pass(p, s, d, zre, zim, nullptr, n, 1, 1, 0, 0, nullptr, false, 1.0, stream));
+        const void* ta = (const char*)d_ftables + table_stride * b;
+        const void* tb = gb ? (const char*)d_ftables + table_stride * (b + 1) : nullptr;
+        HIPCHK(launch_accumulate_pair(zre, zim, ta, tb, are, aim, s.nx, s.ny, s.m, 1.0 / (double)n, b == 0, d, stream));
+    }
+    // inverse of the accumulated (Hermitian) spectrum; the imaginary part is rounding only
+    HIPCHK(y_pass(p, s, d, are, aim, nullptr, n, 1, /*fwd=*/0, /*inv=*/1, /*mul=*/0, nullptr, false, 1.0, stream));
+    HIPCHK(xt_transform(p, s, d, 1, are, aim, d_grad, nullptr, nullptr, nullptr, n, n, 1, stream));
     return ok();
 }
 

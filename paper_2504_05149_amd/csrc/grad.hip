@@ -53,6 +53,57 @@ hipError_t launch_unpack_tables(const void* zre, const void* zim, void* ta, void
     return hipGetLastError();
 }
 
+// acc[k] (+)= s * ( G_a^[k] conj(Ta[k]) + G_b^[k] conj(Tb[k]) ), with G_a^, G_b^ unpacked from
+// the spectrum Z^ = G_a^ + i G_b^ of a packed pair (tb may be null: single field, G_b^ = 0).
+template <typename T>
+__global__ void accumulate_pair_kernel(const T* zre, const T* zim, const void* ta, const void* tb, T* accre,
+                                       T* accim, int nx, int ny, int m, T scale, int first) {
+    using C2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+    const long long n = (long long)nx * ny * m;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int kx = (int)(idx % nx);
+        const int ky = (int)((idx / nx) % ny);
+        const int kt = (int)(idx / ((long long)nx * ny));
+        const long long midx = ((long long)((m - kt) % m) * ny + (ny - ky) % ny) * nx + (nx - kx) % nx;
+        const T zr = zre[idx], zi = zim[idx];
+        const T cr = zre[midx], ci = -zim[midx];
+        // G_a = (z + c)/2, G_b = (z - c)/(2i)
+        const T ar = (T)0.5 * (zr + cr), ai = (T)0.5 * (zi + ci);
+        const T br = (T)0.5 * (zi - ci), bi = -(T)0.5 * (zr - cr);
+        const C2 wa = reinterpret_cast<const C2*>(ta)[idx];
+        // G_a conj(Ta)
+        T re = ar * wa.x + ai * wa.y;
+        T im = ai * wa.x - ar * wa.y;
+        if (tb) {
+            const C2 wb = reinterpret_cast<const C2*>(tb)[idx];
+            re += br * wb.x + bi * wb.y;
+            im += bi * wb.x - br * wb.y;
+        }
+        re *= scale;
+        im *= scale;
+        if (first) {
+            accre[idx] = re;
+            accim[idx] = im;
+        } else {
+            accre[idx] += re;
+            accim[idx] += im;
+        }
+    }
+}
+
+hipError_t launch_accumulate_pair(const void* zre, const void* zim, const void* ta, const void* tb, void* accre,
+                                  void* accim, int nx, int ny, int m, double scale, int first, bool dbl,
+                                  hipStream_t s) {
+    if (dbl)
+        hipLaunchKernelGGL(accumulate_pair_kernel<double>, dim3(2048), dim3(256), 0, s, (const double*)zre,
+                           (const double*)zim, ta, tb, (double*)accre, (double*)accim, nx, ny, m, scale, first);
+    else
+        hipLaunchKernelGGL(accumulate_pair_kernel<float>, dim3(2048), dim3(256), 0, s, (const float*)zre,
+                           (const float*)zim, ta, tb, (float*)accre, (float*)accim, nx, ny, m, (float)scale, first);
+    return hipGetLastError();
+}
+
 // basis[q][j][i] = sum_images max(0, 1 - |r/h - q|), h = r_max/(n_knots-1)
 __global__ void profile_basis_kernel(double* basis, int n_knots, double r_max, int nx, int ny) {
     const long long npts = (long long)nx * ny;

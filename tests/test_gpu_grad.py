@@ -139,3 +139,19 @@ def test_fp64_finite_differences_on_gpu(rng):
                loss_of(_dev(f, torch.float64), _dev(prof - e, torch.float64))) / (2 * h)
         ana = pd.grad[idx].item()
         assert abs(num - ana) <= 1e-5 * max(1.0, abs(ana)), (idx, num, ana)
+
+
+@pytest.mark.parametrize("dt,batch", [("f64", 3), ("f32", 4), ("f64", 1)])
+def test_kernel_grad_accumulates_over_batch(dt, batch, rng):
+    case(f"kernel gradient summed over the batch, 32x24x16 {dt} batch={batch}")
+    nx, ny, m = 32, 24, 16
+    f = sample_fields(24, batch, 8, nx, ny, m)
+    g = rng.standard_normal((batch, m, ny, nx))
+    plan = se2.Plan([(nx, ny, m)], dtype=dt)
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    tabs = plan.field_coeffs(0, _dev(f, tdt))
+    out = plan.kernel_grad(0, _dev(g, tdt), tabs).cpu().numpy().astype(np.float64)
+    ref = sum(OA.grad_kernel_samples(f[b], g[b]) for b in range(batch))
+    err = rel_l2(out, ref)
+    print(f"  rel-L2 {err:.2e}", flush=True)
+    assert err <= (TOL64 if dt == "f64" else tol32(nx * ny * m))
