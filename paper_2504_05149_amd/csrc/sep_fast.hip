@@ -15,6 +15,9 @@
 //   3. transpose rows -> columns through LDS in chunks of 32 rows;
 //   4. theta convolution of a whole column in registers (one column per thread);
 //   5. store columns (each wave writes 1 KB contiguous per theta row).
+//   Every input and output byte is touched once, so the pass streams with
+//   nontemporal loads and stores (measured faster for this pass and for the
+//   y pass that reads its output).
 // y_pencil_fast<NY>    one block per 16 adjacent x-pairs (float2 columns) at one theta:
 //   the same 16 x R2 scheme along y, product with Ty/NY.
 #include "regfft.hpp"
@@ -58,7 +61,9 @@ xt_slab_fast(FastSepArgs a) {
     constexpr int RPT = M / G;           // theta rows per thread in row layout
     constexpr int RC = M < 32 ? M : 32;  // rows per transpose chunk
     constexpr int H = M / RC;
-    constexpr int P = NX + (R2 % 16);    // LDS row pitch (complex)
+    // LDS row pitch (complex): rows g and g + 1 start half a 64-bank cycle apart, so the
+    // two row groups of a half-wave never share a bank
+    constexpr int P = NX + (R2 == 16 ? 16 : R2 % 16);
     constexpr int MV = M / TPC;          // theta values per thread in column layout
     static_assert(G <= RC && RPT >= 1 && M % G == 0, "tile geometry");
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -66,8 +71,8 @@ xt_slab_fast(FastSepArgs a) {
     float2* tw_f = buf + RC * P;                         // [k1][t] = w_NX^{t k1}
     float2* tw_i = tw_f + 16 * R2;                       // [t][k1]
     float2* fx = tw_i + 16 * R2;                         // Tx / NX
-    float2* ft = fx + NX;                                // Tt / M
-    float2* twm = ft + M;                                // w_M^j (TPC == 2)
+    float2* ft = fx + NX;                                // Tt / M (TPC == 1)
+    float4* cm = reinterpret_cast<float4*>(ft);          // [hh][k] = (S_k, E_hh,k) (TPC == 2)
     const int tid = threadIdx.x;
 
     const int nslab = a.ny / 2;
@@ -107,9 +112,21 @@ xt_slab_fast(FastSepArgs a) {
         tw_i[t * 16 + k1] = w;
     }
     for (int i = tid; i < NX; i += NT) fx[i] = chain_factor(tx, ntab, i, 1.0f / NX, a.conj_tab);
-    for (int i = tid; i < M; i += NT) ft[i] = chain_factor(tt, ntab, i, 1.0f / M, a.conj_tab);
-    if (TPC == 2)
-        for (int i = tid; i < M; i += NT) twm[i] = a.twt[i];
+    if constexpr (TPC == 1) {
+        for (int i = tid; i < M; i += NT) ft[i] = chain_factor(tt, ntab, i, 1.0f / M, a.conj_tab);
+    } else {
+        // the radix-2 step across the lane pair, the product with Tt and the inverse
+        // radix-2 step fold into one 2 x 2 matrix per k < M/2 (see the column phase)
+        for (int k = tid; k < MV; k += NT) {
+            const float2 f0 = chain_factor(tt, ntab, k, 1.0f / M, a.conj_tab);
+            const float2 f1 = chain_factor(tt, ntab, k + MV, 1.0f / M, a.conj_tab);
+            const float2 sk = add<float>(f0, f1), dk = sub<float>(f0, f1);
+            const float2 b = a.twt[k];  // w_M^k
+            const float2 e0 = mul<float>(b, dk), e1 = mulc<float>(dk, b);
+            cm[k] = make_float4(sk.x, sk.y, e0.x, e0.y);
+            cm[MV + k] = make_float4(sk.x, sk.y, e1.x, e1.y);
+        }
+    }
     __syncthreads();
 
     const int t = tid % R2, g = tid / R2;
@@ -124,7 +141,7 @@ xt_slab_fast(FastSepArgs a) {
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int off = (g + G * i) * pl + t + R2 * r;
-            w[i][r] = make_float2(in0[off], in1[off]);
+            w[i][r] = make_float2(__builtin_nontemporal_load(in0 + off), __builtin_nontemporal_load(in1 + off));
         }
     }
     // 2. x convolution (16 x R2 decomposition)
@@ -190,28 +207,21 @@ xt_slab_fast(FastSepArgs a) {
         for (int k = 0; k < M; ++k) v[k] = mul<float>(v[k], ft[k]);
         RegDFT<M, true, float>::run(v);
     } else {
-        // theta = hh + 2 s: DFT over s, twiddle w_M^{hh k1}, radix-2 across the lane pair
+        // theta = hh + 2 s.  With Y_h = DFT over s of lane h's values and b = w_M^k,
+        // X[k] = Y_0 + b Y_1 and X[k + M/2] = Y_0 - b Y_1; after the product with
+        // F = Tt / M the inputs of the two inverse DFTs over s are
+        //   U_0 = S Y_0 + (b D) Y_1,   U_1 = (conj(b) D) Y_0 + S Y_1,
+        // S = F[k] + F[k + M/2], D = F[k] - F[k + M/2]: each lane combines its own
+        // value with its neighbour's (DPP swap) through two precomputed factors.
         RegDFT<MV, false, float>::run(v);
-        if (hh) {
+        const float4* cmh = cm + MV * hh;
 #pragma unroll
-            for (int k1 = 1; k1 < MV; ++k1) v[k1] = mul<float>(v[k1], twm[k1]);
-        }
-#pragma unroll
-        for (int k1 = 0; k1 < MV; ++k1) {
-            const float2 o = swap_lane1(v[k1]);
-            // lane hh = 0 keeps X[k1] = Y0 + Y1', lane hh = 1 keeps X[k1 + M/2] = Y0 - Y1'
-            v[k1] = hh ? sub<float>(o, v[k1]) : add<float>(v[k1], o);
-            v[k1] = mul<float>(v[k1], ft[k1 + MV * hh]);
-        }
-#pragma unroll
-        for (int k1 = 0; k1 < MV; ++k1) {
-            const float2 o = swap_lane1(v[k1]);
-            // U_hh[k1] = X'[k1] + (-1)^hh X'[k1 + M/2]
-            v[k1] = hh ? sub<float>(o, v[k1]) : add<float>(v[k1], o);
-        }
-        if (hh) {
-#pragma unroll
-            for (int k1 = 1; k1 < MV; ++k1) v[k1] = mulc<float>(v[k1], twm[k1]);
+        for (int k = 0; k < MV; ++k) {
+            const float2 o = swap_lane1(v[k]);
+            const float4 c = cmh[k];
+            const float2 y = v[k];
+            v[k].x = c.x * y.x - c.y * y.y + c.z * o.x - c.w * o.y;
+            v[k].y = c.x * y.y + c.y * y.x + c.z * o.y + c.w * o.x;
         }
         RegDFT<MV, true, float>::run(v);
     }
@@ -221,8 +231,8 @@ xt_slab_fast(FastSepArgs a) {
 #pragma unroll
     for (int l = 0; l < MV; ++l) {
         const int off = (TPC * l + hh) * pl + xc;
-        out0[off] = v[l].x;
-        out1[off] = v[l].y;
+        __builtin_nontemporal_store(v[l].x, out0 + off);
+        __builtin_nontemporal_store(v[l].y, out1 + off);
     }
 }
 
@@ -348,7 +358,7 @@ template <int NX, int M>
 static size_t slab_fast_lds() {
     constexpr int R2 = NX / 16;
     constexpr int RC = M < 32 ? M : 32;
-    constexpr int P = NX + (R2 % 16);
+    constexpr int P = NX + (R2 == 16 ? 16 : R2 % 16);
     return sizeof(float2) * ((size_t)RC * P + 32 * R2 + NX + 2 * M);
 }
 
