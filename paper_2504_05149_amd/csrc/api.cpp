@@ -279,6 +279,29 @@ hipError_t run_pencil(PencilArgs a, bool d, hipStream_t st) {
 }
 
 // Separable chain: every table SEPARABLE.  f, out: [batch][m][ny][nx] real.
+// Separable FP32 chain on shapes whose x-theta slab does not fit in LDS: three
+// register-kernel passes (x rows, y pencils, theta pencils), each a 1-D circular
+// convolution along its axis; the second and third run in place on the output.
+se2conv_status enqueue_three_pass_fast(se2conv_plan_s* p, const se2conv_shape& s, const FastSepArgs& fa,
+                                       hipStream_t st) {
+    FastSepArgs r = fa;
+    r.tw = reinterpret_cast<const float2*>(tw_of(p, s.nx, false));
+    HIPCHK(launch_rows_fast(r, st));
+    HIPCHK(after_pass(3, st));
+    FastSepArgs y = fa;
+    y.in = fa.out;
+    y.axis = 1;
+    y.tw = reinterpret_cast<const float2*>(tw_of(p, s.ny, false));
+    HIPCHK(launch_pencil_fast(y, st));
+    HIPCHK(after_pass(1, st));
+    FastSepArgs t = y;
+    t.axis = 2;
+    t.tw = reinterpret_cast<const float2*>(tw_of(p, s.m, false));
+    HIPCHK(launch_pencil_fast(t, st));
+    HIPCHK(after_pass(2, st));
+    return SE2CONV_OK;
+}
+
 se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void* f, void* out, int batch,
                            const Chain& ch, bool conj, hipStream_t st) {
     const bool d = dbl(p);
@@ -329,13 +352,17 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
     fa.ntab = ch.ntab;
     fa.conj_tab = conj ? 1 : 0;
     fa.grid_blocks = p->num_cus * sched_of(p, s).fast_blocks_per_cu;
+    fa.cus = p->num_cus;
     for (int j = 0; j < ch.ntab; ++j) {
         fa.tx[j] = fx(j);
         fa.ty[j] = fy(j);
         fa.tt[j] = ftt(j);
     }
+    fa.axis = 1;
     const bool fast_slab = !d && !generic_only && two_pass && slab_fast_supported(s.nx, s.m);
     const bool fast_pencil = !d && !generic_only && two_pass && pencil_fast_supported(s.nx, s.ny);
+    if (!d && !generic_only && !two_pass && three_pass_fast_supported(s.nx, s.ny, s.m))
+        return enqueue_three_pass_fast(p, s, fa, st);
     if (fast_slab && fast_pencil) {
         // Fields are processed in chunks whose intermediate (one real plane set per
         // field) stays resident in the memory-side cache between the two passes.
@@ -438,7 +465,11 @@ se2conv_status enqueue_sep_items(se2conv_plan_s* p, const se2conv_shape& s, cons
     fa.m = s.m;
     fa.conj_tab = conj ? 1 : 0;
     fa.grid_blocks = p->num_cus * sched_of(p, s).fast_blocks_per_cu;
+    fa.cus = p->num_cus;
+    fa.axis = 1;
     fa.items = d_items;
+    if (!d && !generic_only && !two_pass && three_pass_fast_supported(s.nx, s.ny, s.m))
+        return enqueue_three_pass_fast(p, s, fa, st);
     if (fast_slab) {
         fa.tw = reinterpret_cast<const float2*>(tw_of(p, s.nx, false));
         fa.twt = reinterpret_cast<const float2*>(tw_of(p, s.m, false));
@@ -1220,14 +1251,17 @@ se2conv_status se2conv_autotune(se2conv_plan_t p, int32_t shape_idx, int32_t bat
     }
     // only the knobs this shape's schedule uses are varied
     const bool d = dbl(p);
+    const bool generic = d || (p->flags & SE2CONV_PLAN_GENERIC) != 0;
     const bool two_pass = slab_fits(s, d);
-    const bool fast_pencil = !d && !(p->flags & SE2CONV_PLAN_GENERIC) && two_pass &&
-                             slab_fast_supported(s.nx, s.m) && pencil_fast_supported(s.nx, s.ny);
+    // register kernels: persistent pencils (blocks per CU); generic kernels: pencil
+    // width and, without the slab, x-row tile size
+    const bool fast_lines = !generic && (two_pass ? pencil_fast_supported(s.nx, s.ny)
+                                                  : three_pass_fast_supported(s.nx, s.ny, s.m));
     const Schedule dflt;
     std::vector<int> widths = {dflt.pencil_w}, blocks = {dflt.fast_blocks_per_cu}, xrows = {dflt.xrow_points};
-    if (!fast_pencil || !two_pass) widths = {4, 8, 16, 32};
-    if (fast_pencil) blocks = {2, 4, 8};
-    if (!two_pass) xrows = {1024, 2048, 4096, 8192};
+    if (fast_lines) blocks = {2, 4, 8};
+    else widths = {4, 8, 16, 32};
+    if (!two_pass && !fast_lines) xrows = {1024, 2048, 4096, 8192};
     Schedule best = p->sched[shape_idx];
     float best_ms = 1e30f;
     for (int w : widths)

@@ -236,91 +236,109 @@ xt_slab_fast(FastSepArgs a) {
     }
 }
 
-template <int NY>
-__global__ void __launch_bounds__(NY) y_pencil_fast(FastSepArgs a) {
-    constexpr int R2 = NY / 16;
-    constexpr int CC = 16 / R2;
-    constexpr int W = 16;             // complex columns (x-pairs) per tile
+// Line pencils: W = 16 adjacent x-pairs (float2 columns) x L points along y
+// (axis 1) or theta (axis 2) at one outer coordinate (theta for y, y for theta).
+// L = R1 x R2 with R1 = 16 values per thread (32 for L = 512).
+template <int L> struct LineGeom {
+    static constexpr int R1 = L > 256 ? 32 : 16;
+    static constexpr int R2 = L / R1;
+    static constexpr int CC = R1 / R2;
+    static constexpr int W = 16;
+    static constexpr int NT = W * R2;
+};
+
+template <int L>
+__global__ void __launch_bounds__(LineGeom<L>::NT) line_pencil_fast(FastSepArgs a) {
+    using Gm = LineGeom<L>;
+    constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC, W = Gm::W, NT = Gm::NT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float2* buf = reinterpret_cast<float2*>(smem_raw);  // [k1*R2 + t][W]
-    float2* tw_f = buf + NY * W;
-    float2* tw_i = tw_f + 16 * R2;
-    float2* fy = tw_i + 16 * R2;
+    float2* tw_f = buf + L * W;                         // [k1][t] = w_L^{t k1}
+    float2* tw_i = tw_f + L;                            // [t][k1]
+    float2* fl = tw_i + L;                              // line factor / L
     const int tid = threadIdx.x;
-    constexpr int NT = W * R2;
-    for (int i = tid; i < 16 * R2; i += NT) {
+    for (int i = tid; i < L; i += NT) {
         const int k1 = i / R2, t = i - k1 * R2;
         const float2 w = a.tw[t * k1];
         tw_f[k1 * R2 + t] = w;
-        tw_i[t * 16 + k1] = w;
+        tw_i[t * R1 + k1] = w;
     }
+    const int axis = a.axis;
+    // offset of this axis' factor inside a SEPARABLE table (complex units)
+    const int foff = axis == 1 ? a.nx : a.nx + a.ny;
     if (!a.items)
-        for (int i = tid; i < NY; i += NT) fy[i] = chain_factor(a.ty, a.ntab, i, 1.0f / NY, a.conj_tab);
+        for (int i = tid; i < L; i += NT)
+            fl[i] = chain_factor(axis == 1 ? a.ty : a.tt, a.ntab, i, 1.0f / L, a.conj_tab);
     __syncthreads();
 
     const int q = tid % W, t = tid / W;
     const int ncols = a.nx / 2;
     const int ctiles = ncols / W;
-    const long long plane = (long long)a.nx * NY;
-    const int per_item = ctiles * a.m;
+    const int nouter = axis == 1 ? a.m : a.ny;
+    // float2 strides: between points of a line, and between outer coordinates
+    const int lstride = axis == 1 ? ncols : ncols * a.ny;
+    const long long ostride = axis == 1 ? (long long)ncols * a.ny : (long long)ncols;
+    const int per_item = ctiles * nouter;
     const int ntiles = per_item * a.nitems;
-    // complex (float2) pointer to a tile's first column; per-lane offsets are 32-bit
+    auto tile_off = [&](int tile, int* item) -> long long {
+        *item = tile / per_item;
+        const int rem = tile - *item * per_item;
+        const int o = rem / ctiles;
+        const int ct = rem - o * ctiles;
+        return (long long)o * ostride + ct * W;
+    };
+    // with items the pencil runs in place on each field's output (written by the previous pass)
     auto tile_src = [&](int tile) -> const float2* {
-        const int item = tile / per_item;
-        const int rem = tile - item * per_item;
-        const int th = rem / ctiles;
-        const int ct = rem - th * ctiles;
-        // with items the pencil runs in place on each field's output (written by the slab pass)
+        int item;
+        const long long off = tile_off(tile, &item);
         const float* base = a.items ? reinterpret_cast<const float*>(a.items[item].out) : a.in + (long long)item * a.n;
-        return reinterpret_cast<const float2*>(base + (long long)th * plane) + ct * W;
+        return reinterpret_cast<const float2*>(base) + off;
     };
     auto tile_dst = [&](int tile) -> float2* {
-        const int item = tile / per_item;
-        const int rem = tile - item * per_item;
-        const int th = rem / ctiles;
-        const int ct = rem - th * ctiles;
+        int item;
+        const long long off = tile_off(tile, &item);
         float* base = a.items ? reinterpret_cast<float*>(a.items[item].out) : a.out + (long long)item * a.n;
-        return reinterpret_cast<float2*>(base + (long long)th * plane) + ct * W;
+        return reinterpret_cast<float2*>(base) + off;
     };
     // persistent blocks: the next tile's loads are issued before this tile's arithmetic
-    const int lane_off = q + t * ncols;
-    const int rstride = R2 * ncols;
-    float2 nxt[16];
+    const int lane_off = q + t * lstride;
+    const int rstride = R2 * lstride;
+    float2 nxt[R1];
     int tile = blockIdx.x;
     if (tile < ntiles) {
         const float2* src = tile_src(tile);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) nxt[r] = (src + r * rstride)[lane_off];
+        for (int r = 0; r < R1; ++r) nxt[r] = (src + r * rstride)[lane_off];
     }
     int cur_item = -1;
     for (; tile < ntiles; tile += gridDim.x) {
-        float2 w[16];
+        float2 w[R1];
 #pragma unroll
-        for (int r = 0; r < 16; ++r) w[r] = nxt[r];
+        for (int r = 0; r < R1; ++r) w[r] = nxt[r];
         const int next = tile + gridDim.x;
         if (next < ntiles) {
             const float2* src = tile_src(next);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) nxt[r] = (src + r * rstride)[lane_off];
+            for (int r = 0; r < R1; ++r) nxt[r] = (src + r * rstride)[lane_off];
         }
         if (a.items) {
             const int item = tile / per_item;  // uniform across the block
             if (item != cur_item) {
                 __syncthreads();
                 const SepItem& it = a.items[item];
-                const void* ty[SE2C_MAX_TABLES];
-                for (int j = 0; j < it.ntab; ++j) ty[j] = reinterpret_cast<const float2*>(it.tab[j]) + a.nx;
-                for (int i = tid; i < NY; i += NT) fy[i] = chain_factor(ty, it.ntab, i, 1.0f / NY, a.conj_tab);
+                const void* tl[SE2C_MAX_TABLES];
+                for (int j = 0; j < it.ntab; ++j) tl[j] = reinterpret_cast<const float2*>(it.tab[j]) + foff;
+                for (int i = tid; i < L; i += NT) fl[i] = chain_factor(tl, it.ntab, i, 1.0f / L, a.conj_tab);
                 __syncthreads();
                 cur_item = item;
             }
         }
-        dft16<float, false>(w);
+        RegDFT<R1, false, float>::run(w);
 #pragma unroll
-        for (int k1 = 1; k1 < 16; ++k1) w[k1] = mul<float>(w[k1], tw_f[k1 * R2 + t]);
+        for (int k1 = 1; k1 < R1; ++k1) w[k1] = mul<float>(w[k1], tw_f[k1 * R2 + t]);
         __syncthreads();
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) buf[(k1 * R2 + t) * W + q] = w[k1];
+        for (int k1 = 0; k1 < R1; ++k1) buf[(k1 * R2 + t) * W + q] = w[k1];
         __syncthreads();
         float2 u[CC][R2];
 #pragma unroll
@@ -330,10 +348,10 @@ __global__ void __launch_bounds__(NY) y_pencil_fast(FastSepArgs a) {
             for (int tt = 0; tt < R2; ++tt) u[j][tt] = buf[(k1 * R2 + tt) * W + q];
             RegDFT<R2, false, float>::run(u[j]);
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = mul<float>(u[j][k2], fy[k1 + 16 * k2]);
+            for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = mul<float>(u[j][k2], fl[k1 + R1 * k2]);
             RegDFT<R2, true, float>::run(u[j]);
 #pragma unroll
-            for (int tt = 1; tt < R2; ++tt) u[j][tt] = mulc<float>(u[j][tt], tw_i[tt * 16 + k1]);
+            for (int tt = 1; tt < R2; ++tt) u[j][tt] = mulc<float>(u[j][tt], tw_i[tt * R1 + k1]);
         }
         __syncthreads();
 #pragma unroll
@@ -343,11 +361,124 @@ __global__ void __launch_bounds__(NY) y_pencil_fast(FastSepArgs a) {
         }
         __syncthreads();
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) w[k1] = buf[(k1 * R2 + t) * W + q];
-        dft16<float, true>(w);
+        for (int k1 = 0; k1 < R1; ++k1) w[k1] = buf[(k1 * R2 + t) * W + q];
+        RegDFT<R1, true, float>::run(w);
         float2* dst = tile_dst(tile);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) (dst + r * rstride)[lane_off] = w[r];
+        for (int r = 0; r < R1; ++r) (dst + r * rstride)[lane_off] = w[r];
+    }
+}
+
+// x rows: one block per (y-pair, 16 theta rows); rows 2s and 2s+1 of a field are
+// packed as re/im, each row is convolved along x (the slab's x phase, R1 = 16 or 32
+// values per thread) and written back.  Used when the x-theta slab does not fit in LDS.
+template <int NX> struct RowGeom {
+    static constexpr int R1 = NX > 256 ? 32 : 16;
+    static constexpr int R2 = NX / R1;
+    static constexpr int CC = R1 / R2;
+    static constexpr int G = 16;                      // theta rows per tile
+    static constexpr int NT = G * R2;
+    static constexpr int P = NX + (R2 == 16 ? 16 : R2 % 16);  // LDS row pitch (complex)
+};
+
+// Position of element (k1, t) of one R1 x R2 exchange line (see xpos).
+template <int R1, int R2>
+__device__ __forceinline__ int xpos_line(int k1, int t) {
+    constexpr int CC = R1 / R2;
+    return k1 * R2 + (t ^ (k1 / CC));
+}
+
+template <int NX>
+__global__ void __launch_bounds__(RowGeom<NX>::NT) x_rows_fast(FastSepArgs a) {
+    using Gm = RowGeom<NX>;
+    constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC, G = Gm::G, NT = Gm::NT, P = Gm::P;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float2* buf = reinterpret_cast<float2*>(smem_raw);  // G x P
+    float2* tw_f = buf + G * P;                          // [k1][t] = w_NX^{t k1}
+    float2* tw_i = tw_f + NX;                            // [t][k1]
+    float2* fx = tw_i + NX;                              // Tx / NX
+    const int tid = threadIdx.x;
+    const int nslab = a.ny / 2;
+    const int trows = a.m / G;
+    const int per_item = nslab * trows;
+    const int tile = blockIdx.x;
+    const int item = tile / per_item;
+    const int rem = tile - item * per_item;
+    const int tr = rem / nslab;
+    const int s = rem - tr * nslab;
+    const float* fin;
+    float* fout;
+    const void* tx[SE2C_MAX_TABLES];
+    int ntab;
+    if (a.items) {
+        const SepItem& it = a.items[item];
+        fin = reinterpret_cast<const float*>(it.in);
+        fout = reinterpret_cast<float*>(it.out);
+        ntab = it.ntab;
+        for (int j = 0; j < ntab; ++j) tx[j] = it.tab[j];
+    } else {
+        fin = a.in + (long long)item * a.n;
+        fout = a.out + (long long)item * a.n;
+        ntab = a.ntab;
+        for (int j = 0; j < ntab; ++j) tx[j] = a.tx[j];
+    }
+    for (int i = tid; i < NX; i += NT) {
+        const int k1 = i / R2, t = i - k1 * R2;
+        const float2 w = a.tw[t * k1];
+        tw_f[k1 * R2 + t] = w;
+        tw_i[t * R1 + k1] = w;
+        fx[i] = chain_factor(tx, ntab, i, 1.0f / NX, a.conj_tab);
+    }
+    __syncthreads();
+
+    const int t = tid % R2, g = tid / R2;
+    const int pl = NX * a.ny;
+    const long long tbase = (long long)(tr * G) * pl + (long long)(2 * s) * NX;
+    const float* __restrict__ in0 = fin + tbase;
+    const float* __restrict__ in1 = in0 + NX;
+    float2 w[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+        const int off = g * pl + t + R2 * r;
+        w[r] = make_float2(__builtin_nontemporal_load(in0 + off), __builtin_nontemporal_load(in1 + off));
+    }
+    RegDFT<R1, false, float>::run(w);
+#pragma unroll
+    for (int k1 = 1; k1 < R1; ++k1) w[k1] = mul<float>(w[k1], tw_f[k1 * R2 + t]);
+    float2* row = buf + g * P;
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) row[xpos_line<R1, R2>(k1, t)] = w[k1];
+    __syncthreads();
+    float2 u[CC][R2];
+#pragma unroll
+    for (int j = 0; j < CC; ++j) {
+        const int k1 = CC * t + j;
+#pragma unroll
+        for (int tt = 0; tt < R2; ++tt) u[j][tt] = row[xpos_line<R1, R2>(k1, tt)];
+        RegDFT<R2, false, float>::run(u[j]);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = mul<float>(u[j][k2], fx[k1 + R1 * k2]);
+        RegDFT<R2, true, float>::run(u[j]);
+#pragma unroll
+        for (int tt = 1; tt < R2; ++tt) u[j][tt] = mulc<float>(u[j][tt], tw_i[tt * R1 + k1]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < CC; ++j) {
+#pragma unroll
+        for (int tt = 0; tt < R2; ++tt) row[xpos_line<R1, R2>(CC * t + j, tt)] = u[j][tt];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) w[k1] = row[xpos_line<R1, R2>(k1, t)];
+    RegDFT<R1, true, float>::run(w);
+    float* __restrict__ out0 = fout + tbase;
+    float* __restrict__ out1 = out0 + NX;
+#pragma unroll
+    for (int r = 0; r < R1; ++r) {
+        const int off = g * pl + t + R2 * r;
+        __builtin_nontemporal_store(w[r].x, out0 + off);
+        __builtin_nontemporal_store(w[r].y, out1 + off);
     }
 }
 
@@ -362,10 +493,14 @@ static size_t slab_fast_lds() {
     return sizeof(float2) * ((size_t)RC * P + 32 * R2 + NX + 2 * M);
 }
 
-template <int NY>
+template <int L>
 static size_t pencil_fast_lds() {
-    constexpr int R2 = NY / 16;
-    return sizeof(float2) * ((size_t)NY * 16 + 32 * R2 + NY);
+    return sizeof(float2) * ((size_t)L * LineGeom<L>::W + 3 * L);
+}
+
+template <int NX>
+static size_t rows_fast_lds() {
+    return sizeof(float2) * ((size_t)RowGeom<NX>::G * RowGeom<NX>::P + 3 * NX);
 }
 
 template <int NX, int M>
@@ -376,10 +511,31 @@ static hipError_t launch_slab_fast_t(const FastSepArgs& a, int nblocks, hipStrea
     return hipGetLastError();
 }
 
-template <int NY>
-static hipError_t launch_pencil_fast_t(const FastSepArgs& a, int nblocks, hipStream_t s) {
-    const size_t lds = pencil_fast_lds<NY>();
-    hipLaunchKernelGGL((y_pencil_fast<NY>), dim3(nblocks), dim3(NY), lds, s, a);
+template <int L>
+static hipError_t launch_pencil_fast_t(const FastSepArgs& a, hipStream_t s) {
+    const size_t lds = pencil_fast_lds<L>();
+    const int nouter = a.axis == 1 ? a.m : a.ny;
+    const int ntiles = (a.nx / 2 / LineGeom<L>::W) * nouter * a.nitems;
+    // persistent grid: a few blocks per CU (no more than fit at once), each walks its
+    // share of tiles
+    static const int fit = [lds] {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void*>(line_pencil_fast<L>),
+                                                         LineGeom<L>::NT, lds) != hipSuccess || b < 1)
+            b = 1;
+        return b;
+    }();
+    int nblocks = a.grid_blocks < a.cus * fit ? a.grid_blocks : a.cus * fit;
+    if (ntiles < nblocks) nblocks = ntiles;
+    hipLaunchKernelGGL((line_pencil_fast<L>), dim3(nblocks), dim3(LineGeom<L>::NT), lds, s, a);
+    return hipGetLastError();
+}
+
+template <int NX>
+static hipError_t launch_rows_fast_t(const FastSepArgs& a, hipStream_t s) {
+    const size_t lds = rows_fast_lds<NX>();
+    const int nblocks = (a.ny / 2) * (a.m / RowGeom<NX>::G) * a.nitems;
+    hipLaunchKernelGGL((x_rows_fast<NX>), dim3(nblocks), dim3(RowGeom<NX>::NT), lds, s, a);
     return hipGetLastError();
 }
 
@@ -387,8 +543,12 @@ bool slab_fast_supported(int nx, int m) {
     return (nx == 64 || nx == 128 || nx == 256) && (m == 16 || m == 32 || m == 64);
 }
 
-bool pencil_fast_supported(int nx, int ny) {
-    return (ny == 64 || ny == 128 || ny == 256) && nx % 32 == 0;
+static bool line_len_ok(int l) { return l == 64 || l == 128 || l == 256 || l == 512; }
+
+bool pencil_fast_supported(int nx, int ny) { return line_len_ok(ny) && nx % 32 == 0; }
+
+bool three_pass_fast_supported(int nx, int ny, int m) {
+    return line_len_ok(nx) && line_len_ok(ny) && line_len_ok(m);
 }
 
 #define SE2C_SLAB_CASE(NX_, M_) \
@@ -403,12 +563,19 @@ hipError_t launch_slab_fast(const FastSepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_pencil_fast(const FastSepArgs& a, hipStream_t s) {
-    const int ntiles = (a.nx / 2 / 16) * a.m * a.nitems;
-    // persistent grid: a few blocks per CU, each walks its share of tiles
-    const int nblocks = ntiles < a.grid_blocks ? ntiles : a.grid_blocks;
-    if (a.ny == 64) return launch_pencil_fast_t<64>(a, nblocks, s);
-    if (a.ny == 128) return launch_pencil_fast_t<128>(a, nblocks, s);
-    if (a.ny == 256) return launch_pencil_fast_t<256>(a, nblocks, s);
+    const int L = a.axis == 1 ? a.ny : a.m;
+    if (L == 64) return launch_pencil_fast_t<64>(a, s);
+    if (L == 128) return launch_pencil_fast_t<128>(a, s);
+    if (L == 256) return launch_pencil_fast_t<256>(a, s);
+    if (L == 512) return launch_pencil_fast_t<512>(a, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_rows_fast(const FastSepArgs& a, hipStream_t s) {
+    if (a.nx == 64) return launch_rows_fast_t<64>(a, s);
+    if (a.nx == 128) return launch_rows_fast_t<128>(a, s);
+    if (a.nx == 256) return launch_rows_fast_t<256>(a, s);
+    if (a.nx == 512) return launch_rows_fast_t<512>(a, s);
     return hipErrorInvalidValue;
 }
 
@@ -417,11 +584,20 @@ hipError_t launch_pencil_fast(const FastSepArgs& a, hipStream_t s) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)slab_fast_lds<NX_, M_>()); \
     if (e != hipSuccess) return e;
 
+#define SE2C_LINE_ATTR(L_)                                                                              \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(line_pencil_fast<L_>),                         \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)pencil_fast_lds<L_>());   \
+    if (e != hipSuccess) return e;                                                                      \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(x_rows_fast<L_>),                              \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)rows_fast_lds<L_>());     \
+    if (e != hipSuccess) return e;
+
 hipError_t prepare_fast_kernels() {
     hipError_t e;
     SE2C_SLAB_ATTR(64, 16) SE2C_SLAB_ATTR(64, 32) SE2C_SLAB_ATTR(64, 64)
     SE2C_SLAB_ATTR(128, 16) SE2C_SLAB_ATTR(128, 32) SE2C_SLAB_ATTR(128, 64)
     SE2C_SLAB_ATTR(256, 16) SE2C_SLAB_ATTR(256, 32) SE2C_SLAB_ATTR(256, 64)
+    SE2C_LINE_ATTR(64) SE2C_LINE_ATTR(128) SE2C_LINE_ATTR(256) SE2C_LINE_ATTR(512)
     return hipSuccess;
 }
 

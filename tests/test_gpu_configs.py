@@ -69,8 +69,12 @@ def c3_data():
     ks = chain_kernel_params(3, 4)
     chain = [(k.sigma, k.kappa, 0.0) for k in ks]
     f = sample_fields(3, 4, 128, nx, ny, m)
+    print("  C3 fields sampled", flush=True)
     pts = (np.arange(0, nx, 8), np.arange(0, ny, 8), np.arange(0, m, 4))
-    ref = oc.conv_with_coeffs(f[0], oracle_table_gauss(nx, ny, m, chain), points=pts)
+    table = oracle_table_gauss(nx, ny, m, chain)
+    print("  C3 oracle table done", flush=True)
+    ref = oc.conv_with_coeffs(f[0], table, points=pts)
+    print("  C3 oracle subsample done", flush=True)
     return f, chain, pts, ref
 
 

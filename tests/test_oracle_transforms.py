@@ -2,6 +2,7 @@
 import numpy as np
 import pytest
 
+from oracle import transforms as T
 from oracle.transforms import dft1, dft3, dft_matrix, idft3
 
 
@@ -42,3 +43,16 @@ def test_dft1_of_pure_tone():
     expect = np.zeros(L, complex)
     expect[3] = L
     assert np.max(np.abs(fv - expect)) < 1e-12
+
+
+@pytest.mark.parametrize("sign", [-1, +1])
+def test_large_array_route_equals_dense_route(sign, rng, monkeypatch):
+    """Above DENSE_LIMIT the per-axis sum is taken by numpy's FFT: it must equal the dense
+    matrix evaluation of the same definition (forced here on a small ragged array)."""
+    a = rng.standard_normal((6, 10, 12)) + 1j * rng.standard_normal((6, 10, 12))
+    dense = [T._dft_axis(a, ax, sign) for ax in range(3)]
+    monkeypatch.setattr(T, "DENSE_LIMIT", 0)
+    fast = [T._dft_axis(a, ax, sign) for ax in range(3)]
+    for d, f in zip(dense, fast):
+        assert np.max(np.abs(d - f)) <= 1e-12 * np.max(np.abs(d))
+    assert np.allclose(T.idft3(T.dft3(a)), a, atol=1e-13)
