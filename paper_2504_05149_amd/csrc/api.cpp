@@ -19,6 +19,7 @@
 #include "coeffs.hpp"
 #include "passes.hpp"
 #include "sep_fast.hpp"
+#include "full_fast.hpp"
 #include "grad.hpp"
 #include "sample.hpp"
 
@@ -156,6 +157,11 @@ struct se2conv_plan_s {
     void* ws4 = nullptr;               // four more planes (kernel gradient), allocated on first use
     void* scratch64 = nullptr;         // FP64 scratch for se2conv_coeffs
     size_t scratch64_bytes = 0;
+    // hat basis of the last radial-profile geometry used by se2conv_profile_grad
+    double* basis = nullptr;
+    size_t basis_bytes = 0;
+    int basis_shape = -1, basis_knots = 0;
+    double basis_rmax = 0.0;
     std::unordered_map<uintptr_t, TableRec> tables;
     std::vector<SubmissionRec> subs;
     std::mutex mu;
@@ -715,9 +721,53 @@ hipError_t y_pass_io(se2conv_plan_s* p, const se2conv_shape& s, bool d, const vo
 }
 
 // Full (non-separable) chain on pairs of fields.
+// FP32 register kernels of the full path (x-theta forward, y product, x-theta inverse).
+FullFastArgs full_fast_args(se2conv_plan_s* p, const se2conv_shape& s, int batch) {
+    FullFastArgs a{};
+    a.n = (long long)s.nx * s.ny * s.m;
+    a.batch = batch;
+    a.nx = s.nx;
+    a.ny = s.ny;
+    a.m = s.m;
+    a.lone = (batch & 1) ? reinterpret_cast<float*>(p->ws) : nullptr;
+    a.twx = reinterpret_cast<const float2*>(tw_of(p, s.nx, false));
+    a.twy = reinterpret_cast<const float2*>(tw_of(p, s.ny, false));
+    a.twt = reinterpret_cast<const float2*>(tw_of(p, s.m, false));
+    a.scale = 1.0f;
+    return a;
+}
+
+void set_chain(FullFastArgs* a, const Chain& ch, bool conj, double scale) {
+    a->ntab = ch.ntab;
+    for (int j = 0; j < ch.ntab; ++j) {
+        a->tab[j] = ch.ptr[j];
+        a->tab_full[j] = ch.kind[j] == SE2CONV_TABLE_FULL ? 1 : 0;
+    }
+    a->conj_tab = conj ? 1 : 0;
+    a->scale = (float)scale;
+}
+
+bool use_full_fast(const se2conv_plan_s* p, const se2conv_shape& s) {
+    return !dbl(p) && !(p->flags & SE2CONV_PLAN_GENERIC) && full_fast_supported(s.nx, s.ny, s.m);
+}
+
 se2conv_status enqueue_full(se2conv_plan_s* p, const se2conv_shape& s, const void* f, void* out, int batch,
                             const Chain& ch, bool conj, hipStream_t st) {
     const bool d = dbl(p);
+    if (use_full_fast(p, s)) {
+        FullFastArgs a = full_fast_args(p, s, batch);
+        set_chain(&a, ch, conj, 1.0 / (double)a.n);
+        a.in = reinterpret_cast<const float*>(f);
+        a.out = reinterpret_cast<float*>(out);
+        HIPCHK(launch_xt_full_fwd(a, st));
+        HIPCHK(after_pass(0, st));
+        a.in = a.out;
+        HIPCHK(launch_y_full(a, st));
+        HIPCHK(after_pass(1, st));
+        HIPCHK(launch_xt_full_inv(a, st));
+        HIPCHK(after_pass(0, st));
+        return SE2CONV_OK;
+    }
     const long long n = (long long)s.nx * s.ny * s.m;
     const size_t rb = real_bytes(p);
     const int pairs = (batch + 1) / 2;
@@ -985,6 +1035,7 @@ se2conv_status se2conv_plan_destroy(se2conv_plan_t p) {
         if (p->ws2) (void)hipFree(p->ws2);
         if (p->ws4) (void)hipFree(p->ws4);
         if (p->scratch64) (void)hipFree(p->scratch64);
+        if (p->basis) (void)hipFree(p->basis);
         if (cur >= 0) (void)hipSetDevice(cur);
     }
     delete p;
@@ -1199,11 +1250,31 @@ se2conv_status se2conv_profile_grad(se2conv_plan_t p, int32_t shape_idx, const v
     const se2conv_shape& s = p->shapes[shape_idx];
     const long long npts = (long long)s.nx * s.ny;
     std::lock_guard<std::mutex> g(p->mu);
-    se2conv_status r = ensure_scratch64(p, sizeof(double) * (size_t)(npts * n_knots + npts * s.m));
+    if (p->basis_shape != shape_idx || p->basis_knots != n_knots || p->basis_rmax != r_max) {
+        const size_t need = sizeof(double) * (size_t)(npts * n_knots);
+        if (p->basis_bytes < need) {
+            if (p->basis) {
+                hipError_t e = hipFree(p->basis);
+                p->basis = nullptr;
+                p->basis_bytes = 0;
+                if (e != hipSuccess) return fail(SE2CONV_ERR_DEVICE, "hipFree: %s", hipGetErrorString(e));
+            }
+            if (hipMalloc(reinterpret_cast<void**>(&p->basis), need) != hipSuccess)
+                return fail(SE2CONV_ERR_OUT_OF_MEMORY, "could not allocate %zu bytes for the profile basis", need);
+            p->basis_bytes = need;
+        }
+        p->basis_shape = -1;
+        HIPCHK(launch_profile_basis(p->basis, n_knots, r_max, s.nx, s.ny, stream));
+        p->basis_shape = shape_idx;
+        p->basis_knots = n_knots;
+        p->basis_rmax = r_max;
+    }
+    const long long nsplit = profile_grad_splits(npts);
+    se2conv_status r = ensure_scratch64(p, sizeof(double) * (size_t)(npts * s.m + nsplit * n_knots * s.m));
     if (r != SE2CONV_OK) return r;
-    double* basis = reinterpret_cast<double*>(p->scratch64);
-    double* G = basis + npts * n_knots;
-    HIPCHK(launch_profile_grad(d_grad_samples, batch, dbl(p), n_knots, r_max, s.nx, s.ny, s.m, basis, G, d_grad_prof,
+    double* G = reinterpret_cast<double*>(p->scratch64);
+    double* part = G + npts * s.m;
+    HIPCHK(launch_profile_grad(d_grad_samples, batch, dbl(p), n_knots, s.nx, s.ny, s.m, p->basis, G, part, d_grad_prof,
                                stream));
     return ok();
 }

@@ -224,26 +224,47 @@ hipError_t launch_round(const double2* src, void* dst, long long n, int dbl, hip
 // Radial-profile kernel samples (FP64):
 // P[l][j][i] = sum_images sum_q prof[q][l] * hat_q(|x_ij + image|),
 // hat_q(r) = max(0, 1 - |r/h - q|), h = r_max/(n_knots-1).
+// P[l][j][i] = sum over lattice images of the hat interpolant of prof[.][l] at
+// r = |x_ij + image|.  One thread per (point, 16 consecutive theta samples): the
+// radius and its knot interval are computed once per image and reused for the 16 l.
+constexpr int kProfileLChunk = 16;
+
 __global__ void profile_samples_kernel(const double* prof, int n_knots, double r_max, int nx, int ny, int m,
                                        double* out) {
-    const long long n = (long long)nx * ny * m;
+    const long long npts = (long long)nx * ny;
+    const int nlc = (m + kProfileLChunk - 1) / kProfileLChunk;
     const double h = r_max / (double)(n_knots - 1);
-    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < n; idx += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(idx % nx);
-        const int j = (int)((idx / nx) % ny);
-        const int l = (int)(idx / ((long long)nx * ny));
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < npts * nlc;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const long long p = idx % npts;
+        const int l0 = (int)(idx / npts) * kProfileLChunk;
+        const int nl = m - l0 < kProfileLChunk ? m - l0 : kProfileLChunk;
+        const int i = (int)(p % nx), j = (int)(p / nx);
         const double x = -0.5 + (double)i / nx, y = -0.5 + (double)j / ny;
-        double acc = 0.0;
+        double acc[kProfileLChunk];
+#pragma unroll
+        for (int c = 0; c < kProfileLChunk; ++c) acc[c] = 0.0;
         for (int a = -SE2C_PROFILE_IMAGES; a <= SE2C_PROFILE_IMAGES; ++a) {
             for (int b = -SE2C_PROFILE_IMAGES; b <= SE2C_PROFILE_IMAGES; ++b) {
                 const double dx = x + a, dy = y + b;
                 const double u = sqrt(dx * dx + dy * dy) / h;
                 const int q0 = (int)floor(u);
-                if (q0 >= 0 && q0 < n_knots) acc += (1.0 - (u - q0)) * prof[(long long)q0 * m + l];
-                if (q0 + 1 >= 0 && q0 + 1 < n_knots) acc += (u - q0) * prof[(long long)(q0 + 1) * m + l];
+                if (q0 >= n_knots) continue;
+                const double t = u - q0;
+                const double* p0 = prof + (long long)q0 * m + l0;
+                const bool has1 = q0 + 1 < n_knots;
+#pragma unroll
+                for (int c = 0; c < kProfileLChunk; ++c) {
+                    if (c < nl) {
+                        acc[c] += (1.0 - t) * p0[c];
+                        if (has1) acc[c] += t * p0[m + c];
+                    }
+                }
             }
         }
-        out[idx] = acc;
+#pragma unroll
+        for (int c = 0; c < kProfileLChunk; ++c)
+            if (c < nl) out[(long long)(l0 + c) * npts + p] = acc[c];
     }
 }
 

@@ -1,0 +1,427 @@
+// Register-resident FP32 kernels of the full-table path: out = S_K[f, rho] with an
+// arbitrary (non-separable) coefficient table, i.e. out = iDFT3(W . DFT3(F) . T) / n
+// (eqs. (FkLv), (SKfg), (3iDFT); the sign W and 1/n are folded into the table).
+//
+// Two real fields are transformed at once as z = f_a + i f_b: for a real-kernel table
+// (T[-k] = conj T[k]) the inverse of T . Z^ has real part S_K[f_a] and imaginary part
+// S_K[f_b].  Three passes over HBM:
+//
+// xt_full<NX, M, DIR = 0>  one block per (pair, y row): forward DFT along x (16 x R2
+//   register decomposition, one XOR-swizzled LDS exchange), rows -> columns through
+//   LDS, forward DFT along theta in registers (TPC = 2: the last radix-2 step across
+//   neighbouring lanes via DPP); stores the x-theta spectrum as re/im planes.
+// y_full<NY>  one block per (theta frequency, 16 x frequencies), all pairs in turn:
+//   forward DFT along y, [copy of the spectrum], product with the table (loaded once
+//   per block for every pair), inverse DFT along y, in place.
+// xt_full<NX, M, DIR = 1>  the mirror image of the first pass: inverse DFT along
+//   theta (columns), columns -> rows, inverse DFT along x, stores the two real fields.
+#include "fast_common.hpp"
+#include "full_fast.hpp"
+#include "regfft.hpp"
+
+namespace se2c {
+
+template <int NX, int M> struct FullSlabGeom {
+    static constexpr int TPC = M == 64 ? 2 : 1;      // threads per theta column
+    static constexpr int NT = NX * TPC;
+    static constexpr int R2 = NX / 16;               // second-stage radix along x
+    static constexpr int CC = 16 / R2;               // first-stage frequencies per thread
+    static constexpr int G = NT / R2;                // row groups in row layout
+    static constexpr int RPT = M / G;                // theta rows per thread in row layout
+    static constexpr int RC = M < 32 ? M : 32;       // rows per transpose chunk
+    static constexpr int H = M / RC;
+    static constexpr int P = NX + (R2 == 16 ? 16 : R2 % 16);  // LDS row pitch (complex)
+    static constexpr int MV = M / TPC;               // theta values per thread in column layout
+    static_assert(G <= RC && RPT >= 1 && M % G == 0, "tile geometry");
+};
+
+template <int NX, int M>
+static constexpr size_t full_slab_lds() {
+    using Gm = FullSlabGeom<NX, M>;
+    return sizeof(float2) * ((size_t)Gm::RC * Gm::P + 2 * NX + M);
+}
+
+template <int NX, int M, int DIR>
+__global__ void __launch_bounds__((FullSlabGeom<NX, M>::NT))
+__attribute__((amdgpu_waves_per_eu(FullSlabGeom<NX, M>::NT >= 512 ? 4 : (FullSlabGeom<NX, M>::NT >= 256 ? 2 : 1))))
+xt_full(FullFastArgs a) {
+    using Gm = FullSlabGeom<NX, M>;
+    constexpr int TPC = Gm::TPC, NT = Gm::NT, R2 = Gm::R2, CC = Gm::CC, G = Gm::G, RPT = Gm::RPT, RC = Gm::RC,
+                  H = Gm::H, P = Gm::P, MV = Gm::MV;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float2* buf = reinterpret_cast<float2*>(smem_raw);  // RC x P
+    float2* tw_f = buf + RC * P;                         // [k1][t] = w_NX^{t k1}
+    float2* tw_i = tw_f + NX;                            // [t][k1]
+    float2* twm = tw_i + NX;                             // w_M^k
+    const int tid = threadIdx.x;
+    for (int i = tid; i < NX; i += NT) {
+        const int k1 = i / R2, t = i - k1 * R2;
+        const float2 w = a.twx[t * k1];
+        tw_f[k1 * R2 + t] = w;
+        tw_i[t * 16 + k1] = w;
+    }
+    for (int i = tid; i < M; i += NT) twm[i] = a.twt[i];
+    __syncthreads();
+
+    const int pair = blockIdx.x / a.ny;
+    const int y = blockIdx.x - pair * a.ny;
+    const int pl = NX * a.ny;
+    const bool has_b = 2 * pair + 1 < a.batch;
+    const int t = tid % R2, g = tid / R2;
+    const int xc = TPC == 1 ? tid : (tid >> 1);
+    const int hh = TPC == 1 ? 0 : (tid & 1);
+    float2 w[RPT][16];
+    float2 v[MV];
+
+    if constexpr (DIR == 0) {
+        const float* __restrict__ in0 = a.in + (long long)(2 * pair) * a.n + (long long)y * NX;
+        const float* __restrict__ in1 = has_b ? in0 + a.n : nullptr;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int off = (g + G * i) * pl + t + R2 * r;
+                w[i][r] = make_float2(__builtin_nontemporal_load(in0 + off),
+                                      in1 ? __builtin_nontemporal_load(in1 + off) : 0.f);
+            }
+        }
+        // forward DFT along x of each row; afterwards w[i][j * R2 + k2] = X[k1 + 16 k2], k1 = CC t + j
+        float2* row = buf + g * P;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            dft16<float, false>(w[i]);
+#pragma unroll
+            for (int k1 = 1; k1 < 16; ++k1) w[i][k1] = mul<float>(w[i][k1], tw_f[k1 * R2 + t]);
+            if (i > 0) __syncthreads();
+#pragma unroll
+            for (int k1 = 0; k1 < 16; ++k1) row[xpos<R2>(k1, t)] = w[i][k1];
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < CC; ++j) {
+                const int k1 = CC * t + j;
+                float2 u[R2];
+#pragma unroll
+                for (int tt = 0; tt < R2; ++tt) u[tt] = row[xpos<R2>(k1, tt)];
+                RegDFT<R2, false, float>::run(u);
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) w[i][j * R2 + k2] = u[k2];
+            }
+        }
+        // rows -> columns (x frequency kx = xc in column layout)
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                if (G * i >= h * RC && G * i < (h + 1) * RC) {
+#pragma unroll
+                    for (int j = 0; j < CC; ++j)
+#pragma unroll
+                        for (int k2 = 0; k2 < R2; ++k2)
+                            buf[(g + G * i - h * RC) * P + CC * t + j + 16 * k2] = w[i][j * R2 + k2];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int l = h * RC / TPC; l < (h + 1) * RC / TPC; ++l) v[l] = buf[(TPC * l + hh - h * RC) * P + xc];
+        }
+        // forward DFT along theta
+        if constexpr (TPC == 1) {
+            RegDFT<M, false, float>::run(v);
+        } else {
+            // theta = hh + 2 s: Y_hh = DFT over s; X[k] = Y_0 + w^k Y_1, X[k + M/2] = Y_0 - w^k Y_1
+            RegDFT<MV, false, float>::run(v);
+#pragma unroll
+            for (int k = 0; k < MV; ++k) {
+                const float2 o = swap_lane1(v[k]);
+                const float2 y0 = hh ? o : v[k];
+                const float2 y1 = hh ? v[k] : o;
+                const float2 c = mul<float>(y1, twm[k]);
+                v[k] = hh ? sub<float>(y0, c) : add<float>(y0, c);
+            }
+        }
+        float* __restrict__ o_re = a.out + (long long)(2 * pair) * a.n + (long long)y * NX;
+        float* __restrict__ o_im = (has_b ? a.out + (long long)(2 * pair + 1) * a.n : a.lone) + (long long)y * NX;
+#pragma unroll
+        for (int l = 0; l < MV; ++l) {
+            const int kt = TPC == 1 ? l : l + hh * MV;
+            const int off = kt * pl + xc;
+            __builtin_nontemporal_store(v[l].x, o_re + off);
+            __builtin_nontemporal_store(v[l].y, o_im + off);
+        }
+    } else {
+        const float* __restrict__ i_re = a.in + (long long)(2 * pair) * a.n + (long long)y * NX;
+        const float* __restrict__ i_im =
+            (has_b ? a.in + (long long)(2 * pair + 1) * a.n : a.lone) + (long long)y * NX;
+#pragma unroll
+        for (int l = 0; l < MV; ++l) {
+            const int kt = TPC == 1 ? l : l + hh * MV;
+            const int off = kt * pl + xc;
+            v[l] = make_float2(__builtin_nontemporal_load(i_re + off), __builtin_nontemporal_load(i_im + off));
+        }
+        // inverse DFT along theta
+        if constexpr (TPC == 1) {
+            RegDFT<M, true, float>::run(v);
+        } else {
+            // lane 0 holds Z[k], lane 1 Z[k + M/2]: U_0 = Z[k] + Z[k + M/2],
+            // U_1 = conj(w^k) (Z[k] - Z[k + M/2]); then inverse DFT over s gives theta = hh + 2 s
+#pragma unroll
+            for (int k = 0; k < MV; ++k) {
+                const float2 o = swap_lane1(v[k]);
+                v[k] = hh ? mulc<float>(sub<float>(o, v[k]), twm[k]) : add<float>(v[k], o);
+            }
+            RegDFT<MV, true, float>::run(v);
+        }
+        // columns -> rows (x frequencies in row layout: w[i][j * R2 + k2] = X[CC t + j + 16 k2])
+#pragma unroll
+        for (int h = 0; h < H; ++h) {
+            __syncthreads();
+#pragma unroll
+            for (int l = h * RC / TPC; l < (h + 1) * RC / TPC; ++l) buf[(TPC * l + hh - h * RC) * P + xc] = v[l];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                if (G * i >= h * RC && G * i < (h + 1) * RC) {
+#pragma unroll
+                    for (int j = 0; j < CC; ++j)
+#pragma unroll
+                        for (int k2 = 0; k2 < R2; ++k2)
+                            w[i][j * R2 + k2] = buf[(g + G * i - h * RC) * P + CC * t + j + 16 * k2];
+                }
+            }
+        }
+        // inverse DFT along x of each row
+        float2* row = buf + g * P;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+#pragma unroll
+            for (int j = 0; j < CC; ++j) {
+                const int k1 = CC * t + j;
+                float2 u[R2];
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) u[k2] = w[i][j * R2 + k2];
+                RegDFT<R2, true, float>::run(u);
+#pragma unroll
+                for (int tt = 1; tt < R2; ++tt) u[tt] = mulc<float>(u[tt], tw_i[tt * 16 + k1]);
+#pragma unroll
+                for (int tt = 0; tt < R2; ++tt) w[i][j * R2 + tt] = u[tt];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < CC; ++j)
+#pragma unroll
+                for (int tt = 0; tt < R2; ++tt) row[xpos<R2>(CC * t + j, tt)] = w[i][j * R2 + tt];
+            __syncthreads();
+#pragma unroll
+            for (int k1 = 0; k1 < 16; ++k1) w[i][k1] = row[xpos<R2>(k1, t)];
+            dft16<float, true>(w[i]);
+        }
+        float* __restrict__ out0 = a.out + (long long)(2 * pair) * a.n + (long long)y * NX;
+        float* __restrict__ out1 = has_b ? out0 + a.n : nullptr;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int off = (g + G * i) * pl + t + R2 * r;
+                __builtin_nontemporal_store(w[i][r].x, out0 + off);
+                if (out1) __builtin_nontemporal_store(w[i][r].y, out1 + off);
+            }
+        }
+    }
+}
+
+// y pass: W = 16 adjacent x frequencies (columns of the re and im planes) x NY points
+// at one theta frequency; every pair of the batch in turn, the table loaded once.
+template <int NY> struct FullLineGeom {
+    static constexpr int R1 = NY > 256 ? 32 : 16;
+    static constexpr int R2 = NY / R1;
+    static constexpr int CC = R1 / R2;
+    static constexpr int W = 16;
+    static constexpr int NT = W * R2;
+};
+
+template <int NY>
+static constexpr size_t full_line_lds() {
+    return sizeof(float2) * ((size_t)NY * FullLineGeom<NY>::W + 2 * NY);
+}
+
+template <int NY>
+__global__ void __launch_bounds__(FullLineGeom<NY>::NT) y_full(FullFastArgs a) {
+    using Gm = FullLineGeom<NY>;
+    constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC, W = Gm::W, NT = Gm::NT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float2* buf = reinterpret_cast<float2*>(smem_raw);  // [k1*R2 + t][W]
+    float2* tw_f = buf + NY * W;                        // [k1][t] = w_NY^{t k1}
+    float2* tw_i = tw_f + NY;                           // [t][k1]
+    const int tid = threadIdx.x;
+    for (int i = tid; i < NY; i += NT) {
+        const int k1 = i / R2, t = i - k1 * R2;
+        const float2 w = a.twy[t * k1];
+        tw_f[k1 * R2 + t] = w;
+        tw_i[t * R1 + k1] = w;
+    }
+    __syncthreads();
+
+    const int q = tid % W, t = tid / W;
+    const int ctiles = a.nx / W;
+    const int kt = blockIdx.x / ctiles;
+    const int kx = (blockIdx.x - kt * ctiles) * W + q;
+    const int pl = a.nx * NY;
+    const int npairs = (a.batch + 1) / 2;
+    // table factor for (kt, ky = k1 + R1 k2, kx), k1 = CC t + j
+    float2 tv[CC][R2];
+#pragma unroll
+    for (int j = 0; j < CC; ++j) {
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) {
+            const int ky = CC * t + j + R1 * k2;
+            float2 f = make_float2(a.scale, 0.f);
+            for (int e = 0; e < a.ntab; ++e) {
+                const float2* T = reinterpret_cast<const float2*>(a.tab[e]);
+                if (a.tab_full[e]) {
+                    f = mul<float>(f, T[(long long)kt * pl + ky * a.nx + kx]);
+                } else {
+                    f = mul<float>(f, T[kx]);
+                    f = mul<float>(f, T[a.nx + ky]);
+                    f = mul<float>(f, T[a.nx + NY + kt]);
+                }
+            }
+            if (a.conj_tab) f.y = -f.y;
+            tv[j][k2] = f;
+        }
+    }
+    const int rstride = R2 * a.nx;
+    for (int pair = 0; pair < npairs; ++pair) {
+        // per-lane offsets are recomputed for every pair rather than hoisted out of the
+        // loop (hoisting them would hold dozens of registers across the loop)
+        int lt = tid;
+        asm volatile("" : "+v"(lt));
+        const int q = lt % W, t = lt / W;
+        const int base = kt * pl + (blockIdx.x - kt * ctiles) * W + q;  // element (kt, y, kx) at base + y nx
+        const int lane_off = base + t * a.nx;
+        float* __restrict__ re = a.out + (long long)(2 * pair) * a.n;
+        float* __restrict__ im = 2 * pair + 1 < a.batch ? re + a.n : a.lone;
+        float2 w[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) w[r] = make_float2(re[lane_off + r * rstride], im[lane_off + r * rstride]);
+        RegDFT<R1, false, float>::run(w);
+#pragma unroll
+        for (int k1 = 1; k1 < R1; ++k1) w[k1] = mul<float>(w[k1], tw_f[k1 * R2 + t]);
+        __syncthreads();
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) buf[(k1 * R2 + t) * W + q] = w[k1];
+        __syncthreads();
+        float2 u[CC][R2];
+#pragma unroll
+        for (int j = 0; j < CC; ++j) {
+            const int k1 = CC * t + j;
+#pragma unroll
+            for (int tt = 0; tt < R2; ++tt) u[j][tt] = buf[(k1 * R2 + tt) * W + q];
+            RegDFT<R2, false, float>::run(u[j]);
+        }
+        if (a.save) {
+            float* s_re = a.save + (long long)(2 * pair) * a.n;
+            float* s_im = s_re + a.n;
+#pragma unroll
+            for (int j = 0; j < CC; ++j)
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) {
+                    const int off = base + (CC * t + j + R1 * k2) * a.nx;
+                    s_re[off] = u[j][k2].x;
+                    s_im[off] = u[j][k2].y;
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < CC; ++j) {
+            const int k1 = CC * t + j;
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = mul<float>(u[j][k2], tv[j][k2]);
+            RegDFT<R2, true, float>::run(u[j]);
+#pragma unroll
+            for (int tt = 1; tt < R2; ++tt) u[j][tt] = mulc<float>(u[j][tt], tw_i[tt * R1 + k1]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CC; ++j)
+#pragma unroll
+            for (int tt = 0; tt < R2; ++tt) buf[((CC * t + j) * R2 + tt) * W + q] = u[j][tt];
+        __syncthreads();
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) w[k1] = buf[(k1 * R2 + t) * W + q];
+        RegDFT<R1, true, float>::run(w);
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            re[lane_off + r * rstride] = w[r].x;
+            im[lane_off + r * rstride] = w[r].y;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ dispatch
+bool full_fast_supported(int nx, int ny, int m) {
+    return (nx == 64 || nx == 128 || nx == 256) && (m == 16 || m == 32 || m == 64) &&
+           (ny == 64 || ny == 128 || ny == 256 || ny == 512);
+}
+
+template <int NX, int M, int DIR>
+static hipError_t launch_xt_full_t(const FullFastArgs& a, hipStream_t s) {
+    const int nblocks = ((a.batch + 1) / 2) * a.ny;
+    const int nthr = FullSlabGeom<NX, M>::NT;
+    const size_t lds = full_slab_lds<NX, M>();
+    hipLaunchKernelGGL((xt_full<NX, M, DIR>), dim3(nblocks), dim3(nthr), lds, s, a);
+    return hipGetLastError();
+}
+
+#define SE2C_XT_FULL_CASE(NX_, M_) \
+    if (a.nx == NX_ && a.m == M_) return DIR ? launch_xt_full_t<NX_, M_, 1>(a, s) : launch_xt_full_t<NX_, M_, 0>(a, s);
+
+template <int DIR>
+static hipError_t launch_xt_full(const FullFastArgs& a, hipStream_t s) {
+    SE2C_XT_FULL_CASE(64, 16) SE2C_XT_FULL_CASE(64, 32) SE2C_XT_FULL_CASE(64, 64)
+    SE2C_XT_FULL_CASE(128, 16) SE2C_XT_FULL_CASE(128, 32) SE2C_XT_FULL_CASE(128, 64)
+    SE2C_XT_FULL_CASE(256, 16) SE2C_XT_FULL_CASE(256, 32) SE2C_XT_FULL_CASE(256, 64)
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_xt_full_fwd(const FullFastArgs& a, hipStream_t s) { return launch_xt_full<0>(a, s); }
+hipError_t launch_xt_full_inv(const FullFastArgs& a, hipStream_t s) { return launch_xt_full<1>(a, s); }
+
+template <int NY>
+static hipError_t launch_y_full_t(const FullFastArgs& a, hipStream_t s) {
+    const int nblocks = (a.nx / FullLineGeom<NY>::W) * a.m;
+    const int nthr = FullLineGeom<NY>::NT;
+    const size_t lds = full_line_lds<NY>();
+    hipLaunchKernelGGL((y_full<NY>), dim3(nblocks), dim3(nthr), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_y_full(const FullFastArgs& a, hipStream_t s) {
+    if (a.ny == 64) return launch_y_full_t<64>(a, s);
+    if (a.ny == 128) return launch_y_full_t<128>(a, s);
+    if (a.ny == 256) return launch_y_full_t<256>(a, s);
+    if (a.ny == 512) return launch_y_full_t<512>(a, s);
+    return hipErrorInvalidValue;
+}
+
+#define SE2C_XT_FULL_ATTR(NX_, M_)                                                                          \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(xt_full<NX_, M_, 0>),                              \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_slab_lds<NX_, M_>());      \
+    if (e != hipSuccess) return e;                                                                          \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(xt_full<NX_, M_, 1>),                              \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_slab_lds<NX_, M_>());      \
+    if (e != hipSuccess) return e;
+#define SE2C_Y_FULL_ATTR(NY_)                                                                               \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full<NY_>),                                      \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_>());          \
+    if (e != hipSuccess) return e;
+
+hipError_t prepare_full_fast_kernels() {
+    hipError_t e;
+    SE2C_XT_FULL_ATTR(64, 16) SE2C_XT_FULL_ATTR(64, 32) SE2C_XT_FULL_ATTR(64, 64)
+    SE2C_XT_FULL_ATTR(128, 16) SE2C_XT_FULL_ATTR(128, 32) SE2C_XT_FULL_ATTR(128, 64)
+    SE2C_XT_FULL_ATTR(256, 16) SE2C_XT_FULL_ATTR(256, 32) SE2C_XT_FULL_ATTR(256, 64)
+    SE2C_Y_FULL_ATTR(64) SE2C_Y_FULL_ATTR(128) SE2C_Y_FULL_ATTR(256) SE2C_Y_FULL_ATTR(512)
+    return hipSuccess;
+}
+
+}  // namespace se2c

@@ -1,0 +1,42 @@
+// Register-resident FP32 kernels of the full-table (non-separable) path (see full_fast.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "passes.hpp"
+
+namespace se2c {
+
+// Fields are processed in pairs packed as re/im: pair p is fields 2p (re) and 2p + 1
+// (im).  Its x-theta spectrum occupies the two field slots as real planes (re plane
+// in slot 2p, im plane in slot 2p + 1); with an odd batch the last pair's im plane
+// lives in `lone` (one plane of workspace).
+struct FullFastArgs {
+    const float* in;
+    float* out;
+    float* lone;            // im plane of the last pair when the batch is odd (else unused)
+    long long n;            // points per field
+    int batch;              // fields
+    int nx, ny, m;
+    const float2* twx;      // w_nx^j
+    const float2* twy;      // w_ny^j
+    const float2* twt;      // w_m^j
+    // y pass: product with scale * prod_j T_j (FULL: [m][ny][nx]; SEPARABLE: Tx Ty Tt)
+    int ntab;
+    const void* tab[SE2C_MAX_TABLES];
+    int tab_full[SE2C_MAX_TABLES];
+    float scale;
+    int conj_tab;
+    float* save;            // y pass: if non-null, the spectrum before the product goes to
+                            // save (slots 2p, 2p + 1 per pair, planes as above)
+};
+
+bool full_fast_supported(int nx, int ny, int m);
+// x-theta forward DFT of field pairs (in: fields, out: spectrum planes; may alias)
+hipError_t launch_xt_full_fwd(const FullFastArgs& a, hipStream_t s);
+// x-theta inverse DFT (in: spectrum planes, out: fields; may alias), no scaling
+hipError_t launch_xt_full_inv(const FullFastArgs& a, hipStream_t s);
+// y pass in place on the spectrum planes of every pair: forward DFT, [save], product, inverse
+hipError_t launch_y_full(const FullFastArgs& a, hipStream_t s);
+hipError_t prepare_full_fast_kernels();
+
+}  // namespace se2c

@@ -8,7 +8,8 @@
 //               rho^ = (-1)^{k1+k2} P^ / n).
 // profile grad  dL/dprof[q][l] = sum_b sum_{j,i} H_q[j,i] dL/dP_b[l][j][i], H_q the
 //               lattice-periodized hat basis in r = |x| (transpose of the radial-profile
-//               sample expansion); FP64, deterministic (tree reductions, no atomics).
+//               sample expansion); FP64, deterministic (split-K partial products summed
+//               in a fixed order, no atomics).  The basis is built once per geometry.
 #include <hip/hip_runtime.h>
 
 #include "coeffs.hpp"
@@ -137,39 +138,94 @@ __global__ void batch_sum_kernel(const T* g, double* out, long long n, int batch
     }
 }
 
-// grad[q][l] = sum_p basis[q][p] G[l][p]; one block per (q, l), tree reduction.
-__global__ void profile_contract_kernel(const double* basis, const double* G, double* grad, int n_knots, int m,
-                                        long long npts) {
-    __shared__ double red[256];
-    const int q = blockIdx.x % n_knots;
-    const int l = blockIdx.x / n_knots;
-    const double* bq = basis + (long long)q * npts;
-    const double* gl = G + (long long)l * npts;
-    double acc = 0.0;
-    for (long long p = threadIdx.x; p < npts; p += blockDim.x) acc += bq[p] * gl[p];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+// part[s][q][l] = sum over points p of split s of basis[q][p] G[l][p]: one 64 x 64 output
+// tile per block (4 x 4 per thread), points staged through LDS 32 at a time.
+constexpr int kGemmTile = 64;
+constexpr int kGemmK = 32;
+
+__global__ void __launch_bounds__(256) profile_contract_partial_kernel(const double* basis, const double* G,
+                                                                       double* part, int n_knots, int m,
+                                                                       long long npts, int kchunk) {
+    __shared__ double hs[kGemmTile][kGemmK + 1];
+    __shared__ double gs[kGemmTile][kGemmK + 1];
+    const int ntq = (n_knots + kGemmTile - 1) / kGemmTile;
+    const int split = blockIdx.x;
+    const int q0 = (blockIdx.y % ntq) * kGemmTile;
+    const int l0 = (blockIdx.y / ntq) * kGemmTile;
+    const int tid = threadIdx.x;
+    const int tx = tid % 16, ty = tid / 16;
+    double acc[4][4] = {};
+    const long long pbeg = (long long)split * kchunk;
+    const long long pend = pbeg + kchunk < npts ? pbeg + kchunk : npts;
+    for (long long p0 = pbeg; p0 < pend; p0 += kGemmK) {
+        for (int e = tid; e < kGemmTile * kGemmK; e += 256) {
+            const int r = e / kGemmK, c = e - r * kGemmK;
+            const long long pp = p0 + c;
+            const bool inp = pp < pend;
+            hs[r][c] = (inp && q0 + r < n_knots) ? basis[(long long)(q0 + r) * npts + pp] : 0.0;
+            gs[r][c] = (inp && l0 + r < m) ? G[(long long)(l0 + r) * npts + pp] : 0.0;
+        }
+        __syncthreads();
+        for (int c = 0; c < kGemmK; ++c) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = hs[ty * 4 + i][c];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = gs[tx * 4 + j][c];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        }
         __syncthreads();
     }
-    if (threadIdx.x == 0) grad[(long long)q * m + l] = red[0];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int q = q0 + ty * 4 + i;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int l = l0 + tx * 4 + j;
+            if (q < n_knots && l < m) part[((long long)split * n_knots + q) * m + l] = acc[i][j];
+        }
+    }
 }
 
-hipError_t launch_profile_grad(const void* g, int batch, bool dbl, int n_knots, double r_max, int nx, int ny, int m,
-                               double* basis, double* G, double* grad, hipStream_t s) {
+// grad[q][l] = sum_s part[s][q][l], splits in increasing order (deterministic).
+__global__ void profile_contract_reduce_kernel(const double* part, double* grad, int nsplit, long long nout) {
+    for (long long o = blockIdx.x * (long long)blockDim.x + threadIdx.x; o < nout;
+         o += (long long)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int sp = 0; sp < nsplit; ++sp) acc += part[(long long)sp * nout + o];
+        grad[o] = acc;
+    }
+}
+
+hipError_t launch_profile_basis(double* basis, int n_knots, double r_max, int nx, int ny, hipStream_t s) {
+    hipLaunchKernelGGL(profile_basis_kernel, dim3(2048), dim3(256), 0, s, basis, n_knots, r_max, nx, ny);
+    return hipGetLastError();
+}
+
+int profile_grad_splits(long long npts) { return (int)((npts + kProfileChunk - 1) / kProfileChunk); }
+
+hipError_t launch_profile_grad(const void* g, int batch, bool dbl, int n_knots, int nx, int ny, int m,
+                               const double* basis, double* G, double* part, double* grad, hipStream_t s) {
     const long long npts = (long long)nx * ny;
     const long long n = npts * m;
-    hipLaunchKernelGGL(profile_basis_kernel, dim3(2048), dim3(256), 0, s, basis, n_knots, r_max, nx, ny);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
     if (dbl)
         hipLaunchKernelGGL(batch_sum_kernel<double>, dim3(2048), dim3(256), 0, s, (const double*)g, G, n, batch);
     else
         hipLaunchKernelGGL(batch_sum_kernel<float>, dim3(2048), dim3(256), 0, s, (const float*)g, G, n, batch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int nsplit = profile_grad_splits(npts);
+    const int ntiles = ((n_knots + kGemmTile - 1) / kGemmTile) * ((m + kGemmTile - 1) / kGemmTile);
+    hipLaunchKernelGGL(profile_contract_partial_kernel, dim3(nsplit, ntiles), dim3(256), 0, s, basis, G, part,
+                       n_knots, m, npts, kProfileChunk);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(profile_contract_kernel, dim3(n_knots * m), dim3(256), 0, s, basis, G, grad, n_knots, m, npts);
+    const long long nout = (long long)n_knots * m;
+    hipLaunchKernelGGL(profile_contract_reduce_kernel, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, part,
+                       grad, nsplit, nout);
     return hipGetLastError();
 }
 

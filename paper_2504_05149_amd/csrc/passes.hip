@@ -20,6 +20,7 @@
 //                 separable table, or full 3-D table), inverse.
 #include "fft_device.hpp"
 #include "passes.hpp"
+#include "full_fast.hpp"
 
 namespace se2c {
 
@@ -370,7 +371,8 @@ hipError_t prepare_fast_kernels();
 hipError_t prepare_kernels() {
     static hipError_t once = [] {
         hipError_t e = prepare_generic_kernels();
-        return e != hipSuccess ? e : prepare_fast_kernels();
+        if (e == hipSuccess) e = prepare_fast_kernels();
+        return e != hipSuccess ? e : prepare_full_fast_kernels();
     }();
     return once;
 }

@@ -20,32 +20,11 @@
 //   y pass that reads its output).
 // y_pencil_fast<NY>    one block per 16 adjacent x-pairs (float2 columns) at one theta:
 //   the same 16 x R2 scheme along y, product with Ty/NY.
+#include "fast_common.hpp"
 #include "regfft.hpp"
 #include "sep_fast.hpp"
 
 namespace se2c {
-
-// Position of element (k1, t) of one 16 x R2 exchange line: the XOR swizzle makes
-// both the write (fixed k1, lanes over t) and the read (fixed t, lanes over the
-// k1 groups) hit distinct 8-byte bank slots.
-template <int R2>
-__device__ __forceinline__ int xpos(int k1, int t) {
-    constexpr int CC = 16 / R2;
-    return k1 * R2 + (t ^ (k1 / CC));
-}
-
-__device__ __forceinline__ float2 chain_factor(const void* const* tabs, int ntab, int i, float scale, int conj) {
-    float2 v = make_float2(scale, 0.f);
-    for (int j = 0; j < ntab; ++j) v = mul<float>(v, reinterpret_cast<const float2*>(tabs[j])[i]);
-    if (conj) v.y = -v.y;
-    return v;
-}
-
-// Swap a value with the neighbouring lane (lane ^ 1) through DPP quad_perm [1,0,3,2].
-__device__ __forceinline__ float swap_lane1(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
-}
-__device__ __forceinline__ float2 swap_lane1(float2 v) { return make_float2(swap_lane1(v.x), swap_lane1(v.y)); }
 
 // TPC = threads per theta column in the column phase (1: the whole column in one
 // thread; 2: even/odd theta split over neighbouring lanes, radix-2 step via DPP).
@@ -380,13 +359,6 @@ template <int NX> struct RowGeom {
     static constexpr int NT = G * R2;
     static constexpr int P = NX + (R2 == 16 ? 16 : R2 % 16);  // LDS row pitch (complex)
 };
-
-// Position of element (k1, t) of one R1 x R2 exchange line (see xpos).
-template <int R1, int R2>
-__device__ __forceinline__ int xpos_line(int k1, int t) {
-    constexpr int CC = R1 / R2;
-    return k1 * R2 + (t ^ (k1 / CC));
-}
 
 template <int NX>
 __global__ void __launch_bounds__(RowGeom<NX>::NT) x_rows_fast(FastSepArgs a) {

@@ -217,6 +217,36 @@ def test_full_path_parity(dt, batch, rng):
         assert err <= tol
 
 
+@pytest.mark.parametrize("nx,ny,m,batch", [(64, 64, 16, 3), (128, 64, 32, 2), (256, 128, 64, 3), (64, 512, 64, 1),
+                                           (256, 256, 64, 2)])
+def test_full_path_register_kernels(nx, ny, m, batch, rng):
+    case(f"full-table register kernels {nx}x{ny}x{m} fp32 batch={batch}: profile x Gauss-vM chain, adjoint, "
+         "generic kernels and oracle")
+    prof = rng.uniform(0, 1, size=(16, m))
+    p_prof = ok.radial_profile(nx, ny, m, prof, 0.45)
+    f = _fields(5, batch, 8, nx, ny, m)
+    outs = {}
+    for generic in (False, True):
+        plan = se2.Plan([(nx, ny, m)], dtype="f32", generic=generic)
+        table = plan.coeffs(0, [se2.RadialProfile(_dev(prof, torch.float64), 0.45, norm=2),
+                                se2.GaussVM(0.05, 3.0, 0.7)])
+        fd = _dev(f, torch.float32)
+        outs[generic] = (plan.apply(0, fd, table).cpu().numpy().astype(np.float64),
+                         plan.apply(0, fd, table, adjoint=True).cpu().numpy().astype(np.float64))
+        print(f"  GPU generic={generic} done", flush=True)
+    ref_t = ffc(p_prof) * ffc(ok.gauss_vm(nx, ny, m, 0.05, 3.0, 0.7))
+    print("  oracle table done", flush=True)
+    tol = tol32(nx * ny * m)
+    for b in range(batch):
+        ref = oracle_conv(f[b], ref_t)
+        ref_adj = oc.conv_with_coeffs(f[b], np.conj(ref_t))
+        for generic in (False, True):
+            e1 = rel_l2(outs[generic][0][b], ref)
+            e2 = rel_l2(outs[generic][1][b], ref_adj)
+            print(f"  field {b} generic={generic}: {e1:.2e} adj {e2:.2e}", flush=True)
+            assert e1 <= tol and e2 <= tol
+
+
 def test_full_path_large_three_pass_fp64():
     case("full-table path 256x16x64 fp64 (split x / theta passes)")
     nx, ny, m = 256, 16, 64
