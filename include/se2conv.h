@@ -194,6 +194,54 @@ se2conv_status se2conv_profile_grad(se2conv_plan_t plan, int32_t shape_idx, cons
 se2conv_status se2conv_apply(se2conv_plan_t plan, int32_t shape_idx, const void* d_f, const void* d_table,
                              void* d_out, int32_t batch, uint32_t flags, hipStream_t stream);
 
+/*
+ * Fused differentiation (FP32 plans on shapes with register kernels, see
+ * se2conv_fused_supported; other plans use se2conv_field_coeffs + se2conv_kernel_grad).
+ *
+ * Field spectra: the 3-D DFT (eq. (3DFT), no sign factor, no 1/n) of the batch's fields
+ * taken two at a time as z_p = f_{2p} + i f_{2p+1}: plane 2p holds Re Z_p and plane 2p+1
+ * holds Im Z_p, each [M][Ny][Nx] FP32 in frequency order [k3][k2][k1].  With an odd batch
+ * the last field is paired with zero.  A buffer of spectra is 2 * ceil(batch / 2) planes.
+ *
+ * The kernel-sample gradient of a loss over the batch follows from eqs. (FkLv), (SKfg):
+ * for out_b = S_K[f_b, rho] with rho^ = (-1)^{k1+k2} P^ / n and g_b = dL/dout_b,
+ *   dL/dP = sum_b (1/n^2) iDFT( (-1)^{k1+k2} G_b^ conj(F_b^) )   (unnormalised iDFT)
+ *         = (1/n^2) Re iDFT( (-1)^{k1+k2} sum_p Z_{g,p} conj(Z_{f,p}) ),
+ * the pair form following from the Hermitian symmetry of real fields' spectra.
+ */
+
+/* Nonzero when the fused entry points below support this plan and shape. */
+int32_t se2conv_fused_supported(se2conv_plan_t plan, int32_t shape_idx);
+
+/*
+ * se2conv_field_spectra: field spectra of d_f (device [batch][M][Ny][Nx] FP32) into
+ * d_spectra (device, 2 * ceil(batch / 2) planes, caller-owned).
+ */
+se2conv_status se2conv_field_spectra(se2conv_plan_t plan, int32_t shape_idx, const void* d_f, int32_t batch,
+                                     void* d_spectra, hipStream_t stream);
+
+/*
+ * se2conv_apply_save: se2conv_apply (forward, one table) that also writes the field
+ * spectra of d_f to d_spectra (the checkpoint of the backward pass) from inside its y
+ * pass.  d_out == d_f is allowed; d_spectra must not overlap either.
+ */
+se2conv_status se2conv_apply_save(se2conv_plan_t plan, int32_t shape_idx, const void* d_f, const void* d_table,
+                                  void* d_out, int32_t batch, void* d_spectra, hipStream_t stream);
+
+/*
+ * se2conv_backward: both gradients of a loss through out = S_K[f, rho] (one table):
+ *   d_grad_f  device [batch][M][Ny][Nx]: dL/df_b = S_K[g_b, conj rho] (the adjoint apply);
+ *   d_grad_p  device [M][Ny][Nx]: dL/dP summed over the batch, P the samples of the kernel
+ *             whose FFC table is d_table;
+ * from d_g = dL/dout (device [batch][M][Ny][Nx]) and the field spectra d_spectra of the
+ * forward's fields.  Four passes: x-theta forward of g, one y pass (adjoint product and
+ * gradient accumulation), x-theta inverses of both results.  d_grad_f may equal d_g.
+ * Uses three workspace planes of the largest shape (allocated on first use).
+ */
+se2conv_status se2conv_backward(se2conv_plan_t plan, int32_t shape_idx, const void* d_g, const void* d_table,
+                                const void* d_spectra, int32_t batch, void* d_grad_f, void* d_grad_p,
+                                hipStream_t stream);
+
 /* One problem of a heterogeneous submission: out = Re S_K[f, tables[0] * ... ]. */
 typedef struct {
     int32_t shape_idx;

@@ -133,7 +133,9 @@ def uneven_problem_list(config: int, n_problems: int,
 
 
 def rel_l2(a: np.ndarray, b: np.ndarray) -> float:
-    a = np.asarray(a, dtype=np.float64)
-    b = np.asarray(b, dtype=np.float64)
-    den = math.sqrt(float(np.sum(b * b)))
-    return math.sqrt(float(np.sum((a - b) ** 2))) / (den if den > 0 else 1.0)
+    """||a - b||_2 / ||b||_2 (real or complex arrays)."""
+    dt = np.complex128 if (np.iscomplexobj(a) or np.iscomplexobj(b)) else np.float64
+    a = np.asarray(a, dtype=dt)
+    b = np.asarray(b, dtype=dt)
+    den = math.sqrt(float(np.sum(np.abs(b) ** 2)))
+    return math.sqrt(float(np.sum(np.abs(a - b) ** 2))) / (den if den > 0 else 1.0)

@@ -25,6 +25,7 @@ EXPORTED = [
     "se2conv_plan", "se2conv_plan_destroy", "se2conv_coeffs", "se2conv_table_info",
     "se2conv_apply", "se2conv_chain", "se2conv_pass_times", "se2conv_field_coeffs", "se2conv_profile_grad",
     "se2conv_powers", "se2conv_sample_bumps", "se2conv_autotune", "se2conv_kernel_grad",
+    "se2conv_fused_supported", "se2conv_field_spectra", "se2conv_apply_save", "se2conv_backward",
     "se2conv_status_string",
     "se2conv_last_error",
 ]
@@ -89,6 +90,10 @@ def load() -> ctypes.CDLL:
     lib.se2conv_sample_bumps.argtypes = [vp, i32, vp, i32, ctypes.c_double, ctypes.c_double, vp, vp]
     lib.se2conv_autotune.argtypes = [vp, i32, i32, vp]
     lib.se2conv_kernel_grad.argtypes = [vp, i32, vp, vp, sz, i32, vp, vp]
+    lib.se2conv_fused_supported.argtypes = [vp, i32]
+    lib.se2conv_field_spectra.argtypes = [vp, i32, vp, i32, vp, vp]
+    lib.se2conv_apply_save.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp]
+    lib.se2conv_backward.argtypes = [vp, i32, vp, vp, vp, i32, vp, vp, vp]
     lib.se2conv_status_string.argtypes = [i32]
     lib.se2conv_status_string.restype = ctypes.c_char_p
     lib.se2conv_last_error.argtypes = []
@@ -96,7 +101,8 @@ def load() -> ctypes.CDLL:
     for name in ["se2conv_plan", "se2conv_plan_destroy", "se2conv_coeffs", "se2conv_table_info",
                  "se2conv_apply", "se2conv_chain", "se2conv_pass_times", "se2conv_field_coeffs",
                  "se2conv_profile_grad", "se2conv_powers", "se2conv_sample_bumps", "se2conv_autotune",
-                 "se2conv_kernel_grad"]:
+                 "se2conv_kernel_grad", "se2conv_fused_supported", "se2conv_field_spectra", "se2conv_apply_save",
+                 "se2conv_backward"]:
         getattr(lib, name).restype = i32
     _lib = lib
     return lib

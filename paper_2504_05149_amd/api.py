@@ -174,6 +174,50 @@ class Plan:
                                               out.data_ptr(), _stream_handle(stream)))
         return out
 
+    def fused_supported(self, shape_idx: int) -> bool:
+        """True when field_spectra / apply_save / backward run for this plan and shape."""
+        return bool(self._lib.se2conv_fused_supported(self.handle, shape_idx))
+
+    def _spectra_buffer(self, shape_idx: int, batch: int, device) -> torch.Tensor:
+        nx, ny, m = self.shapes[shape_idx]
+        return torch.empty(2 * ((batch + 1) // 2), m, ny, nx, dtype=torch.float32, device=device)
+
+    def field_spectra(self, shape_idx: int, f: torch.Tensor, stream=None) -> torch.Tensor:
+        """3-D DFTs of field pairs packed as re/im: [2 ceil(B/2), M, Ny, Nx] FP32 planes."""
+        _require(f, self.tdtype)
+        nx, ny, m = self.shapes[shape_idx]
+        batch = f.numel() // (nx * ny * m)
+        spec = self._spectra_buffer(shape_idx, batch, f.device)
+        L.check(self._lib.se2conv_field_spectra(self.handle, shape_idx, f.data_ptr(), batch, spec.data_ptr(),
+                                                _stream_handle(stream)))
+        return spec
+
+    def apply_save(self, shape_idx: int, f: torch.Tensor, table: Table, out: torch.Tensor | None = None,
+                   stream=None):
+        """Forward apply that also returns the field spectra (the backward's checkpoint)."""
+        _require(f, self.tdtype)
+        nx, ny, m = self.shapes[shape_idx]
+        batch = f.numel() // (nx * ny * m)
+        if out is None:
+            out = torch.empty_like(f)
+        spec = self._spectra_buffer(shape_idx, batch, f.device)
+        L.check(self._lib.se2conv_apply_save(self.handle, shape_idx, f.data_ptr(), table.ptr, out.data_ptr(), batch,
+                                             spec.data_ptr(), _stream_handle(stream)))
+        return out, spec
+
+    def backward(self, shape_idx: int, g: torch.Tensor, table: Table, spectra: torch.Tensor,
+                 grad_f: torch.Tensor | None = None, stream=None):
+        """(dL/df, sum_b dL/dP) through out = S_K[f, table] from g = dL/dout and f's spectra."""
+        _require(g, self.tdtype)
+        nx, ny, m = self.shapes[shape_idx]
+        batch = g.numel() // (nx * ny * m)
+        if grad_f is None:
+            grad_f = torch.empty_like(g)
+        grad_p = torch.empty(m, ny, nx, dtype=self.tdtype, device=g.device)
+        L.check(self._lib.se2conv_backward(self.handle, shape_idx, g.data_ptr(), table.ptr, spectra.data_ptr(),
+                                           batch, grad_f.data_ptr(), grad_p.data_ptr(), _stream_handle(stream)))
+        return grad_f, grad_p
+
     def profile_grad(self, shape_idx: int, grad_samples: torch.Tensor, n_knots: int, r_max: float,
                      stream=None) -> torch.Tensor:
         """sum over the batch of the hat-basis transpose of dL/dP: a float64 [n_knots, M] tensor."""

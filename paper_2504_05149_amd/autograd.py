@@ -9,8 +9,12 @@ map prof -> P is linear).  Gradients (all computed by the HIP library):
              (se2conv_field_coeffs), accumulated spectrally (se2conv_kernel_grad);
 * dL/dprof = hat-basis transpose of sum_b dL/dP_b (se2conv_profile_grad).
 
-checkpoint=True computes the field tables in the forward pass and keeps them for
-the backward pass; checkpoint=False recomputes them in the backward pass.
+On FP32 plans with register kernels the backward is fused (se2conv_backward):
+one y pass produces the adjoint product for dL/df and accumulates sum_b dL/dP_b
+against the fields' packed spectra (se2conv_field_spectra / se2conv_apply_save).
+
+checkpoint=True keeps the field tables (or spectra, saved by the forward's own y
+pass) for the backward pass; checkpoint=False recomputes them in the backward pass.
 """
 from __future__ import annotations
 
@@ -26,11 +30,17 @@ class RadialProfileConv(torch.autograd.Function):
         f = f.detach().contiguous()
         prof = prof.detach().contiguous()
         table = plan.coeffs(shape_idx, [RadialProfile(prof, r_max, norm=L.KNORM_NONE)])
-        out = plan.apply(shape_idx, f, table)
+        ctx.fused = plan.fused_supported(shape_idx)
+        ctx.ftabs = ctx.spectra = None
+        if ctx.fused and checkpoint:
+            out, ctx.spectra = plan.apply_save(shape_idx, f, table)
+        else:
+            out = plan.apply(shape_idx, f, table)
+            if checkpoint:
+                ctx.ftabs = plan.field_coeffs(shape_idx, f)
         ctx.plan, ctx.shape_idx, ctx.r_max = plan, shape_idx, r_max
         ctx.table = table
         ctx.n_knots = prof.shape[0]
-        ctx.ftabs = plan.field_coeffs(shape_idx, f) if checkpoint else None
         ctx.save_for_backward(f)
         return out
 
@@ -40,6 +50,12 @@ class RadialProfileConv(torch.autograd.Function):
         plan, sidx = ctx.plan, ctx.shape_idx
         g = g.contiguous()
         grad_f = grad_prof = None
+        if ctx.fused:
+            spectra = ctx.spectra if ctx.spectra is not None else plan.field_spectra(sidx, f)
+            grad_f, grad_p = plan.backward(sidx, g, ctx.table, spectra)
+            if ctx.needs_input_grad[1]:
+                grad_prof = plan.profile_grad(sidx, grad_p, ctx.n_knots, ctx.r_max)
+            return (grad_f if ctx.needs_input_grad[0] else None), grad_prof, None, None, None, None
         if ctx.needs_input_grad[0]:
             grad_f = plan.apply(sidx, g, ctx.table, adjoint=True)
         if ctx.needs_input_grad[1]:

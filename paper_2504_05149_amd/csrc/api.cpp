@@ -1479,6 +1479,129 @@ se2conv_status se2conv_apply(se2conv_plan_t p, int32_t shape_idx, const void* d_
     return ok();
 }
 
+// ---- fused differentiation (register kernels of the full path)
+int32_t se2conv_fused_supported(se2conv_plan_t p, int32_t shape_idx) {
+    if (!p || p->host_only || shape_idx < 0 || shape_idx >= (int)p->shapes.size()) return 0;
+    return use_full_fast(p, p->shapes[shape_idx]) ? 1 : 0;
+}
+
+namespace {
+
+se2conv_status check_fused(se2conv_plan_s* p, int32_t shape_idx) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (shape_idx < 0 || shape_idx >= (int)p->shapes.size())
+        return fail(SE2CONV_ERR_INVALID_ARG, "shape_idx %d out of range", shape_idx);
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    if (!use_full_fast(p, p->shapes[shape_idx]))
+        return fail(SE2CONV_ERR_UNSUPPORTED_SIZE,
+                    "fused differentiation needs an FP32 plan without SE2CONV_PLAN_GENERIC and nx in {64,128,256}, "
+                    "m in {16,32,64}, ny in {64,128,256,512}");
+    return SE2CONV_OK;
+}
+
+bool overlaps(const void* a, size_t na, const void* b, size_t nb) {
+    const char* x = (const char*)a;
+    const char* y = (const char*)b;
+    return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+se2conv_status se2conv_field_spectra(se2conv_plan_t p, int32_t shape_idx, const void* d_f, int32_t batch,
+                                     void* d_spectra, hipStream_t stream) {
+    se2conv_status r = check_fused(p, shape_idx);
+    if (r != SE2CONV_OK) return r;
+    if (batch < 1 || !d_f || !d_spectra || !aligned16(d_f) || !aligned16(d_spectra))
+        return fail(SE2CONV_ERR_INVALID_ARG, "need batch >= 1 and 16-byte aligned device pointers");
+    const se2conv_shape& s = p->shapes[shape_idx];
+    FullFastArgs a = full_fast_args(p, s, batch);
+    const size_t plane = sizeof(float) * (size_t)a.n;
+    if (overlaps(d_f, plane * batch, d_spectra, plane * 2 * ((batch + 1) / 2)))
+        return fail(SE2CONV_ERR_INVALID_ARG, "d_spectra overlaps d_f");
+    a.in = reinterpret_cast<const float*>(d_f);
+    a.out = reinterpret_cast<float*>(d_spectra);
+    a.save = a.out;
+    a.lone = (batch & 1) ? a.out + (long long)batch * a.n : nullptr;
+    HIPCHK(launch_xt_full_fwd(a, stream));
+    HIPCHK(launch_y_full_spectra(a, stream));
+    return ok();
+}
+
+se2conv_status se2conv_apply_save(se2conv_plan_t p, int32_t shape_idx, const void* d_f, const void* d_table,
+                                  void* d_out, int32_t batch, void* d_spectra, hipStream_t stream) {
+    se2conv_status r = validate_io(p, shape_idx, d_f, d_out, batch);
+    if (r != SE2CONV_OK) return r;
+    r = check_fused(p, shape_idx);
+    if (r != SE2CONV_OK) return r;
+    const se2conv_shape& s = p->shapes[shape_idx];
+    FullFastArgs a = full_fast_args(p, s, batch);
+    const size_t plane = sizeof(float) * (size_t)a.n;
+    const size_t sbytes = plane * 2 * ((batch + 1) / 2);
+    if (!d_spectra || !aligned16(d_spectra) || overlaps(d_f, plane * batch, d_spectra, sbytes) ||
+        overlaps(d_out, plane * batch, d_spectra, sbytes))
+        return fail(SE2CONV_ERR_INVALID_ARG, "d_spectra must be 16-byte aligned and not overlap d_f or d_out");
+    Chain ch;
+    bool all_sep = true;
+    const void* tabs[1] = {d_table};
+    r = lookup_chain(p, shape_idx, tabs, 1, &ch, &all_sep);
+    if (r != SE2CONV_OK) return r;
+    set_chain(&a, ch, false, 1.0 / (double)a.n);
+    a.in = reinterpret_cast<const float*>(d_f);
+    a.out = reinterpret_cast<float*>(d_out);
+    a.save = reinterpret_cast<float*>(d_spectra);
+    HIPCHK(launch_xt_full_fwd(a, stream));
+    a.in = a.out;
+    HIPCHK(launch_y_full(a, stream));
+    HIPCHK(launch_xt_full_inv(a, stream));
+    return ok();
+}
+
+se2conv_status se2conv_backward(se2conv_plan_t p, int32_t shape_idx, const void* d_g, const void* d_table,
+                                const void* d_spectra, int32_t batch, void* d_grad_f, void* d_grad_p,
+                                hipStream_t stream) {
+    se2conv_status r = validate_io(p, shape_idx, d_g, d_grad_f, batch);
+    if (r != SE2CONV_OK) return r;
+    r = check_fused(p, shape_idx);
+    if (r != SE2CONV_OK) return r;
+    const se2conv_shape& s = p->shapes[shape_idx];
+    FullFastArgs a = full_fast_args(p, s, batch);
+    const size_t plane = sizeof(float) * (size_t)a.n;
+    const size_t sbytes = plane * 2 * ((batch + 1) / 2);
+    if (!d_spectra || !d_grad_p || !aligned16(d_spectra) || !aligned16(d_grad_p))
+        return fail(SE2CONV_ERR_INVALID_ARG, "d_spectra and d_grad_p must be 16-byte aligned device pointers");
+    if (overlaps(d_grad_f, plane * batch, d_spectra, sbytes) || overlaps(d_grad_f, plane * batch, d_grad_p, plane) ||
+        overlaps(d_g, plane * batch, d_grad_p, plane) || overlaps(d_spectra, sbytes, d_grad_p, plane))
+        return fail(SE2CONV_ERR_INVALID_ARG, "d_grad_f, d_grad_p and d_spectra must not overlap");
+    Chain ch;
+    bool all_sep = true;
+    const void* tabs[1] = {d_table};
+    r = lookup_chain(p, shape_idx, tabs, 1, &ch, &all_sep);
+    if (r != SE2CONV_OK) return r;
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        if (!p->ws2 && hipMalloc(&p->ws2, 2 * p->ws_bytes) != hipSuccess)
+            return fail(SE2CONV_ERR_OUT_OF_MEMORY, "backward workspace (%zu bytes)", 2 * p->ws_bytes);
+    }
+    float* acc = reinterpret_cast<float*>(p->ws2);
+    set_chain(&a, ch, true, 1.0 / (double)a.n);
+    a.in = reinterpret_cast<const float*>(d_g);
+    a.out = reinterpret_cast<float*>(d_grad_f);
+    HIPCHK(launch_xt_full_fwd(a, stream));
+    a.in = a.out;
+    a.zf = reinterpret_cast<const float*>(d_spectra);
+    a.acc = acc;
+    a.acc_scale = (float)(1.0 / ((double)a.n * (double)a.n));
+    HIPCHK(launch_y_full_backward(a, stream));
+    HIPCHK(launch_xt_full_inv(a, stream));
+    // x-theta inverse of the accumulated spectrum: real part = dL/dP (imaginary part dropped)
+    FullFastArgs b = full_fast_args(p, s, 1);
+    b.in = acc;
+    b.lone = acc + a.n;
+    b.out = reinterpret_cast<float*>(d_grad_p);
+    HIPCHK(launch_xt_full_inv(b, stream));
+    return ok();
+}
+
 se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int32_t n_probs, uint32_t flags,
                              hipStream_t stream) {
     if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");

@@ -10,9 +10,10 @@
 //   register decomposition, one XOR-swizzled LDS exchange), rows -> columns through
 //   LDS, forward DFT along theta in registers (TPC = 2: the last radix-2 step across
 //   neighbouring lanes via DPP); stores the x-theta spectrum as re/im planes.
-// y_full<NY>  one block per (theta frequency, 16 x frequencies), all pairs in turn:
-//   forward DFT along y, [copy of the spectrum], product with the table (loaded once
-//   per block for every pair), inverse DFT along y, in place.
+// y_full<NY, MODE>  one block per (theta frequency, 16 x frequencies), all pairs in
+//   turn: forward DFT along y, [copy of the spectrum], product with the table (loaded
+//   once per block for every pair), inverse DFT along y, in place; MODE 2 also
+//   accumulates the kernel-sample gradient of the batch (see below).
 // xt_full<NX, M, DIR = 1>  the mirror image of the first pass: inverse DFT along
 //   theta (columns), columns -> rows, inverse DFT along x, stores the two real fields.
 #include "fast_common.hpp"
@@ -245,7 +246,14 @@ static constexpr size_t full_line_lds() {
     return sizeof(float2) * ((size_t)NY * FullLineGeom<NY>::W + 2 * NY);
 }
 
-template <int NY>
+// MODE 0 (convolve): forward DFT along y, [copy of the spectrum to save], product
+//   with scale * prod T (conjugated for the adjoint), inverse DFT, in place.
+// MODE 1 (spectra): forward DFT along y written to save; nothing else.
+// MODE 2 (backward): as MODE 0 on the upstream gradient g (the adjoint product), and
+//   in the same sweep A[k] = sum_pairs Z_g[k] conj(Z_f[k]) with the field spectra Z_f
+//   (zf); at the end W[k] A[k] / n^2 goes through the inverse DFT along y to acc (two
+//   planes).  Its x-theta inverse has real part dL/dP summed over the batch.
+template <int NY, int MODE>
 __global__ void __launch_bounds__(FullLineGeom<NY>::NT) y_full(FullFastArgs a) {
     using Gm = FullLineGeom<NY>;
     constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC, W = Gm::W, NT = Gm::NT;
@@ -262,33 +270,42 @@ __global__ void __launch_bounds__(FullLineGeom<NY>::NT) y_full(FullFastArgs a) {
     }
     __syncthreads();
 
-    const int q = tid % W, t = tid / W;
     const int ctiles = a.nx / W;
     const int kt = blockIdx.x / ctiles;
-    const int kx = (blockIdx.x - kt * ctiles) * W + q;
     const int pl = a.nx * NY;
     const int npairs = (a.batch + 1) / 2;
     // table factor for (kt, ky = k1 + R1 k2, kx), k1 = CC t + j
     float2 tv[CC][R2];
+    if constexpr (MODE != 1) {
+        const int q = tid % W, t = tid / W;
+        const int kx = (blockIdx.x - kt * ctiles) * W + q;
 #pragma unroll
-    for (int j = 0; j < CC; ++j) {
+        for (int j = 0; j < CC; ++j) {
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) {
-            const int ky = CC * t + j + R1 * k2;
-            float2 f = make_float2(a.scale, 0.f);
-            for (int e = 0; e < a.ntab; ++e) {
-                const float2* T = reinterpret_cast<const float2*>(a.tab[e]);
-                if (a.tab_full[e]) {
-                    f = mul<float>(f, T[(long long)kt * pl + ky * a.nx + kx]);
-                } else {
-                    f = mul<float>(f, T[kx]);
-                    f = mul<float>(f, T[a.nx + ky]);
-                    f = mul<float>(f, T[a.nx + NY + kt]);
+            for (int k2 = 0; k2 < R2; ++k2) {
+                const int ky = CC * t + j + R1 * k2;
+                float2 f = make_float2(a.scale, 0.f);
+                for (int e = 0; e < a.ntab; ++e) {
+                    const float2* T = reinterpret_cast<const float2*>(a.tab[e]);
+                    if (a.tab_full[e]) {
+                        f = mul<float>(f, T[(long long)kt * pl + ky * a.nx + kx]);
+                    } else {
+                        f = mul<float>(f, T[kx]);
+                        f = mul<float>(f, T[a.nx + ky]);
+                        f = mul<float>(f, T[a.nx + NY + kt]);
+                    }
                 }
+                if (a.conj_tab) f.y = -f.y;
+                tv[j][k2] = f;
             }
-            if (a.conj_tab) f.y = -f.y;
-            tv[j][k2] = f;
         }
+    }
+    float2 acc[CC][R2];
+    if constexpr (MODE == 2) {
+#pragma unroll
+        for (int j = 0; j < CC; ++j)
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) acc[j][k2] = make_float2(0.f, 0.f);
     }
     const int rstride = R2 * a.nx;
     for (int pair = 0; pair < npairs; ++pair) {
@@ -319,7 +336,7 @@ __global__ void __launch_bounds__(FullLineGeom<NY>::NT) y_full(FullFastArgs a) {
             for (int tt = 0; tt < R2; ++tt) u[j][tt] = buf[(k1 * R2 + tt) * W + q];
             RegDFT<R2, false, float>::run(u[j]);
         }
-        if (a.save) {
+        if (MODE == 1 || a.save) {
             float* s_re = a.save + (long long)(2 * pair) * a.n;
             float* s_im = s_re + a.n;
 #pragma unroll
@@ -329,6 +346,20 @@ __global__ void __launch_bounds__(FullLineGeom<NY>::NT) y_full(FullFastArgs a) {
                     const int off = base + (CC * t + j + R1 * k2) * a.nx;
                     s_re[off] = u[j][k2].x;
                     s_im[off] = u[j][k2].y;
+                }
+        }
+        if constexpr (MODE == 1) continue;
+        if constexpr (MODE == 2) {
+            const float* z_re = a.zf + (long long)(2 * pair) * a.n;
+            const float* z_im = z_re + a.n;
+#pragma unroll
+            for (int j = 0; j < CC; ++j)
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) {
+                    const int off = base + (CC * t + j + R1 * k2) * a.nx;
+                    const float2 z = make_float2(z_re[off], z_im[off]);
+                    acc[j][k2].x += u[j][k2].x * z.x + u[j][k2].y * z.y;  // u conj(z)
+                    acc[j][k2].y += u[j][k2].y * z.x - u[j][k2].x * z.y;
                 }
         }
 #pragma unroll
@@ -353,6 +384,44 @@ __global__ void __launch_bounds__(FullLineGeom<NY>::NT) y_full(FullFastArgs a) {
         for (int r = 0; r < R1; ++r) {
             re[lane_off + r * rstride] = w[r].x;
             im[lane_off + r * rstride] = w[r].y;
+        }
+    }
+    if constexpr (MODE == 2) {
+        // W[k] = (-1)^(kx + ky) and 1/n^2, then the inverse DFT along y of the accumulator
+        const int q = tid % W, t = tid / W;
+        const int kx = (blockIdx.x - kt * ctiles) * W + q;
+        const int base = kt * pl + kx;
+        const float s2 = a.acc_scale;
+#pragma unroll
+        for (int j = 0; j < CC; ++j) {
+            const int k1 = CC * t + j;
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) {
+                const int ky = k1 + R1 * k2;
+                const float sg = ((kx + ky) & 1) ? -s2 : s2;
+                acc[j][k2] = make_float2(acc[j][k2].x * sg, acc[j][k2].y * sg);
+            }
+            RegDFT<R2, true, float>::run(acc[j]);
+#pragma unroll
+            for (int tt = 1; tt < R2; ++tt) acc[j][tt] = mulc<float>(acc[j][tt], tw_i[tt * R1 + k1]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CC; ++j)
+#pragma unroll
+            for (int tt = 0; tt < R2; ++tt) buf[((CC * t + j) * R2 + tt) * W + q] = acc[j][tt];
+        __syncthreads();
+        float2 w[R1];
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) w[k1] = buf[(k1 * R2 + t) * W + q];
+        RegDFT<R1, true, float>::run(w);
+        float* __restrict__ o_re = a.acc;
+        float* __restrict__ o_im = a.acc + a.n;
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            const int off = base + (t + R2 * r) * a.nx;
+            o_re[off] = w[r].x;
+            o_im[off] = w[r].y;
         }
     }
 }
@@ -386,22 +455,27 @@ static hipError_t launch_xt_full(const FullFastArgs& a, hipStream_t s) {
 hipError_t launch_xt_full_fwd(const FullFastArgs& a, hipStream_t s) { return launch_xt_full<0>(a, s); }
 hipError_t launch_xt_full_inv(const FullFastArgs& a, hipStream_t s) { return launch_xt_full<1>(a, s); }
 
-template <int NY>
+template <int NY, int MODE>
 static hipError_t launch_y_full_t(const FullFastArgs& a, hipStream_t s) {
     const int nblocks = (a.nx / FullLineGeom<NY>::W) * a.m;
     const int nthr = FullLineGeom<NY>::NT;
     const size_t lds = full_line_lds<NY>();
-    hipLaunchKernelGGL((y_full<NY>), dim3(nblocks), dim3(nthr), lds, s, a);
+    hipLaunchKernelGGL((y_full<NY, MODE>), dim3(nblocks), dim3(nthr), lds, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_y_full(const FullFastArgs& a, hipStream_t s) {
-    if (a.ny == 64) return launch_y_full_t<64>(a, s);
-    if (a.ny == 128) return launch_y_full_t<128>(a, s);
-    if (a.ny == 256) return launch_y_full_t<256>(a, s);
-    if (a.ny == 512) return launch_y_full_t<512>(a, s);
+template <int MODE>
+static hipError_t launch_y_full_mode(const FullFastArgs& a, hipStream_t s) {
+    if (a.ny == 64) return launch_y_full_t<64, MODE>(a, s);
+    if (a.ny == 128) return launch_y_full_t<128, MODE>(a, s);
+    if (a.ny == 256) return launch_y_full_t<256, MODE>(a, s);
+    if (a.ny == 512) return launch_y_full_t<512, MODE>(a, s);
     return hipErrorInvalidValue;
 }
+
+hipError_t launch_y_full(const FullFastArgs& a, hipStream_t s) { return launch_y_full_mode<0>(a, s); }
+hipError_t launch_y_full_spectra(const FullFastArgs& a, hipStream_t s) { return launch_y_full_mode<1>(a, s); }
+hipError_t launch_y_full_backward(const FullFastArgs& a, hipStream_t s) { return launch_y_full_mode<2>(a, s); }
 
 #define SE2C_XT_FULL_ATTR(NX_, M_)                                                                          \
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(xt_full<NX_, M_, 0>),                              \
@@ -410,10 +484,11 @@ hipError_t launch_y_full(const FullFastArgs& a, hipStream_t s) {
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(xt_full<NX_, M_, 1>),                              \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_slab_lds<NX_, M_>());      \
     if (e != hipSuccess) return e;
-#define SE2C_Y_FULL_ATTR(NY_)                                                                               \
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full<NY_>),                                      \
+#define SE2C_Y_FULL_ATTR1(NY_, MODE_)                                                                       \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full<NY_, MODE_>),                               \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_>());          \
     if (e != hipSuccess) return e;
+#define SE2C_Y_FULL_ATTR(NY_) SE2C_Y_FULL_ATTR1(NY_, 0) SE2C_Y_FULL_ATTR1(NY_, 1) SE2C_Y_FULL_ATTR1(NY_, 2)
 
 hipError_t prepare_full_fast_kernels() {
     hipError_t e;

@@ -28,6 +28,10 @@ struct FullFastArgs {
     int conj_tab;
     float* save;            // y pass: if non-null, the spectrum before the product goes to
                             // save (slots 2p, 2p + 1 per pair, planes as above)
+    // backward y pass
+    const float* zf;        // field spectra (slots 2p, 2p + 1 per pair)
+    float* acc;             // two planes: W A / n^2 after the inverse DFT along y
+    float acc_scale;        // 1 / n^2
 };
 
 bool full_fast_supported(int nx, int ny, int m);
@@ -37,6 +41,10 @@ hipError_t launch_xt_full_fwd(const FullFastArgs& a, hipStream_t s);
 hipError_t launch_xt_full_inv(const FullFastArgs& a, hipStream_t s);
 // y pass in place on the spectrum planes of every pair: forward DFT, [save], product, inverse
 hipError_t launch_y_full(const FullFastArgs& a, hipStream_t s);
+// y pass: forward DFT only, written to save
+hipError_t launch_y_full_spectra(const FullFastArgs& a, hipStream_t s);
+// y pass of the backward: adjoint product in place, kernel-sample gradient accumulated to acc
+hipError_t launch_y_full_backward(const FullFastArgs& a, hipStream_t s);
 hipError_t prepare_full_fast_kernels();
 
 }  // namespace se2c

@@ -155,3 +155,101 @@ def test_kernel_grad_accumulates_over_batch(dt, batch, rng):
     err = rel_l2(out, ref)
     print(f"  rel-L2 {err:.2e}", flush=True)
     assert err <= (TOL64 if dt == "f64" else tol32(nx * ny * m))
+
+
+# ------------------------------------------------- fused differentiation (register kernels)
+FUSED = [(64, 64, 16, 3), (128, 64, 32, 2), (64, 128, 64, 1)]
+
+
+@pytest.mark.parametrize("nx,ny,m,batch", FUSED)
+def test_field_spectra_match_oracle_dft(nx, ny, m, batch):
+    case(f"field spectra (packed pairs) {nx}x{ny}x{m} fp32 batch={batch}")
+    from oracle.transforms import dft3
+    f = sample_fields(25, batch, 8, nx, ny, m)
+    plan = se2.Plan([(nx, ny, m)], dtype="f32")
+    assert plan.fused_supported(0)
+    spec = plan.field_spectra(0, _dev(f, torch.float32)).cpu().numpy().astype(np.float64)
+    assert spec.shape[0] == 2 * ((batch + 1) // 2)
+    for p in range((batch + 1) // 2):
+        z = f[2 * p] + (1j * f[2 * p + 1] if 2 * p + 1 < batch else 0.0)
+        ref = dft3(z)
+        got = spec[2 * p] + 1j * spec[2 * p + 1]
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))  # complex rel-L2
+        print(f"  pair {p}: rel-L2 {err:.2e}", flush=True)
+        assert err <= tol32(nx * ny * m)
+
+
+def test_apply_save_matches_apply_and_spectra(rng):
+    case("apply_save == apply and field_spectra (bitwise), 128x64x32 fp32 batch 3")
+    nx, ny, m, batch = 128, 64, 32, 3
+    prof = rng.uniform(0, 1, size=(12, m))
+    f = _dev(sample_fields(26, batch, 8, nx, ny, m), torch.float32)
+    plan = se2.Plan([(nx, ny, m)], dtype="f32")
+    table = plan.coeffs(0, [se2.RadialProfile(_dev(prof, torch.float64), 0.45, norm=2)])
+    out_a = plan.apply(0, f, table)
+    out_s, spec = plan.apply_save(0, f, table)
+    spec2 = plan.field_spectra(0, f)
+    torch.cuda.synchronize()
+    assert torch.equal(out_a, out_s)
+    assert torch.equal(spec, spec2)
+
+
+@pytest.mark.parametrize("nx,ny,m,batch", FUSED)
+def test_fused_backward_matches_oracle(nx, ny, m, batch, rng):
+    case(f"fused backward {nx}x{ny}x{m} fp32 batch={batch}: dL/df and sum_b dL/dP vs oracle")
+    prof = rng.uniform(0, 1, size=(10, m))
+    f = sample_fields(27, batch, 8, nx, ny, m)
+    g = rng.standard_normal((batch, m, ny, nx))
+    plan = se2.Plan([(nx, ny, m)], dtype="f32")
+    table = plan.coeffs(0, [se2.RadialProfile(_dev(prof, torch.float64), 0.4, norm=2)])
+    spec = plan.field_spectra(0, _dev(f, torch.float32))
+    gf, gp = plan.backward(0, _dev(g, torch.float32), table, spec)
+    gf = gf.cpu().numpy().astype(np.float64)
+    gp = gp.cpu().numpy().astype(np.float64)
+    ref_t = ffc(ok.radial_profile(nx, ny, m, prof, 0.4))
+    tol = tol32(nx * ny * m)
+    for b in range(batch):
+        e = rel_l2(gf[b], oc.conv_with_coeffs(g[b], np.conj(ref_t)))
+        print(f"  grad_f field {b}: {e:.2e}", flush=True)
+        assert e <= tol
+    ref_p = sum(OA.grad_kernel_samples(f[b], g[b]) for b in range(batch))
+    e = rel_l2(gp, ref_p)
+    print(f"  grad_P (batch sum): {e:.2e}", flush=True)
+    assert e <= tol
+
+
+@pytest.mark.parametrize("checkpoint", [True, False])
+def test_fused_autograd_matches_oracle(checkpoint, rng):
+    case(f"autograd through the fused backward, 64x64x16 fp32 checkpoint={checkpoint}")
+    nx = ny = 64
+    m, batch, nk, rmax = 16, 3, 10, 0.4
+    f, prof, target = _loss_parts(nx, ny, m, batch, nk, rmax, 28, rng)
+    plan = se2.Plan([(nx, ny, m)], dtype="f32")
+    assert plan.fused_supported(0)
+    fd = _dev(f, torch.float32).requires_grad_(True)
+    pd = _dev(prof, torch.float64).requires_grad_(True)
+    out = radial_profile_conv(fd, pd, plan, 0, rmax, checkpoint)
+    loss = ((out.double() - _dev(target, torch.float64)) ** 2).sum()
+    loss.backward()
+    ref_loss, ref_gf, ref_gprof = _oracle_grads(f, prof, target, nk, rmax)
+    e_loss = abs(loss.item() - ref_loss) / abs(ref_loss)
+    e_gf = rel_l2(fd.grad.cpu().numpy(), ref_gf)
+    e_gp = rel_l2(pd.grad.cpu().numpy(), ref_gprof)
+    print(f"  loss {e_loss:.2e} grad_f {e_gf:.2e} grad_prof {e_gp:.2e}", flush=True)
+    assert e_loss <= 1e-4 and e_gf <= 1e-4 and e_gp <= 1e-4
+
+
+def test_fused_checkpoint_and_recompute_identical(rng):
+    case("fused backward: checkpoint vs recompute bitwise identical, 64x64x16 fp32")
+    nx = ny = 64
+    m, batch, nk, rmax = 16, 2, 8, 0.4
+    f, prof, target = _loss_parts(nx, ny, m, batch, nk, rmax, 29, rng)
+    plan = se2.Plan([(nx, ny, m)], dtype="f32")
+    grads = []
+    for ck in (True, False):
+        fd = _dev(f, torch.float32).requires_grad_(True)
+        pd = _dev(prof, torch.float64).requires_grad_(True)
+        out = radial_profile_conv(fd, pd, plan, 0, rmax, ck)
+        ((out.double() - _dev(target, torch.float64)) ** 2).sum().backward()
+        grads.append((fd.grad.clone(), pd.grad.clone()))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
