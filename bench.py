@@ -166,7 +166,8 @@ def run_c4(steps, warmup):
             fd = f.detach().requires_grad_(True)
             pd = prof.detach().requires_grad_(True)
             out = radial_profile_conv(fd, pd, plan, 0, rmax, checkpoint=ck)
-            loss = ((out - target) ** 2).sum()
+            # ||out - target||^2 (sum over batch and grid), one fused kernel each way
+            loss = torch.nn.functional.mse_loss(out, target, reduction="sum")
             loss.backward()
             return loss
         for _ in range(warmup):

@@ -53,7 +53,7 @@ xt_full(FullFastArgs a) {
     float2* buf = reinterpret_cast<float2*>(smem_raw);  // RC x P
     float2* tw_f = buf + RC * P;                         // [k1][t] = w_NX^{t k1}
     float2* tw_i = tw_f + NX;                            // [t][k1]
-    float2* twm = tw_i + NX;                             // w_M^k
+    float2* twl = tw_i + NX;                             // TPC == 2: [h][k] = 1 (h = 0), w_M^k (h = 1)
     const int tid = threadIdx.x;
     for (int i = tid; i < NX; i += NT) {
         const int k1 = i / R2, t = i - k1 * R2;
@@ -61,7 +61,8 @@ xt_full(FullFastArgs a) {
         tw_f[k1 * R2 + t] = w;
         tw_i[t * 16 + k1] = w;
     }
-    for (int i = tid; i < M; i += NT) twm[i] = a.twt[i];
+    if (TPC == 2)
+        for (int i = tid; i < M; i += NT) twl[i] = i < MV ? make_float2(1.f, 0.f) : a.twt[i - MV];
     __syncthreads();
 
     const int pair = blockIdx.x / a.ny;
@@ -75,15 +76,18 @@ xt_full(FullFastArgs a) {
     float2 v[MV];
 
     if constexpr (DIR == 0) {
+        // a lone last field is paired with zero (its row is read twice and masked, which
+        // keeps the loads free of per-load branches)
         const float* __restrict__ in0 = a.in + (long long)(2 * pair) * a.n + (long long)y * NX;
-        const float* __restrict__ in1 = has_b ? in0 + a.n : nullptr;
+        const float* __restrict__ in1 = has_b ? in0 + a.n : in0;
+        const float im_mask = has_b ? 1.f : 0.f;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int off = (g + G * i) * pl + t + R2 * r;
                 w[i][r] = make_float2(__builtin_nontemporal_load(in0 + off),
-                                      in1 ? __builtin_nontemporal_load(in1 + off) : 0.f);
+                                      im_mask * __builtin_nontemporal_load(in1 + off));
             }
         }
         // forward DFT along x of each row; afterwards w[i][j * R2 + k2] = X[k1 + 16 k2], k1 = CC t + j
@@ -131,14 +135,16 @@ xt_full(FullFastArgs a) {
             RegDFT<M, false, float>::run(v);
         } else {
             // theta = hh + 2 s: Y_hh = DFT over s; X[k] = Y_0 + w^k Y_1, X[k + M/2] = Y_0 - w^k Y_1
+            // Lane h first multiplies its own value by twl[h][k] (1 or w^k); with o the
+            // neighbour's product, lane 0 keeps b + o and lane 1 o - b (no divergent code).
             RegDFT<MV, false, float>::run(v);
+            const float sg = hh ? -1.f : 1.f;
+            const float2* twh = twl + hh * MV;
 #pragma unroll
             for (int k = 0; k < MV; ++k) {
-                const float2 o = swap_lane1(v[k]);
-                const float2 y0 = hh ? o : v[k];
-                const float2 y1 = hh ? v[k] : o;
-                const float2 c = mul<float>(y1, twm[k]);
-                v[k] = hh ? sub<float>(y0, c) : add<float>(y0, c);
+                const float2 b = mul<float>(v[k], twh[k]);
+                const float2 o = swap_lane1(b);
+                v[k] = make_float2(fmaf(sg, b.x, o.x), fmaf(sg, b.y, o.y));
             }
         }
         float* __restrict__ o_re = a.out + (long long)(2 * pair) * a.n + (long long)y * NX;
@@ -166,10 +172,15 @@ xt_full(FullFastArgs a) {
         } else {
             // lane 0 holds Z[k], lane 1 Z[k + M/2]: U_0 = Z[k] + Z[k + M/2],
             // U_1 = conj(w^k) (Z[k] - Z[k + M/2]); then inverse DFT over s gives theta = hh + 2 s
+            // d = own sign + neighbour (lane 0: Z[k] + Z[k + M/2], lane 1: Z[k] - Z[k + M/2]),
+            // then lane h multiplies by conj(twl[h][k]) (1 or conj(w^k))
+            const float sg = hh ? -1.f : 1.f;
+            const float2* twh = twl + hh * MV;
 #pragma unroll
             for (int k = 0; k < MV; ++k) {
                 const float2 o = swap_lane1(v[k]);
-                v[k] = hh ? mulc<float>(sub<float>(o, v[k]), twm[k]) : add<float>(v[k], o);
+                const float2 d = make_float2(fmaf(sg, v[k].x, o.x), fmaf(sg, v[k].y, o.y));
+                v[k] = mulc<float>(d, twh[k]);
             }
             RegDFT<MV, true, float>::run(v);
         }
@@ -217,15 +228,17 @@ xt_full(FullFastArgs a) {
             for (int k1 = 0; k1 < 16; ++k1) w[i][k1] = row[xpos<R2>(k1, t)];
             dft16<float, true>(w[i]);
         }
+        // the imaginary part of a lone last field (rounding only) goes back to its
+        // workspace plane, which this block has finished reading
         float* __restrict__ out0 = a.out + (long long)(2 * pair) * a.n + (long long)y * NX;
-        float* __restrict__ out1 = has_b ? out0 + a.n : nullptr;
+        float* __restrict__ out1 = has_b ? out0 + a.n : a.lone + (long long)y * NX;
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int off = (g + G * i) * pl + t + R2 * r;
                 __builtin_nontemporal_store(w[i][r].x, out0 + off);
-                if (out1) __builtin_nontemporal_store(w[i][r].y, out1 + off);
+                __builtin_nontemporal_store(w[i][r].y, out1 + off);
             }
         }
     }

@@ -190,13 +190,23 @@ __global__ void __launch_bounds__(256) profile_contract_partial_kernel(const dou
     }
 }
 
-// grad[q][l] = sum_s part[s][q][l], splits in increasing order (deterministic).
-__global__ void profile_contract_reduce_kernel(const double* part, double* grad, int nsplit, long long nout) {
-    for (long long o = blockIdx.x * (long long)blockDim.x + threadIdx.x; o < nout;
-         o += (long long)gridDim.x * blockDim.x) {
-        double acc = 0.0;
-        for (int sp = 0; sp < nsplit; ++sp) acc += part[(long long)sp * nout + o];
-        grad[o] = acc;
+// grad[o] = sum_s part[s][o] (o = q m + l): 16 outputs per block, split s summed by
+// thread group s mod 16 in increasing order, then the 16 group sums in order
+// (a fixed summation order: bitwise reproducible).
+__global__ void __launch_bounds__(256) profile_contract_reduce_kernel(const double* part, double* grad, int nsplit,
+                                                                      long long nout) {
+    __shared__ double red[16][17];
+    const int oi = threadIdx.x % 16, grp = threadIdx.x / 16;
+    const long long o = (long long)blockIdx.x * 16 + oi;
+    double acc = 0.0;
+    if (o < nout)
+        for (int sp = grp; sp < nsplit; sp += 16) acc += part[(long long)sp * nout + o];
+    red[grp][oi] = acc;
+    __syncthreads();
+    if (grp == 0 && o < nout) {
+        double t = 0.0;
+        for (int gi = 0; gi < 16; ++gi) t += red[gi][oi];
+        grad[o] = t;
     }
 }
 
@@ -224,7 +234,7 @@ hipError_t launch_profile_grad(const void* g, int batch, bool dbl, int n_knots, 
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long nout = (long long)n_knots * m;
-    hipLaunchKernelGGL(profile_contract_reduce_kernel, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, part,
+    hipLaunchKernelGGL(profile_contract_reduce_kernel, dim3((unsigned)((nout + 15) / 16)), dim3(256), 0, s, part,
                        grad, nsplit, nout);
     return hipGetLastError();
 }

@@ -10,7 +10,7 @@ hipError_t launch_accumulate_pair(const void* zre, const void* zim, const void* 
                                   void* accim, int nx, int ny, int m, double scale, int first, bool dbl,
                                   hipStream_t s);
 // points per split of the profile-gradient contraction
-constexpr int kProfileChunk = 256;
+constexpr int kProfileChunk = 64;
 int profile_grad_splits(long long npts);
 // basis[q][j][i]: hat function q (knots r_q = q r_max / (n_knots - 1)) at |x_ij|, lattice-periodized
 hipError_t launch_profile_basis(double* basis, int n_knots, double r_max, int nx, int ny, hipStream_t s);
