@@ -141,3 +141,22 @@ def test_corrupt_tuning_cache_falls_back_to_defaults(tmp_path, monkeypatch):
     res = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True)
     assert res.returncode == 0, res.stderr
     assert res.stdout.strip() == str(8 * (32 + 32 + 16))
+
+
+def test_fused_entry_points_validate_on_host():
+    lib = L.load()
+    p = se2.Plan([(64, 64, 16)], dtype="f32", host_only=True)
+    h = p.handle
+    assert lib.se2conv_fused_supported(None, 0) == 0
+    assert lib.se2conv_fused_supported(h, 0) == 0          # host-only plans run nothing
+    assert lib.se2conv_fused_supported(h, 3) == 0
+    assert lib.se2conv_field_spectra(None, 0, 256, 1, 512, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_field_spectra(h, 2, 256, 1, 512, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_field_spectra(h, 0, 256, 1, 512, None) == L.ERR_DEVICE
+    # argument checks come before the device check
+    assert lib.se2conv_apply_save(h, 0, 256, 4096, 512, 0, 1 << 30, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_apply_save(h, 0, None, 4096, 512, 1, 1 << 30, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_apply_save(h, 0, 1 << 20, 4096, 1 << 24, 1, 1 << 30, None) == L.ERR_DEVICE
+    assert lib.se2conv_backward(h, 0, 1 << 20, 4096, 1 << 30, 0, 1 << 24, 1 << 28, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_backward(h, 0, 1 << 20, 4096, 1 << 30, 1, 1 << 24, 1 << 28, None) == L.ERR_DEVICE
+    assert b"host-only" in lib.se2conv_last_error()
