@@ -412,7 +412,9 @@ __global__ void __launch_bounds__(RowGeom<NX>::NT) x_rows_fast(FastSepArgs a) {
 #pragma unroll
     for (int r = 0; r < R1; ++r) {
         const int off = g * pl + t + R2 * r;
-        w[r] = make_float2(__builtin_nontemporal_load(in0 + off), __builtin_nontemporal_load(in1 + off));
+        // plain loads: with 64-byte row segments a streaming hint re-fetched the other
+        // half of each line (1.32x the algorithmic read bytes, and slower)
+        w[r] = make_float2(in0[off], in1[off]);
     }
     RegDFT<R1, false, float>::run(w);
 #pragma unroll
