@@ -118,10 +118,21 @@ int threads_for(long long P, bool d) {
 // Tunable launch parameters of one shape (se2conv_autotune picks them by timing).
 struct Schedule {
     int pencil_w = 16;          // generic pencils: columns per tile (clamped to the LDS/thread limits)
-    int fast_blocks_per_cu = 4; // persistent fast y pencil
+    int fast_blocks_per_cu = 8; // persistent register pencils (capped by occupancy)
     int xrow_points = 4096;     // three-pass schedule: points per x-row tile
     bool tuned = false;
 };
+
+// Untuned defaults per dtype (the autotuner's usual picks on MI355X: narrower generic
+// pencils and longer x-row tiles for FP64).
+Schedule default_schedule(bool d) {
+    Schedule s;
+    if (d) {
+        s.pencil_w = 8;
+        s.xrow_points = 8192;
+    }
+    return s;
+}
 
 struct TableRec {
     int32_t shape_idx;
@@ -249,10 +260,10 @@ int rows_for_xpass(const se2conv_shape& s, int points = 4096) {
 
 // The schedule of a shape (shapes are looked up by value: passes receive the shape).
 const Schedule& sched_of(const se2conv_plan_s* p, const se2conv_shape& s) {
-    static const Schedule dflt;
+    static const Schedule dflt32 = default_schedule(false), dflt64 = default_schedule(true);
     for (size_t i = 0; i < p->shapes.size(); ++i)
         if (p->shapes[i].nx == s.nx && p->shapes[i].ny == s.ny && p->shapes[i].m == s.m) return p->sched[i];
-    return dflt;
+    return dbl(p) ? dflt64 : dflt32;
 }
 
 int pencil_width(int ncols, int L, bool d, int want = 16) {
@@ -965,7 +976,7 @@ se2conv_status se2conv_plan(const se2conv_shape* shapes, int32_t n_shapes, se2co
     p->dtype = dtype;
     p->flags = flags;
     p->shapes.assign(shapes, shapes + n_shapes);
-    p->sched.assign(n_shapes, Schedule());
+    p->sched.assign(n_shapes, default_schedule(dtype == SE2CONV_F64));
     load_tune_cache(p);
     if (flags & SE2CONV_PLAN_HOST_ONLY) {
         p->host_only = true;
@@ -1328,7 +1339,7 @@ se2conv_status se2conv_autotune(se2conv_plan_t p, int32_t shape_idx, int32_t bat
     // width and, without the slab, x-row tile size
     const bool fast_lines = !generic && (two_pass ? pencil_fast_supported(s.nx, s.ny)
                                                   : three_pass_fast_supported(s.nx, s.ny, s.m));
-    const Schedule dflt;
+    const Schedule dflt = default_schedule(d);
     std::vector<int> widths = {dflt.pencil_w}, blocks = {dflt.fast_blocks_per_cu}, xrows = {dflt.xrow_points};
     if (fast_lines) blocks = {2, 4, 8};
     else widths = {4, 8, 16, 32};
