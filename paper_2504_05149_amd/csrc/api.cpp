@@ -175,6 +175,11 @@ struct se2conv_plan_s {
     double basis_rmax = 0.0;
     std::unordered_map<uintptr_t, TableRec> tables;
     std::vector<SubmissionRec> subs;
+    // concurrent shape classes in se2conv_chain: auxiliary streams (default priority)
+    // and the fork / join events around them, created on first use
+    std::vector<hipStream_t> aux;
+    hipEvent_t ev_fork = nullptr;
+    std::vector<hipEvent_t> ev_join;
     std::mutex mu;
     // pass timing (SE2CONV_TIMING)
     bool timing = false;
@@ -1039,6 +1044,9 @@ se2conv_status se2conv_plan_destroy(se2conv_plan_t p) {
             if (g.d_items) (void)hipFree(g.d_items);
         }
         for (auto ev : p->ev_pool) (void)hipEventDestroy(ev);
+        for (auto st : p->aux) (void)hipStreamDestroy(st);
+        for (auto ev : p->ev_join) (void)hipEventDestroy(ev);
+        if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
         for (auto ev : p->ev_rec) (void)hipEventDestroy(ev);
         for (auto& kv : p->tw32) (void)hipFree(kv.second);
         for (auto& kv : p->tw64) (void)hipFree(kv.second);
@@ -1613,6 +1621,37 @@ se2conv_status se2conv_backward(se2conv_plan_t p, int32_t shape_idx, const void*
     return ok();
 }
 
+namespace {
+
+constexpr int kChainStreams = 4;
+
+// Auxiliary streams and events of the plan (created once, under the plan mutex).
+se2conv_status ensure_aux_streams(se2conv_plan_s* p) {
+    std::lock_guard<std::mutex> g(p->mu);
+    if (!p->aux.empty()) return SE2CONV_OK;
+    std::vector<hipStream_t> st(kChainStreams, nullptr);
+    std::vector<hipEvent_t> ev(kChainStreams, nullptr);
+    hipEvent_t fork = nullptr;
+    bool good = hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; good && i < kChainStreams; ++i)
+        good = hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) == hipSuccess;
+    if (!good) {
+        for (auto x : st)
+            if (x) (void)hipStreamDestroy(x);
+        for (auto x : ev)
+            if (x) (void)hipEventDestroy(x);
+        if (fork) (void)hipEventDestroy(fork);
+        return fail(SE2CONV_ERR_DEVICE, "could not create the chain streams");
+    }
+    p->aux = st;
+    p->ev_join = ev;
+    p->ev_fork = fork;
+    return SE2CONV_OK;
+}
+
+}  // namespace
+
 se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int32_t n_probs, uint32_t flags,
                              hipStream_t stream) {
     if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
@@ -1699,13 +1738,49 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
         p->subs.push_back(nr);
         rec = &p->subs.back();
     }
+    // Shape classes are independent: with several of them (and no per-pass timing) they run
+    // concurrently on the plan's auxiliary streams, forked from and joined back into the
+    // caller's stream (under capture this makes parallel branches of the graph).
+    const int ngroups = (int)rec->groups.size();
+    const bool fan_out = ngroups > 1 && !(flags & SE2CONV_TIMING);
+    if (fan_out) {
+        se2conv_status r = ensure_aux_streams(p);
+        if (r != SE2CONV_OK) return r;
+    }
     auto submit = [&]() -> se2conv_status {
         // every separable problem: one launch per pass per shape group
-        for (size_t gi = 0; gi < rec->groups.size(); ++gi) {
-            const int sidx = rec->groups[gi].first;
-            const SepItem* items = reinterpret_cast<const SepItem*>(rec->d_items) + rec->groups[gi].second;
-            se2conv_status r = enqueue_sep_items(p, p->shapes[sidx], items, rec->group_counts[gi], conj, stream);
-            if (r != SE2CONV_OK) return r;
+        if (fan_out) {
+            // largest classes first, dealt round-robin over the streams
+            std::vector<int> order(ngroups);
+            for (int gi = 0; gi < ngroups; ++gi) order[gi] = gi;
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+                const se2conv_shape& sa = p->shapes[rec->groups[a].first];
+                const se2conv_shape& sb = p->shapes[rec->groups[b].first];
+                return (long long)sa.nx * sa.ny * sa.m * rec->group_counts[a] >
+                       (long long)sb.nx * sb.ny * sb.m * rec->group_counts[b];
+            });
+            const int nst = std::min(ngroups, kChainStreams);
+            HIPCHK(hipEventRecord(p->ev_fork, stream));
+            for (int k = 0; k < nst; ++k) HIPCHK(hipStreamWaitEvent(p->aux[k], p->ev_fork, 0));
+            for (int oi = 0; oi < ngroups; ++oi) {
+                const int gi = order[oi];
+                const int sidx = rec->groups[gi].first;
+                const SepItem* items = reinterpret_cast<const SepItem*>(rec->d_items) + rec->groups[gi].second;
+                se2conv_status r =
+                    enqueue_sep_items(p, p->shapes[sidx], items, rec->group_counts[gi], conj, p->aux[oi % nst]);
+                if (r != SE2CONV_OK) return r;
+            }
+            for (int k = 0; k < nst; ++k) {
+                HIPCHK(hipEventRecord(p->ev_join[k], p->aux[k]));
+                HIPCHK(hipStreamWaitEvent(stream, p->ev_join[k], 0));
+            }
+        } else {
+            for (int gi = 0; gi < ngroups; ++gi) {
+                const int sidx = rec->groups[gi].first;
+                const SepItem* items = reinterpret_cast<const SepItem*>(rec->d_items) + rec->groups[gi].second;
+                se2conv_status r = enqueue_sep_items(p, p->shapes[sidx], items, rec->group_counts[gi], conj, stream);
+                if (r != SE2CONV_OK) return r;
+            }
         }
         // problems with full tables: one submission each
         for (int i = 0; i < n_probs; ++i) {
