@@ -20,6 +20,17 @@ __device__ __forceinline__ int xpos(int k1, int t) {
     return xpos_line<16, R2>(k1, t);
 }
 
+// Synchronisation of the lanes of one wavefront around an LDS exchange among them:
+// release / acquire fences at wavefront scope and a wave barrier, so neither the
+// compiler nor the hardware moves this wave's LDS reads ahead of its earlier writes.
+// Used where every line of an exchange lives in one wavefront (R2 <= 16 consecutive
+// lanes), instead of a workgroup barrier.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // scale * prod_j tabs[j][i] (conjugated for the adjoint)
 __device__ __forceinline__ float2 chain_factor(const void* const* tabs, int ntab, int i, float scale, int conj) {
     float2 v = make_float2(scale, 0.f);

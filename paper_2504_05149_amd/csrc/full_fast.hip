@@ -441,8 +441,8 @@ __global__ void __launch_bounds__(FullLineGeom<NY>::NT) y_full(FullFastArgs a) {
 
 // ------------------------------------------------------------------ dispatch
 bool full_fast_supported(int nx, int ny, int m) {
-    return (nx == 64 || nx == 128 || nx == 256) && (m == 16 || m == 32 || m == 64) &&
-           (ny == 64 || ny == 128 || ny == 256 || ny == 512);
+    return (nx == 32 || nx == 64 || nx == 128 || nx == 256) && (m == 16 || m == 32 || m == 64) &&
+           (ny == 32 || ny == 64 || ny == 128 || ny == 256 || ny == 512);
 }
 
 template <int NX, int M, int DIR>
@@ -459,6 +459,7 @@ static hipError_t launch_xt_full_t(const FullFastArgs& a, hipStream_t s) {
 
 template <int DIR>
 static hipError_t launch_xt_full(const FullFastArgs& a, hipStream_t s) {
+    SE2C_XT_FULL_CASE(32, 16) SE2C_XT_FULL_CASE(32, 32) SE2C_XT_FULL_CASE(32, 64)
     SE2C_XT_FULL_CASE(64, 16) SE2C_XT_FULL_CASE(64, 32) SE2C_XT_FULL_CASE(64, 64)
     SE2C_XT_FULL_CASE(128, 16) SE2C_XT_FULL_CASE(128, 32) SE2C_XT_FULL_CASE(128, 64)
     SE2C_XT_FULL_CASE(256, 16) SE2C_XT_FULL_CASE(256, 32) SE2C_XT_FULL_CASE(256, 64)
@@ -479,6 +480,7 @@ static hipError_t launch_y_full_t(const FullFastArgs& a, hipStream_t s) {
 
 template <int MODE>
 static hipError_t launch_y_full_mode(const FullFastArgs& a, hipStream_t s) {
+    if (a.ny == 32) return launch_y_full_t<32, MODE>(a, s);
     if (a.ny == 64) return launch_y_full_t<64, MODE>(a, s);
     if (a.ny == 128) return launch_y_full_t<128, MODE>(a, s);
     if (a.ny == 256) return launch_y_full_t<256, MODE>(a, s);
@@ -505,10 +507,11 @@ hipError_t launch_y_full_backward(const FullFastArgs& a, hipStream_t s) { return
 
 hipError_t prepare_full_fast_kernels() {
     hipError_t e;
+    SE2C_XT_FULL_ATTR(32, 16) SE2C_XT_FULL_ATTR(32, 32) SE2C_XT_FULL_ATTR(32, 64)
     SE2C_XT_FULL_ATTR(64, 16) SE2C_XT_FULL_ATTR(64, 32) SE2C_XT_FULL_ATTR(64, 64)
     SE2C_XT_FULL_ATTR(128, 16) SE2C_XT_FULL_ATTR(128, 32) SE2C_XT_FULL_ATTR(128, 64)
     SE2C_XT_FULL_ATTR(256, 16) SE2C_XT_FULL_ATTR(256, 32) SE2C_XT_FULL_ATTR(256, 64)
-    SE2C_Y_FULL_ATTR(64) SE2C_Y_FULL_ATTR(128) SE2C_Y_FULL_ATTR(256) SE2C_Y_FULL_ATTR(512)
+    SE2C_Y_FULL_ATTR(32) SE2C_Y_FULL_ATTR(64) SE2C_Y_FULL_ATTR(128) SE2C_Y_FULL_ATTR(256) SE2C_Y_FULL_ATTR(512)
     return hipSuccess;
 }
 

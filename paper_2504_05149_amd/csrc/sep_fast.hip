@@ -514,15 +514,15 @@ static hipError_t launch_rows_fast_t(const FastSepArgs& a, hipStream_t s) {
 }
 
 bool slab_fast_supported(int nx, int m) {
-    return (nx == 64 || nx == 128 || nx == 256) && (m == 16 || m == 32 || m == 64);
+    return (nx == 32 || nx == 64 || nx == 128 || nx == 256) && (m == 16 || m == 32 || m == 64);
 }
 
-static bool line_len_ok(int l) { return l == 64 || l == 128 || l == 256 || l == 512; }
+static bool line_len_ok(int l) { return l == 32 || l == 64 || l == 128 || l == 256 || l == 512; }
 
 bool pencil_fast_supported(int nx, int ny) { return line_len_ok(ny) && nx % 32 == 0; }
 
 bool three_pass_fast_supported(int nx, int ny, int m) {
-    return line_len_ok(nx) && line_len_ok(ny) && line_len_ok(m);
+    return nx >= 64 && line_len_ok(nx) && line_len_ok(ny) && line_len_ok(m);
 }
 
 #define SE2C_SLAB_CASE(NX_, M_) \
@@ -530,6 +530,7 @@ bool three_pass_fast_supported(int nx, int ny, int m) {
 
 hipError_t launch_slab_fast(const FastSepArgs& a, hipStream_t s) {
     const int nblocks = (a.ny / 2) * a.nitems;  // one block per y-pair slab
+    SE2C_SLAB_CASE(32, 16) SE2C_SLAB_CASE(32, 32) SE2C_SLAB_CASE(32, 64)
     SE2C_SLAB_CASE(64, 16) SE2C_SLAB_CASE(64, 32) SE2C_SLAB_CASE(64, 64)
     SE2C_SLAB_CASE(128, 16) SE2C_SLAB_CASE(128, 32) SE2C_SLAB_CASE(128, 64)
     SE2C_SLAB_CASE(256, 16) SE2C_SLAB_CASE(256, 32) SE2C_SLAB_CASE(256, 64)
@@ -538,6 +539,7 @@ hipError_t launch_slab_fast(const FastSepArgs& a, hipStream_t s) {
 
 hipError_t launch_pencil_fast(const FastSepArgs& a, hipStream_t s) {
     const int L = a.axis == 1 ? a.ny : a.m;
+    if (L == 32) return launch_pencil_fast_t<32>(a, s);
     if (L == 64) return launch_pencil_fast_t<64>(a, s);
     if (L == 128) return launch_pencil_fast_t<128>(a, s);
     if (L == 256) return launch_pencil_fast_t<256>(a, s);
@@ -568,10 +570,14 @@ hipError_t launch_rows_fast(const FastSepArgs& a, hipStream_t s) {
 
 hipError_t prepare_fast_kernels() {
     hipError_t e;
+    SE2C_SLAB_ATTR(32, 16) SE2C_SLAB_ATTR(32, 32) SE2C_SLAB_ATTR(32, 64)
     SE2C_SLAB_ATTR(64, 16) SE2C_SLAB_ATTR(64, 32) SE2C_SLAB_ATTR(64, 64)
     SE2C_SLAB_ATTR(128, 16) SE2C_SLAB_ATTR(128, 32) SE2C_SLAB_ATTR(128, 64)
     SE2C_SLAB_ATTR(256, 16) SE2C_SLAB_ATTR(256, 32) SE2C_SLAB_ATTR(256, 64)
     SE2C_LINE_ATTR(64) SE2C_LINE_ATTR(128) SE2C_LINE_ATTR(256) SE2C_LINE_ATTR(512)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(line_pencil_fast<32>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)pencil_fast_lds<32>());
+    if (e != hipSuccess) return e;
     return hipSuccess;
 }
 

@@ -168,7 +168,9 @@ def test_headline_256x256x64_batch16_chain8_sampled():
                                      # slab too large for LDS: x rows + y pencils + theta pencils
                                      (512, 64, 64), (128, 64, 256), (64, 64, 512),
                                      # 512-point y pencils after the slab
-                                     (64, 512, 64)])
+                                     (64, 512, 64),
+                                     # 32-point lines
+                                     (32, 32, 16), (32, 64, 64), (64, 32, 32)])
 def test_register_kernels_match_generic_and_oracle(nx, ny, m):
     batch = 3 if nx * ny * m < (1 << 20) else 2
     case(f"register vs generic kernels {nx}x{ny}x{m} fp32 batch {batch}, chain of 3, adjoint too")
@@ -218,7 +220,7 @@ def test_full_path_parity(dt, batch, rng):
 
 
 @pytest.mark.parametrize("nx,ny,m,batch", [(64, 64, 16, 3), (128, 64, 32, 2), (256, 128, 64, 3), (64, 512, 64, 1),
-                                           (256, 256, 64, 2)])
+                                           (256, 256, 64, 2), (32, 32, 64, 3), (32, 64, 16, 2)])
 def test_full_path_register_kernels(nx, ny, m, batch, rng):
     case(f"full-table register kernels {nx}x{ny}x{m} fp32 batch={batch}: profile x Gauss-vM chain, adjoint, "
          "generic kernels and oracle")
