@@ -4,22 +4,28 @@
 // The separable product commutes with transforms along the other axes, so the
 // convolution factorises into 1-D circular convolutions along x, y and theta
 // (each: DFT, product with the 1-D factor, inverse DFT; the 3-D DFT of eq.
-// (3DFT) is the composition of the three 1-D DFTs).  Two passes over HBM:
+// (3DFT) is the composition of the three 1-D DFTs).  Two passes over HBM when
+// an x-theta slab fits in LDS, three otherwise:
 //
-// xt_slab_fast<NX, M>  one block per y-pair (rows 2s, 2s+1 packed as re/im):
+// xt_slab_fast<NX, M, TPC>  one block per y-pair (rows 2s, 2s+1 packed as re/im):
 //   1. load the pair in row layout: thread (g, t) holds x = t + R2 r (r < 16) of
-//      rows theta = g + 16 i;
+//      rows theta = g + G i;
 //   2. x convolution as a 16 x R2 decomposition: radix-16 DFT in registers,
 //      twiddles w_NX^{t k1}, one LDS exchange (XOR-swizzled, bank-conflict
 //      free), radix-R2 DFT, product with Tx/NX, and the mirror-image inverse;
 //   3. transpose rows -> columns through LDS in chunks of 32 rows;
-//   4. theta convolution of a whole column in registers (one column per thread);
+//   4. theta convolution of a whole column in registers (TPC = 2: the column is
+//      split over a lane pair, and the radix-2 step, product and inverse step
+//      are one 2 x 2 matrix per frequency);
 //   5. store columns (each wave writes 1 KB contiguous per theta row).
 //   Every input and output byte is touched once, so the pass streams with
 //   nontemporal loads and stores (measured faster for this pass and for the
 //   y pass that reads its output).
-// y_pencil_fast<NY>    one block per 16 adjacent x-pairs (float2 columns) at one theta:
-//   the same 16 x R2 scheme along y, product with Ty/NY.
+// line_pencil_fast<L>  16 adjacent x-pairs (float2 columns) x L points along y or
+//   theta: the same R1 x R2 scheme (R1 = 16, or 32 for L = 512), product with
+//   Ty/NY or Tt/M; persistent, with the next tile's loads issued early.
+// x_rows_fast<NX>  three-pass schedule: the slab's x convolution alone on 16
+//   theta-rows of one y-pair per block (NX up to 512).
 #include "fast_common.hpp"
 #include "regfft.hpp"
 #include "sep_fast.hpp"
