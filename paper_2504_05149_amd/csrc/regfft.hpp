@@ -1,10 +1,11 @@
 // In-register DFT codelets with compile-time twiddles (FP32/FP64).
 //
-// dft_reg<N, INV>(v): natural-order in, natural-order out, v[0..N-1] held in
-// registers (every index is a compile-time constant after unrolling).  N = 2, 4,
-// 8, 16 use the hand-written butterflies of fft_device.hpp; N = 16 * B (B = 2, 4)
-// is composed as B radix-16 DFTs on the stride-B subsequences, twiddles
-// w_N^{b k1}, then 16 radix-B DFTs.  The codelet twiddles are evaluated at compile
+// RegDFT<N, INV>(v): natural-order in, natural-order out, v[0..N-1] held in
+// registers (every index is a compile-time constant after unrolling).  N = 2, 3, 4,
+// 8, 16 use the hand-written butterflies of fft_device.hpp; composite N = A * B
+// (A = 16, 8, 4 or 2; B = N / A, e.g. 32 = 16 x 2, 96 = 16 x 6, 6 = 2 x 3) is composed
+// as B A-point DFTs on the stride-B subsequences, twiddles w_N^{b k1}, then A B-point
+// DFTs.  The codelet twiddles are evaluated at compile
 // time in double (Taylor series on a quarter turn) and rounded to T.
 #pragma once
 #include <type_traits>
@@ -60,20 +61,29 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
+// Composite size N = A * B: A-point DFTs on the B stride-B subsequences, twiddles
+// w_N^{b k1}, then A B-point DFTs (decimation in time).  A is 16 when 16 divides N,
+// else the largest of 8, 4, 2 dividing N; sizes 3 * 2^k end in the radix-3 codelet.
+template <int N> struct RegSplit {
+    static constexpr int A = (N % 16 == 0) ? 16 : (N % 8 == 0) ? 8 : (N % 4 == 0) ? 4 : 2;
+    static constexpr int B = N / A;
+};
+
 template <int N, bool INV, typename T> struct RegDFT {
     static __device__ __forceinline__ void run(C<T>* v) {
-        static_assert(N % 16 == 0 && N > 16, "composite codelet");
-        constexpr int B = N / 16;
-        C<T> t[B][16];
+        constexpr int A = RegSplit<N>::A;
+        constexpr int B = RegSplit<N>::B;
+        static_assert(A * B == N && B > 1, "composite codelet");
+        C<T> t[B][A];
 #pragma unroll
         for (int b = 0; b < B; ++b) {
 #pragma unroll
-            for (int a = 0; a < 16; ++a) t[b][a] = v[b + B * a];
-            dft16<T, INV>(t[b]);
+            for (int a = 0; a < A; ++a) t[b][a] = v[b + B * a];
+            RegDFT<A, INV, T>::run(t[b]);
         }
         static_for<1, B>([&](auto bc) {
             constexpr int b = decltype(bc)::value;
-            static_for<1, 16>([&](auto kc) {
+            static_for<1, A>([&](auto kc) {
                 constexpr int k1 = decltype(kc)::value;
                 constexpr double c = cos2pi(b * k1, N);
                 constexpr double s = sin2pi(b * k1, N);
@@ -81,15 +91,18 @@ template <int N, bool INV, typename T> struct RegDFT {
             });
         });
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) {
+        for (int k1 = 0; k1 < A; ++k1) {
             C<T> u[B];
 #pragma unroll
             for (int b = 0; b < B; ++b) u[b] = t[b][k1];
             RegDFT<B, INV, T>::run(u);
 #pragma unroll
-            for (int k2 = 0; k2 < B; ++k2) v[k1 + 16 * k2] = u[k2];
+            for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = u[k2];
         }
     }
+};
+template <bool INV, typename T> struct RegDFT<3, INV, T> {
+    static __device__ __forceinline__ void run(C<T>* v) { dft3<T, INV>(v); }
 };
 template <bool INV, typename T> struct RegDFT<2, INV, T> {
     static __device__ __forceinline__ void run(C<T>* v) { dft2<T, INV>(v); }

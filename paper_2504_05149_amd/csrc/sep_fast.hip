@@ -32,30 +32,44 @@
 
 namespace se2c {
 
-// TPC = threads per theta column in the column phase (1: the whole column in one
-// thread; 2: even/odd theta split over neighbouring lanes, radix-2 step via DPP).
-// Two workgroups share a CU (LDS); the register cap keeps both resident.
-template <int NX, int M, int TPC>
-__global__ void __launch_bounds__(NX * TPC)
-__attribute__((amdgpu_waves_per_eu(NX * TPC >= 512 ? 4 : (NX * TPC >= 256 ? 2 : 1))))
-xt_slab_fast(FastSepArgs a) {
-    constexpr int NT = NX * TPC;
-    constexpr int R2 = NX / 16;          // second-stage radix along x
-    constexpr int CC = 16 / R2;          // first-stage frequencies owned per thread after the exchange
-    constexpr int G = NT / R2;           // row groups in row layout
-    constexpr int RPT = M / G;           // theta rows per thread in row layout
-    constexpr int RC = M < 32 ? M : 32;  // rows per transpose chunk
-    constexpr int H = M / RC;
+// Slab geometry.  TPC = threads per theta column in the column phase (1: the whole
+// column in one thread; 2: even/odd theta split over neighbouring lanes).  The x phase
+// splits a row into R1 values per thread x R2 lanes (R1 = 16; R1 = NX / 4 for
+// NX = 3 * 2^k) and processes G rows at a time (G the largest power of two that fits
+// the workgroup and a transpose chunk); for NX = 3 * 2^k the remaining lanes (whole
+// wavefronts) idle during the x phase.
+constexpr int pow2_floor(int v) { return v >= 32 ? 32 : v >= 16 ? 16 : v >= 8 ? 8 : v >= 4 ? 4 : v >= 2 ? 2 : 1; }
+
+template <int NX, int M> struct SlabGeom {
+    static constexpr int TPC = M == 64 ? 2 : 1;
+    static constexpr int NT = NX * TPC;
+    static constexpr int R1 = (NX % 3 == 0) ? NX / 4 : 16;
+    static constexpr int R2 = NX / R1;
+    static constexpr int CC = R1 / R2;
+    static constexpr int RC = M < 32 ? M : 32;        // rows per transpose chunk
+    static constexpr int H = M / RC;
+    static constexpr int G = pow2_floor(NT / R2 < RC ? NT / R2 : RC);  // rows per x round
+    static constexpr int RPT = M / G;                  // theta rows per thread in row layout
+    static constexpr int XT = G * R2;                  // lanes of the x phase
     // LDS row pitch (complex): rows g and g + 1 start half a 64-bank cycle apart, so the
     // two row groups of a half-wave never share a bank
-    constexpr int P = NX + (R2 == 16 ? 16 : R2 % 16);
-    constexpr int MV = M / TPC;          // theta values per thread in column layout
-    static_assert(G <= RC && RPT >= 1 && M % G == 0, "tile geometry");
+    static constexpr int P = NX + (R2 == 16 ? 16 : R2 % 16);
+    static constexpr int MV = M / TPC;                 // theta values per thread in column layout
+    static_assert(R1 * R2 == NX && CC * R2 == R1 && M % G == 0 && XT <= NT && XT % 32 == 0, "slab geometry");
+};
+
+template <int NX, int M>
+__global__ void __launch_bounds__((SlabGeom<NX, M>::NT))
+__attribute__((amdgpu_waves_per_eu(SlabGeom<NX, M>::NT >= 512 ? 4 : (SlabGeom<NX, M>::NT >= 256 ? 2 : 1))))
+xt_slab_fast(FastSepArgs a) {
+    using Gm = SlabGeom<NX, M>;
+    constexpr int TPC = Gm::TPC, NT = Gm::NT, R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC, G = Gm::G, RPT = Gm::RPT,
+                  RC = Gm::RC, H = Gm::H, P = Gm::P, MV = Gm::MV, XT = Gm::XT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float2* buf = reinterpret_cast<float2*>(smem_raw);  // RC x P
     float2* tw_f = buf + RC * P;                         // [k1][t] = w_NX^{t k1}
-    float2* tw_i = tw_f + 16 * R2;                       // [t][k1]
-    float2* fx = tw_i + 16 * R2;                         // Tx / NX
+    float2* tw_i = tw_f + NX;                            // [t][k1]
+    float2* fx = tw_i + NX;                              // Tx / NX
     float2* ft = fx + NX;                                // Tt / M (TPC == 1)
     float4* cm = reinterpret_cast<float4*>(ft);          // [hh][k] = (S_k, E_hh,k) (TPC == 2)
     const int tid = threadIdx.x;
@@ -90,11 +104,11 @@ xt_slab_fast(FastSepArgs a) {
             tt[j] = a.tt[j];
         }
     }
-    for (int i = tid; i < 16 * R2; i += NT) {
+    for (int i = tid; i < NX; i += NT) {
         const int k1 = i / R2, t = i - k1 * R2;
         const float2 w = a.tw[t * k1];
         tw_f[k1 * R2 + t] = w;
-        tw_i[t * 16 + k1] = w;
+        tw_i[t * R1 + k1] = w;
     }
     for (int i = tid; i < NX; i += NT) fx[i] = chain_factor(tx, ntab, i, 1.0f / NX, a.conj_tab);
     if constexpr (TPC == 1) {
@@ -115,57 +129,70 @@ xt_slab_fast(FastSepArgs a) {
     __syncthreads();
 
     const int t = tid % R2, g = tid / R2;
+    const bool xlane = XT == NT || tid < XT;   // takes part in the x phase (lanes from XT on idle)
     // uniform tile base; per-lane offsets stay 32-bit (Nx Ny M < 2^30 is checked on the host)
     const float* __restrict__ in0 = fin + (long long)(2 * s) * NX;
     const float* __restrict__ in1 = in0 + NX;
 
     // 1. row-layout loads: rows theta = g + G i, columns x = t + R2 r
-    float2 w[RPT][16];
+    float2 w[RPT][R1];
+    if (xlane) {
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
+        for (int i = 0; i < RPT; ++i) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            const int off = (g + G * i) * pl + t + R2 * r;
-            w[i][r] = make_float2(__builtin_nontemporal_load(in0 + off), __builtin_nontemporal_load(in1 + off));
+            for (int r = 0; r < R1; ++r) {
+                const int off = (g + G * i) * pl + t + R2 * r;
+                w[i][r] = make_float2(__builtin_nontemporal_load(in0 + off), __builtin_nontemporal_load(in1 + off));
+            }
         }
     }
-    // 2. x convolution (16 x R2 decomposition)
+    // 2. x convolution (R1 x R2 decomposition)
+    if (xlane) {
 #pragma unroll
-    for (int i = 0; i < RPT; ++i) {
-        dft16<float, false>(w[i]);
+        for (int i = 0; i < RPT; ++i) {
+            RegDFT<R1, false, float>::run(w[i]);
 #pragma unroll
-        for (int k1 = 1; k1 < 16; ++k1) w[i][k1] = mul<float>(w[i][k1], tw_f[k1 * R2 + t]);
+            for (int k1 = 1; k1 < R1; ++k1) w[i][k1] = mul<float>(w[i][k1], tw_f[k1 * R2 + t]);
+        }
     }
     float2* row = buf + g * P;
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         if (i > 0) __syncthreads();
+        if (xlane) {
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) row[xpos<R2>(k1, t)] = w[i][k1];
+            for (int k1 = 0; k1 < R1; ++k1) row[xpos_line<R1, R2>(k1, t)] = w[i][k1];
+        }
         __syncthreads();
         float2 u[CC][R2];
+        if (xlane) {
 #pragma unroll
-        for (int j = 0; j < CC; ++j) {
-            const int k1 = CC * t + j;
+            for (int j = 0; j < CC; ++j) {
+                const int k1 = CC * t + j;
 #pragma unroll
-            for (int tt = 0; tt < R2; ++tt) u[j][tt] = row[xpos<R2>(k1, tt)];
-            RegDFT<R2, false, float>::run(u[j]);
+                for (int tt = 0; tt < R2; ++tt) u[j][tt] = row[xpos_line<R1, R2>(k1, tt)];
+                RegDFT<R2, false, float>::run(u[j]);
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = mul<float>(u[j][k2], fx[k1 + 16 * k2]);
-            RegDFT<R2, true, float>::run(u[j]);
+                for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = mul<float>(u[j][k2], fx[k1 + R1 * k2]);
+                RegDFT<R2, true, float>::run(u[j]);
 #pragma unroll
-            for (int tt = 1; tt < R2; ++tt) u[j][tt] = mulc<float>(u[j][tt], tw_i[tt * 16 + k1]);
+                for (int tt = 1; tt < R2; ++tt) u[j][tt] = mulc<float>(u[j][tt], tw_i[tt * R1 + k1]);
+            }
         }
         __syncthreads();
+        if (xlane) {
 #pragma unroll
-        for (int j = 0; j < CC; ++j) {
+            for (int j = 0; j < CC; ++j) {
 #pragma unroll
-            for (int tt = 0; tt < R2; ++tt) row[xpos<R2>(CC * t + j, tt)] = u[j][tt];
+                for (int tt = 0; tt < R2; ++tt) row[xpos_line<R1, R2>(CC * t + j, tt)] = u[j][tt];
+            }
         }
         __syncthreads();
+        if (xlane) {
 #pragma unroll
-        for (int k1 = 0; k1 < 16; ++k1) w[i][k1] = row[xpos<R2>(k1, t)];
-        dft16<float, true>(w[i]);
+            for (int k1 = 0; k1 < R1; ++k1) w[i][k1] = row[xpos_line<R1, R2>(k1, t)];
+            RegDFT<R1, true, float>::run(w[i]);
+        }
     }
     // 3. rows -> columns through LDS, RC rows at a time
     const int xc = TPC == 1 ? tid : (tid >> 1);   // column owned in column layout
@@ -174,11 +201,13 @@ xt_slab_fast(FastSepArgs a) {
 #pragma unroll
     for (int h = 0; h < H; ++h) {
         __syncthreads();
+        if (xlane) {
 #pragma unroll
-        for (int i = 0; i < RPT; ++i) {
-            if (G * i >= h * RC && G * i < (h + 1) * RC) {
+            for (int i = 0; i < RPT; ++i) {
+                if (G * i >= h * RC && G * i < (h + 1) * RC) {
 #pragma unroll
-                for (int r = 0; r < 16; ++r) buf[(g + G * i - h * RC) * P + t + R2 * r] = w[i][r];
+                    for (int r = 0; r < R1; ++r) buf[(g + G * i - h * RC) * P + t + R2 * r] = w[i][r];
+                }
             }
         }
         __syncthreads();
@@ -224,17 +253,20 @@ xt_slab_fast(FastSepArgs a) {
 // Line pencils: W = 16 adjacent x-pairs (float2 columns) x L points along y
 // (axis 1) or theta (axis 2) at one outer coordinate (theta for y, y for theta).
 // L = R1 x R2 with R1 = 16 values per thread (32 for L = 512).
-template <int L> struct LineGeom {
-    static constexpr int R1 = L > 256 ? 32 : 16;
+// W = 16 adjacent x-pairs per tile (8 when the x-pair count is not a multiple of 16).
+// L = 3 * 2^k lines use R1 = L / 4 values per thread (a mixed-radix register DFT).
+template <int L, int WW> struct LineGeom {
+    static constexpr int R1 = (L % 3 == 0) ? L / 4 : (L > 256 ? 32 : 16);
     static constexpr int R2 = L / R1;
     static constexpr int CC = R1 / R2;
-    static constexpr int W = 16;
+    static constexpr int W = WW;
     static constexpr int NT = W * R2;
+    static_assert(R1 * R2 == L && CC * R2 == R1, "line geometry");
 };
 
-template <int L>
-__global__ void __launch_bounds__(LineGeom<L>::NT) line_pencil_fast(FastSepArgs a) {
-    using Gm = LineGeom<L>;
+template <int L, int WW>
+__global__ void __launch_bounds__((LineGeom<L, WW>::NT)) line_pencil_fast(FastSepArgs a) {
+    using Gm = LineGeom<L, WW>;
     constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC, W = Gm::W, NT = Gm::NT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float2* buf = reinterpret_cast<float2*>(smem_raw);  // [k1*R2 + t][W]
@@ -463,19 +495,15 @@ __global__ void __launch_bounds__(RowGeom<NX>::NT) x_rows_fast(FastSepArgs a) {
 }
 
 // ------------------------------------------------------------------ dispatch
-template <int M> constexpr int slab_tpc() { return M == 64 ? 2 : 1; }
-
 template <int NX, int M>
 static size_t slab_fast_lds() {
-    constexpr int R2 = NX / 16;
-    constexpr int RC = M < 32 ? M : 32;
-    constexpr int P = NX + (R2 == 16 ? 16 : R2 % 16);
-    return sizeof(float2) * ((size_t)RC * P + 32 * R2 + NX + 2 * M);
+    using Gm = SlabGeom<NX, M>;
+    return sizeof(float2) * ((size_t)Gm::RC * Gm::P + 3 * NX + 2 * M);
 }
 
-template <int L>
+template <int L, int W>
 static size_t pencil_fast_lds() {
-    return sizeof(float2) * ((size_t)L * LineGeom<L>::W + 3 * L);
+    return sizeof(float2) * ((size_t)L * W + 3 * L);
 }
 
 template <int NX>
@@ -486,29 +514,35 @@ static size_t rows_fast_lds() {
 template <int NX, int M>
 static hipError_t launch_slab_fast_t(const FastSepArgs& a, int nblocks, hipStream_t s) {
     const size_t lds = slab_fast_lds<NX, M>();
-    constexpr int TPC = slab_tpc<M>();
-    hipLaunchKernelGGL((xt_slab_fast<NX, M, TPC>), dim3(nblocks), dim3(NX * TPC), lds, s, a);
+    const int nthr = SlabGeom<NX, M>::NT;
+    hipLaunchKernelGGL((xt_slab_fast<NX, M>), dim3(nblocks), dim3(nthr), lds, s, a);
     return hipGetLastError();
 }
 
-template <int L>
+template <int L, int W>
 static hipError_t launch_pencil_fast_t(const FastSepArgs& a, hipStream_t s) {
-    const size_t lds = pencil_fast_lds<L>();
+    const size_t lds = pencil_fast_lds<L, W>();
     const int nouter = a.axis == 1 ? a.m : a.ny;
-    const int ntiles = (a.nx / 2 / LineGeom<L>::W) * nouter * a.nitems;
+    const int ntiles = (a.nx / 2 / W) * nouter * a.nitems;
     // persistent grid: a few blocks per CU (no more than fit at once), each walks its
     // share of tiles
     static const int fit = [lds] {
         int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void*>(line_pencil_fast<L>),
-                                                         LineGeom<L>::NT, lds) != hipSuccess || b < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void*>(line_pencil_fast<L, W>),
+                                                         LineGeom<L, W>::NT, lds) != hipSuccess || b < 1)
             b = 1;
         return b;
     }();
     int nblocks = a.grid_blocks < a.cus * fit ? a.grid_blocks : a.cus * fit;
     if (ntiles < nblocks) nblocks = ntiles;
-    hipLaunchKernelGGL((line_pencil_fast<L>), dim3(nblocks), dim3(LineGeom<L>::NT), lds, s, a);
+    const int nthr = LineGeom<L, W>::NT;
+    hipLaunchKernelGGL((line_pencil_fast<L, W>), dim3(nblocks), dim3(nthr), lds, s, a);
     return hipGetLastError();
+}
+
+template <int L>
+static hipError_t launch_pencil_w(const FastSepArgs& a, hipStream_t s) {
+    return (a.nx / 2) % 16 == 0 ? launch_pencil_fast_t<L, 16>(a, s) : launch_pencil_fast_t<L, 8>(a, s);
 }
 
 template <int NX>
@@ -520,15 +554,18 @@ static hipError_t launch_rows_fast_t(const FastSepArgs& a, hipStream_t s) {
 }
 
 bool slab_fast_supported(int nx, int m) {
-    return (nx == 32 || nx == 64 || nx == 128 || nx == 256) && (m == 16 || m == 32 || m == 64);
+    return (nx == 32 || nx == 48 || nx == 64 || nx == 96 || nx == 128 || nx == 256) && (m == 16 || m == 32 || m == 64);
 }
 
-static bool line_len_ok(int l) { return l == 32 || l == 64 || l == 128 || l == 256 || l == 512; }
+static bool line_len_ok(int l) {
+    return l == 32 || l == 48 || l == 64 || l == 96 || l == 128 || l == 256 || l == 512;
+}
 
-bool pencil_fast_supported(int nx, int ny) { return line_len_ok(ny) && nx % 32 == 0; }
+// columns come in x-pairs, W = 16 or 8 of them per tile
+bool pencil_fast_supported(int nx, int ny) { return line_len_ok(ny) && nx % 16 == 0; }
 
 bool three_pass_fast_supported(int nx, int ny, int m) {
-    return nx >= 64 && line_len_ok(nx) && line_len_ok(ny) && line_len_ok(m);
+    return (nx == 64 || nx == 128 || nx == 256 || nx == 512) && line_len_ok(ny) && line_len_ok(m);
 }
 
 #define SE2C_SLAB_CASE(NX_, M_) \
@@ -537,6 +574,8 @@ bool three_pass_fast_supported(int nx, int ny, int m) {
 hipError_t launch_slab_fast(const FastSepArgs& a, hipStream_t s) {
     const int nblocks = (a.ny / 2) * a.nitems;  // one block per y-pair slab
     SE2C_SLAB_CASE(32, 16) SE2C_SLAB_CASE(32, 32) SE2C_SLAB_CASE(32, 64)
+    SE2C_SLAB_CASE(48, 16) SE2C_SLAB_CASE(48, 32) SE2C_SLAB_CASE(48, 64)
+    SE2C_SLAB_CASE(96, 16) SE2C_SLAB_CASE(96, 32) SE2C_SLAB_CASE(96, 64)
     SE2C_SLAB_CASE(64, 16) SE2C_SLAB_CASE(64, 32) SE2C_SLAB_CASE(64, 64)
     SE2C_SLAB_CASE(128, 16) SE2C_SLAB_CASE(128, 32) SE2C_SLAB_CASE(128, 64)
     SE2C_SLAB_CASE(256, 16) SE2C_SLAB_CASE(256, 32) SE2C_SLAB_CASE(256, 64)
@@ -545,11 +584,13 @@ hipError_t launch_slab_fast(const FastSepArgs& a, hipStream_t s) {
 
 hipError_t launch_pencil_fast(const FastSepArgs& a, hipStream_t s) {
     const int L = a.axis == 1 ? a.ny : a.m;
-    if (L == 32) return launch_pencil_fast_t<32>(a, s);
-    if (L == 64) return launch_pencil_fast_t<64>(a, s);
-    if (L == 128) return launch_pencil_fast_t<128>(a, s);
-    if (L == 256) return launch_pencil_fast_t<256>(a, s);
-    if (L == 512) return launch_pencil_fast_t<512>(a, s);
+    if (L == 32) return launch_pencil_w<32>(a, s);
+    if (L == 48) return launch_pencil_w<48>(a, s);
+    if (L == 64) return launch_pencil_w<64>(a, s);
+    if (L == 96) return launch_pencil_w<96>(a, s);
+    if (L == 128) return launch_pencil_w<128>(a, s);
+    if (L == 256) return launch_pencil_w<256>(a, s);
+    if (L == 512) return launch_pencil_w<512>(a, s);
     return hipErrorInvalidValue;
 }
 
@@ -562,28 +603,31 @@ hipError_t launch_rows_fast(const FastSepArgs& a, hipStream_t s) {
 }
 
 #define SE2C_SLAB_ATTR(NX_, M_)                                                                        \
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(xt_slab_fast<NX_, M_, slab_tpc<M_>()>),        \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(xt_slab_fast<NX_, M_>),                        \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)slab_fast_lds<NX_, M_>()); \
     if (e != hipSuccess) return e;
 
-#define SE2C_LINE_ATTR(L_)                                                                              \
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(line_pencil_fast<L_>),                         \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)pencil_fast_lds<L_>());   \
-    if (e != hipSuccess) return e;                                                                      \
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(x_rows_fast<L_>),                              \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)rows_fast_lds<L_>());     \
+#define SE2C_PENCIL_ATTR(L_, W_)                                                                          \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(line_pencil_fast<L_, W_>),                       \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)pencil_fast_lds<L_, W_>());  \
+    if (e != hipSuccess) return e;
+#define SE2C_LINE_ATTR(L_) SE2C_PENCIL_ATTR(L_, 16) SE2C_PENCIL_ATTR(L_, 8)
+#define SE2C_ROWS_ATTR(NX_)                                                                                \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(x_rows_fast<NX_>),                               \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)rows_fast_lds<NX_>());      \
     if (e != hipSuccess) return e;
 
 hipError_t prepare_fast_kernels() {
     hipError_t e;
     SE2C_SLAB_ATTR(32, 16) SE2C_SLAB_ATTR(32, 32) SE2C_SLAB_ATTR(32, 64)
+    SE2C_SLAB_ATTR(48, 16) SE2C_SLAB_ATTR(48, 32) SE2C_SLAB_ATTR(48, 64)
+    SE2C_SLAB_ATTR(96, 16) SE2C_SLAB_ATTR(96, 32) SE2C_SLAB_ATTR(96, 64)
     SE2C_SLAB_ATTR(64, 16) SE2C_SLAB_ATTR(64, 32) SE2C_SLAB_ATTR(64, 64)
     SE2C_SLAB_ATTR(128, 16) SE2C_SLAB_ATTR(128, 32) SE2C_SLAB_ATTR(128, 64)
     SE2C_SLAB_ATTR(256, 16) SE2C_SLAB_ATTR(256, 32) SE2C_SLAB_ATTR(256, 64)
-    SE2C_LINE_ATTR(64) SE2C_LINE_ATTR(128) SE2C_LINE_ATTR(256) SE2C_LINE_ATTR(512)
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(line_pencil_fast<32>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)pencil_fast_lds<32>());
-    if (e != hipSuccess) return e;
+    SE2C_LINE_ATTR(32) SE2C_LINE_ATTR(48) SE2C_LINE_ATTR(64) SE2C_LINE_ATTR(96) SE2C_LINE_ATTR(128)
+    SE2C_LINE_ATTR(256) SE2C_LINE_ATTR(512)
+    SE2C_ROWS_ATTR(64) SE2C_ROWS_ATTR(128) SE2C_ROWS_ATTR(256) SE2C_ROWS_ATTR(512)
     return hipSuccess;
 }
 

@@ -170,7 +170,9 @@ def test_headline_256x256x64_batch16_chain8_sampled():
                                      # 512-point y pencils after the slab
                                      (64, 512, 64),
                                      # 32-point lines
-                                     (32, 32, 16), (32, 64, 64), (64, 32, 32)])
+                                     (32, 32, 16), (32, 64, 64), (64, 32, 32),
+                                     # 3 * 2^k lines (mixed-radix register DFTs, 8-column pencils)
+                                     (48, 48, 16), (96, 96, 64), (48, 96, 32), (96, 48, 64), (48, 64, 64)])
 def test_register_kernels_match_generic_and_oracle(nx, ny, m):
     batch = 3 if nx * ny * m < (1 << 20) else 2
     case(f"register vs generic kernels {nx}x{ny}x{m} fp32 batch {batch}, chain of 3, adjoint too")
