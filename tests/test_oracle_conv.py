@@ -85,6 +85,21 @@ def test_closed_form_c0_and_convergence():
     assert errs[1] < 1e-12 and errs[2] < 1e-12
 
 
+def test_closed_form_on_odd_grids():
+    # The paper's own grids are odd, L = 2K+1 with |k| <= K (Sec. 3.2).  There the
+    # sign (-1)^{k1+k2} belongs to the signed frequency, not the DFT index, and the
+    # series is a trigonometric interpolant of the convolution: the error against
+    # the continuous closed form must fall quickly as L grows (odd x, y and theta).
+    bf = bump_field(93, 0, 6, s=0.05, kappa=3.0)
+    chain = [KernelParams(0.04, 5.0, 0.4), KernelParams(0.03, 2.0, 1.1)]
+    errs = []
+    for nx, ny, m in [(25, 27, 25), (41, 43, 45), (61, 63, 65)]:
+        f = sample_field(bf, nx, ny, m)
+        ps = [K.gauss_vm(nx, ny, m, k.sigma, k.kappa, k.theta0, normalize="continuous") for k in chain]
+        errs.append(rel_l2(C.conv_chain(f, ps), CF.conv_closed_form(bf, chain, nx, ny, m)))
+    assert errs[0] < 1e-3 and errs[1] < 1e-9 and errs[2] < 1e-13, errs
+
+
 def test_closed_form_chain_with_angle_offsets():
     # Asymmetric bumps and kernels with theta offsets: catches transposed axes,
     # a conjugated angular phase or a dropped kernel.

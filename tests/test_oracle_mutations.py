@@ -74,6 +74,44 @@ def test_planted_mistake_is_caught(monkeypatch, target, name, repl):
     assert max(e) > 1e-3, (name, e)
 
 
+def _odd_grid_pin():
+    """Closed-form error of a two-kernel chain on an odd grid (Sec. 3.2, L = 2K+1)."""
+    bf = bump_field(93, 0, 6, s=0.05, kappa=3.0)
+    chain = [KernelParams(0.04, 5.0, 0.4), KernelParams(0.03, 2.0, 1.1)]
+    nx, ny, m = 41, 43, 45
+    f = sample_field(bf, nx, ny, m)
+    ps = [K.gauss_vm(nx, ny, m, k.sigma, k.kappa, k.theta0, normalize="continuous") for k in chain]
+    return rel_l2(C.conv_chain(f, ps), CF.conv_closed_form(bf, chain, nx, ny, m))
+
+
+def _index_parity_w(nx, ny, m):
+    # (-1)^{t1+t2} of the DFT index instead of the signed frequency
+    s1 = np.where(np.arange(nx) % 2 == 0, 1.0, -1.0)
+    s2 = np.where(np.arange(ny) % 2 == 0, 1.0, -1.0)
+    return np.broadcast_to(np.outer(s2, s1)[None], (m, ny, nx)).copy()
+
+
+def _phi_index_parity(length, points, grid, spatial):
+    e = _orig_phi(length, points, grid, False)
+    if spatial:
+        e = e * np.where(np.arange(length) % 2 == 0, 1.0, -1.0)[None, :]
+    return e
+
+
+def test_unmutated_odd_grid_pin_is_tight():
+    assert _odd_grid_pin() < 1e-9
+
+
+@pytest.mark.parametrize("target,name,repl", [
+    (FF, "sign_w", _index_parity_w),
+    (FF, "_phi_axis", _phi_index_parity),
+])
+def test_index_parity_on_odd_grids_is_caught(monkeypatch, target, name, repl):
+    # on even grids index parity and signed parity agree; on odd grids they do not
+    monkeypatch.setattr(target, name, repl)
+    assert _odd_grid_pin() > 1e-3
+
+
 def _phi_parity_on_theta(length, points, grid, spatial):
     # The (-1)^k parity factor applied to the angular axis instead of x and y.
     return _orig_phi(length, points, grid, not spatial)
