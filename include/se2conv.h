@@ -15,8 +15,14 @@
  * "device" are HIP device pointers of the plan's device; the caller owns them.
  * All calls are asynchronous on the given stream; argument errors are detected
  * on the host before anything is enqueued and leave no partial state.
- * Supported sizes: Nx, Ny even, 8 <= Nx, Ny <= 512; 2 <= M <= 512; every size
- * of the form 2^a 3^b.
+ * Supported sizes: 8 <= Nx, Ny <= 512; 2 <= M <= 512; Nx Ny M < 2^30.  Any
+ * length: the paper's odd grids L = 2K+1 (Sec. 3.2) and even grids alike.  The
+ * frequency of DFT index t is the signed one, t for t <= (L-1)/2, else t - L (for
+ * odd L the paper's set |k| <= K; for even L the reading {-L/2, ..., L/2-1}), and
+ * the sign (-1)^{k1+k2} of eq. (FkLv) uses it.  Lengths 2^a 3^b run on radix
+ * 16/8/4/3/2 Stockham stages; prime factors 5 and 7 have codelets; any other
+ * prime factor p is one direct-summation stage (O(p) work per point).  With odd
+ * Nx or Ny every chain runs on the field-pair passes.
  */
 #ifndef SE2CONV_H
 #define SE2CONV_H

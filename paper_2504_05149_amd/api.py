@@ -150,13 +150,15 @@ class Plan:
         _require(f, self.tdtype)
         nx, ny, m = self.shapes[shape_idx]
         batch = f.numel() // (nx * ny * m)
-        cdt = torch.complex64 if self.dtype == L.F32 else torch.complex128
-        buf = torch.empty(batch, m, ny, nx, dtype=cdt, device=f.device)
-        stride = buf[0].numel() * buf.element_size()
+        nbytes = nx * ny * m * (8 if self.dtype == L.F32 else 16)
+        stride = (nbytes + 15) // 16 * 16  # the ABI wants 16-byte aligned tables
+        buf = torch.empty(batch * stride, dtype=torch.uint8, device=f.device)
         L.check(self._lib.se2conv_field_coeffs(self.handle, shape_idx, f.data_ptr(), batch, buf.data_ptr(), stride,
                                                _stream_handle(stream)))
-        raw = buf.view(torch.uint8).view(batch, -1)
-        return [Table(self, shape_idx, raw[b], L.TABLE_FULL) for b in range(batch)]
+        tabs = [Table(self, shape_idx, buf[b * stride:b * stride + nbytes], L.TABLE_FULL) for b in range(batch)]
+        for t in tabs:
+            t.stride = stride
+        return tabs
 
     def kernel_grad(self, shape_idx: int, g: torch.Tensor, ftables: list, stream=None) -> torch.Tensor:
         """sum_b dL/dP_b for dL/dout_b = g_b, given the fields' FFC tables (one [M, Ny, Nx] tensor)."""
@@ -166,7 +168,7 @@ class Plan:
         if len(ftables) != batch:
             raise ValueError("need one field table per field")
         base = ftables[0].ptr
-        stride = ftables[1].ptr - base if batch > 1 else ftables[0].buf.numel()
+        stride = getattr(ftables[0], "stride", None) or ftables[0].buf.numel()
         if any(t.ptr != base + b * stride for b, t in enumerate(ftables)):
             raise ValueError("field tables must come from one se2conv_field_coeffs call")
         out = torch.empty(m, ny, nx, dtype=self.tdtype, device=g.device)

@@ -51,20 +51,9 @@ se2conv_status ok() {
             return fail(SE2CONV_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-bool is_2a3b(int n) {
-    if (n <= 0) return false;
-    while (n % 2 == 0) n /= 2;
-    while (n % 3 == 0) n /= 3;
-    return n == 1;
-}
-
 bool shape_supported(const se2conv_shape& s, std::string* why) {
     if (s.nx < 8 || s.nx > 512 || s.ny < 8 || s.ny > 512) {
         *why = "Nx and Ny must lie in [8, 512]";
-        return false;
-    }
-    if ((s.nx & 1) || (s.ny & 1)) {
-        *why = "Nx and Ny must be even";
         return false;
     }
     if ((long long)s.nx * s.ny * s.m >= (1LL << 30)) {
@@ -75,43 +64,59 @@ bool shape_supported(const se2conv_shape& s, std::string* why) {
         *why = "M must lie in [2, 512]";
         return false;
     }
-    if (!is_2a3b(s.nx) || !is_2a3b(s.ny) || !is_2a3b(s.m)) {
-        *why = "every size must be of the form 2^a 3^b";
-        return false;
-    }
     return true;
 }
 
+// Even Nx and Ny allow the pair packings of the separable passes (two rows or two
+// columns of one field as one complex line); other shapes run every chain on the
+// field-pair (plane) passes.
+bool pair_layout(const se2conv_shape& s) { return !(s.nx & 1) && !(s.ny & 1); }
+
+// Stockham radices of one length: 16/8/4/2 for the power of two, codelets 3, 5, 7,
+// and direct-summation stages for any other prime factor; largest radices first
+// (the first stage needs no twiddles).
 RadixPlan make_radix_plan(int L) {
     RadixPlan p{};
     p.L = L;
     p.nst = 0;
-    int n = L;
-    while (n % 3 == 0) {
-        p.r[p.nst++] = 3;
-        n /= 3;
+    int n = L, p2 = 1;
+    while (n % 2 == 0) {
+        n /= 2;
+        p2 *= 2;
     }
-    while (n >= 16 && n % 16 == 0) {
+    while (p2 >= 16) {
         p.r[p.nst++] = 16;
-        n /= 16;
+        p2 /= 16;
     }
-    if (n == 8) p.r[p.nst++] = 8, n = 1;
-    if (n == 4) p.r[p.nst++] = 4, n = 1;
-    if (n == 2) p.r[p.nst++] = 2, n = 1;
-    // put the largest radices first (the first stage needs no twiddles)
+    if (p2 > 1) p.r[p.nst++] = p2;
+    for (int f = 3; f * f <= n || n > 1; f += 2) {
+        if (f * f > n) f = n;  // the rest is prime
+        while (n % f == 0) {
+            p.r[p.nst++] = f;
+            n /= f;
+        }
+    }
     std::sort(p.r, p.r + p.nst, [](int a, int b) { return a > b; });
     return p;
 }
 
 constexpr size_t kMaxLds = 160 * 1024;
 
-int max_threads(bool d) { return d ? 512 : 1024; }
+// A length with a prime factor above 3 runs on the kernels with the radix-5/7 and
+// direct stages, which are limited to 512 threads per workgroup (as FP64 is).
+bool odd_len(int L) {
+    while (L % 2 == 0) L /= 2;
+    while (L % 3 == 0) L /= 3;
+    return L != 1;
+}
 
-int threads_for(long long P, bool d) {
+int max_threads(bool d, bool odd = false) { return (d || odd) ? 512 : 1024; }
+
+int threads_for(long long P, bool d, bool odd) {
     long long t = (P + SE2C_MAXV - 1) / SE2C_MAXV;
     t = ((t + 63) / 64) * 64;
     if (t < 64) t = 64;
-    if (t > max_threads(d)) t = max_threads(d);
+    if (t > max_threads(d, odd)) t = max_threads(d, odd);
     return (int)t;
 }
 
@@ -238,7 +243,8 @@ bool slab_fits(const se2conv_shape& s, bool d) {
     a.rows_per_tile = s.m;
     a.pad = 0;
     const long long P = (long long)s.nx * s.m;
-    return P <= (long long)SE2C_MAXV * max_threads(d) && slab_lds_bytes(a, d) <= kMaxLds;
+    const bool odd = odd_len(s.nx) || odd_len(s.m);
+    return P <= (long long)SE2C_MAXV * max_threads(d, odd) && slab_lds_bytes(a, d) <= kMaxLds;
 }
 
 // Fields per launch of the separable two-pass schedule.  Measured on MI355X at
@@ -273,14 +279,15 @@ const Schedule& sched_of(const se2conv_plan_s* p, const se2conv_shape& s) {
 
 int pencil_width(int ncols, int L, bool d, int want = 16) {
     int W = want;
-    while (W > 1 && (long long)W * L > (long long)SE2C_MAXV * max_threads(d)) W /= 2;
+    while (W > 1 && (long long)W * L > (long long)SE2C_MAXV * max_threads(d, odd_len(L))) W /= 2;
     if (ncols < W) W = ncols;
     return W;
 }
 
 hipError_t run_slab(SlabArgs a, bool d, hipStream_t st) {
     const long long P = (long long)a.rows_per_tile * a.nx;
-    const int nthr = threads_for(P, d);
+    const int nthr = threads_for(P, d, odd_len(a.nx) || (a.do_t && odd_len(a.m)));
+    if (P > (long long)SE2C_MAXV * nthr) return hipErrorInvalidConfiguration;  // tile larger than the workgroup covers
     const long long ntiles = (long long)a.nslab * a.ntile_t * a.nitems;
     const int nb = (int)std::min<long long>(ntiles, 1 << 20);
     hipError_t e = launch_slab(a, d, nthr, nb, st);
@@ -290,7 +297,8 @@ hipError_t run_slab(SlabArgs a, bool d, hipStream_t st) {
 
 hipError_t run_pencil(PencilArgs a, bool d, hipStream_t st) {
     const long long P = (long long)a.p.L * a.W;
-    const int nthr = threads_for(P, d);
+    const int nthr = threads_for(P, d, odd_len(a.p.L));
+    if (P > (long long)SE2C_MAXV * nthr) return hipErrorInvalidConfiguration;
     const int ncol_tiles = (a.ncols + a.W - 1) / a.W;
     const int nother = a.axis == 1 ? a.m : a.ny;
     const long long ntiles = (long long)ncol_tiles * nother * a.nitems;
@@ -845,7 +853,7 @@ se2conv_status validate_io(se2conv_plan_s* p, int32_t shape_idx, const void* f, 
 se2conv_status enqueue_problem(se2conv_plan_s* p, int shape_idx, const void* f, void* out, int batch,
                                const Chain& ch, bool all_sep, bool conj, hipStream_t st) {
     const se2conv_shape& s = p->shapes[shape_idx];
-    if (all_sep) return enqueue_sep(p, s, f, out, batch, ch, conj, st);
+    if (all_sep && pair_layout(s)) return enqueue_sep(p, s, f, out, batch, ch, conj, st);
     return enqueue_full(p, s, f, out, batch, ch, conj, st);
 }
 
@@ -1674,7 +1682,7 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
         bool all_sep = true;
         r = lookup_chain(p, q.shape_idx, q.tables, q.n_tables, &chains[i], &all_sep);
         if (r != SE2CONV_OK) return fail(r, "problem %d: %s", i, g_last_error.c_str());
-        seps[i] = all_sep;
+        seps[i] = all_sep && pair_layout(p->shapes[q.shape_idx]);
         key.push_back((uint64_t)q.shape_idx);
         key.push_back((uint64_t)q.batch);
         key.push_back((uint64_t)(uintptr_t)q.f);

@@ -113,7 +113,7 @@ __global__ void sep_factor_kernel(SepKernelParams kp, int nx, int ny, int m, dou
             im -= g[i] * s;
         }
         double sg = 1.0;
-        if (axis < 2 && (k & 1)) sg = -1.0;  // (-1)^k; L even so index parity = signed parity
+        if (axis < 2 && (signed_freq(k, L) & 1)) sg = -1.0;  // (-1)^k of the signed frequency
         re *= sg * norm;
         im *= sg * norm;
         double2 v;
@@ -149,7 +149,7 @@ __global__ void full_fold_kernel(const double* re, const double* im, double2* ac
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
         const int kx = (int)(i % nx);
         const int ky = (int)((i / nx) % ny);
-        const double sg = ((kx + ky) & 1) ? -inv : inv;
+        const double sg = ((signed_freq(kx, nx) + signed_freq(ky, ny)) & 1) ? -inv : inv;
         double2 v;
         v.x = re[i] * sg;
         v.y = im[i] * sg;

@@ -49,6 +49,17 @@ template <typename T, bool INV> __device__ __forceinline__ C<T> rotw(C<T> a, T c
 #define SE2C_COS_PI8 0.92387953251128675612818318939678828682
 #define SE2C_SIN_PI8 0.38268343236508977172845998403039886676
 #define SE2C_SQRT3_2 0.86602540378443864676372317075293618347
+// cos and sin of 2 pi j / 5 and 2 pi j / 7
+#define SE2C_C5_1 0.30901699437494742410229341718281905886
+#define SE2C_C5_2 -0.80901699437494742410229341718281905886
+#define SE2C_S5_1 0.95105651629515357211643933337938214340
+#define SE2C_S5_2 0.58778525229247312916870595463907276860
+#define SE2C_C7_1 0.62348980185873353052500488400423981063
+#define SE2C_C7_2 -0.22252093395631440428890256449679475947
+#define SE2C_C7_3 -0.90096886790241912623610231950744505117
+#define SE2C_S7_1 0.78183148246802980870844452667405775023
+#define SE2C_S7_2 0.97492791218182360701813168299393121723
+#define SE2C_S7_3 0.43388373911755812047576833284835875461
 
 template <typename T, bool INV> __device__ __forceinline__ void dft2(C<T>* a) {
     C<T> t = a[0];
@@ -66,6 +77,45 @@ template <typename T, bool INV> __device__ __forceinline__ void dft3(C<T>* a) {
     a[0] = add<T>(a[0], s);
     a[1] = add<T>(m, r);
     a[2] = sub<T>(m, r);
+}
+
+// Odd prime length P: X_k = b_k + (-+i) d_k and X_{P-k} = b_k - (-+i) d_k with
+// b_k = a_0 + sum_j cos(2 pi jk/P) (a_j + a_{P-j}), d_k = sum_j sin(2 pi jk/P) (a_j - a_{P-j}).
+template <typename T, bool INV> __device__ __forceinline__ void dft5(C<T>* a) {
+    const T c1 = (T)SE2C_C5_1, c2 = (T)SE2C_C5_2, s1 = (T)SE2C_S5_1, s2 = (T)SE2C_S5_2;
+    const C<T> p1 = add<T>(a[1], a[4]), m1 = sub<T>(a[1], a[4]);
+    const C<T> p2 = add<T>(a[2], a[3]), m2 = sub<T>(a[2], a[3]);
+    const C<T> b1 = mk<T>(a[0].x + c1 * p1.x + c2 * p2.x, a[0].y + c1 * p1.y + c2 * p2.y);
+    const C<T> b2 = mk<T>(a[0].x + c2 * p1.x + c1 * p2.x, a[0].y + c2 * p1.y + c1 * p2.y);
+    const C<T> d1 = rot<T, INV>(mk<T>(s1 * m1.x + s2 * m2.x, s1 * m1.y + s2 * m2.y));
+    const C<T> d2 = rot<T, INV>(mk<T>(s2 * m1.x - s1 * m2.x, s2 * m1.y - s1 * m2.y));
+    a[0] = add<T>(a[0], add<T>(p1, p2));
+    a[1] = add<T>(b1, d1);
+    a[4] = sub<T>(b1, d1);
+    a[2] = add<T>(b2, d2);
+    a[3] = sub<T>(b2, d2);
+}
+
+template <typename T, bool INV> __device__ __forceinline__ void dft7(C<T>* a) {
+    const T c1 = (T)SE2C_C7_1, c2 = (T)SE2C_C7_2, c3 = (T)SE2C_C7_3;
+    const T s1 = (T)SE2C_S7_1, s2 = (T)SE2C_S7_2, s3 = (T)SE2C_S7_3;
+    const C<T> p1 = add<T>(a[1], a[6]), m1 = sub<T>(a[1], a[6]);
+    const C<T> p2 = add<T>(a[2], a[5]), m2 = sub<T>(a[2], a[5]);
+    const C<T> p3 = add<T>(a[3], a[4]), m3 = sub<T>(a[3], a[4]);
+    // cos(2 pi jk/7) and sin(2 pi jk/7) for k = 1, 2, 3 (jk reduced mod 7; sin is odd)
+    const C<T> b1 = mk<T>(a[0].x + c1 * p1.x + c2 * p2.x + c3 * p3.x, a[0].y + c1 * p1.y + c2 * p2.y + c3 * p3.y);
+    const C<T> b2 = mk<T>(a[0].x + c2 * p1.x + c3 * p2.x + c1 * p3.x, a[0].y + c2 * p1.y + c3 * p2.y + c1 * p3.y);
+    const C<T> b3 = mk<T>(a[0].x + c3 * p1.x + c1 * p2.x + c2 * p3.x, a[0].y + c3 * p1.y + c1 * p2.y + c2 * p3.y);
+    const C<T> d1 = rot<T, INV>(mk<T>(s1 * m1.x + s2 * m2.x + s3 * m3.x, s1 * m1.y + s2 * m2.y + s3 * m3.y));
+    const C<T> d2 = rot<T, INV>(mk<T>(s2 * m1.x - s3 * m2.x - s1 * m3.x, s2 * m1.y - s3 * m2.y - s1 * m3.y));
+    const C<T> d3 = rot<T, INV>(mk<T>(s3 * m1.x - s1 * m2.x + s2 * m3.x, s3 * m1.y - s1 * m2.y + s2 * m3.y));
+    a[0] = add<T>(a[0], add<T>(p1, add<T>(p2, p3)));
+    a[1] = add<T>(b1, d1);
+    a[6] = sub<T>(b1, d1);
+    a[2] = add<T>(b2, d2);
+    a[5] = sub<T>(b2, d2);
+    a[3] = add<T>(b3, d3);
+    a[4] = sub<T>(b3, d3);
 }
 
 template <typename T, bool INV> __device__ __forceinline__ void dft4(C<T>* a) {
@@ -129,9 +179,16 @@ template <int R, typename T, bool INV> __device__ __forceinline__ void dftR(C<T>
     if constexpr (R == 2) dft2<T, INV>(a);
     else if constexpr (R == 3) dft3<T, INV>(a);
     else if constexpr (R == 4) dft4<T, INV>(a);
+    else if constexpr (R == 5) dft5<T, INV>(a);
+    else if constexpr (R == 7) dft7<T, INV>(a);
     else if constexpr (R == 8) dft8<T, INV>(a);
     else dft16<T, INV>(a);
 }
+
+// Signed frequency of DFT index t on a length-L axis: t for t <= (L-1)/2, else t - L.
+// For odd L = 2K+1 this is the set |k| <= K; for even L it is {-L/2, ..., L/2-1}, and
+// (-1)^k of the signed frequency equals (-1)^t only when L is even.
+__host__ __device__ inline int signed_freq(int t, int L) { return t <= (L - 1) / 2 ? t : t - L; }
 
 // Division by a small runtime divisor d (1 <= d, n < 2^21) via a 32x32->64
 // multiply by ceil(2^42/d): exact for all n < 2^21 because n*d < 2^42.
@@ -158,6 +215,7 @@ struct StageGeom {
     FastDiv div_nbl;  // L/R (butterflies per line)
     FastDiv div_ns;   // Ns
     FastDiv div_nl;   // nlines
+    FastDiv div_l;    // L
     int tw_step;      // L/(Ns*R)
 };
 
@@ -210,15 +268,75 @@ __device__ __forceinline__ void stockham_stage(C<T>* buf, const C<T>* tw, const 
     __syncthreads();
 }
 
-// Radix plan for one transform length: up to 6 stages.
+// One radix-R stage by direct summation, for prime R without a codelet.  Output
+// rr of butterfly j (k = j mod Ns) is sum_r v_r w_L^{r k L/(Ns R)} w_R^{r rr}
+// = sum_r v_r w_L^{r (k L/(Ns R) + rr L/R) mod L}: one table twiddle per term, O(R)
+// work per point.  Every thread computes up to MAXV outputs (the tile holds at
+// most MAXV points per thread), the workgroup synchronises, then they are written.
+template <typename T, int MAXV, bool INV>
+__device__ __forceinline__ void direct_stage(C<T>* buf, const C<T>* tw, const StageGeom g, int R, bool line_fast,
+                                             int tid, int nthr) {
+    const int nbl = g.L / R;
+    const int total = g.L * g.nlines;
+    // element e -> (line, output rr, butterfly j = jq Ns + k)
+    auto split = [&](int e, int& line, int& rr, int& j, int& jq, int& k) {
+        int q;
+        if (line_fast) {
+            q = (int)fdiv((uint32_t)e, g.div_nl);
+            line = e - q * g.nlines;
+        } else {
+            line = (int)fdiv((uint32_t)e, g.div_l);
+            q = e - line * g.L;
+        }
+        rr = (int)fdiv((uint32_t)q, g.div_nbl);
+        j = q - rr * nbl;
+        jq = (int)fdiv((uint32_t)j, g.div_ns);
+        k = j - jq * g.Ns;
+    };
+    C<T> acc[MAXV];
+#pragma unroll
+    for (int u = 0; u < MAXV; ++u) {
+        const int e = tid + u * nthr;
+        acc[u] = mk<T>((T)0, (T)0);
+        if (e < total) {
+            int line, rr, j, jq, k;
+            split(e, line, rr, j, jq, k);
+            const C<T>* src = buf + line * g.ls + j * g.es;
+            const int step = k * g.tw_step + rr * nbl;  // < L
+            int idx = 0;
+            C<T> sum = mk<T>((T)0, (T)0);
+            for (int r = 0; r < R; ++r) {
+                const C<T> v = src[r * nbl * g.es];
+                const C<T> w = tw[idx];
+                sum = add<T>(sum, INV ? mulc<T>(v, w) : mul<T>(v, w));
+                idx += step;
+                if (idx >= g.L) idx -= g.L;
+            }
+            acc[u] = sum;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MAXV; ++u) {
+        const int e = tid + u * nthr;
+        if (e < total) {
+            int line, rr, j, jq, k;
+            split(e, line, rr, j, jq, k);
+            buf[line * g.ls + (jq * g.Ns * R + k + rr * g.Ns) * g.es] = acc[u];
+        }
+    }
+    __syncthreads();
+}
+
+// Radix plan for one transform length: up to 8 stages.
 struct RadixPlan {
     int L;
     int nst;
-    int r[6];
+    int r[8];
 };
 
 // Transform 'nlines' lines of length p.L (forward or inverse) in LDS.
-template <typename T, int MAXV, bool INV>
+template <typename T, int MAXV, bool INV, bool ODD = false>
 __device__ void line_fft(C<T>* buf, const C<T>* tw, const RadixPlan& p, int es, int ls, int nlines,
                          bool line_fast, int tid, int nthr) {
     int Ns = 1;
@@ -233,13 +351,22 @@ __device__ void line_fft(C<T>* buf, const C<T>* tw, const RadixPlan& p, int es, 
         g.div_nbl = make_fastdiv((uint32_t)(p.L / R));
         g.div_ns = make_fastdiv((uint32_t)Ns);
         g.div_nl = make_fastdiv((uint32_t)nlines);
+        g.div_l = make_fastdiv((uint32_t)p.L);
         g.tw_step = p.L / (Ns * R);
         switch (R) {
             case 16: stockham_stage<T, 16, MAXV, INV>(buf, tw, g, line_fast, tid, nthr); break;
             case 8: stockham_stage<T, 8, MAXV, INV>(buf, tw, g, line_fast, tid, nthr); break;
             case 4: stockham_stage<T, 4, MAXV, INV>(buf, tw, g, line_fast, tid, nthr); break;
             case 3: stockham_stage<T, 3, MAXV, INV>(buf, tw, g, line_fast, tid, nthr); break;
-            default: stockham_stage<T, 2, MAXV, INV>(buf, tw, g, line_fast, tid, nthr); break;
+            case 2: stockham_stage<T, 2, MAXV, INV>(buf, tw, g, line_fast, tid, nthr); break;
+            default:
+                // radices other than 2^a 3^b exist only in kernels instantiated with ODD
+                if constexpr (ODD) {
+                    if (R == 5) stockham_stage<T, 5, MAXV, INV>(buf, tw, g, line_fast, tid, nthr);
+                    else if (R == 7) stockham_stage<T, 7, MAXV, INV>(buf, tw, g, line_fast, tid, nthr);
+                    else direct_stage<T, MAXV, INV>(buf, tw, g, R, line_fast, tid, nthr);
+                }
+                break;
         }
         Ns *= R;
     }

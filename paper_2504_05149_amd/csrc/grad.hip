@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include "coeffs.hpp"
+#include "fft_device.hpp"
 #include "grad.hpp"
 
 namespace se2c {
@@ -31,7 +32,7 @@ __global__ void unpack_tables_kernel(const T* zre, const T* zim, void* ta, void*
         const long long midx = ((long long)mt * ny + my) * nx + mx;
         const T zr = zre[idx], zi = zim[idx];
         const T cr = zre[midx], ci = -zim[midx];  // conj Z^[-k]
-        const T s = ((kx + ky) & 1) ? -inv : inv;
+        const T s = ((signed_freq(kx, nx) + signed_freq(ky, ny)) & 1) ? -inv : inv;
         C2 a, b;
         a.x = (T)0.5 * (zr + cr) * s;
         a.y = (T)0.5 * (zi + ci) * s;

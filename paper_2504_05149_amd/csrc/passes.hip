@@ -31,8 +31,8 @@ __device__ __forceinline__ void load_tw(C<T>* dst, const void* src, int L, int t
 }
 
 // ---------------------------------------------------------------- slab pass
-template <typename T, int MAXV>
-__global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) slab_kernel(SlabArgs a) {
+template <typename T, int MAXV, bool ODD>
+__global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) slab_kernel(SlabArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C<T>* tile = reinterpret_cast<C<T>*>(smem_raw);
     const int pitch = a.nx + a.pad;                 // row pitch (complex) in LDS
@@ -124,8 +124,8 @@ __global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) slab_kernel(SlabArgs a) {
 
         // ---- forward
         if (a.fwd) {
-            line_fft<T, MAXV, false>(tile, twx, a.px, 1, pitch, rows, false, tid, nthr);
-            if (a.do_t) line_fft<T, MAXV, false>(tile, twt, a.pt, pitch, 1, a.nx, true, tid, nthr);
+            line_fft<T, MAXV, false, ODD>(tile, twx, a.px, 1, pitch, rows, false, tid, nthr);
+            if (a.do_t) line_fft<T, MAXV, false, ODD>(tile, twt, a.pt, pitch, 1, a.nx, true, tid, nthr);
         }
         // ---- separable spectral product: z[kt][kx] *= Tx[kx] * Tt[kt] / (nx*m)
         if (a.mul) {
@@ -139,8 +139,8 @@ __global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) slab_kernel(SlabArgs a) {
         }
         // ---- inverse
         if (a.inv) {
-            if (a.do_t) line_fft<T, MAXV, true>(tile, twt, a.pt, pitch, 1, a.nx, true, tid, nthr);
-            line_fft<T, MAXV, true>(tile, twx, a.px, 1, pitch, rows, false, tid, nthr);
+            if (a.do_t) line_fft<T, MAXV, true, ODD>(tile, twt, a.pt, pitch, 1, a.nx, true, tid, nthr);
+            line_fft<T, MAXV, true, ODD>(tile, twx, a.px, 1, pitch, rows, false, tid, nthr);
         }
 
         // ---- store
@@ -168,8 +168,8 @@ __global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) slab_kernel(SlabArgs a) {
 }
 
 // -------------------------------------------------------------- pencil pass
-template <typename T, int MAXV>
-__global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) pencil_kernel(PencilArgs a) {
+template <typename T, int MAXV, bool ODD>
+__global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) pencil_kernel(PencilArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C<T>* tile = reinterpret_cast<C<T>*>(smem_raw);
     const int L = a.p.L;
@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) pencil_kernel(PencilArgs 
         }
         __syncthreads();
 
-        if (a.fwd) line_fft<T, MAXV, false>(tile, tw, a.p, pitch, 1, a.W, true, tid, nthr);
+        if (a.fwd) line_fft<T, MAXV, false, ODD>(tile, tw, a.p, pitch, 1, a.W, true, tid, nthr);
         if (a.mul == 1) {
             for (int i = tid; i < P; i += nthr) {
                 const int e = i / a.W;
@@ -285,7 +285,7 @@ __global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) pencil_kernel(PencilArgs 
             }
             __syncthreads();
         }
-        if (a.inv) line_fft<T, MAXV, true>(tile, tw, a.p, pitch, 1, a.W, true, tid, nthr);
+        if (a.inv) line_fft<T, MAXV, true, ODD>(tile, tw, a.p, pitch, 1, a.W, true, tid, nthr);
 
         if (a.mode == 0) {
             T* obase_ptr = a.items ? reinterpret_cast<T*>(a.items[item].out)
@@ -316,25 +316,38 @@ __global__ void __launch_bounds__(SE2C_MAX_THREADS(T)) pencil_kernel(PencilArgs 
 }
 
 // ------------------------------------------------------------ host launchers
-template <typename T, int MAXV>
+template <typename T, int MAXV, bool ODD>
 static hipError_t launch_slab_t(const SlabArgs& a, int nthr, int nblocks, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((slab_kernel<T, MAXV>), dim3(nblocks), dim3(nthr), lds, s, a);
+    hipLaunchKernelGGL((slab_kernel<T, MAXV, ODD>), dim3(nblocks), dim3(nthr), lds, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int MAXV>
+template <typename T, int MAXV, bool ODD>
 static hipError_t launch_pencil_t(const PencilArgs& a, int nthr, int nblocks, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((pencil_kernel<T, MAXV>), dim3(nblocks), dim3(nthr), lds, s, a);
+    hipLaunchKernelGGL((pencil_kernel<T, MAXV, ODD>), dim3(nblocks), dim3(nthr), lds, s, a);
     return hipGetLastError();
+}
+
+// Lengths with a prime factor above 3 need the kernels that carry the radix-5/7
+// codelets and the direct stage (kept out of the 2^a 3^b kernels, whose register
+// allocation they would raise).  Those kernels take at most 512 threads.
+static bool needs_odd_stages(const RadixPlan& p) {
+    for (int i = 0; i < p.nst; ++i)
+        if (p.r[i] != 2 && p.r[i] != 3 && p.r[i] != 4 && p.r[i] != 8 && p.r[i] != 16) return true;
+    return false;
 }
 
 // Allow every pass kernel the full 160 KB of LDS (done once, outside any capture).
 hipError_t prepare_generic_kernels() {
     const int lds = 160 * 1024;
-    const void* fns[] = {reinterpret_cast<const void*>(slab_kernel<float, SE2C_MAXV>),
-                         reinterpret_cast<const void*>(slab_kernel<double, SE2C_MAXV>),
-                         reinterpret_cast<const void*>(pencil_kernel<float, SE2C_MAXV>),
-                         reinterpret_cast<const void*>(pencil_kernel<double, SE2C_MAXV>)};
+    const void* fns[] = {reinterpret_cast<const void*>(slab_kernel<float, SE2C_MAXV, false>),
+                         reinterpret_cast<const void*>(slab_kernel<double, SE2C_MAXV, false>),
+                         reinterpret_cast<const void*>(pencil_kernel<float, SE2C_MAXV, false>),
+                         reinterpret_cast<const void*>(pencil_kernel<double, SE2C_MAXV, false>),
+                         reinterpret_cast<const void*>(slab_kernel<float, SE2C_MAXV, true>),
+                         reinterpret_cast<const void*>(slab_kernel<double, SE2C_MAXV, true>),
+                         reinterpret_cast<const void*>(pencil_kernel<float, SE2C_MAXV, true>),
+                         reinterpret_cast<const void*>(pencil_kernel<double, SE2C_MAXV, true>)};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
@@ -354,14 +367,23 @@ size_t pencil_lds_bytes(const PencilArgs& a, bool dbl) {
 
 hipError_t launch_slab(const SlabArgs& a, bool dbl, int nthr, int nblocks, hipStream_t s) {
     const size_t lds = slab_lds_bytes(a, dbl);
-    if (dbl) return launch_slab_t<double, SE2C_MAXV>(a, nthr, nblocks, lds, s);
-    return launch_slab_t<float, SE2C_MAXV>(a, nthr, nblocks, lds, s);
+    const bool odd = needs_odd_stages(a.px) || (a.do_t && needs_odd_stages(a.pt));
+    if (odd) {
+        if (dbl) return launch_slab_t<double, SE2C_MAXV, true>(a, nthr, nblocks, lds, s);
+        return launch_slab_t<float, SE2C_MAXV, true>(a, nthr, nblocks, lds, s);
+    }
+    if (dbl) return launch_slab_t<double, SE2C_MAXV, false>(a, nthr, nblocks, lds, s);
+    return launch_slab_t<float, SE2C_MAXV, false>(a, nthr, nblocks, lds, s);
 }
 
 hipError_t launch_pencil(const PencilArgs& a, bool dbl, int nthr, int nblocks, hipStream_t s) {
     const size_t lds = pencil_lds_bytes(a, dbl);
-    if (dbl) return launch_pencil_t<double, SE2C_MAXV>(a, nthr, nblocks, lds, s);
-    return launch_pencil_t<float, SE2C_MAXV>(a, nthr, nblocks, lds, s);
+    if (needs_odd_stages(a.p)) {
+        if (dbl) return launch_pencil_t<double, SE2C_MAXV, true>(a, nthr, nblocks, lds, s);
+        return launch_pencil_t<float, SE2C_MAXV, true>(a, nthr, nblocks, lds, s);
+    }
+    if (dbl) return launch_pencil_t<double, SE2C_MAXV, false>(a, nthr, nblocks, lds, s);
+    return launch_pencil_t<float, SE2C_MAXV, false>(a, nthr, nblocks, lds, s);
 }
 
 }  // namespace se2c

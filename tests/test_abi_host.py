@@ -34,11 +34,17 @@ def test_status_strings():
     assert lib.se2conv_status_string(99) == b"unknown status"
 
 
-@pytest.mark.parametrize("shape", [(50, 32, 32), (7, 8, 8), (8, 8, 1), (1024, 8, 8), (10, 8, 8), (8, 8, 5)])
+@pytest.mark.parametrize("shape", [(7, 8, 8), (8, 8, 1), (1024, 8, 8), (8, 600, 8), (8, 8, 513)])
 def test_unsupported_sizes(shape):
     with pytest.raises(se2.Se2convError) as e:
         se2.Plan([shape], host_only=True)
     assert e.value.status == L.ERR_UNSUPPORTED_SIZE
+
+
+@pytest.mark.parametrize("shape", [(31, 31, 31), (33, 41, 43), (101, 53, 17), (50, 32, 35), (10, 8, 5)])
+def test_odd_and_prime_sizes_are_accepted(shape):
+    # the paper's odd grids L = 2K+1 (Sec. 3.2) and lengths with any prime factor
+    se2.Plan([shape], host_only=True).close()
 
 
 def test_bad_plan_arguments():

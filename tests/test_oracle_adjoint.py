@@ -1,5 +1,6 @@
 """Pins for oracle.adjoint: gradients against brute force and finite differences."""
 import numpy as np
+import pytest
 
 from oracle import adjoint as A
 from oracle import conv as C
@@ -12,10 +13,11 @@ def test_kernel_gradient_matches_explicit_loop_form(rng):
     assert np.max(np.abs(A.grad_kernel_samples(f, g) - A.grad_kernel_direct(f, g))) < 1e-13
 
 
-def test_kernel_gradient_by_finite_differences(rng):
-    f = rng.standard_normal((4, 8, 8))
-    p = rng.standard_normal((4, 8, 8))
-    target = rng.standard_normal((4, 8, 8))
+@pytest.mark.parametrize("shape", [(4, 8, 8), (5, 7, 9)])  # even grid, odd grid (L = 2K+1)
+def test_kernel_gradient_by_finite_differences(rng, shape):
+    f = rng.standard_normal(shape)
+    p = rng.standard_normal(shape)
+    target = rng.standard_normal(shape)
 
     def loss(pp):
         r = C.conv_chain(f, [pp]) - target
@@ -23,7 +25,7 @@ def test_kernel_gradient_by_finite_differences(rng):
     g = 2.0 * (C.conv_chain(f, [p]) - target)
     grad = A.grad_kernel_samples(f, g)
     h = 1e-3
-    for idx in [(0, 0, 0), (1, 3, 5), (3, 7, 2), (2, 4, 4)]:
+    for idx in [(0, 0, 0), (1, 3, 5), (3, 6, 2), (2, 4, 4)]:
         e = np.zeros_like(p)
         e[idx] = h
         fd = (loss(p + e) - loss(p - e)) / (2 * h)
@@ -31,17 +33,19 @@ def test_kernel_gradient_by_finite_differences(rng):
         assert abs(fd - grad[idx]) < 1e-8 * max(1.0, abs(fd))
 
 
-def test_field_gradient_by_finite_differences(rng):
-    f = rng.standard_normal((4, 8, 8))
-    p = K.gauss_vm(8, 8, 4, 0.1, 2.0, 0.5)
-    target = rng.standard_normal((4, 8, 8))
+@pytest.mark.parametrize("shape", [(4, 8, 8), (5, 7, 9)])
+def test_field_gradient_by_finite_differences(rng, shape):
+    m, ny, nx = shape
+    f = rng.standard_normal(shape)
+    p = K.gauss_vm(nx, ny, m, 0.1, 2.0, 0.5)
+    target = rng.standard_normal(shape)
 
     def loss(ff):
         r = C.conv_chain(ff, [p]) - target
         return float(np.sum(r * r))
     grad = A.grad_field(2.0 * (C.conv_chain(f, [p]) - target), [p])
     h = 1e-3
-    for idx in [(0, 1, 2), (3, 7, 7), (2, 0, 5)]:
+    for idx in [(0, 1, 2), (3, 6, 6), (2, 0, 5)]:
         e = np.zeros_like(f)
         e[idx] = h
         fd = (loss(f + e) - loss(f - e)) / (2 * h)
