@@ -16,7 +16,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .ffc import ffc, sign_w, synthesize
+from .ffc import ffc, sign_w, signed_freqs, synthesize
 from .transforms import dft3, idft3
 
 
@@ -48,6 +48,56 @@ def conv_with_coeffs(f: np.ndarray, table: np.ndarray, points=None) -> np.ndarra
     """Re S_K with a given coefficient table, optionally only at some grid points."""
     h = ffc(f) * table
     return synthesize(h, points=points).real
+
+
+def conv_on_grid(f: np.ndarray, kernels, grid, adjoint: bool = False) -> np.ndarray:
+    """Re S_K[f, rho_1, ...] evaluated on a finer (Gx, Gy, Gm) grid, G >= L per axis.
+
+    The coefficients are those of the sampling grid Omega_L; only the evaluation
+    points change (Sec. 4.1 eq. (MatSKfonG), Sec. 6.1 eq. (MatSKfgonG)).
+    """
+    h = ffc(f)
+    for p in kernels:
+        c = ffc(p)
+        h = h * (np.conj(c) if adjoint else c)
+    return synthesize(h, grid=grid).real
+
+
+def _pad_axis(length: int, grid: int) -> np.ndarray:
+    """Q[g, t]: weight of L-grid index t at N-grid index g in the zero-padded spectrum.
+
+    Prop. LtoN1D: coefficient k (|k| <= K, L = 2K+1) moves from index tau_L(k) to
+    tau_N(k); the rest of the N-spectrum is zero.  Even L: the index L/2 is split in
+    halves between tau_N(-L/2) and tau_N(+L/2) (the same index when N = L).
+    """
+    q = np.zeros((grid, length))
+    for t, k in enumerate(signed_freqs(length)):
+        if length % 2 == 0 and t == length // 2:
+            q[np.mod(-k, grid), t] += 0.5
+            q[np.mod(k, grid), t] += 0.5
+        else:
+            q[np.mod(k, grid), t] = 1.0
+    return q
+
+
+def padded_matrix_form(f: np.ndarray, kernels, grid) -> np.ndarray:
+    """Algorithm 3 with N > L: (N_prod / n^2) iDFT_N(W . Q_f . Q_rho), eq. (MatSKfgonG).
+
+    Q is the zero-padded DFT (eq. (Qf)); W = (-1)^{k1+k2} of the signed frequency
+    on the N-grid (eq. (W)).  A chain of q kernels multiplies their DFTs, each with
+    a factor 1/n, and W enters q times (W . W = 1), as in the power form of Alg. 4.
+    """
+    m, ny, nx = f.shape
+    gx, gy, gm = grid
+    n = float(nx * ny * m)
+    h = dft3(f)
+    for p in kernels:
+        h = h * dft3(p) / n
+    qx, qy, qt = _pad_axis(nx, gx), _pad_axis(ny, gy), _pad_axis(m, gm)
+    big = np.einsum("ct,bs,ar,tsr->cba", qt, qy, qx, h)
+    if len(kernels) % 2 == 1:
+        big = big * sign_w(gx, gy, gm)
+    return (float(gx * gy * gm) / n * idft3(big)).real
 
 
 def alg3_matrix_form(f: np.ndarray, p: np.ndarray) -> np.ndarray:

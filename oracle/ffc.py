@@ -16,6 +16,11 @@ not change any on-grid value.
 The finite Fourier series is evaluated by explicit synthesis
     S(w) = sum_k c[k] phi_k(w),
 with phi_k at x = -1/2 + a/G written exactly as (-1)^k * exp(2 pi i ((k a) mod G)/G).
+G may exceed L: that is the evaluation of S_K on a finer grid (Sec. 4.1, eq.
+(MatSKfonG)).  The paper states it for odd L only.  For even L the index L/2 holds
+both frequencies +-L/2 (they coincide on Omega_L); off the grid this oracle splits
+it in halves between phi_{-L/2} and phi_{+L/2}, so that a real field stays real.
+On Omega_L itself the split changes nothing.
 """
 from __future__ import annotations
 
@@ -72,6 +77,11 @@ def _phi_axis(length: int, points: np.ndarray, grid: int, spatial: bool) -> np.n
     a = np.asarray(points, dtype=np.int64)
     red = np.mod(np.outer(a, k), grid).astype(np.float64)
     e = np.exp(2j * np.pi * red / grid)
+    if length % 2 == 0:
+        # Nyquist index: average of the factors of k = -L/2 and k = +L/2
+        h = length // 2
+        plus = np.exp(2j * np.pi * np.mod(a * h, grid).astype(np.float64) / grid)
+        e[:, h] = 0.5 * (e[:, h] + plus)
     if spatial:
         e = e * np.where(k % 2 == 0, 1.0, -1.0)[None, :]
     return e
