@@ -201,6 +201,26 @@ se2conv_status se2conv_apply(se2conv_plan_t plan, int32_t shape_idx, const void*
                              void* d_out, int32_t batch, uint32_t flags, hipStream_t stream);
 
 /*
+ * se2conv_apply_padded: out[b] = Re S_K[f[b], chain] evaluated on a finer grid
+ * (paper Sec. 4.1 eq. (MatSKfonG), Sec. 6.1 eq. (MatSKfgonG), Prop. LtoN1D: the
+ * iDFT of the zero-padded product spectrum).
+ *   shape_idx       the sampling grid L of d_f and d_table.
+ *   out_shape_idx   another shape of the same plan, the evaluation grid N, with
+ *                   N >= L on every axis (N = L gives se2conv_apply's result).
+ *   d_f             device [batch][Lm][Ly][Lx], d_out device [batch][Nm][Ny][Nx], plan
+ *                   dtype, 16-byte aligned, not overlapping.
+ * Every coefficient keeps its signed frequency k (|k| <= K for odd L = 2K+1); the
+ * rest of the N-spectrum is zero.  For even L (a reading: the paper states odd L)
+ * the index L/2 carries +-L/2 together and is split in halves between the two on a
+ * finer grid, so real fields give real values.  Runs on the field-pair passes, one
+ * pair at a time, with the plan workspace: calls on one plan must not overlap on
+ * different streams.  Flags: SE2CONV_ADJOINT, SE2CONV_TIMING.
+ */
+se2conv_status se2conv_apply_padded(se2conv_plan_t plan, int32_t shape_idx, const void* d_f, const void* d_table,
+                                    int32_t out_shape_idx, void* d_out, int32_t batch, uint32_t flags,
+                                    hipStream_t stream);
+
+/*
  * Fused differentiation (FP32 plans on shapes with register kernels, see
  * se2conv_fused_supported; other plans use se2conv_field_coeffs + se2conv_kernel_grad).
  *

@@ -145,6 +145,25 @@ class Plan:
                                         _stream_handle(stream)))
         return out
 
+    def apply_padded(self, shape_idx: int, f: torch.Tensor, table: Table, out_shape_idx: int,
+                     out: torch.Tensor | None = None, adjoint: bool = False, stream=None,
+                     timing: bool = False) -> torch.Tensor:
+        """Re S_K[f, chain] on the finer grid of shape out_shape_idx (zero-padded evaluation)."""
+        _require(f, self.tdtype)
+        nx, ny, m = self.shapes[shape_idx]
+        gx, gy, gm = self.shapes[out_shape_idx]
+        if f.shape[-3:] != (m, ny, nx):
+            raise ValueError(f"field shape {tuple(f.shape)} does not end in {(m, ny, nx)}")
+        batch = f.numel() // (nx * ny * m)
+        if out is None:
+            out = torch.empty(tuple(f.shape[:-3]) + (gm, gy, gx), dtype=f.dtype, device=f.device)
+        _require(out, self.tdtype)
+        L.check(self._lib.se2conv_apply_padded(self.handle, shape_idx, f.data_ptr(), table.ptr, out_shape_idx,
+                                               out.data_ptr(), batch,
+                                               (L.ADJOINT if adjoint else 0) | (L.TIMING if timing else 0),
+                                               _stream_handle(stream)))
+        return out
+
     def field_coeffs(self, shape_idx: int, f: torch.Tensor, stream=None) -> list:
         """FFC tables of each field of f (FULL tables in the plan dtype), one Table per field."""
         _require(f, self.tdtype)

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libse2conv.so")
-SOURCES = ["api.cpp", "passes.hip", "coeffs.hip", "sep_fast.hip", "full_fast.hip", "grad.hip", "sample.hip"]
+SOURCES = ["api.cpp", "passes.hip", "coeffs.hip", "sep_fast.hip", "full_fast.hip", "grad.hip", "sample.hip", "pad.hip"]
 ARCH = os.environ.get("SE2CONV_ARCH", "gfx950")
 
 

@@ -262,11 +262,17 @@ int sep_chunk_fields(const se2conv_plan_s* p, const se2conv_shape& s, int batch)
     return batch;
 }
 
+// Theta rows per x-row tile: the largest divisor of M within the point budget, or,
+// when M has no divisor near the budget (a prime M, say), equal chunks of at most
+// the budget with a shorter last one.
 int rows_for_xpass(const se2conv_shape& s, int points = 4096) {
+    const int rmax = std::max(1, std::min(s.m, points / s.nx));
     int best = 1;
-    for (int r = 1; r <= s.m; ++r)
-        if (s.m % r == 0 && (long long)r * s.nx <= points) best = r;
-    return best;
+    for (int r = 1; r <= rmax; ++r)
+        if (s.m % r == 0) best = r;
+    if (2 * best >= rmax) return best;
+    const int nt = (s.m + rmax - 1) / rmax;
+    return (s.m + nt - 1) / nt;
 }
 
 // The schedule of a shape (shapes are looked up by value: passes receive the shape).
@@ -427,7 +433,7 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
         a.scale = 1.0 / ((double)s.nx * s.m);
     } else {
         a.rows_per_tile = rows_for_xpass(s, sched_of(p, s).xrow_points);
-        a.ntile_t = s.m / a.rows_per_tile;
+        a.ntile_t = (s.m + a.rows_per_tile - 1) / a.rows_per_tile;
         a.do_t = 0;
         a.scale = 1.0 / (double)s.nx;
     }
@@ -531,7 +537,7 @@ se2conv_status enqueue_sep_items(se2conv_plan_s* p, const se2conv_shape& s, cons
             a.scale = 1.0 / ((double)s.nx * s.m);
         } else {
             a.rows_per_tile = rows_for_xpass(s, sched_of(p, s).xrow_points);
-            a.ntile_t = s.m / a.rows_per_tile;
+            a.ntile_t = (s.m + a.rows_per_tile - 1) / a.rows_per_tile;
             a.do_t = 0;
             a.scale = 1.0 / (double)s.nx;
         }
@@ -609,7 +615,7 @@ hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int d
     }
     // split: x rows and theta pencils (planes mode), in the right order
     a.rows_per_tile = rows_for_xpass(s, sched_of(p, s).xrow_points);
-    a.ntile_t = s.m / a.rows_per_tile;
+    a.ntile_t = (s.m + a.rows_per_tile - 1) / a.rows_per_tile;
     a.do_t = 0;
     PencilArgs b{};
     b.mode = 1;
@@ -1507,6 +1513,76 @@ se2conv_status se2conv_apply(se2conv_plan_t p, int32_t shape_idx, const void* d_
 }
 
 // ---- fused differentiation (register kernels of the full path)
+se2conv_status se2conv_apply_padded(se2conv_plan_t p, int32_t shape_idx, const void* d_f, const void* d_table,
+                                    int32_t out_shape_idx, void* d_out, int32_t batch, uint32_t flags,
+                                    hipStream_t stream) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    const int nsh = (int)p->shapes.size();
+    if (shape_idx < 0 || shape_idx >= nsh || out_shape_idx < 0 || out_shape_idx >= nsh)
+        return fail(SE2CONV_ERR_INVALID_ARG, "shape index out of range");
+    const se2conv_shape& s = p->shapes[shape_idx];
+    const se2conv_shape& g = p->shapes[out_shape_idx];
+    if (g.nx < s.nx || g.ny < s.ny || g.m < s.m)
+        return fail(SE2CONV_ERR_INVALID_ARG, "output grid %d x %d x %d is coarser than the sampling grid %d x %d x %d",
+                    g.nx, g.ny, g.m, s.nx, s.ny, s.m);
+    if (batch < 1) return fail(SE2CONV_ERR_INVALID_ARG, "batch must be >= 1 (got %d)", batch);
+    if (!d_f || !d_out || !aligned16(d_f) || !aligned16(d_out))
+        return fail(SE2CONV_ERR_INVALID_ARG, "f and out must be non-null and 16-byte aligned");
+    if (flags & ~(SE2CONV_ADJOINT | SE2CONV_TIMING))
+        return fail(SE2CONV_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    const long long n = (long long)s.nx * s.ny * s.m;
+    const long long ng = (long long)g.nx * g.ny * g.m;
+    const size_t rb = real_bytes(p);
+    {
+        const char* a = (const char*)d_f;
+        const char* b = (const char*)d_out;
+        const long long fb = (long long)batch * n * (long long)rb, ob = (long long)batch * ng * (long long)rb;
+        if (a < b + ob && b < a + fb) return fail(SE2CONV_ERR_INVALID_ARG, "d_out must not overlap d_f");
+    }
+    Chain ch;
+    bool all_sep = true;
+    const void* tabs[1] = {d_table};
+    se2conv_status r = lookup_chain(p, shape_idx, tabs, 1, &ch, &all_sep);
+    if (r != SE2CONV_OK) return r;
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        if (!p->ws2 && hipMalloc(&p->ws2, 2 * p->ws_bytes) != hipSuccess)
+            return fail(SE2CONV_ERR_OUT_OF_MEMORY, "workspace (%zu bytes)", 2 * p->ws_bytes);
+    }
+    const bool d = dbl(p);
+    const bool conj = (flags & SE2CONV_ADJOINT) != 0;
+    if (flags & SE2CONV_TIMING) {
+        std::lock_guard<std::mutex> lk(p->mu);
+        HIPCHK(record_event(p, stream, true));
+        g_timing_plan = p;
+    }
+    // product spectrum of one field pair on the sampling grid (plan workspace planes)
+    void* hre = p->ws2;
+    void* him = (char*)p->ws2 + p->ws_bytes;
+    se2conv_status st = SE2CONV_OK;
+    for (int b = 0; b < batch && st == SE2CONV_OK; b += 2) {
+        const bool pair = b + 1 < batch;
+        const void* fa = (const char*)d_f + rb * n * b;
+        const void* fb = pair ? (const char*)d_f + rb * n * (b + 1) : nullptr;
+        void* oa = (char*)d_out + rb * ng * b;
+        // imaginary plane on the finer grid: the second field's output, or the plan
+        // workspace for a field without a partner (its values are discarded)
+        void* ob = pair ? (char*)d_out + rb * ng * (b + 1) : p->ws;
+        hipError_t e = xt_transform(p, s, d, 0, fa, fb, hre, him, nullptr, nullptr, n, n, 1, stream);
+        if (e == hipSuccess)
+            e = y_pass(p, s, d, hre, him, nullptr, n, 1, 1, 0, 2, &ch, conj, 1.0 / (double)n, stream);
+        if (e == hipSuccess)
+            e = launch_pad_spectrum(hre, him, oa, ob, s.nx, s.ny, s.m, g.nx, g.ny, g.m, d, stream);
+        if (e == hipSuccess) e = y_pass(p, g, d, oa, ob, nullptr, ng, 1, 0, 1, 0, nullptr, false, 1.0, stream);
+        if (e == hipSuccess)
+            e = xt_transform(p, g, d, 1, oa, ob, oa, pair ? ob : nullptr, nullptr, nullptr, ng, ng, 1, stream);
+        if (e != hipSuccess) st = fail(SE2CONV_ERR_DEVICE, "padded evaluation: %s", hipGetErrorString(e));
+    }
+    g_timing_plan = nullptr;
+    return st == SE2CONV_OK ? ok() : st;
+}
+
 int32_t se2conv_fused_supported(se2conv_plan_t p, int32_t shape_idx) {
     if (!p || p->host_only || shape_idx < 0 || shape_idx >= (int)p->shapes.size()) return 0;
     return use_full_fast(p, p->shapes[shape_idx]) ? 1 : 0;

@@ -1,0 +1,80 @@
+// Zero-padded spectrum for evaluating S_K on a finer grid (paper Sec. 4.1 eq.
+// (MatSKfonG), Sec. 6.1 eq. (MatSKfgonG), Prop. LtoN1D).
+//
+// The product spectrum H of one field pair lives on the sampling grid L = (Lx, Ly, Lm)
+// as two real planes (re, im), layout [k3][k2][k1].  The spectrum on the finer grid
+// G >= L keeps every signed frequency k of the L-grid at its G-grid index tau_G(k)
+// and is zero elsewhere.  For even L the index L/2 holds the frequencies +-L/2
+// together; on a finer grid it is split in halves between tau_G(-L/2) and
+// tau_G(+L/2), so that the evaluation of a real field stays real (when G = L both are
+// the same index and the value is kept whole).  One thread per G-grid element; every
+// element of the G-spectrum is written.
+#include <hip/hip_runtime.h>
+
+#include "fft_device.hpp"
+#include "passes.hpp"
+
+namespace se2c {
+
+// Source index on the L axis of G-grid index g, and its weight; -1: no source (zero).
+__device__ __forceinline__ int pad_source(int g, int G, int L, bool* half) {
+    const int k = signed_freq(g, G);
+    *half = false;
+    if (L & 1) {
+        const int K = (L - 1) / 2;
+        if (k < -K || k > K) return -1;
+        return k < 0 ? k + L : k;
+    }
+    const int h = L / 2;
+    if (k > -h && k < h) return k < 0 ? k + L : k;
+    if (k == h || k == -h) {
+        *half = G > L;
+        return h;
+    }
+    return -1;
+}
+
+template <typename T>
+__global__ void pad_spectrum_kernel(const T* __restrict__ sre, const T* __restrict__ sim, T* __restrict__ dre,
+                                    T* __restrict__ dim, int lx, int ly, int lm, int gx, int gy, int gm) {
+    const long long total = (long long)gx * gy * gm;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < total;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int g1 = (int)(i % gx);
+        const int g2 = (int)((i / gx) % gy);
+        const int g3 = (int)(i / ((long long)gx * gy));
+        bool h1, h2, h3;
+        const int s1 = pad_source(g1, gx, lx, &h1);
+        const int s2 = pad_source(g2, gy, ly, &h2);
+        const int s3 = pad_source(g3, gm, lm, &h3);
+        T re = (T)0, im = (T)0;
+        if (s1 >= 0 && s2 >= 0 && s3 >= 0) {
+            const long long src = ((long long)s3 * ly + s2) * lx + s1;
+            T w = (T)1;
+            if (h1) w *= (T)0.5;
+            if (h2) w *= (T)0.5;
+            if (h3) w *= (T)0.5;
+            re = w * sre[src];
+            im = w * sim[src];
+        }
+        dre[i] = re;
+        if (dim) dim[i] = im;
+    }
+}
+
+hipError_t launch_pad_spectrum(const void* sre, const void* sim, void* dre, void* dim, int lx, int ly, int lm, int gx,
+                               int gy, int gm, bool dbl, hipStream_t s) {
+    const long long total = (long long)gx * gy * gm;
+    const int nthr = 256;
+    const long long want = (total + nthr - 1) / nthr;
+    const int nb = (int)(want < 8192 ? want : 8192);
+    if (dbl)
+        hipLaunchKernelGGL(pad_spectrum_kernel<double>, dim3(nb), dim3(nthr), 0, s, (const double*)sre,
+                           (const double*)sim, (double*)dre, (double*)dim, lx, ly, lm, gx, gy, gm);
+    else
+        hipLaunchKernelGGL(pad_spectrum_kernel<float>, dim3(nb), dim3(nthr), 0, s, (const float*)sre,
+                           (const float*)sim, (float*)dre, (float*)dim, lx, ly, lm, gx, gy, gm);
+    return hipGetLastError();
+}
+
+}  // namespace se2c

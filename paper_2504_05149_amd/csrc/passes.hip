@@ -73,6 +73,7 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) slab_kernel(S
         const int rem = t - item * tiles_per_item;
         const int slab = rem / a.ntile_t;
         const int t0 = (rem - slab * a.ntile_t) * rows;
+        const int nrow = min(rows, a.m - t0);  // the last theta chunk may be shorter
         const bool last_odd = (a.lone_in1 != nullptr || a.lone_out1 != nullptr) && item == a.nitems - 1;
         if (a.items && a.mul && item != cur_item) {  // per-item chain factors (uniform branch)
             __syncthreads();
@@ -110,7 +111,7 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) slab_kernel(S
             if (in1) in1 += (long long)slab * a.nx;
         }
         __syncthreads();
-        const int P = rows * a.nx;
+        const int P = nrow * a.nx;
         for (int i = tid; i < P; i += nthr) {
             const int r = i / a.nx;
             const int x = i - r * a.nx;
@@ -124,7 +125,7 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) slab_kernel(S
 
         // ---- forward
         if (a.fwd) {
-            line_fft<T, MAXV, false, ODD>(tile, twx, a.px, 1, pitch, rows, false, tid, nthr);
+            line_fft<T, MAXV, false, ODD>(tile, twx, a.px, 1, pitch, nrow, false, tid, nthr);
             if (a.do_t) line_fft<T, MAXV, false, ODD>(tile, twt, a.pt, pitch, 1, a.nx, true, tid, nthr);
         }
         // ---- separable spectral product: z[kt][kx] *= Tx[kx] * Tt[kt] / (nx*m)
@@ -140,7 +141,7 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) slab_kernel(S
         // ---- inverse
         if (a.inv) {
             if (a.do_t) line_fft<T, MAXV, true, ODD>(tile, twt, a.pt, pitch, 1, a.nx, true, tid, nthr);
-            line_fft<T, MAXV, true, ODD>(tile, twx, a.px, 1, pitch, rows, false, tid, nthr);
+            line_fft<T, MAXV, true, ODD>(tile, twx, a.px, 1, pitch, nrow, false, tid, nthr);
         }
 
         // ---- store

@@ -112,6 +112,29 @@ def test_apply_validation_on_host_only_plan():
     assert lib.se2conv_coeffs(h, 0, ctypes.byref(d), 1, 1 << 16, ctypes.byref(n), None) == L.ERR_DEVICE
 
 
+def test_apply_padded_validation_on_host_only_plan():
+    lib = L.load()
+    p = se2.Plan([(32, 32, 16), (48, 40, 16), (24, 32, 16)], dtype="f32", host_only=True)
+    h = p.handle
+    fake_table = 4096
+    ok_f, ok_out = 1 << 20, 1 << 30
+    # shape indices out of range, an output grid coarser than the sampling grid
+    assert lib.se2conv_apply_padded(h, 3, ok_f, fake_table, 1, ok_out, 1, 0, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_apply_padded(h, 0, ok_f, fake_table, -1, ok_out, 1, 0, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_apply_padded(h, 0, ok_f, fake_table, 2, ok_out, 1, 0, None) == L.ERR_INVALID_ARG
+    assert b"coarser" in lib.se2conv_last_error()
+    # batch, null / misaligned pointers, flags, overlap of input and output
+    assert lib.se2conv_apply_padded(h, 0, ok_f, fake_table, 1, ok_out, 0, 0, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_apply_padded(h, 0, None, fake_table, 1, ok_out, 1, 0, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_apply_padded(h, 0, ok_f + 4, fake_table, 1, ok_out, 1, 0, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_apply_padded(h, 0, ok_f, fake_table, 1, ok_out, 1, 0x80, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_apply_padded(h, 0, ok_f, fake_table, 1, ok_f + 1024, 1, 0, None) == L.ERR_INVALID_ARG
+    assert b"overlap" in lib.se2conv_last_error()
+    # valid geometry: refused only because the table is not this plan's
+    assert lib.se2conv_apply_padded(h, 0, ok_f, fake_table, 1, ok_out, 1, 0, None) == L.ERR_INVALID_ARG
+    assert b"not produced by this plan" in lib.se2conv_last_error()
+
+
 def test_chain_validation_on_host_only_plan():
     lib = L.load()
     p = se2.Plan([(32, 32, 16)], dtype="f32", host_only=True)
