@@ -67,6 +67,29 @@ def gauss_vm_function(sigma, kappa, theta0=0.0):
     return rho
 
 
+def se2_log_sq_norm(x, y, t):
+    """||log(x, R_t)^v||^2 for the principal matrix logarithm of SE(2), t in [-pi, pi].
+
+    With g = [[R_t, x], [0, 1]], log g = [[t J, v], [0, 0]] where x = V(t) v and
+    V(t) = (sin t / t) I + ((1 - cos t) / t) J, a rotation scaled by 2|sin(t/2)|/|t|.
+    Hence |v| = |x| (t/2) / sin(t/2) and ||log^v||^2 = ((t/2)/sin(t/2))^2 |x|^2 + t^2.
+    """
+    h = 0.5 * np.asarray(t, dtype=np.float64)
+    safe = np.where(h == 0.0, 1.0, h)
+    fac = np.where(h == 0.0, 1.0, safe / np.sin(safe))
+    return fac * fac * (x * x + y * y) + (2.0 * h) ** 2
+
+
+def exp_gauss_function(sigma):
+    """Exponential-coordinates Gaussian rho(x, R) = exp(-||log(x, R)^v||^2 / (2 sigma^2))
+    (Sec. 6.3, eq. (gbS0)); theta is wrapped to (-pi, pi] for the principal logarithm.
+    Radial in translations (it depends on |x| only), not separable."""
+    def rho(x, y, t):
+        tw = np.where(t > np.pi, t - 2.0 * np.pi, t)
+        return np.exp(-se2_log_sq_norm(x, y, tw) / (2.0 * sigma * sigma))
+    return rho
+
+
 def anisotropic_function(sx, sy, kappa, theta0=0.0):
     """Non-radial control kernel exp(-x^2/2sx^2 - y^2/2sy^2) exp(kappa cos(theta-theta0))."""
     def rho(x, y, t):
