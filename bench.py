@@ -38,7 +38,11 @@ WORKLOADS = {
     # the paper's odd grids L = 2K+1: a prime length (direct-summation stages)
     "odd101": (101, 101, 101, 4, 32, 2, "f32", 5),
     "odd101_f64": (101, 101, 101, 4, 32, 2, "f64", 5),
+    # exponential-coordinates Gaussian (non-separable radial kernel, FULL table)
+    "expgauss": (256, 256, 64, 8, 32, 1, "f32", 2),
 }
+# workloads whose kernel is not a chain of Gauss-vM kernels: (kind, sigma)
+EXP_GAUSS_SIGMA = {"expgauss": 0.05}
 SPECIAL = ("c2", "c4", "padded")
 
 
@@ -54,8 +58,9 @@ def lib_source_hash() -> str:
 
 def describe(name):
     nx, ny, m, batch, nb, lc, dt, cfg = WORKLOADS[name]
-    return {"workload": f"{nx}x{ny}x{m} {dt}, batch {batch} fields of {nb} Gauss-vM bumps, "
-                        f"chain of {lc} Gauss-vM kernels (folded FP64 table)",
+    kern = (f"exponential-coordinates Gaussian kernel sigma={EXP_GAUSS_SIGMA[name]} (FULL FP64-generated table)"
+            if name in EXP_GAUSS_SIGMA else f"chain of {lc} Gauss-vM kernels (folded FP64 table)")
+    return {"workload": f"{nx}x{ny}x{m} {dt}, batch {batch} fields of {nb} Gauss-vM bumps, {kern}",
             "grid": [nx, ny, m], "batch": batch, "bumps": nb, "chain": lc, "seed_config": cfg}
 
 
@@ -74,7 +79,11 @@ def run_gpu(name, steps, warmup, tune=True):
         plan.autotune(0, batch=batch)
     t_tune = time.perf_counter() - t_tune
     ks = chain_kernel_params(cfg, lc)
-    table = plan.coeffs(0, [se2.GaussVM(k.sigma, k.kappa, k.theta0) for k in ks])
+    if name in EXP_GAUSS_SIGMA:
+        ks = None
+        table = plan.coeffs(0, [se2.ExpGauss(EXP_GAUSS_SIGMA[name])])
+    else:
+        table = plan.coeffs(0, [se2.GaussVM(k.sigma, k.kappa, k.theta0) for k in ks])
     f_host = sample_fields(cfg, batch, nb, nx, ny, m, dtype=np.float32 if dt == "f32" else np.float64)
     f = torch.from_numpy(f_host).to("cuda")
     out = torch.empty_like(f)
@@ -101,7 +110,7 @@ def run_gpu(name, steps, warmup, tune=True):
     out_host = out.cpu().numpy()
     plan.close()
     return dict(elapsed=elapsed, avg_ms=avg, launches=launches, f_host=f_host, out_host=out_host, ks=ks,
-                shape=(nx, ny, m), batch=batch, dtype=dt, tune_s=t_tune if tune else None)
+                shape=(nx, ny, m), batch=batch, dtype=dt, tune_s=t_tune if tune else None, name=name)
 
 
 def run_c2(steps, warmup):
@@ -296,7 +305,11 @@ def cpu_baseline(res, budget_s: float):
     from oracle import kernels as ok
 
     nx, ny, m = res["shape"]
-    ps = [ok.gauss_vm(nx, ny, m, k.sigma, k.kappa, k.theta0) for k in res["ks"]]
+    if res["ks"] is None:
+        p = ok.sample_function(ok.exp_gauss_function(EXP_GAUSS_SIGMA[res["name"]]), nx, ny, m, images=3)
+        ps = [p / p.mean()]
+    else:
+        ps = [ok.gauss_vm(nx, ny, m, k.sigma, k.kappa, k.theta0) for k in res["ks"]]
     table = oc.coeff_product(ps)
     f = res["f_host"].astype(np.float64)
     done = 0

@@ -94,7 +94,13 @@ typedef enum {
     /* radial profile: P[l][j][i] = sum_images sum_q prof[q][l] hat_q(|x_ij + image|),
        hat_q piecewise-linear with knots r_q = q r_max/(n_knots-1); `data` is the
        device FP64 array prof[n_knots][M]; 0 < r_max <= 1. */
-    SE2CONV_K_RADIAL_PROFILE = 2
+    SE2CONV_K_RADIAL_PROFILE = 2,
+    /* exponential-coordinates Gaussian (Sec. 6.3, eq. (gbS0)):
+       rho(x, R_theta) = exp(-||log(x, R_theta)^v||^2 / (2 sigma^2)) with the principal
+       logarithm, ||log^v||^2 = ((theta/2) / sin(theta/2))^2 |x|^2 + theta^2, theta
+       wrapped to (-pi, pi]; periodized over the lattice.  Radial in translations, not
+       separable: its table is FULL.  Uses `sigma` (> 0). */
+    SE2CONV_K_EXP_GAUSS = 3
 } se2conv_kernel_kind;
 
 /* normalisation (kernel flags, bits 0..1) */
@@ -105,7 +111,7 @@ typedef enum {
 typedef struct {
     int32_t kind;      /* se2conv_kernel_kind */
     uint32_t flags;    /* SE2CONV_KNORM_* */
-    double sigma;      /* GAUSS_VM: translational width (> 0) */
+    double sigma;      /* GAUSS_VM: translational width (> 0); EXP_GAUSS: width (> 0) */
     double kappa;      /* GAUSS_VM: von Mises concentration (>= 0) */
     double theta0;     /* GAUSS_VM: angular centre */
     const void* data;  /* SAMPLES / RADIAL_PROFILE: device FP64 array (see kind) */

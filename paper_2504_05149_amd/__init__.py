@@ -5,4 +5,4 @@ The compute path is libse2conv.so (hand-written HIP kernels behind a C ABI,
 include/se2conv.h); this package is its Python binding.
 """
 from ._lib import LIB_PATH, Se2convError  # noqa: F401
-from .api import GaussVM, Plan, RadialProfile, Samples, Table  # noqa: F401
+from .api import ExpGauss, GaussVM, Plan, RadialProfile, Samples, Table  # noqa: F401

@@ -15,7 +15,7 @@ OK, ERR_INVALID_ARG, ERR_UNSUPPORTED_SIZE, ERR_OUT_OF_MEMORY, ERR_DEVICE, ERR_IN
 F32, F64 = 0, 1
 PLAN_HOST_ONLY = 0x1
 PLAN_GENERIC = 0x2
-K_GAUSS_VM, K_SAMPLES, K_RADIAL_PROFILE = 0, 1, 2
+K_GAUSS_VM, K_SAMPLES, K_RADIAL_PROFILE, K_EXP_GAUSS = 0, 1, 2, 3
 KNORM_DISCRETE, KNORM_CONTINUOUS, KNORM_NONE = 0, 1, 2
 TABLE_SEPARABLE, TABLE_FULL = 0, 1
 ADJOINT, GRAPH, TIMING = 0x1, 0x2, 0x4

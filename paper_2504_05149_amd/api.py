@@ -37,6 +37,13 @@ class RadialProfile:
     norm: int = L.KNORM_NONE
 
 
+@dataclasses.dataclass
+class ExpGauss:
+    """Exponential-coordinates Gaussian exp(-||log(x, R)^v||^2 / (2 sigma^2)) (FULL table)."""
+    sigma: float
+    norm: int = L.KNORM_DISCRETE
+
+
 def _stream_handle(stream) -> int:
     if stream is None:
         stream = torch.cuda.current_stream()
@@ -55,6 +62,8 @@ def _desc(k) -> L.KernelDesc:
         _require(k.prof, torch.float64)
         d.kind, d.flags, d.data = L.K_RADIAL_PROFILE, k.norm, k.prof.data_ptr()
         d.n_knots, d.r_max = int(k.prof.shape[0]), float(k.r_max)
+    elif isinstance(k, ExpGauss):
+        d.kind, d.flags, d.sigma = L.K_EXP_GAUSS, k.norm, k.sigma
     else:
         raise TypeError(f"unknown kernel descriptor {k!r}")
     return d

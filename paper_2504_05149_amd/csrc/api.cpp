@@ -1111,6 +1111,13 @@ se2conv_status se2conv_coeffs(se2conv_plan_t p, int32_t shape_idx, const se2conv
                 if (norm == SE2CONV_KNORM_CONTINUOUS)
                     return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: continuous normalisation needs GAUSS_VM", j);
                 break;
+            case SE2CONV_K_EXP_GAUSS:
+                sep = false;
+                if (!(k.sigma > 0.0) || !std::isfinite(k.sigma))
+                    return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: need finite sigma > 0", j);
+                if (norm == SE2CONV_KNORM_CONTINUOUS)
+                    return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: continuous normalisation needs GAUSS_VM", j);
+                break;
             default:
                 return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: unknown kind %d", j, k.kind);
         }
@@ -1159,6 +1166,9 @@ se2conv_status se2conv_coeffs(se2conv_plan_t p, int32_t shape_idx, const se2conv
             const double* src = reinterpret_cast<const double*>(k.data);
             if (k.kind == SE2CONV_K_RADIAL_PROFILE) {
                 HIPCHK(launch_profile_samples(src, k.n_knots, k.r_max, s.nx, s.ny, s.m, samp, stream));
+                src = samp;
+            } else if (k.kind == SE2CONV_K_EXP_GAUSS) {
+                HIPCHK(launch_exp_gauss_samples(k.sigma, s.nx, s.ny, s.m, samp, stream));
                 src = samp;
             }
             // FP64 forward 3-D DFT of the real samples into (re, im) planes

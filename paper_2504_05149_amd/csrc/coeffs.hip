@@ -268,6 +268,38 @@ __global__ void profile_samples_kernel(const double* prof, int n_knots, double r
     }
 }
 
+// Exponential-coordinates Gaussian exp(-((t/2)/sin(t/2))^2 |x + l|^2 / (2 sigma^2) - t^2 / (2 sigma^2)),
+// summed over lattice images l, with theta_l wrapped to (-pi, pi] (principal logarithm of
+// SE(2)).  One thread per grid point.
+__global__ void exp_gauss_samples_kernel(double sigma, int nx, int ny, int m, double* out) {
+    const long long n = (long long)nx * ny * m;
+    const double inv2s2 = 1.0 / (2.0 * sigma * sigma);
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < n;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(idx % nx);
+        const int j = (int)((idx / nx) % ny);
+        const int l = (int)(idx / ((long long)nx * ny));
+        double t = 2.0 * M_PI * (double)l / (double)m;
+        if (t > M_PI) t -= 2.0 * M_PI;
+        const double h = 0.5 * t;
+        const double fac = (h == 0.0) ? 1.0 : h / sin(h);
+        const double x = -0.5 + (double)i / nx, y = -0.5 + (double)j / ny;
+        double acc = 0.0;
+        for (int a = -SE2C_GAUSS_IMAGES; a <= SE2C_GAUSS_IMAGES; ++a) {
+            for (int b = -SE2C_GAUSS_IMAGES; b <= SE2C_GAUSS_IMAGES; ++b) {
+                const double dx = x + a, dy = y + b;
+                acc += exp(-fac * fac * (dx * dx + dy * dy) * inv2s2);
+            }
+        }
+        out[idx] = acc * exp(-t * t * inv2s2);
+    }
+}
+
+hipError_t launch_exp_gauss_samples(double sigma, int nx, int ny, int m, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(exp_gauss_samples_kernel, dim3(2048), dim3(256), 0, s, sigma, nx, ny, m, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_profile_samples(const double* prof, int n_knots, double r_max, int nx, int ny, int m, double* out,
                                   hipStream_t s) {
     hipLaunchKernelGGL(profile_samples_kernel, dim3(2048), dim3(256), 0, s, prof, n_knots, r_max, nx, ny, m, out);

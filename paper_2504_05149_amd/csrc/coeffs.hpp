@@ -20,6 +20,7 @@ hipError_t launch_full_fold(const double* re, const double* im, double2* acc, lo
 hipError_t launch_full_fold_sep(const double2* sep, double2* acc, long long n, int nx, int ny, int first,
                                 hipStream_t s);
 hipError_t launch_round(const double2* src, void* dst, long long n, int dbl, hipStream_t s);
+hipError_t launch_exp_gauss_samples(double sigma, int nx, int ny, int m, double* out, hipStream_t s);
 hipError_t launch_profile_samples(const double* prof, int n_knots, double r_max, int nx, int ny, int m, double* out,
                                   hipStream_t s);
 
