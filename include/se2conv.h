@@ -207,6 +207,20 @@ se2conv_status se2conv_apply(se2conv_plan_t plan, int32_t shape_idx, const void*
                              void* d_out, int32_t batch, uint32_t flags, hipStream_t stream);
 
 /*
+ * se2conv_apply_complex: out[b] = S_K[f[b], chain] for complex-valued fields
+ * f: SE(2) -> C (the paper's setting, Sec. 3.2).  Every kernel kind is real in space,
+ * so S_K[a + i b] = S_K[a] + i S_K[b]: the real and imaginary parts of one field are
+ * the two planes of one pair of the full-table passes, read and written interleaved.
+ *   d_f, d_out  device arrays [batch][M][Ny][Nx] of complex values (re, im adjacent;
+ *               complex64 for F32 plans, complex128 for F64), 16-byte aligned;
+ *               d_out == d_f (in place) is allowed, other overlaps are not.
+ *   d_table     a table produced by se2conv_coeffs for this plan and shape.
+ * Runs on the generic passes (every size).  Flags: SE2CONV_ADJOINT, SE2CONV_TIMING.
+ */
+se2conv_status se2conv_apply_complex(se2conv_plan_t plan, int32_t shape_idx, const void* d_f, const void* d_table,
+                                     void* d_out, int32_t batch, uint32_t flags, hipStream_t stream);
+
+/*
  * se2conv_apply_padded: out[b] = Re S_K[f[b], chain] evaluated on a finer grid
  * (paper Sec. 4.1 eq. (MatSKfonG), Sec. 6.1 eq. (MatSKfgonG), Prop. LtoN1D: the
  * iDFT of the zero-padded product spectrum).

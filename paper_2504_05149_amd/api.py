@@ -154,6 +154,23 @@ class Plan:
                                         _stream_handle(stream)))
         return out
 
+    def apply_complex(self, shape_idx: int, f: torch.Tensor, table: Table, out: torch.Tensor | None = None,
+                      adjoint: bool = False, stream=None, timing: bool = False) -> torch.Tensor:
+        """S_K[f, chain] for complex-valued fields f (complex64 / complex128 by plan dtype)."""
+        cdt = torch.complex64 if self.dtype == L.F32 else torch.complex128
+        _require(f, cdt)
+        nx, ny, m = self.shapes[shape_idx]
+        if f.shape[-3:] != (m, ny, nx):
+            raise ValueError(f"field shape {tuple(f.shape)} does not end in {(m, ny, nx)}")
+        batch = f.numel() // (nx * ny * m)
+        if out is None:
+            out = torch.empty_like(f)
+        _require(out, cdt)
+        L.check(self._lib.se2conv_apply_complex(self.handle, shape_idx, f.data_ptr(), table.ptr, out.data_ptr(),
+                                                batch, (L.ADJOINT if adjoint else 0) | (L.TIMING if timing else 0),
+                                                _stream_handle(stream)))
+        return out
+
     def apply_padded(self, shape_idx: int, f: torch.Tensor, table: Table, out_shape_idx: int,
                      out: torch.Tensor | None = None, adjoint: bool = False, stream=None,
                      timing: bool = False) -> torch.Tensor:

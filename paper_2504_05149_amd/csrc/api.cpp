@@ -581,9 +581,10 @@ se2conv_status enqueue_sep_items(se2conv_plan_s* p, const se2conv_shape& s, cons
 // plane pairs.  in/out planes per item: (in0 + it*stride, in1 + it*stride).
 hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int dir, const void* in0,
                         const void* in1, void* out0, void* out1, const void* lone_in1, void* lone_out1,
-                        long long stride_in, long long stride_out, int nitems, hipStream_t st) {
+                        long long stride_in, long long stride_out, int nitems, hipStream_t st, int cplx = 0) {
     const RadixPlan px = make_radix_plan(s.nx), pt = make_radix_plan(s.m);
     SlabArgs a{};
+    a.cplx = cplx;
     a.in0 = in0;
     a.in1 = in1;
     a.out0 = out0;
@@ -618,6 +619,7 @@ hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int d
     a.ntile_t = (s.m + a.rows_per_tile - 1) / a.rows_per_tile;
     a.do_t = 0;
     PencilArgs b{};
+    b.cplx = cplx;
     b.mode = 1;
     b.axis = 2;
     b.nx = s.nx;
@@ -662,8 +664,9 @@ hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int d
 // y pencils on complex plane pairs: forward, optional product, inverse.
 hipError_t y_pass(se2conv_plan_s* p, const se2conv_shape& s, bool d, void* re, void* im, void* lone_im,
                   long long stride, int nitems, int fwd, int inv, int mul, const Chain* ch, bool conj,
-                  double scale, hipStream_t st) {
+                  double scale, hipStream_t st, int cplx = 0) {
     PencilArgs b{};
+    b.cplx = cplx;
     b.in0 = re;
     b.in1 = im;
     b.out0 = re;
@@ -1591,6 +1594,53 @@ se2conv_status se2conv_apply_padded(se2conv_plan_t p, int32_t shape_idx, const v
     }
     g_timing_plan = nullptr;
     return st == SE2CONV_OK ? ok() : st;
+}
+
+se2conv_status se2conv_apply_complex(se2conv_plan_t p, int32_t shape_idx, const void* d_f, const void* d_table,
+                                     void* d_out, int32_t batch, uint32_t flags, hipStream_t stream) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (shape_idx < 0 || shape_idx >= (int)p->shapes.size())
+        return fail(SE2CONV_ERR_INVALID_ARG, "shape_idx %d out of range", shape_idx);
+    if (batch < 1) return fail(SE2CONV_ERR_INVALID_ARG, "batch must be >= 1 (got %d)", batch);
+    if (!d_f || !d_out || !aligned16(d_f) || !aligned16(d_out))
+        return fail(SE2CONV_ERR_INVALID_ARG, "f and out must be non-null and 16-byte aligned");
+    if (flags & ~(SE2CONV_ADJOINT | SE2CONV_TIMING))
+        return fail(SE2CONV_ERR_INVALID_ARG, "unknown flags 0x%x", flags);
+    const se2conv_shape& s = p->shapes[shape_idx];
+    const long long n = (long long)s.nx * s.ny * s.m;
+    const size_t rb = real_bytes(p);
+    {
+        const char* a = (const char*)d_f;
+        const char* b = (const char*)d_out;
+        const long long bytes = 2LL * batch * n * (long long)rb;
+        if (a != b && a < b + bytes && b < a + bytes)
+            return fail(SE2CONV_ERR_INVALID_ARG, "f and out overlap without being equal");
+    }
+    Chain ch;
+    bool all_sep = true;
+    const void* tabs[1] = {d_table};
+    se2conv_status r = lookup_chain(p, shape_idx, tabs, 1, &ch, &all_sep);
+    if (r != SE2CONV_OK) return r;
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    const bool d = dbl(p);
+    if (flags & SE2CONV_TIMING) {
+        std::lock_guard<std::mutex> lk(p->mu);
+        HIPCHK(record_event(p, stream, true));
+        g_timing_plan = p;
+    }
+    // Re and Im of each field are the two planes of one pair, interleaved: the element
+    // stride is 2, the field stride 2n reals.
+    const void* f_im = (const char*)d_f + rb;
+    void* o_im = (char*)d_out + rb;
+    hipError_t e = xt_transform(p, s, d, 0, d_f, f_im, d_out, o_im, nullptr, nullptr, 2 * n, 2 * n, batch, stream, 1);
+    if (e == hipSuccess)
+        e = y_pass(p, s, d, d_out, o_im, nullptr, 2 * n, batch, 1, 1, 2, &ch, (flags & SE2CONV_ADJOINT) != 0,
+                   1.0 / (double)n, stream, 1);
+    if (e == hipSuccess)
+        e = xt_transform(p, s, d, 1, d_out, o_im, d_out, o_im, nullptr, nullptr, 2 * n, 2 * n, batch, stream, 1);
+    g_timing_plan = nullptr;
+    if (e != hipSuccess) return fail(SE2CONV_ERR_DEVICE, "complex apply: %s", hipGetErrorString(e));
+    return ok();
 }
 
 int32_t se2conv_fused_supported(se2conv_plan_t p, int32_t shape_idx) {

@@ -37,6 +37,7 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) slab_kernel(S
     C<T>* tile = reinterpret_cast<C<T>*>(smem_raw);
     const int pitch = a.nx + a.pad;                 // row pitch (complex) in LDS
     const int rows = a.rows_per_tile;
+    const int es = a.cplx ? 2 : 1;                  // element stride of the planes (interleaved complex: 2)
     C<T>* twx = tile + rows * pitch;
     C<T>* twt = twx + a.nx;
     C<T>* fx = twt + a.m;                           // separable factors (scaled)
@@ -105,17 +106,17 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) slab_kernel(S
             in0 += (long long)(2 * slab) * a.nx;
             in1 = in0 + a.nx;
         } else {
-            in0 += (long long)slab * a.nx;
+            in0 += (long long)slab * a.nx * es;
             in1 = last_odd ? reinterpret_cast<const T*>(a.lone_in1)
                            : (a.in1 ? reinterpret_cast<const T*>(a.in1) + (long long)item * a.item_stride_in : nullptr);
-            if (in1) in1 += (long long)slab * a.nx;
+            if (in1) in1 += (long long)slab * a.nx * es;
         }
         __syncthreads();
         const int P = nrow * a.nx;
         for (int i = tid; i < P; i += nthr) {
             const int r = i / a.nx;
             const int x = i - r * a.nx;
-            const long long off = (long long)(t0 + r) * plane + x;
+            const long long off = ((long long)(t0 + r) * plane + x) * es;
             C<T> v;
             v.x = in0[off];
             v.y = in1 ? in1[off] : (T)0;
@@ -152,15 +153,15 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) slab_kernel(S
             out0 += (long long)(2 * slab) * a.nx;
             out1 = out0 + a.nx;
         } else {
-            out0 += (long long)slab * a.nx;
+            out0 += (long long)slab * a.nx * es;
             out1 = last_odd ? reinterpret_cast<T*>(a.lone_out1)
                             : (a.out1 ? reinterpret_cast<T*>(a.out1) + (long long)item * a.item_stride_out : nullptr);
-            if (out1) out1 += (long long)slab * a.nx;
+            if (out1) out1 += (long long)slab * a.nx * es;
         }
         for (int i = tid; i < P; i += nthr) {
             const int r = i / a.nx;
             const int x = i - r * a.nx;
-            const long long off = (long long)(t0 + r) * plane + x;
+            const long long off = ((long long)(t0 + r) * plane + x) * es;
             const C<T> v = tile[r * pitch + x];
             out0[off] = v.x;
             if (out1) out1[off] = v.y;
@@ -191,6 +192,7 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) pencil_kernel
     }
 
     const long long plane = (long long)a.nx * a.ny;
+    const int es = a.cplx ? 2 : 1;  // element stride of the planes (interleaved complex: 2)
     // element stride along the transform axis (in real elements)
     const long long astride = (a.axis == 1) ? (long long)a.nx : plane;
     const int nother = (a.axis == 1) ? a.m : a.ny;
@@ -235,16 +237,16 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) pencil_kernel
                 tile[e * pitch + c] = v;
             }
         } else {
-            const T* in0 = reinterpret_cast<const T*>(a.in0) + (long long)item * a.item_stride_in + obase;
+            const T* in0 = reinterpret_cast<const T*>(a.in0) + (long long)item * a.item_stride_in + obase * es;
             const T* in1 = last_odd ? reinterpret_cast<const T*>(a.lone_in1)
                                     : (a.in1 ? reinterpret_cast<const T*>(a.in1) + (long long)item * a.item_stride_in : nullptr);
-            if (in1) in1 += obase;
+            if (in1) in1 += obase * es;
             for (int i = tid; i < P; i += nthr) {
                 const int e = i / a.W;
                 const int c = i - e * a.W;
                 C<T> v = mk<T>((T)0, (T)0);
                 if (c0 + c < a.ncols) {
-                    const long long off = e * astride + c0 + c;
+                    const long long off = (e * astride + c0 + c) * es;
                     v.x = in0[off];
                     v.y = in1 ? in1[off] : (T)0;
                 }
@@ -298,15 +300,15 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) pencil_kernel
                 if (c0 + c < a.ncols) out[(e * astride) / 2 + c0 + c] = tile[e * pitch + c];
             }
         } else {
-            T* out0 = reinterpret_cast<T*>(a.out0) + (long long)item * a.item_stride_out + obase;
+            T* out0 = reinterpret_cast<T*>(a.out0) + (long long)item * a.item_stride_out + obase * es;
             T* out1 = last_odd ? reinterpret_cast<T*>(a.lone_out1)
                                : (a.out1 ? reinterpret_cast<T*>(a.out1) + (long long)item * a.item_stride_out : nullptr);
-            if (out1) out1 += obase;
+            if (out1) out1 += obase * es;
             for (int i = tid; i < P; i += nthr) {
                 const int e = i / a.W;
                 const int c = i - e * a.W;
                 if (c0 + c < a.ncols) {
-                    const long long off = e * astride + c0 + c;
+                    const long long off = (e * astride + c0 + c) * es;
                     const C<T> v = tile[e * pitch + c];
                     out0[off] = v.x;
                     if (out1) out1[off] = v.y;

@@ -53,6 +53,7 @@ struct SlabArgs {
     const void* twx;
     const void* twt;
     const SepItem* items;   // device; non-null: item i reads items[i] (y-pair modes, separable product)
+    int cplx;               // plane mode: planes are interleaved (complex fields; in1 = in0 + 1, element stride 2)
 };
 
 // Tile = W adjacent columns x L points along axis (1 = y, 2 = theta) at a fixed
@@ -86,6 +87,7 @@ struct PencilArgs {
     RadixPlan p;
     const void* tw;
     const SepItem* items;   // device; non-null: item i reads items[i] (x-pair mode, 1-D factor product)
+    int cplx;               // plane mode: planes are interleaved (complex fields; in1 = in0 + 1, element stride 2)
 };
 
 size_t slab_lds_bytes(const SlabArgs& a, bool dbl);

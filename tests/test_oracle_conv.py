@@ -30,6 +30,18 @@ def test_route1_equals_direct_quadrature_radial(shape):
     assert rel_l2(a, b) < 1e-13
 
 
+def test_complex_field_route1_equals_quadrature_of_parts():
+    # f: SE(2) -> C (Sec. 3.2): route 1 on the complex field against the direct
+    # quadrature applied to its real and imaginary parts (the kernel is real)
+    a = _field(8, 12, 8, seed=6)
+    b = _field(8, 12, 8, seed=7)
+    rho = K.gauss_vm_function(0.1, 2.0, 0.4)
+    p = K.sample_function(rho, 8, 12, 8)
+    out = C.conv_chain(a + 1j * b, [p], return_complex=True)
+    ref = Q.quadrature_conv(a, rho) + 1j * Q.quadrature_conv(b, rho)
+    assert rel_l2(out, ref) < 1e-13
+
+
 def test_route1_equals_direct_quadrature_chain():
     f = _field(8, 8, 8, seed=1)
     rhos = [K.gauss_vm_function(0.09, 1.5, 0.2), K.gauss_vm_function(0.13, 3.0, 2.0)]
