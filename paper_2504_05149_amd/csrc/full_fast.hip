@@ -246,17 +246,42 @@ xt_full(FullFastArgs a) {
 
 // y pass: W = 16 adjacent x frequencies (columns of the re and im planes) x NY points
 // at one theta frequency; every pair of the batch in turn, the table loaded once.
-template <int NY> struct FullLineGeom {
+// Columns per workgroup: 32 (128-byte row segments per plane, one workgroup round at
+// 256^2 x 64) where the LDS allows; the backward keeps 16 (its accumulator and table
+// registers limit occupancy either way).
+template <int NY, int MODE> struct YFullW {
+    static constexpr int W = (MODE != 2 && NY <= 256) ? 32 : 16;
+};
+
+template <int NY, int MODE> struct FullLineGeom {
     static constexpr int R1 = NY > 256 ? 32 : 16;
     static constexpr int R2 = NY / R1;
     static constexpr int CC = R1 / R2;
-    static constexpr int W = 16;
+    static constexpr int W = YFullW<NY, MODE>::W;
     static constexpr int NT = W * R2;
 };
 
-template <int NY>
+template <int NY, int MODE>
 static constexpr size_t full_line_lds() {
-    return sizeof(float2) * ((size_t)NY * FullLineGeom<NY>::W + 2 * NY);
+    return sizeof(float2) * ((size_t)NY * FullLineGeom<NY, MODE>::W + 2 * NY);
+}
+
+// scale * prod_e T_e at (kt, ky, kx), conjugated for the adjoint
+__device__ __forceinline__ float2 full_table_factor(const FullFastArgs& a, int NYv, int kt, int ky, int kx) {
+    const int pl = a.nx * NYv;
+    float2 f = make_float2(a.scale, 0.f);
+    for (int e = 0; e < a.ntab; ++e) {
+        const float2* T = reinterpret_cast<const float2*>(a.tab[e]);
+        if (a.tab_full[e]) {
+            f = mul<float>(f, T[(long long)kt * pl + ky * a.nx + kx]);
+        } else {
+            f = mul<float>(f, T[kx]);
+            f = mul<float>(f, T[a.nx + ky]);
+            f = mul<float>(f, T[a.nx + NYv + kt]);
+        }
+    }
+    if (a.conj_tab) f.y = -f.y;
+    return f;
 }
 
 // MODE 0 (convolve): forward DFT along y, [copy of the spectrum to save], product
@@ -266,9 +291,11 @@ static constexpr size_t full_line_lds() {
 //   in the same sweep A[k] = sum_pairs Z_g[k] conj(Z_f[k]) with the field spectra Z_f
 //   (zf); at the end W[k] A[k] / n^2 goes through the inverse DFT along y to acc (two
 //   planes).  Its x-theta inverse has real part dL/dP summed over the batch.
-template <int NY, int MODE>
-__global__ void __launch_bounds__(FullLineGeom<NY>::NT) y_full(FullFastArgs a) {
-    using Gm = FullLineGeom<NY>;
+// T1: the chain is one FULL table (read with 32-bit offsets; the general product loop,
+// compiled in, would cost the registers of a fourth wave per SIMD).
+template <int NY, int MODE, bool T1 = false>
+__global__ void __launch_bounds__((FullLineGeom<NY, MODE>::NT)) y_full(FullFastArgs a) {
+    using Gm = FullLineGeom<NY, MODE>;
     constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC, W = Gm::W, NT = Gm::NT;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float2* buf = reinterpret_cast<float2*>(smem_raw);  // [k1*R2 + t][W]
@@ -287,31 +314,17 @@ __global__ void __launch_bounds__(FullLineGeom<NY>::NT) y_full(FullFastArgs a) {
     const int kt = blockIdx.x / ctiles;
     const int pl = a.nx * NY;
     const int npairs = (a.batch + 1) / 2;
-    // table factor for (kt, ky = k1 + R1 k2, kx), k1 = CC t + j
+    // table factor for (kt, ky = k1 + R1 k2, kx), k1 = CC t + j: held in registers across
+    // the pair loop by the backward; the convolution re-reads it per pair (cache hits after
+    // the first pair), which keeps it within 128 registers (four waves per SIMD)
     float2 tv[CC][R2];
-    if constexpr (MODE != 1) {
+    if constexpr (MODE == 2) {
         const int q = tid % W, t = tid / W;
         const int kx = (blockIdx.x - kt * ctiles) * W + q;
 #pragma unroll
-        for (int j = 0; j < CC; ++j) {
+        for (int j = 0; j < CC; ++j)
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) {
-                const int ky = CC * t + j + R1 * k2;
-                float2 f = make_float2(a.scale, 0.f);
-                for (int e = 0; e < a.ntab; ++e) {
-                    const float2* T = reinterpret_cast<const float2*>(a.tab[e]);
-                    if (a.tab_full[e]) {
-                        f = mul<float>(f, T[(long long)kt * pl + ky * a.nx + kx]);
-                    } else {
-                        f = mul<float>(f, T[kx]);
-                        f = mul<float>(f, T[a.nx + ky]);
-                        f = mul<float>(f, T[a.nx + NY + kt]);
-                    }
-                }
-                if (a.conj_tab) f.y = -f.y;
-                tv[j][k2] = f;
-            }
-        }
+            for (int k2 = 0; k2 < R2; ++k2) tv[j][k2] = full_table_factor(a, NY, kt, CC * t + j + R1 * k2, kx);
     }
     float2 acc[CC][R2];
     if constexpr (MODE == 2) {
@@ -378,8 +391,26 @@ __global__ void __launch_bounds__(FullLineGeom<NY>::NT) y_full(FullFastArgs a) {
 #pragma unroll
         for (int j = 0; j < CC; ++j) {
             const int k1 = CC * t + j;
+            if constexpr (MODE == 2) {
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = mul<float>(u[j][k2], tv[j][k2]);
+                for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = mul<float>(u[j][k2], tv[j][k2]);
+            } else if constexpr (T1) {
+                // one FULL table: 32-bit byte offsets from the uniform table base
+                const char* T = reinterpret_cast<const char*>(a.tab[0]);
+                const unsigned o0 = (unsigned)(base + k1 * a.nx) * 8u;
+                const unsigned ostep = (unsigned)(R1 * a.nx) * 8u;
+                const float sc = a.scale, sg = a.conj_tab ? -a.scale : a.scale;
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) {
+                    const float2 tf = *reinterpret_cast<const float2*>(T + (o0 + (unsigned)k2 * ostep));
+                    u[j][k2] = mul<float>(u[j][k2], make_float2(tf.x * sc, tf.y * sg));
+                }
+            } else {
+                const int kx = base - kt * pl;
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2)
+                    u[j][k2] = mul<float>(u[j][k2], full_table_factor(a, NY, kt, k1 + R1 * k2, kx));
+            }
             RegDFT<R2, true, float>::run(u[j]);
 #pragma unroll
             for (int tt = 1; tt < R2; ++tt) u[j][tt] = mulc<float>(u[j][tt], tw_i[tt * R1 + k1]);
@@ -471,10 +502,13 @@ hipError_t launch_xt_full_inv(const FullFastArgs& a, hipStream_t s) { return lau
 
 template <int NY, int MODE>
 static hipError_t launch_y_full_t(const FullFastArgs& a, hipStream_t s) {
-    const int nblocks = (a.nx / FullLineGeom<NY>::W) * a.m;
-    const int nthr = FullLineGeom<NY>::NT;
-    const size_t lds = full_line_lds<NY>();
-    hipLaunchKernelGGL((y_full<NY, MODE>), dim3(nblocks), dim3(nthr), lds, s, a);
+    const int nblocks = (a.nx / FullLineGeom<NY, MODE>::W) * a.m;
+    const int nthr = FullLineGeom<NY, MODE>::NT;
+    const size_t lds = full_line_lds<NY, MODE>();
+    if (MODE == 0 && a.ntab == 1 && a.tab_full[0])
+        hipLaunchKernelGGL((y_full<NY, MODE, true>), dim3(nblocks), dim3(nthr), lds, s, a);
+    else
+        hipLaunchKernelGGL((y_full<NY, MODE, false>), dim3(nblocks), dim3(nthr), lds, s, a);
     return hipGetLastError();
 }
 
@@ -501,9 +535,13 @@ hipError_t launch_y_full_backward(const FullFastArgs& a, hipStream_t s) { return
     if (e != hipSuccess) return e;
 #define SE2C_Y_FULL_ATTR1(NY_, MODE_)                                                                       \
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full<NY_, MODE_>),                               \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_>());          \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_, MODE_>());   \
     if (e != hipSuccess) return e;
-#define SE2C_Y_FULL_ATTR(NY_) SE2C_Y_FULL_ATTR1(NY_, 0) SE2C_Y_FULL_ATTR1(NY_, 1) SE2C_Y_FULL_ATTR1(NY_, 2)
+#define SE2C_Y_FULL_ATTR(NY_)                                                                               \
+    SE2C_Y_FULL_ATTR1(NY_, 0) SE2C_Y_FULL_ATTR1(NY_, 1) SE2C_Y_FULL_ATTR1(NY_, 2)                            \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full<NY_, 0, true>),                             \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_, 0>());       \
+    if (e != hipSuccess) return e;
 
 hipError_t prepare_full_fast_kernels() {
     hipError_t e;
