@@ -178,6 +178,12 @@ struct se2conv_plan_s {
     size_t basis_bytes = 0;
     int basis_shape = -1, basis_knots = 0;
     double basis_rmax = 0.0;
+    // its real 2-D DFT on the quadrant k1 <= Nx/2, k2 <= Ny/2 (radial-profile tables in
+    // se2conv_coeffs), same geometry key
+    double* basis_hat = nullptr;
+    size_t basis_hat_bytes = 0;
+    int bh_shape = -1, bh_knots = 0;
+    double bh_rmax = 0.0;
     std::unordered_map<uintptr_t, TableRec> tables;
     std::vector<SubmissionRec> subs;
     // concurrent shape classes in se2conv_chain: auxiliary streams (default priority)
@@ -936,6 +942,67 @@ se2conv_status ensure_scratch64(se2conv_plan_s* p, size_t bytes) {
 }  // namespace
 
 // ===================================================================== C ABI
+// Hat basis of a radial-profile geometry (shared by the profile gradient and the table
+// builder); rebuilt when the shape, knot count or radius changes.  Caller holds p->mu.
+se2conv_status ensure_profile_basis(se2conv_plan_s* p, int shape_idx, int n_knots, double r_max, hipStream_t stream) {
+    const se2conv_shape& s = p->shapes[shape_idx];
+    if (p->basis_shape == shape_idx && p->basis_knots == n_knots && p->basis_rmax == r_max) return SE2CONV_OK;
+    const size_t need = sizeof(double) * (size_t)((long long)s.nx * s.ny * n_knots);
+    if (p->basis_bytes < need) {
+        if (p->basis) {
+            hipError_t e = hipFree(p->basis);
+            p->basis = nullptr;
+            p->basis_bytes = 0;
+            if (e != hipSuccess) return fail(SE2CONV_ERR_DEVICE, "hipFree: %s", hipGetErrorString(e));
+        }
+        if (hipMalloc(reinterpret_cast<void**>(&p->basis), need) != hipSuccess)
+            return fail(SE2CONV_ERR_OUT_OF_MEMORY, "could not allocate %zu bytes for the profile basis", need);
+        p->basis_bytes = need;
+    }
+    p->basis_shape = -1;
+    p->bh_shape = -1;  // its spectrum is stale too
+    HIPCHK(launch_profile_basis(p->basis, n_knots, r_max, s.nx, s.ny, stream));
+    p->basis_shape = shape_idx;
+    p->basis_knots = n_knots;
+    p->basis_rmax = r_max;
+    return SE2CONV_OK;
+}
+
+// Real 2-D DFT of that basis on the quadrant (FP64), for building radial-profile tables as
+// a contraction over the knots.  tmp: n_knots ny (nx/2+1) double2 of scratch.  Caller
+// holds p->mu.
+se2conv_status ensure_basis_hat(se2conv_plan_s* p, int shape_idx, int n_knots, double r_max, double2* tmp,
+                                hipStream_t stream) {
+    se2conv_status r = ensure_profile_basis(p, shape_idx, n_knots, r_max, stream);
+    if (r != SE2CONV_OK) return r;
+    if (p->bh_shape == shape_idx && p->bh_knots == n_knots && p->bh_rmax == r_max) return SE2CONV_OK;
+    const se2conv_shape& s = p->shapes[shape_idx];
+    const size_t need = sizeof(double) * (size_t)((long long)(s.nx / 2 + 1) * (s.ny / 2 + 1) * n_knots);
+    if (p->basis_hat_bytes < need) {
+        if (p->basis_hat) {
+            hipError_t e = hipFree(p->basis_hat);
+            p->basis_hat = nullptr;
+            p->basis_hat_bytes = 0;
+            if (e != hipSuccess) return fail(SE2CONV_ERR_DEVICE, "hipFree: %s", hipGetErrorString(e));
+        }
+        if (hipMalloc(reinterpret_cast<void**>(&p->basis_hat), need) != hipSuccess)
+            return fail(SE2CONV_ERR_OUT_OF_MEMORY, "could not allocate %zu bytes for the basis spectrum", need);
+        p->basis_hat_bytes = need;
+    }
+    HIPCHK(launch_basis_dft(p->basis, reinterpret_cast<const double2*>(tw_of(p, s.nx, true)),
+                            reinterpret_cast<const double2*>(tw_of(p, s.ny, true)), n_knots, s.nx, s.ny, tmp,
+                            p->basis_hat, stream));
+    p->bh_shape = shape_idx;
+    p->bh_knots = n_knots;
+    p->bh_rmax = r_max;
+    return SE2CONV_OK;
+}
+
+// The knot contraction applies when its per-k3 sums fit the fold kernel.
+bool profile_by_basis(const se2conv_shape& s, int n_knots) {
+    return s.m <= kProfileFoldMaxM && n_knots <= kProfileFoldMaxM;
+}
+
 extern "C" {
 
 se2conv_status se2conv_pass_times(se2conv_plan_t p, float* ms, int32_t* kinds, int32_t cap, int32_t* n) {
@@ -1072,6 +1139,7 @@ se2conv_status se2conv_plan_destroy(se2conv_plan_t p) {
         if (p->ws4) (void)hipFree(p->ws4);
         if (p->scratch64) (void)hipFree(p->scratch64);
         if (p->basis) (void)hipFree(p->basis);
+        if (p->basis_hat) (void)hipFree(p->basis_hat);
         if (cur >= 0) (void)hipSetDevice(cur);
     }
     delete p;
@@ -1139,7 +1207,12 @@ se2conv_status se2conv_coeffs(se2conv_plan_t p, int32_t shape_idx, const se2conv
     std::lock_guard<std::mutex> g(p->mu);
     const int nsep = s.nx + s.ny + s.m;
     // FP64 scratch: sep accumulator | (full) accumulator n | spectrum re n | im n | samples n
-    const size_t need = sizeof(double2) * nsep + (sep ? 0 : (sizeof(double2) * n + 3 * sizeof(double) * n));
+    // (re .. samples also serve as the basis-DFT temporary of a radial profile)
+    size_t need = sizeof(double2) * nsep + (sep ? 0 : (sizeof(double2) * n + 3 * sizeof(double) * n));
+    for (int j = 0; j < n_kernels && !sep; ++j)
+        if (kernels[j].kind == SE2CONV_K_RADIAL_PROFILE && profile_by_basis(s, kernels[j].n_knots))
+            need = std::max(need, sizeof(double2) * (nsep + (size_t)n) +
+                                      sizeof(double2) * (size_t)((long long)kernels[j].n_knots * s.ny * (s.nx / 2 + 1)));
     se2conv_status r = ensure_scratch64(p, need);
     if (r != SE2CONV_OK) return r;
     auto* sepacc = reinterpret_cast<double2*>(p->scratch64);
@@ -1165,6 +1238,15 @@ se2conv_status se2conv_coeffs(se2conv_plan_t p, int32_t shape_idx, const se2conv
                 HIPCHK(launch_full_fold_sep(sepacc, full, n, s.nx, s.ny, first_full, stream));
                 first_full = false;
             }
+        } else if (k.kind == SE2CONV_K_RADIAL_PROFILE && profile_by_basis(s, k.n_knots)) {
+            // P^ = sum_q prof^[q] H_q^ with the basis spectrum cached per geometry
+            auto* tmp = reinterpret_cast<double2*>(re);
+            se2conv_status rb = ensure_basis_hat(p, shape_idx, k.n_knots, k.r_max, tmp, stream);
+            if (rb != SE2CONV_OK) return rb;
+            HIPCHK(launch_profile_fold(reinterpret_cast<const double*>(k.data),
+                                       reinterpret_cast<const double2*>(tw_of(p, s.m, true)), p->basis_hat, k.n_knots,
+                                       s.nx, s.ny, s.m, norm == 0 ? 0 : 1, tmp, full, first_full, stream));
+            first_full = false;
         } else {
             const double* src = reinterpret_cast<const double*>(k.data);
             if (k.kind == SE2CONV_K_RADIAL_PROFILE) {
@@ -1296,24 +1378,9 @@ se2conv_status se2conv_profile_grad(se2conv_plan_t p, int32_t shape_idx, const v
     const se2conv_shape& s = p->shapes[shape_idx];
     const long long npts = (long long)s.nx * s.ny;
     std::lock_guard<std::mutex> g(p->mu);
-    if (p->basis_shape != shape_idx || p->basis_knots != n_knots || p->basis_rmax != r_max) {
-        const size_t need = sizeof(double) * (size_t)(npts * n_knots);
-        if (p->basis_bytes < need) {
-            if (p->basis) {
-                hipError_t e = hipFree(p->basis);
-                p->basis = nullptr;
-                p->basis_bytes = 0;
-                if (e != hipSuccess) return fail(SE2CONV_ERR_DEVICE, "hipFree: %s", hipGetErrorString(e));
-            }
-            if (hipMalloc(reinterpret_cast<void**>(&p->basis), need) != hipSuccess)
-                return fail(SE2CONV_ERR_OUT_OF_MEMORY, "could not allocate %zu bytes for the profile basis", need);
-            p->basis_bytes = need;
-        }
-        p->basis_shape = -1;
-        HIPCHK(launch_profile_basis(p->basis, n_knots, r_max, s.nx, s.ny, stream));
-        p->basis_shape = shape_idx;
-        p->basis_knots = n_knots;
-        p->basis_rmax = r_max;
+    {
+        se2conv_status rb = ensure_profile_basis(p, shape_idx, n_knots, r_max, stream);
+        if (rb != SE2CONV_OK) return rb;
     }
     const long long nsplit = profile_grad_splits(npts);
     se2conv_status r = ensure_scratch64(p, sizeof(double) * (size_t)(npts * s.m + nsplit * n_knots * s.m));

@@ -300,6 +300,170 @@ hipError_t launch_exp_gauss_samples(double sigma, int nx, int ny, int m, double*
     return hipGetLastError();
 }
 
+// ------------------------------------- radial-profile tables from the basis spectrum
+// The samples of a radial profile are P[l] = sum_q prof[q][l] H_q with H_q the periodized
+// hat basis on the spatial grid, so their 3-D DFT (eq. (3DFT)) is
+//     P^[k3][k2][k1] = sum_q prof^[k3][q] H_q^[k2][k1],
+// prof^ the DFT of prof along theta and H_q^ the 2-D DFT of H_q (built once per geometry).
+// H_q is real, periodic and even in x and in y (H[j][N - i] = H[j][i], the grid point
+// x_{N-i} being -x_i mod 1), so H_q^ is real and even in k1 and in k2: only the quadrant
+// 0 <= k1 <= Nx/2, 0 <= k2 <= Ny/2 is kept, as real numbers.  The FFC table is then
+// (-1)^{k1+k2} P^ / norm (eq. (FkLv)), all in FP64.
+
+// X[q][j][k1] = sum_i H[q][j][i] w_nx^{k1 i}, k1 <= nx/2
+__global__ void basis_dft_x_kernel(const double* basis, const double2* twx, int nq, int nx, int ny, double2* out) {
+    const int hx = nx / 2 + 1;
+    const long long total = (long long)nq * ny * hx;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int k1 = (int)(idx % hx);
+        const long long row = idx / hx;  // q * ny + j
+        const double* h = basis + row * nx;
+        double re = 0.0, im = 0.0;
+        int t = 0;
+        for (int i = 0; i < nx; ++i) {
+            const double2 w = twx[t];
+            re += h[i] * w.x;
+            im += h[i] * w.y;
+            t += k1;
+            if (t >= nx) t -= nx;
+        }
+        out[idx] = make_double2(re, im);
+    }
+}
+
+// hr[q][k2][k1] = Re sum_j X[q][j][k1] w_ny^{k2 j}, k1 <= nx/2, k2 <= ny/2 (the imaginary
+// part vanishes by the symmetry above)
+__global__ void basis_dft_y_kernel(const double2* X, const double2* twy, int nq, int nx, int ny, double* out) {
+    const int hx = nx / 2 + 1, hy = ny / 2 + 1;
+    const long long quad = (long long)hx * hy;
+    const long long total = (long long)nq * quad;
+    for (long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x; idx < total;
+         idx += (long long)gridDim.x * blockDim.x) {
+        const int q = (int)(idx / quad);
+        const long long rem = idx - (long long)q * quad;
+        const int k2 = (int)(rem / hx), k1 = (int)(rem % hx);
+        const double2* x = X + (long long)q * ny * hx + k1;
+        double re = 0.0;
+        int t = 0;
+        for (int j = 0; j < ny; ++j) {
+            const double2 v = x[(long long)j * hx];
+            const double2 w = twy[t];
+            re += v.x * w.x - v.y * w.y;
+            t += k2;
+            if (t >= ny) t -= ny;
+        }
+        out[idx] = re;
+    }
+}
+
+// phT[g][q][i] = prof^[k3 = g + 4 i][q] = sum_l prof[q][l] w_m^{k3 l} (zero for k3 >= m):
+// the values one wave of the fold kernel needs for knot q, contiguous
+__global__ void profile_theta_dft_kernel(const double* prof, const double2* twm, int nq, int m, double2* pht) {
+    constexpr int KI = kProfileFoldMaxM / 4;
+    for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < 4 * nq * KI; idx += gridDim.x * blockDim.x) {
+        const int i = idx % KI;
+        const int q = (idx / KI) % nq;
+        const int g = idx / (KI * nq);
+        const int k3 = g + 4 * i;
+        double re = 0.0, im = 0.0;
+        if (k3 < m) {
+            int t = 0;
+            for (int l = 0; l < m; ++l) {
+                const double v = prof[(long long)q * m + l];
+                re += v * twm[t].x;
+                im += v * twm[t].y;
+                t += k3;
+                if (t >= m) t -= m;
+            }
+        }
+        pht[idx] = make_double2(re, im);
+    }
+}
+
+// acc[k3][k2][k1] (*)= (-1)^{k1+k2} / norm * sum_q prof^[k3][q] hr[q][|k2|][|k1|], norm = P^[0]
+// (the sample sum, discrete mass) or n.  One lane per quadrant frequency (|k1|, |k2|); the
+// four waves of a block split k3 (wave g: k3 = g + 4 i), each lane keeping 16 complex sums
+// while hr[q] streams through; the wave-uniform prof^ values come through scalar loads.
+// Each result goes to the up to four mirrored frequencies.  Requires m, n_knots <= 64.
+__global__ void __launch_bounds__(256) profile_fold_kernel(const double* hr, const double2* pht, int nq, int nx,
+                                                           int ny, int m, int norm_mode, double2* acc, int first) {
+    constexpr int KI = kProfileFoldMaxM / 4;
+    const int hx = nx / 2 + 1, hy = ny / 2 + 1;
+    const long long quad = (long long)hx * hy;
+    const long long nxy = (long long)nx * ny;
+    const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const long long kq0 = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
+    const long long kq = kq0 < quad ? kq0 : quad - 1;  // clamped lanes compute, never store
+    double2 sum[KI];
+#pragma unroll
+    for (int i = 0; i < KI; ++i) sum[i] = make_double2(0.0, 0.0);
+    const double2* pw = pht + (long long)g * nq * KI;
+    double h = hr[kq];
+    for (int q = 0; q < nq; ++q) {
+        const double hn = hr[(long long)(q + 1 < nq ? q + 1 : q) * quad + kq];
+#pragma unroll
+        for (int i = 0; i < KI; ++i) {
+            const double2 a = pw[q * KI + i];
+            sum[i].x += a.x * h;
+            sum[i].y += a.y * h;
+        }
+        h = hn;
+    }
+    if (kq0 >= quad) return;
+    double inv = 1.0 / (double)(nxy * m);
+    if (norm_mode == 0) {
+        double s0 = 0.0;  // P^[0,0,0]: the sum of the (real) samples
+        for (int q = 0; q < nq; ++q) s0 += pht[(long long)q * KI].x * hr[(long long)q * quad];
+        inv = 1.0 / s0;
+    }
+    const int a1 = (int)(kq % hx), a2 = (int)(kq / hx);
+    const int m1 = (nx - a1) % nx, m2 = (ny - a2) % ny;  // mirrored indices
+    const double sg = ((signed_freq(a1, nx) + signed_freq(a2, ny)) & 1) ? -inv : inv;
+    const long long pos[4] = {(long long)a2 * nx + a1, (long long)a2 * nx + m1, (long long)m2 * nx + a1,
+                              (long long)m2 * nx + m1};
+    const bool use[4] = {true, m1 != a1, m2 != a2, m1 != a1 && m2 != a2};
+#pragma unroll
+    for (int i = 0; i < KI; ++i) {
+        const int k3 = g + 4 * i;
+        if (k3 < m) {
+            const double2 v = make_double2(sum[i].x * sg, sum[i].y * sg);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (!use[c]) continue;
+                const long long o = (long long)k3 * nxy + pos[c];
+                double2 w = v;
+                if (!first) {
+                    const double2 b = acc[o];
+                    w = make_double2(b.x * v.x - b.y * v.y, b.x * v.y + b.y * v.x);
+                }
+                acc[o] = w;
+            }
+        }
+    }
+}
+
+hipError_t launch_basis_dft(const double* basis, const double2* twx, const double2* twy, int nq, int nx, int ny,
+                            double2* tmp, double* hr, hipStream_t s) {
+    hipLaunchKernelGGL(basis_dft_x_kernel, dim3(4096), dim3(256), 0, s, basis, twx, nq, nx, ny, tmp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(basis_dft_y_kernel, dim3(4096), dim3(256), 0, s, tmp, twy, nq, nx, ny, hr);
+    return hipGetLastError();
+}
+
+hipError_t launch_profile_fold(const double* prof, const double2* twm, const double* hr, int nq, int nx, int ny,
+                               int m, int norm_mode, double2* pht, double2* acc, int first, hipStream_t s) {
+    const int np = 4 * nq * (kProfileFoldMaxM / 4);
+    hipLaunchKernelGGL(profile_theta_dft_kernel, dim3((np + 255) / 256), dim3(256), 0, s, prof, twm, nq, m, pht);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const long long quad = (long long)(nx / 2 + 1) * (ny / 2 + 1);
+    hipLaunchKernelGGL(profile_fold_kernel, dim3((unsigned)((quad + 63) / 64)), dim3(256), 0, s, hr, pht, nq, nx, ny,
+                       m, norm_mode, acc, first);
+    return hipGetLastError();
+}
+
 hipError_t launch_profile_samples(const double* prof, int n_knots, double r_max, int nx, int ny, int m, double* out,
                                   hipStream_t s) {
     hipLaunchKernelGGL(profile_samples_kernel, dim3(2048), dim3(256), 0, s, prof, n_knots, r_max, nx, ny, m, out);

@@ -20,6 +20,15 @@ hipError_t launch_full_fold(const double* re, const double* im, double2* acc, lo
 hipError_t launch_full_fold_sep(const double2* sep, double2* acc, long long n, int nx, int ny, int first,
                                 hipStream_t s);
 hipError_t launch_round(const double2* src, void* dst, long long n, int dbl, hipStream_t s);
+// Radial-profile tables from the 2-D DFT of the hat basis (cached per geometry):
+// hr[q][k2][k1], 0 <= k1 <= nx/2, 0 <= k2 <= ny/2, the real spectrum of basis[q] (tmp:
+// nq ny (nx/2+1) double2 of scratch), then the FFC table folded into acc for profiles with
+// M <= kProfileFoldMaxM and n_knots <= kProfileFoldMaxM (pht: 4 n_knots 16 double2).
+constexpr int kProfileFoldMaxM = 64;
+hipError_t launch_basis_dft(const double* basis, const double2* twx, const double2* twy, int nq, int nx, int ny,
+                            double2* tmp, double* hr, hipStream_t s);
+hipError_t launch_profile_fold(const double* prof, const double2* twm, const double* hr, int nq, int nx, int ny,
+                               int m, int norm_mode, double2* pht, double2* acc, int first, hipStream_t s);
 hipError_t launch_exp_gauss_samples(double sigma, int nx, int ny, int m, double* out, hipStream_t s);
 hipError_t launch_profile_samples(const double* prof, int n_knots, double r_max, int nx, int ny, int m, double* out,
                                   hipStream_t s);
