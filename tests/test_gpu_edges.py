@@ -1,0 +1,113 @@
+"""GPU edge cases against the FP64 oracle: the smallest grids, the longest per-axis
+lengths, the longest runtime chain (8 tables, separable and FULL mixed), long odd
+batches (a lone last field in the pair packing), and the degenerate fields (zero and
+constant inputs)."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2504_05149_amd as se2
+from gpu_common import TOL64, case, oracle_table_gauss, rel_l2, tol32
+from inputs import chain_kernel_params, sample_fields
+from oracle import conv as oc
+from oracle import kernels as ok
+from oracle.ffc import ffc
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype)
+
+
+def _tol(dt, shape):
+    return tol32(shape[0] * shape[1] * shape[2]) if dt == "f32" else TOL64
+
+
+@pytest.mark.parametrize("shape,batch,dt", [
+    ((8, 8, 2), 1, "f32"), ((8, 8, 2), 3, "f64"), ((9, 8, 3), 2, "f32"), ((8, 12, 5), 3, "f64"),
+    ((512, 8, 4), 2, "f32"), ((8, 512, 2), 1, "f32"), ((8, 8, 512), 2, "f32"),
+])
+def test_smallest_and_longest_axes(shape, batch, dt):
+    case(f"edge grid {shape} batch={batch} {dt}: separable and radial-profile tables")
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    plan = se2.Plan([shape], dtype=dt)
+    chain = [(0.15, 2.0, 0.3), (0.1, 1.0, 1.0)]
+    t_sep = plan.coeffs(0, [se2.GaussVM(*c) for c in chain])
+    prof = np.random.default_rng([2504_05149, 83]).uniform(0, 1, size=(5, shape[2]))
+    t_full = plan.coeffs(0, [se2.RadialProfile(_dev(prof, torch.float64), 0.45)])
+    f = sample_fields(15, batch, 4, *shape)
+    o_sep = plan.apply(0, _dev(f, tdt), t_sep).cpu().numpy().astype(np.float64)
+    o_full = plan.apply(0, _dev(f, tdt), t_full).cpu().numpy().astype(np.float64)
+    ref_sep = oracle_table_gauss(*shape, chain)
+    ref_full = ffc(ok.radial_profile(*shape, prof, 0.45))
+    for b in range(batch):
+        e1 = rel_l2(o_sep[b], oc.conv_with_coeffs(f[b], ref_sep))
+        e2 = rel_l2(o_full[b], oc.conv_with_coeffs(f[b], ref_full))
+        print(f"  field {b}: separable {e1:.2e}, full {e2:.2e}", flush=True)
+        assert e1 <= _tol(dt, shape) and e2 <= _tol(dt, shape)
+
+
+@pytest.mark.parametrize("shape,dt", [((32, 32, 16), "f32"), ((45, 33, 21), "f64")])
+def test_longest_runtime_chain_mixed_tables(shape, dt):
+    case(f"runtime chain of 8 tables (6 separable, 2 FULL) {shape} {dt}")
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    plan = se2.Plan([shape], dtype=dt)
+    ks = chain_kernel_params(16, 6, sigma_range=(0.01, 0.05))
+    seps = [(k.sigma, k.kappa, 0.3 * j) for j, k in enumerate(ks)]
+    tabs = [plan.coeffs(0, [se2.GaussVM(*c)]) for c in seps]
+    rng = np.random.default_rng([2504_05149, 84])
+    profs = [rng.uniform(0, 1, size=(6, shape[2])) for _ in range(2)]
+    tabs += [plan.coeffs(0, [se2.RadialProfile(_dev(p, torch.float64), 0.3, norm=0)]) for p in profs]
+    f = sample_fields(16, 3, 8, *shape)
+    fd = _dev(f, tdt)
+    out = torch.empty_like(fd)
+    plan.chain([(0, fd, out, tabs)])
+    torch.cuda.synchronize()
+    out = out.cpu().numpy().astype(np.float64)
+    ref_t = oracle_table_gauss(*shape, seps)
+    for p in profs:
+        c = ffc(ok.radial_profile(*shape, p, 0.3))
+        ref_t = ref_t * c / c[0, 0, 0]
+    worst = max(rel_l2(out[b], oc.conv_with_coeffs(f[b], ref_t)) for b in range(3))
+    print(f"rel-L2 {worst:.2e}", flush=True)
+    assert worst <= _tol(dt, shape)
+
+
+@pytest.mark.parametrize("shape,kind", [((64, 64, 32), "sep"), ((64, 64, 32), "full"), ((33, 35, 17), "sep")])
+def test_long_odd_batch(shape, kind):
+    batch = 17
+    case(f"odd batch of {batch} {shape} {kind} fp32: pair packing with a lone last field")
+    plan = se2.Plan([shape], dtype="f32")
+    if kind == "sep":
+        table = plan.coeffs(0, [se2.GaussVM(0.05, 4.0, 0.2)])
+        ref_t = oracle_table_gauss(*shape, [(0.05, 4.0, 0.2)])
+    else:
+        table = plan.coeffs(0, [se2.ExpGauss(0.07)])
+        p = ok.sample_function(ok.exp_gauss_function(0.07), *shape, images=3)
+        ref_t = ffc(p) / ffc(p)[0, 0, 0]
+    f = sample_fields(17, batch, 4, *shape)
+    out = plan.apply(0, _dev(f, torch.float32), table).cpu().numpy().astype(np.float64)
+    for b in (0, 7, 15, 16):
+        err = rel_l2(out[b], oc.conv_with_coeffs(f[b], ref_t))
+        print(f"  field {b}: rel-L2 {err:.2e}", flush=True)
+        assert err <= tol32(shape[0] * shape[1] * shape[2])
+
+
+@pytest.mark.parametrize("dt", ["f32", "f64"])
+def test_zero_and_constant_fields(dt):
+    shape = (64, 48, 16)
+    case(f"degenerate fields {shape} {dt}: zero stays zero, a constant stays constant (unit-mass kernels)")
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    plan = se2.Plan([shape], dtype=dt)
+    tabs = [plan.coeffs(0, [se2.GaussVM(0.05, 4.0, 0.2), se2.GaussVM(0.03, 9.0, 1.0)]),
+            plan.coeffs(0, [se2.ExpGauss(0.06)])]
+    f = np.zeros((2,) + (shape[2], shape[1], shape[0]))
+    f[1] = 2.5
+    bar = 1e-6 if dt == "f32" else 1e-13
+    for t in tabs:
+        out = plan.apply(0, _dev(f, tdt), t).cpu().numpy().astype(np.float64)
+        assert np.all(out[0] == 0.0)
+        assert np.max(np.abs(out[1] - 2.5)) <= bar * 2.5
