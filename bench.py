@@ -368,11 +368,12 @@ def main():
     value = batch * args.steps / res["elapsed"]
     rb = 4 if res["dtype"] == "f32" else 8
     alg_bytes_step = 2 * rb * n * batch              # read f, write out (algorithmic)
-    # dominant pass = largest total time per step; each launch of a pass streams its
-    # share of the batch once in and once out
+    # dominant pass = largest total time per step; every launch of a pass streams the whole
+    # batch once in and once out (a kind launched twice per step, e.g. the forward and the
+    # inverse x-theta pass of the full-table path, does that twice)
     dom = max(res["avg_ms"], key=lambda k: res["avg_ms"][k] * res["launches"][k])
     dom_ms = res["avg_ms"][dom]
-    alg_bytes_launch = alg_bytes_step / res["launches"][dom]
+    alg_bytes_launch = alg_bytes_step
     achieved = alg_bytes_launch / (dom_ms * 1e-3) / 1e9
     src = lib_source_hash()
     traffic = traffic_for(dom, args.workload, src)
