@@ -43,7 +43,7 @@ WORKLOADS = {
 }
 # workloads whose kernel is not a chain of Gauss-vM kernels: (kind, sigma)
 EXP_GAUSS_SIGMA = {"expgauss": 0.05}
-SPECIAL = ("c2", "c4", "padded")
+SPECIAL = ("c2", "c4", "padded", "powers")
 
 
 def lib_source_hash() -> str:
@@ -231,6 +231,62 @@ def cpu_baseline_padded(f_host, out_host, ks, L, N, budget_s):
                       f"{el:.1f} s"}, errs
 
 
+def run_powers(steps, warmup, cpu_budget=None):
+    """All powers V_p = f * rho^(p), p = 1..4 (Alg. 7: one forward transform, running product,
+    q inverses) with the exponential-coordinates Gaussian, 256x256x64 FP32, batch 8."""
+    import torch
+
+    import paper_2504_05149_amd as se2
+    from inputs import sample_fields
+
+    shape, batch, q, sigma = (256, 256, 64), 8, 4, 0.04
+    plan = se2.Plan([shape], dtype="f32")
+    table = plan.coeffs(0, [se2.ExpGauss(sigma)])
+    f_host = sample_fields(2, batch, 32, *shape, dtype=np.float32)
+    f = torch.from_numpy(f_host).to("cuda")
+    out = None
+    for _ in range(warmup):
+        out = plan.powers(0, f, table, q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = plan.powers(0, f, table, q)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    out_host = out[:, 0].cpu().numpy()
+    plan.close()
+    n = shape[0] * shape[1] * shape[2]
+    alg = 4 * n * batch * (1 + q)  # read the fields once, write q outputs
+    gbps = alg / (ms * 1e-3) / 1e9
+    line = {"metric": "SE(2) convolutions/sec, all powers f * rho^(p), p = 1..4 (Alg. 7)",
+            "value": round(batch * q / (ms * 1e-3), 1), "unit": "conv/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": round(ms, 4), "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"{shape[0]}x{shape[1]}x{shape[2]} fp32, batch {batch} fields of 32 Gauss-vM "
+                                   f"bumps, exponential-coordinates Gaussian sigma={sigma}, q={q} (one output per power)"},
+            "roofline": {"bound": "hbm", "kernel": "whole path", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": None,
+                         "alg_bytes_per_step": alg}}
+    if cpu_budget is not None:
+        from threadpoolctl import threadpool_info
+
+        from inputs import rel_l2
+        from oracle import conv as oc
+        from oracle import kernels as ok
+
+        p = ok.sample_function(ok.exp_gauss_function(sigma), *shape, images=3)
+        t0 = time.perf_counter()
+        ref = oc.alg7_all_powers(f_host[0].astype(np.float64), p / p.mean(), q)
+        el = time.perf_counter() - t0
+        errs = [rel_l2(out_host[k].astype(np.float64), ref[k]) for k in range(q)]
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        line["cpu_baseline"] = {"value": q / el, "unit": "conv/s", "cores": int(threads), "kind": "oracle",
+                                "sample": f"field 0, all {q} powers by the oracle's Alg. 7 (FP64); {el:.1f} s"}
+        line["rel_l2_vs_oracle"] = float(max(errs))
+        line["rel_l2_tol"] = float(2e-6 * np.log2(n))
+    return line
+
+
 def run_c4(steps, warmup):
     """Loss + gradients w.r.t. the field and a 64 x 64 radial profile, 256x256x64 FP32 batch 8."""
     import torch
@@ -382,6 +438,9 @@ def main():
         return
     if args.workload == "c4":
         print(json.dumps(run_c4(args.steps, args.warmup)), flush=True)
+        return
+    if args.workload == "powers":
+        print(json.dumps(run_powers(args.steps, args.warmup, None if args.no_cpu else args.cpu_budget)), flush=True)
         return
     if args.workload == "padded":
         print(json.dumps(run_padded(args.steps, args.warmup, None if args.no_cpu else args.cpu_budget)), flush=True)

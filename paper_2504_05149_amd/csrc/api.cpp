@@ -1524,6 +1524,25 @@ se2conv_status se2conv_powers(se2conv_plan_t p, int32_t shape_idx, const void* d
     const bool d = dbl(p);
     const bool conj = (flags & SE2CONV_ADJOINT) != 0;
     const bool odd = (batch & 1) != 0;
+    if (use_full_fast(p, s) && !odd && (long long)batch * q * s.ny / 2 < (1LL << 31)) {
+        // register kernels: x-theta forward into the last slot, one y pass for every power
+        // (the spectrum stays in registers), one x-theta inverse over all q slots
+        FullFastArgs a = full_fast_args(p, s, batch);
+        set_chain(&a, ch, conj, 1.0 / (double)n);
+        char* last = (char*)d_out + rb * ((long long)(q - 1) * batch * n);
+        a.in = reinterpret_cast<const float*>(d_f);
+        a.out = reinterpret_cast<float*>(last);
+        HIPCHK(launch_xt_full_fwd(a, stream));
+        a.out = reinterpret_cast<float*>(d_out);
+        a.q = q;
+        a.slot = (long long)batch * n;
+        HIPCHK(launch_y_full_powers(a, stream));
+        FullFastArgs b = full_fast_args(p, s, batch * q);
+        b.in = reinterpret_cast<const float*>(d_out);
+        b.out = reinterpret_cast<float*>(d_out);
+        HIPCHK(launch_xt_full_inv(b, stream));
+        return ok();
+    }
     const int pairs = (batch + 1) / 2;
     if (odd) {
         std::lock_guard<std::mutex> g(p->mu);

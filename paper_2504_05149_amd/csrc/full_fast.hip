@@ -250,7 +250,7 @@ xt_full(FullFastArgs a) {
 // 256^2 x 64) where the LDS allows; the backward keeps 16 (its accumulator and table
 // registers limit occupancy either way).
 template <int NY, int MODE> struct YFullW {
-    static constexpr int W = (MODE != 2 && NY <= 256) ? 32 : 16;
+    static constexpr int W = (MODE <= 1 && NY <= 256) ? 32 : 16;
 };
 
 template <int NY, int MODE> struct FullLineGeom {
@@ -267,9 +267,10 @@ static constexpr size_t full_line_lds() {
 }
 
 // scale * prod_e T_e at (kt, ky, kx), conjugated for the adjoint
-__device__ __forceinline__ float2 full_table_factor(const FullFastArgs& a, int NYv, int kt, int ky, int kx) {
+__device__ __forceinline__ float2 full_table_factor(const FullFastArgs& a, int NYv, int kt, int ky, int kx,
+                                                    float scale) {
     const int pl = a.nx * NYv;
-    float2 f = make_float2(a.scale, 0.f);
+    float2 f = make_float2(scale, 0.f);
     for (int e = 0; e < a.ntab; ++e) {
         const float2* T = reinterpret_cast<const float2*>(a.tab[e]);
         if (a.tab_full[e]) {
@@ -324,7 +325,8 @@ __global__ void __launch_bounds__((FullLineGeom<NY, MODE>::NT)) y_full(FullFastA
 #pragma unroll
         for (int j = 0; j < CC; ++j)
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) tv[j][k2] = full_table_factor(a, NY, kt, CC * t + j + R1 * k2, kx);
+            for (int k2 = 0; k2 < R2; ++k2)
+                tv[j][k2] = full_table_factor(a, NY, kt, CC * t + j + R1 * k2, kx, a.scale);
     }
     float2 acc[CC][R2];
     if constexpr (MODE == 2) {
@@ -409,7 +411,7 @@ __global__ void __launch_bounds__((FullLineGeom<NY, MODE>::NT)) y_full(FullFastA
                 const int kx = base - kt * pl;
 #pragma unroll
                 for (int k2 = 0; k2 < R2; ++k2)
-                    u[j][k2] = mul<float>(u[j][k2], full_table_factor(a, NY, kt, k1 + R1 * k2, kx));
+                    u[j][k2] = mul<float>(u[j][k2], full_table_factor(a, NY, kt, k1 + R1 * k2, kx, a.scale));
             }
             RegDFT<R2, true, float>::run(u[j]);
 #pragma unroll
@@ -500,6 +502,99 @@ static hipError_t launch_xt_full(const FullFastArgs& a, hipStream_t s) {
 hipError_t launch_xt_full_fwd(const FullFastArgs& a, hipStream_t s) { return launch_xt_full<0>(a, s); }
 hipError_t launch_xt_full_inv(const FullFastArgs& a, hipStream_t s) { return launch_xt_full<1>(a, s); }
 
+// All powers (Alg. 7) along y, MODE 3 geometry: each workgroup (theta frequency, 16 x
+// frequencies) walks the pairs; a pair's y spectrum Z (forward DFT of the x-theta spectrum
+// planes in the last output slot) stays in registers while, for p = 1..q, the running
+// product H_p = H_{p-1} T (scale 1/n folded in at p = 1, conjugated for the adjoint) is
+// inverted along y into slot p - 1.  The last slot is read before it is written (same
+// workgroup, same pair).  The table factor is re-read for every power (cache hits): held in
+// registers across the powers it would cost a third of the occupancy.
+template <int NY>
+__global__ void __launch_bounds__((FullLineGeom<NY, 3>::NT)) y_full_powers(FullFastArgs a) {
+    using Gm = FullLineGeom<NY, 3>;
+    constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC, W = Gm::W, NT = Gm::NT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float2* buf = reinterpret_cast<float2*>(smem_raw);  // [k1*R2 + t][W]
+    float2* tw_f = buf + NY * W;                        // [k1][t] = w_NY^{t k1}
+    float2* tw_i = tw_f + NY;                           // [t][k1]
+    const int tid = threadIdx.x;
+    for (int i = tid; i < NY; i += NT) {
+        const int k1 = i / R2, t = i - k1 * R2;
+        const float2 w = a.twy[t * k1];
+        tw_f[k1 * R2 + t] = w;
+        tw_i[t * R1 + k1] = w;
+    }
+    __syncthreads();
+
+    const int ctiles = a.nx / W;
+    const int kt = blockIdx.x / ctiles;
+    const int pl = a.nx * NY;
+    const int npairs = a.batch / 2;
+    const int rstride = R2 * a.nx;
+    const float* __restrict__ spec = a.out + (long long)(a.q - 1) * a.slot;
+    for (int pair = 0; pair < npairs; ++pair) {
+        int lt = tid;
+        asm volatile("" : "+v"(lt));
+        const int q = lt % W, t = lt / W;
+        const int base = kt * pl + (blockIdx.x - kt * ctiles) * W + q;
+        const int lane_off = base + t * a.nx;
+        const float* __restrict__ sre = spec + (long long)(2 * pair) * a.n;
+        const float* __restrict__ sim = sre + a.n;
+        float2 w[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) w[r] = make_float2(sre[lane_off + r * rstride], sim[lane_off + r * rstride]);
+        RegDFT<R1, false, float>::run(w);
+#pragma unroll
+        for (int k1 = 1; k1 < R1; ++k1) w[k1] = mul<float>(w[k1], tw_f[k1 * R2 + t]);
+        __syncthreads();
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) buf[(k1 * R2 + t) * W + q] = w[k1];
+        __syncthreads();
+        float2 h[CC][R2];  // running product H_p
+#pragma unroll
+        for (int j = 0; j < CC; ++j) {
+            const int k1 = CC * t + j;
+#pragma unroll
+            for (int tt = 0; tt < R2; ++tt) h[j][tt] = buf[(k1 * R2 + tt) * W + q];
+            RegDFT<R2, false, float>::run(h[j]);
+        }
+#pragma unroll 1
+        for (int pw = 0; pw < a.q; ++pw) {
+            const float sc = pw == 0 ? a.scale : 1.0f;
+            float2 u[CC][R2];
+#pragma unroll
+            for (int j = 0; j < CC; ++j) {
+                const int k1 = CC * t + j;
+                const int kx = base - kt * pl;
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2)
+                    h[j][k2] = mul<float>(h[j][k2], full_table_factor(a, NY, kt, k1 + R1 * k2, kx, sc));
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = h[j][k2];
+                RegDFT<R2, true, float>::run(u[j]);
+#pragma unroll
+                for (int tt = 1; tt < R2; ++tt) u[j][tt] = mulc<float>(u[j][tt], tw_i[tt * R1 + k1]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < CC; ++j)
+#pragma unroll
+                for (int tt = 0; tt < R2; ++tt) buf[((CC * t + j) * R2 + tt) * W + q] = u[j][tt];
+            __syncthreads();
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) w[k1] = buf[(k1 * R2 + t) * W + q];
+            RegDFT<R1, true, float>::run(w);
+            float* __restrict__ ore = a.out + (long long)pw * a.slot + (long long)(2 * pair) * a.n;
+            float* __restrict__ oim = ore + a.n;
+#pragma unroll
+            for (int r = 0; r < R1; ++r) {
+                ore[lane_off + r * rstride] = w[r].x;
+                oim[lane_off + r * rstride] = w[r].y;
+            }
+        }
+    }
+}
+
 template <int NY, int MODE>
 static hipError_t launch_y_full_t(const FullFastArgs& a, hipStream_t s) {
     const int nblocks = (a.nx / FullLineGeom<NY, MODE>::W) * a.m;
@@ -526,6 +621,25 @@ hipError_t launch_y_full(const FullFastArgs& a, hipStream_t s) { return launch_y
 hipError_t launch_y_full_spectra(const FullFastArgs& a, hipStream_t s) { return launch_y_full_mode<1>(a, s); }
 hipError_t launch_y_full_backward(const FullFastArgs& a, hipStream_t s) { return launch_y_full_mode<2>(a, s); }
 
+template <int NY>
+static hipError_t launch_y_full_powers_t(const FullFastArgs& a, hipStream_t s) {
+    const int nblocks = (a.nx / FullLineGeom<NY, 3>::W) * a.m;
+    const int nthr = FullLineGeom<NY, 3>::NT;
+    const size_t lds = full_line_lds<NY, 3>();
+    hipLaunchKernelGGL((y_full_powers<NY>), dim3(nblocks), dim3(nthr), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_y_full_powers(const FullFastArgs& a, hipStream_t s) {
+    if ((a.batch & 1) || a.q < 1) return hipErrorInvalidValue;
+    if (a.ny == 32) return launch_y_full_powers_t<32>(a, s);
+    if (a.ny == 64) return launch_y_full_powers_t<64>(a, s);
+    if (a.ny == 128) return launch_y_full_powers_t<128>(a, s);
+    if (a.ny == 256) return launch_y_full_powers_t<256>(a, s);
+    if (a.ny == 512) return launch_y_full_powers_t<512>(a, s);
+    return hipErrorInvalidValue;
+}
+
 #define SE2C_XT_FULL_ATTR(NX_, M_)                                                                          \
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(xt_full<NX_, M_, 0>),                              \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_slab_lds<NX_, M_>());      \
@@ -541,6 +655,9 @@ hipError_t launch_y_full_backward(const FullFastArgs& a, hipStream_t s) { return
     SE2C_Y_FULL_ATTR1(NY_, 0) SE2C_Y_FULL_ATTR1(NY_, 1) SE2C_Y_FULL_ATTR1(NY_, 2)                            \
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full<NY_, 0, true>),                             \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_, 0>());       \
+    if (e != hipSuccess) return e;                                                                          \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full_powers<NY_>),                               \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_, 3>());       \
     if (e != hipSuccess) return e;
 
 hipError_t prepare_full_fast_kernels() {

@@ -32,6 +32,9 @@ struct FullFastArgs {
     const float* zf;        // field spectra (slots 2p, 2p + 1 per pair)
     float* acc;             // two planes: W A / n^2 after the inverse DFT along y
     float acc_scale;        // 1 / n^2
+    // powers y pass: q output slots of batch fields each, `slot` reals apart, starting at out
+    int q;
+    long long slot;
 };
 
 bool full_fast_supported(int nx, int ny, int m);
@@ -45,6 +48,10 @@ hipError_t launch_y_full(const FullFastArgs& a, hipStream_t s);
 hipError_t launch_y_full_spectra(const FullFastArgs& a, hipStream_t s);
 // y pass of the backward: adjoint product in place, kernel-sample gradient accumulated to acc
 hipError_t launch_y_full_backward(const FullFastArgs& a, hipStream_t s);
+// y pass of all powers (Alg. 7): forward DFT of the spectrum planes in the last slot, then
+// for p = 1..q the running product with the table and its inverse, into slot p - 1
+// (even batch)
+hipError_t launch_y_full_powers(const FullFastArgs& a, hipStream_t s);
 hipError_t prepare_full_fast_kernels();
 
 }  // namespace se2c

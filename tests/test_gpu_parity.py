@@ -379,6 +379,10 @@ def test_foreign_table_is_rejected():
     (32, 32, 16, 2, 3, "f32", "full"),
     (64, 64, 32, 1, 5, "f32", "sep"),
     (48, 32, 24, 2, 2, "f64", "full"),
+    # even FP32 batches on register-kernel shapes: one y pass for every power
+    (64, 64, 32, 2, 5, "f32", "sep"),
+    (128, 64, 64, 4, 3, "f32", "full"),
+    (32, 512, 16, 2, 2, "f32", "full"),
 ])
 def test_all_powers_match_oracle_alg7(nx, ny, m, batch, q, dt, kind, rng):
     case(f"Algorithm 7 powers {nx}x{ny}x{m} {dt} batch={batch} q={q} {kind} table")
@@ -394,6 +398,7 @@ def test_all_powers_match_oracle_alg7(nx, ny, m, batch, q, dt, kind, rng):
         table = plan.coeffs(0, [se2.RadialProfile(_dev(prof, torch.float64), 0.4, norm=0)])
     f = _fields(11, batch, 8, nx, ny, m)
     out = plan.powers(0, _dev(f, tdt), table, q).cpu().numpy().astype(np.float64)
+    adj = plan.powers(0, _dev(f, tdt), table, q, adjoint=True).cpu().numpy().astype(np.float64)
     tol = tol32(nx * ny * m) if dt == "f32" else TOL64
     for b in range(batch):
         refs = oc.alg7_all_powers(f[b], p, q)
@@ -401,6 +406,11 @@ def test_all_powers_match_oracle_alg7(nx, ny, m, batch, q, dt, kind, rng):
             err = rel_l2(out[k, b], refs[k])
             print(f"  field {b} power {k + 1}: {err:.2e}", flush=True)
             assert err <= tol
+        # the adjoint power p is the correlation with rho p times (conjugated coefficients)
+        ref_adj = f[b]
+        for k in range(q):
+            ref_adj = oc.conv_chain(ref_adj, [p], adjoint=True)
+            assert rel_l2(adj[k, b], ref_adj) <= tol, (b, k)
 
 
 # ------------------------------------------------------------ field sampling
