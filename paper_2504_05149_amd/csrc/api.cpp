@@ -173,6 +173,8 @@ struct se2conv_plan_s {
     void* ws4 = nullptr;               // four more planes (kernel gradient), allocated on first use
     void* scratch64 = nullptr;         // FP64 scratch for se2conv_coeffs
     size_t scratch64_bytes = 0;
+    void* pad_ws = nullptr;            // sampling-grid product spectra of se2conv_apply_padded
+    size_t pad_ws_bytes = 0;
     // hat basis of the last radial-profile geometry used by se2conv_profile_grad
     double* basis = nullptr;
     size_t basis_bytes = 0;
@@ -1140,6 +1142,7 @@ se2conv_status se2conv_plan_destroy(se2conv_plan_t p) {
         if (p->scratch64) (void)hipFree(p->scratch64);
         if (p->basis) (void)hipFree(p->basis);
         if (p->basis_hat) (void)hipFree(p->basis_hat);
+        if (p->pad_ws) (void)hipFree(p->pad_ws);
         if (cur >= 0) (void)hipSetDevice(cur);
     }
     delete p;
@@ -1644,10 +1647,23 @@ se2conv_status se2conv_apply_padded(se2conv_plan_t p, int32_t shape_idx, const v
     se2conv_status r = lookup_chain(p, shape_idx, tabs, 1, &ch, &all_sep);
     if (r != SE2CONV_OK) return r;
     if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    const int pairs = (batch + 1) / 2;
+    const bool odd = (batch & 1) != 0;
     {
+        // the product spectra of every pair on the sampling grid (two planes per pair)
         std::lock_guard<std::mutex> lk(p->mu);
-        if (!p->ws2 && hipMalloc(&p->ws2, 2 * p->ws_bytes) != hipSuccess)
-            return fail(SE2CONV_ERR_OUT_OF_MEMORY, "workspace (%zu bytes)", 2 * p->ws_bytes);
+        const size_t need = 2 * (size_t)pairs * (size_t)n * rb;
+        if (p->pad_ws_bytes < need) {
+            if (p->pad_ws) {
+                hipError_t e = hipFree(p->pad_ws);
+                p->pad_ws = nullptr;
+                p->pad_ws_bytes = 0;
+                if (e != hipSuccess) return fail(SE2CONV_ERR_DEVICE, "hipFree: %s", hipGetErrorString(e));
+            }
+            if (hipMalloc(&p->pad_ws, need) != hipSuccess)
+                return fail(SE2CONV_ERR_OUT_OF_MEMORY, "padded-evaluation workspace (%zu bytes)", need);
+            p->pad_ws_bytes = need;
+        }
     }
     const bool d = dbl(p);
     const bool conj = (flags & SE2CONV_ADJOINT) != 0;
@@ -1656,30 +1672,30 @@ se2conv_status se2conv_apply_padded(se2conv_plan_t p, int32_t shape_idx, const v
         HIPCHK(record_event(p, stream, true));
         g_timing_plan = p;
     }
-    // product spectrum of one field pair on the sampling grid (plan workspace planes)
-    void* hre = p->ws2;
-    void* him = (char*)p->ws2 + p->ws_bytes;
-    se2conv_status st = SE2CONV_OK;
-    for (int b = 0; b < batch && st == SE2CONV_OK; b += 2) {
-        const bool pair = b + 1 < batch;
-        const void* fa = (const char*)d_f + rb * n * b;
-        const void* fb = pair ? (const char*)d_f + rb * n * (b + 1) : nullptr;
-        void* oa = (char*)d_out + rb * ng * b;
-        // imaginary plane on the finer grid: the second field's output, or the plan
-        // workspace for a field without a partner (its values are discarded)
-        void* ob = pair ? (char*)d_out + rb * ng * (b + 1) : p->ws;
-        hipError_t e = xt_transform(p, s, d, 0, fa, fb, hre, him, nullptr, nullptr, n, n, 1, stream);
-        if (e == hipSuccess)
-            e = y_pass(p, s, d, hre, him, nullptr, n, 1, 1, 0, 2, &ch, conj, 1.0 / (double)n, stream);
-        if (e == hipSuccess)
-            e = launch_pad_spectrum(hre, him, oa, ob, s.nx, s.ny, s.m, g.nx, g.ny, g.m, d, stream);
-        if (e == hipSuccess) e = y_pass(p, g, d, oa, ob, nullptr, ng, 1, 0, 1, 0, nullptr, false, 1.0, stream);
-        if (e == hipSuccess)
-            e = xt_transform(p, g, d, 1, oa, ob, oa, pair ? ob : nullptr, nullptr, nullptr, ng, ng, 1, stream);
-        if (e != hipSuccess) st = fail(SE2CONV_ERR_DEVICE, "padded evaluation: %s", hipGetErrorString(e));
-    }
+    // sampling grid: pairs of fields packed as re/im (a lone last field pairs with zero);
+    // pair i's planes at pad_ws + 2 i n (re) and + n (im)
+    char* hre = (char*)p->pad_ws;
+    char* him = hre + rb * n;
+    const void* f1 = batch == 1 ? nullptr : (const char*)d_f + rb * n;
+    void* h_lone = odd ? hre + rb * ((long long)(2 * (pairs - 1) + 1) * n) : nullptr;
+    // evaluation grid: the pair's two output fields hold its re / im planes; a lone field's
+    // im plane goes to the plan workspace (discarded)
+    char* ore = (char*)d_out;
+    char* oim = batch == 1 ? nullptr : ore + rb * ng;
+    void* o_lone = odd ? p->ws : nullptr;
+    hipError_t e = xt_transform(p, s, d, 0, d_f, f1, hre, batch == 1 ? nullptr : him, nullptr, h_lone, 2 * n, 2 * n,
+                                pairs, stream);
+    if (e == hipSuccess)
+        e = y_pass(p, s, d, hre, batch == 1 ? nullptr : him, h_lone, 2 * n, pairs, 1, 0, 2, &ch, conj,
+                   1.0 / (double)n, stream);
+    if (e == hipSuccess)
+        e = launch_pad_spectrum(hre, ore, o_lone, pairs, 2 * n, 2 * ng, s.nx, s.ny, s.m, g.nx, g.ny, g.m, d, stream);
+    if (e == hipSuccess) e = y_pass(p, g, d, ore, oim, o_lone, 2 * ng, pairs, 0, 1, 0, nullptr, false, 1.0, stream);
+    if (e == hipSuccess)
+        e = xt_transform(p, g, d, 1, ore, oim, ore, oim, o_lone, nullptr, 2 * ng, 2 * ng, pairs, stream);
     g_timing_plan = nullptr;
-    return st == SE2CONV_OK ? ok() : st;
+    if (e != hipSuccess) return fail(SE2CONV_ERR_DEVICE, "padded evaluation: %s", hipGetErrorString(e));
+    return ok();
 }
 
 se2conv_status se2conv_apply_complex(se2conv_plan_t p, int32_t shape_idx, const void* d_f, const void* d_table,

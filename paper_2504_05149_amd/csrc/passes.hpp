@@ -99,10 +99,11 @@ hipError_t launch_pencil(const PencilArgs& a, bool dbl, int nthr, int nblocks, h
 hipError_t prepare_generic_kernels();
 hipError_t prepare_kernels();
 
-// Zero-padded spectrum of one field pair: L-grid planes (sre, sim) -> G-grid planes
-// (dre, dim), G >= L per axis (pad.hip).
-hipError_t launch_pad_spectrum(const void* sre, const void* sim, void* dre, void* dim, int lx, int ly, int lm, int gx,
-                               int gy, int gm, bool dbl, hipStream_t s);
+// Zero-padded spectra of nitems field pairs: L-grid planes -> G-grid planes, G >= L per
+// axis (pad.hip).
+hipError_t launch_pad_spectrum(const void* src, void* dst, void* lone, int nitems, long long src_stride,
+                               long long dst_stride, int lx, int ly, int lm, int gx, int gy, int gm, bool dbl,
+                               hipStream_t s);
 
 // FP64 twiddles w_L^j = exp(-2 pi i j / L), j in [0, L), written as double2 and float2.
 hipError_t launch_twiddles(double2* out64, float2* out32, int L, hipStream_t s);
