@@ -1672,6 +1672,36 @@ se2conv_status se2conv_apply_padded(se2conv_plan_t p, int32_t shape_idx, const v
         HIPCHK(record_event(p, stream, true));
         g_timing_plan = p;
     }
+    if (!d && !(p->flags & SE2CONV_PLAN_GENERIC) && !odd && full_fast_supported(s.nx, s.ny, s.m) &&
+        full_fast_supported(g.nx, g.ny, g.m)) {
+        // register kernels: x-theta forward and the y spectra on the sampling grid (in the
+        // workspace), then one y pass on the evaluation grid that pads, multiplies by the
+        // table and inverts, and the x-theta inverse in place in the output
+        FullFastArgs a = full_fast_args(p, s, batch);
+        a.in = reinterpret_cast<const float*>(d_f);
+        a.out = reinterpret_cast<float*>(p->pad_ws);
+        a.save = a.out;
+        hipError_t e = launch_xt_full_fwd(a, stream);
+        if (e == hipSuccess) e = after_pass(0, stream);
+        if (e == hipSuccess) e = launch_y_full_spectra(a, stream);
+        if (e == hipSuccess) e = after_pass(1, stream);
+        FullFastArgs b = full_fast_args(p, g, batch);
+        set_chain(&b, ch, conj, 1.0 / (double)n);
+        b.zsrc = reinterpret_cast<const float*>(p->pad_ws);
+        b.lx = s.nx;
+        b.ly = s.ny;
+        b.lm = s.m;
+        b.nl = n;
+        b.in = reinterpret_cast<const float*>(d_out);
+        b.out = reinterpret_cast<float*>(d_out);
+        if (e == hipSuccess) e = launch_y_full_pad_inv(b, stream);
+        if (e == hipSuccess) e = after_pass(1, stream);
+        if (e == hipSuccess) e = launch_xt_full_inv(b, stream);
+        if (e == hipSuccess) e = after_pass(0, stream);
+        g_timing_plan = nullptr;
+        if (e != hipSuccess) return fail(SE2CONV_ERR_DEVICE, "padded evaluation: %s", hipGetErrorString(e));
+        return ok();
+    }
     // sampling grid: pairs of fields packed as re/im (a lone last field pairs with zero);
     // pair i's planes at pad_ws + 2 i n (re) and + n (im)
     char* hre = (char*)p->pad_ws;

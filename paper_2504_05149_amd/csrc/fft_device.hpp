@@ -190,6 +190,27 @@ template <int R, typename T, bool INV> __device__ __forceinline__ void dftR(C<T>
 // (-1)^k of the signed frequency equals (-1)^t only when L is even.
 __host__ __device__ inline int signed_freq(int t, int L) { return t <= (L - 1) / 2 ? t : t - L; }
 
+// Zero padding from a length-L spectrum to a length-G one (G >= L): the L-index that G-index
+// g takes its value from (-1: none, the value is zero), keeping every signed frequency
+// |k| <= (L-1)/2 (odd L).  For even L the index L/2 holds +-L/2 together; when G > L it is
+// split in halves between tau_G(-L/2) and tau_G(+L/2) (*half set), when G = L kept whole.
+__device__ __forceinline__ int pad_source(int g, int G, int L, bool* half) {
+    const int k = signed_freq(g, G);
+    *half = false;
+    if (L & 1) {
+        const int K = (L - 1) / 2;
+        if (k < -K || k > K) return -1;
+        return k < 0 ? k + L : k;
+    }
+    const int h = L / 2;
+    if (k > -h && k < h) return k < 0 ? k + L : k;
+    if (k == h || k == -h) {
+        *half = G > L;
+        return h;
+    }
+    return -1;
+}
+
 // Division by a small runtime divisor d (1 <= d, n < 2^21) via a 32x32->64
 // multiply by ceil(2^42/d): exact for all n < 2^21 because n*d < 2^42.
 struct FastDiv {

@@ -595,6 +595,106 @@ __global__ void __launch_bounds__((FullLineGeom<NY, 3>::NT)) y_full_powers(FullF
     }
 }
 
+// prod_e T_e at (kt, ky, kx) of a grid lx x ly (tables of the sampling grid), conjugated
+// for the adjoint (no scale)
+__device__ __forceinline__ float2 grid_table_factor(const FullFastArgs& a, int lx, int ly, int kt, int ky, int kx) {
+    float2 f = make_float2(1.f, 0.f);
+    for (int e = 0; e < a.ntab; ++e) {
+        const float2* T = reinterpret_cast<const float2*>(a.tab[e]);
+        if (a.tab_full[e]) {
+            f = mul<float>(f, T[((long long)kt * ly + ky) * lx + kx]);
+        } else {
+            f = mul<float>(f, T[kx]);
+            f = mul<float>(f, T[lx + ky]);
+            f = mul<float>(f, T[lx + ly + kt]);
+        }
+    }
+    if (a.conj_tab) f.y = -f.y;
+    return f;
+}
+
+// Evaluation on a finer grid (Sec. 4.1 eq. (MatSKfonG)), y pass on the evaluation grid
+// (NY its Ny), MODE 3 geometry: each workgroup (theta frequency, 16 x frequencies of the
+// evaluation grid) walks the pairs.  A lane's values come from the sampling-grid y spectra
+// (zsrc, two planes per pair) at the padded indices of each axis (pad_source: the same
+// signed frequency; an even length's Nyquist index halved when the grid is finer), times
+// the sampling-grid table factor and scale; zero for frequencies the sampling grid lacks.
+// Then the inverse DFT along y into the evaluation grid's planes (out, two per pair).
+template <int NY>
+__global__ void __launch_bounds__((FullLineGeom<NY, 3>::NT)) y_full_pad_inv(FullFastArgs a) {
+    using Gm = FullLineGeom<NY, 3>;
+    constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC, W = Gm::W, NT = Gm::NT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float2* buf = reinterpret_cast<float2*>(smem_raw);  // [k1*R2 + t][W]
+    float2* tw_i = buf + NY * W + NY;                   // [t][k1]
+    const int tid = threadIdx.x;
+    for (int i = tid; i < NY; i += NT) {
+        const int k1 = i / R2, t = i - k1 * R2;
+        tw_i[t * R1 + k1] = a.twy[t * k1];
+    }
+    __syncthreads();
+
+    const int ctiles = a.nx / W;
+    const int kt = blockIdx.x / ctiles;
+    const int pl = a.nx * NY;
+    const int npairs = a.batch / 2;
+    const int rstride = R2 * a.nx;
+    bool ht;
+    const int st = pad_source(kt, a.m, a.lm, &ht);
+    for (int pair = 0; pair < npairs; ++pair) {
+        int lt = tid;
+        asm volatile("" : "+v"(lt));
+        const int q = lt % W, t = lt / W;
+        const int kx = (blockIdx.x - kt * ctiles) * W + q;
+        const int lane_off = kt * pl + kx + t * a.nx;
+        bool hx;
+        const int sx = pad_source(kx, a.nx, a.lx, &hx);
+        const float* __restrict__ zre = a.zsrc + (long long)(2 * pair) * a.nl;
+        const float* __restrict__ zim = zre + a.nl;
+        float wgt = a.scale;
+        if (hx) wgt *= 0.5f;
+        if (ht) wgt *= 0.5f;
+        float2 u[CC][R2];
+#pragma unroll
+        for (int j = 0; j < CC; ++j) {
+            const int k1 = CC * t + j;
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) {
+                bool hy;
+                const int sy = pad_source(k1 + R1 * k2, NY, a.ly, &hy);
+                float2 v = make_float2(0.f, 0.f);
+                if (st >= 0 && sx >= 0 && sy >= 0) {
+                    const long long o = ((long long)st * a.ly + sy) * a.lx + sx;
+                    const float2 f = grid_table_factor(a, a.lx, a.ly, st, sy, sx);
+                    const float c = hy ? 0.5f * wgt : wgt;
+                    v = mul<float>(make_float2(zre[o] * c, zim[o] * c), f);
+                }
+                u[j][k2] = v;
+            }
+            RegDFT<R2, true, float>::run(u[j]);
+#pragma unroll
+            for (int tt = 1; tt < R2; ++tt) u[j][tt] = mulc<float>(u[j][tt], tw_i[tt * R1 + k1]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < CC; ++j)
+#pragma unroll
+            for (int tt = 0; tt < R2; ++tt) buf[((CC * t + j) * R2 + tt) * W + q] = u[j][tt];
+        __syncthreads();
+        float2 w[R1];
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) w[k1] = buf[(k1 * R2 + t) * W + q];
+        RegDFT<R1, true, float>::run(w);
+        float* __restrict__ ore = a.out + (long long)(2 * pair) * a.n;
+        float* __restrict__ oim = ore + a.n;
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            ore[lane_off + r * rstride] = w[r].x;
+            oim[lane_off + r * rstride] = w[r].y;
+        }
+    }
+}
+
 template <int NY, int MODE>
 static hipError_t launch_y_full_t(const FullFastArgs& a, hipStream_t s) {
     const int nblocks = (a.nx / FullLineGeom<NY, MODE>::W) * a.m;
@@ -630,6 +730,25 @@ static hipError_t launch_y_full_powers_t(const FullFastArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <int NY>
+static hipError_t launch_y_full_pad_inv_t(const FullFastArgs& a, hipStream_t s) {
+    const int nblocks = (a.nx / FullLineGeom<NY, 3>::W) * a.m;
+    const int nthr = FullLineGeom<NY, 3>::NT;
+    const size_t lds = full_line_lds<NY, 3>();
+    hipLaunchKernelGGL((y_full_pad_inv<NY>), dim3(nblocks), dim3(nthr), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_y_full_pad_inv(const FullFastArgs& a, hipStream_t s) {
+    if ((a.batch & 1) || a.lx > a.nx || a.ly > a.ny || a.lm > a.m) return hipErrorInvalidValue;
+    if (a.ny == 32) return launch_y_full_pad_inv_t<32>(a, s);
+    if (a.ny == 64) return launch_y_full_pad_inv_t<64>(a, s);
+    if (a.ny == 128) return launch_y_full_pad_inv_t<128>(a, s);
+    if (a.ny == 256) return launch_y_full_pad_inv_t<256>(a, s);
+    if (a.ny == 512) return launch_y_full_pad_inv_t<512>(a, s);
+    return hipErrorInvalidValue;
+}
+
 hipError_t launch_y_full_powers(const FullFastArgs& a, hipStream_t s) {
     if ((a.batch & 1) || a.q < 1) return hipErrorInvalidValue;
     if (a.ny == 32) return launch_y_full_powers_t<32>(a, s);
@@ -655,6 +774,9 @@ hipError_t launch_y_full_powers(const FullFastArgs& a, hipStream_t s) {
     SE2C_Y_FULL_ATTR1(NY_, 0) SE2C_Y_FULL_ATTR1(NY_, 1) SE2C_Y_FULL_ATTR1(NY_, 2)                            \
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full<NY_, 0, true>),                             \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_, 0>());       \
+    if (e != hipSuccess) return e;                                                                          \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full_pad_inv<NY_>),                              \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_, 3>());       \
     if (e != hipSuccess) return e;                                                                          \
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full_powers<NY_>),                               \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_, 3>());       \

@@ -35,6 +35,12 @@ struct FullFastArgs {
     // powers y pass: q output slots of batch fields each, `slot` reals apart, starting at out
     int q;
     long long slot;
+    // evaluation on a finer grid: the y spectra on the sampling grid (lx, ly, lm; nl points
+    // per plane, two planes per pair) that the y pass of the evaluation grid pads and inverts;
+    // the tables belong to the sampling grid
+    const float* zsrc;
+    int lx, ly, lm;
+    long long nl;
 };
 
 bool full_fast_supported(int nx, int ny, int m);
@@ -52,6 +58,9 @@ hipError_t launch_y_full_backward(const FullFastArgs& a, hipStream_t s);
 // for p = 1..q the running product with the table and its inverse, into slot p - 1
 // (even batch)
 hipError_t launch_y_full_powers(const FullFastArgs& a, hipStream_t s);
+// y pass on the evaluation grid of a padded evaluation: product of the sampling-grid spectra
+// (zsrc) with the table, zero padding to this grid and inverse DFT along y (even batch)
+hipError_t launch_y_full_pad_inv(const FullFastArgs& a, hipStream_t s);
 hipError_t prepare_full_fast_kernels();
 
 }  // namespace se2c

@@ -19,24 +19,6 @@
 
 namespace se2c {
 
-// Source index on the L axis of G-grid index g, and its weight; -1: no source (zero).
-__device__ __forceinline__ int pad_source(int g, int G, int L, bool* half) {
-    const int k = signed_freq(g, G);
-    *half = false;
-    if (L & 1) {
-        const int K = (L - 1) / 2;
-        if (k < -K || k > K) return -1;
-        return k < 0 ? k + L : k;
-    }
-    const int h = L / 2;
-    if (k > -h && k < h) return k < 0 ? k + L : k;
-    if (k == h || k == -h) {
-        *half = G > L;
-        return h;
-    }
-    return -1;
-}
-
 template <typename T>
 __global__ void pad_spectrum_kernel(const T* __restrict__ src, T* __restrict__ dst, T* __restrict__ lone, int nitems,
                                     long long src_stride, long long dst_stride, int lx, int ly, int lm, int gx,

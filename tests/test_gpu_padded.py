@@ -73,3 +73,31 @@ def test_padded_full_table_adjoint_and_identity_grid():
     d = rel_l2(same.cpu().numpy().astype(np.float64), ref_apply.cpu().numpy().astype(np.float64))
     print(f"N = L against se2conv_apply: rel-L2 {d:.2e}", flush=True)
     assert d <= tol32(L[0] * L[1] * L[2])
+
+
+@pytest.mark.parametrize("L,N,kind,adjoint", [((128, 128, 32), (256, 256, 64), "full", True),
+                                              ((64, 32, 16), (128, 64, 32), "sep", False),
+                                              ((32, 32, 16), (32, 32, 16), "full", False)])
+def test_padded_register_kernels(L, N, kind, adjoint):
+    # even FP32 batches on register-kernel grids: x-theta and y spectra on the sampling grid,
+    # then one y pass on the evaluation grid that pads, multiplies and inverts
+    case(f"padded evaluation on register kernels {L} -> {N} {kind} adjoint={adjoint}")
+    plan = se2.Plan([L, N], dtype="f32")
+    if kind == "sep":
+        ps = [ok.gauss_vm(*L, 0.05, 4.0, 0.3), ok.gauss_vm(*L, 0.03, 8.0, 1.2)]
+        table = plan.coeffs(0, [se2.GaussVM(0.05, 4.0, 0.3), se2.GaussVM(0.03, 8.0, 1.2)])
+    else:
+        prof = np.random.default_rng([2504_05149, 85]).uniform(0, 1, size=(12, L[2]))
+        ps = [ok.radial_profile(*L, prof, 0.4)]
+        table = plan.coeffs(0, [se2.RadialProfile(_dev(prof, torch.float64), 0.4)])
+    f = sample_fields(18, 4, 16, *L)
+    fd = _dev(f, torch.float32)
+    out = plan.apply_padded(0, fd, table, 1, adjoint=adjoint).cpu().numpy().astype(np.float64)
+    tol = tol32(N[0] * N[1] * N[2])
+    for b in range(4):
+        err = rel_l2(out[b], oc.conv_on_grid(f[b], ps, N, adjoint=adjoint))
+        print(f"  field {b}: rel-L2 {err:.2e}", flush=True)
+        assert err <= tol
+    if L == N:
+        same = plan.apply(0, fd, table, adjoint=adjoint).cpu().numpy().astype(np.float64)
+        assert rel_l2(out, same) <= tol
