@@ -20,9 +20,11 @@
  * frequency of DFT index t is the signed one, t for t <= (L-1)/2, else t - L (for
  * odd L the paper's set |k| <= K; for even L the reading {-L/2, ..., L/2-1}), and
  * the sign (-1)^{k1+k2} of eq. (FkLv) uses it.  Lengths 2^a 3^b run on radix
- * 16/8/4/3/2 Stockham stages; prime factors 5 and 7 have codelets; any other
- * prime factor p is one direct-summation stage (O(p) work per point).  With odd
- * Nx or Ny every chain runs on the field-pair passes.
+ * 16/8/4/3/2 Stockham stages; prime factors 5 and 7 have codelets; a prime
+ * length p above 7 runs by Rader's algorithm (a cyclic convolution of length p - 1
+ * on the same stages, its kernel spectrum tabulated in FP64 at plan creation); any
+ * other prime factor p of a composite length is one direct-summation stage (O(p)
+ * work per point).  With odd Nx or Ny every chain runs on the field-pair passes.
  */
 #ifndef SE2CONV_H
 #define SE2CONV_H

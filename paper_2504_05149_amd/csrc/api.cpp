@@ -72,14 +72,24 @@ bool shape_supported(const se2conv_shape& s, std::string* why) {
 // field-pair (plane) passes.
 bool pair_layout(const se2conv_shape& s) { return !(s.nx & 1) && !(s.ny & 1); }
 
+bool is_prime(int n) {
+    if (n < 2) return false;
+    for (int f = 2; f * f <= n; ++f)
+        if (n % f == 0) return false;
+    return true;
+}
+
 // Stockham radices of one length: 16/8/4/2 for the power of two, codelets 3, 5, 7,
 // and direct-summation stages for any other prime factor; largest radices first
-// (the first stage needs no twiddles).
+// (the first stage needs no twiddles).  A prime length above 7 runs by Rader's
+// algorithm on the stages of L - 1 (its tables are attached by radix_plan_of).
 RadixPlan make_radix_plan(int L) {
     RadixPlan p{};
     p.L = L;
     p.nst = 0;
-    int n = L, p2 = 1;
+    p.rader = (L > 7 && is_prime(L)) ? 1 : 0;
+    p.rtab = nullptr;
+    int n = p.rader ? L - 1 : L, p2 = 1;
     while (n % 2 == 0) {
         n /= 2;
         p2 *= 2;
@@ -112,8 +122,14 @@ bool odd_len(int L) {
 
 int max_threads(bool d, bool odd = false) { return (d || odd) ? 512 : 1024; }
 
+// Complex values per thread per stage of the generic kernels.
+int maxv(bool odd) { return odd ? SE2C_MAXV_ODD : SE2C_MAXV; }
+
+// Points one generic tile can hold.
+long long tile_capacity(bool d, bool odd) { return (long long)maxv(odd) * max_threads(d, odd); }
+
 int threads_for(long long P, bool d, bool odd) {
-    long long t = (P + SE2C_MAXV - 1) / SE2C_MAXV;
+    long long t = (P + maxv(odd) - 1) / maxv(odd);
     t = ((t + 63) / 64) * 64;
     if (t < 64) t = 64;
     if (t > max_threads(d, odd)) t = max_threads(d, odd);
@@ -167,6 +183,7 @@ struct se2conv_plan_s {
     std::vector<se2conv_shape> shapes;
     std::vector<Schedule> sched;       // one per shape
     std::map<int, void*> tw32, tw64;   // length -> device twiddle table
+    std::map<int, void*> rader32, rader64;  // prime length > 7 -> device Rader tables
     void* ws = nullptr;                // one real plane of the largest shape (plan dtype)
     size_t ws_bytes = 0;
     void* ws2 = nullptr;               // two more planes (field tables), allocated on first use
@@ -210,6 +227,97 @@ size_t cplx_bytes(const se2conv_plan_s* p) { return dbl(p) ? 16 : 8; }
 
 const void* tw_of(se2conv_plan_s* p, int L, bool use64) { return use64 ? p->tw64.at(L) : p->tw32.at(L); }
 
+// Radix plan of one axis for the generic passes, with its Rader tables attached.
+RadixPlan radix_plan_of(se2conv_plan_s* p, int L, bool use64) {
+    RadixPlan r = make_radix_plan(L);
+    if (r.rader) r.rtab = use64 ? p->rader64.at(L) : p->rader32.at(L);
+    return r;
+}
+
+// The twiddle table the plan's stages read: w_L, or w_{L-1} (first block of the
+// Rader tables) for a prime length.
+const void* stage_tw_of(se2conv_plan_s* p, const RadixPlan& r, bool use64) {
+    return r.rader ? r.rtab : tw_of(p, r.L, use64);
+}
+
+// Rader tables of a prime length L (see RadixPlan), computed in FP64 on the host and
+// stored in FP64 and rounded to FP32: twiddles w_{L-1}^j, the spectra
+// B[k] = (1/(L-1)) sum_j w_L^{+-g^-j} w_{L-1}^{jk} for the forward (-) and inverse (+)
+// transforms, and the index maps g^q, g^-q mod L for the smallest generator g.
+// Angles come from exactly reduced integer products.
+void rader_tables(int L, std::vector<unsigned char>& b64, std::vector<unsigned char>& b32) {
+    const int n = L - 1;
+    std::vector<int> fac;
+    for (int f = 2, m = n; m > 1; ++f)
+        if (m % f == 0) {
+            fac.push_back(f);
+            while (m % f == 0) m /= f;
+        }
+    auto powmod = [L](long long a, long long e) {
+        long long r = 1;
+        a %= L;
+        for (; e > 0; e >>= 1, a = a * a % L)
+            if (e & 1) r = r * a % L;
+        return r;
+    };
+    int g = 2;
+    for (;; ++g) {
+        bool gen = true;
+        for (int f : fac) gen = gen && powmod(g, n / f) != 1;
+        if (gen) break;
+    }
+    const long long ginv = powmod(g, L - 2);
+    std::vector<int> pin(n), pout(n);
+    for (int q = 0; q < n; ++q) {
+        pin[q] = (int)powmod(g, q);
+        pout[q] = (int)powmod(ginv, q);
+    }
+    const double two_pi = 6.283185307179586476925286766559;
+    // w_N^r = exp(-2 pi i r / N), exact at the quarter turns
+    auto w = [&](long long r, long long N, double& c, double& sn) {
+        r %= N;
+        if ((4 * r) % N == 0) {
+            const int q = (int)((4 * r) / N) & 3;
+            c = q == 0 ? 1.0 : (q == 2 ? -1.0 : 0.0);
+            sn = q == 1 ? -1.0 : (q == 3 ? 1.0 : 0.0);
+            return;
+        }
+        const double a = two_pi * (double)r / (double)N;
+        c = std::cos(a);
+        sn = -std::sin(a);
+    };
+    std::vector<double> tab(2 * 3 * (size_t)n), bre(n), bim(n);
+    for (int j = 0; j < n; ++j) {
+        w(j, n, tab[2 * j], tab[2 * j + 1]);
+        w(pout[j], L, bre[j], bim[j]);
+    }
+    for (int dir = 0; dir < 2; ++dir) {
+        for (int k = 0; k < n; ++k) {
+            double sr = 0.0, si = 0.0;
+            for (int j = 0; j < n; ++j) {
+                const double bc = bre[j], bs = dir == 1 ? -bim[j] : bim[j];
+                const size_t r = (size_t)(((long long)j * k) % n);
+                const double tc = tab[2 * r], ts = tab[2 * r + 1];
+                sr += bc * tc - bs * ts;
+                si += bc * ts + bs * tc;
+            }
+            tab[2 * ((size_t)(1 + dir) * n + k)] = sr / n;
+            tab[2 * ((size_t)(1 + dir) * n + k) + 1] = si / n;
+        }
+    }
+    const size_t ib = sizeof(int) * 2 * (size_t)n;
+    b64.assign(sizeof(double) * tab.size() + ib, 0);
+    b32.assign(sizeof(float) * tab.size() + ib, 0);
+    std::memcpy(b64.data(), tab.data(), sizeof(double) * tab.size());
+    std::vector<float> t32(tab.begin(), tab.end());
+    std::memcpy(b32.data(), t32.data(), sizeof(float) * t32.size());
+    for (auto* b : {&b64, &b32}) {
+        unsigned char* ip = b->data() + (b->size() - ib);
+        std::memcpy(ip, pin.data(), sizeof(int) * n);
+        std::memcpy(ip + sizeof(int) * n, pout.data(), sizeof(int) * n);
+    }
+}
+
 bool aligned16(const void* ptr) { return (reinterpret_cast<uintptr_t>(ptr) & 15u) == 0; }
 
 // Current plan for pass timing (set by the entry points while they enqueue).
@@ -252,7 +360,7 @@ bool slab_fits(const se2conv_shape& s, bool d) {
     a.pad = 0;
     const long long P = (long long)s.nx * s.m;
     const bool odd = odd_len(s.nx) || odd_len(s.m);
-    return P <= (long long)SE2C_MAXV * max_threads(d, odd) && slab_lds_bytes(a, d) <= kMaxLds;
+    return P <= tile_capacity(d, odd) && slab_lds_bytes(a, d) <= kMaxLds;
 }
 
 // Fields per launch of the separable two-pass schedule.  Measured on MI355X at
@@ -270,10 +378,11 @@ int sep_chunk_fields(const se2conv_plan_s* p, const se2conv_shape& s, int batch)
     return batch;
 }
 
-// Theta rows per x-row tile: the largest divisor of M within the point budget, or,
-// when M has no divisor near the budget (a prime M, say), equal chunks of at most
-// the budget with a shorter last one.
-int rows_for_xpass(const se2conv_shape& s, int points = 4096) {
+// Theta rows per x-row tile: the largest divisor of M within the point budget (capped
+// by what one tile holds), or, when M has no divisor near the budget (a prime M, say),
+// equal chunks of at most the budget with a shorter last one.
+int rows_for_xpass(const se2conv_shape& s, bool d, int points = 4096) {
+    points = (int)std::min<long long>(points, tile_capacity(d, odd_len(s.nx)));
     const int rmax = std::max(1, std::min(s.m, points / s.nx));
     int best = 1;
     for (int r = 1; r <= rmax; ++r)
@@ -293,15 +402,16 @@ const Schedule& sched_of(const se2conv_plan_s* p, const se2conv_shape& s) {
 
 int pencil_width(int ncols, int L, bool d, int want = 16) {
     int W = want;
-    while (W > 1 && (long long)W * L > (long long)SE2C_MAXV * max_threads(d, odd_len(L))) W /= 2;
+    while (W > 1 && (long long)W * L > tile_capacity(d, odd_len(L))) W /= 2;
     if (ncols < W) W = ncols;
     return W;
 }
 
 hipError_t run_slab(SlabArgs a, bool d, hipStream_t st) {
     const long long P = (long long)a.rows_per_tile * a.nx;
-    const int nthr = threads_for(P, d, odd_len(a.nx) || (a.do_t && odd_len(a.m)));
-    if (P > (long long)SE2C_MAXV * nthr) return hipErrorInvalidConfiguration;  // tile larger than the workgroup covers
+    const bool odd = odd_len(a.nx) || (a.do_t && odd_len(a.m));
+    const int nthr = threads_for(P, d, odd);
+    if (P > (long long)maxv(odd) * nthr) return hipErrorInvalidConfiguration;  // tile larger than the workgroup covers
     const long long ntiles = (long long)a.nslab * a.ntile_t * a.nitems;
     const int nb = (int)std::min<long long>(ntiles, 1 << 20);
     hipError_t e = launch_slab(a, d, nthr, nb, st);
@@ -312,7 +422,7 @@ hipError_t run_slab(SlabArgs a, bool d, hipStream_t st) {
 hipError_t run_pencil(PencilArgs a, bool d, hipStream_t st) {
     const long long P = (long long)a.p.L * a.W;
     const int nthr = threads_for(P, d, odd_len(a.p.L));
-    if (P > (long long)SE2C_MAXV * nthr) return hipErrorInvalidConfiguration;
+    if (P > (long long)maxv(odd_len(a.p.L)) * nthr) return hipErrorInvalidConfiguration;
     const int ncol_tiles = (a.ncols + a.W - 1) / a.W;
     const int nother = a.axis == 1 ? a.m : a.ny;
     const long long ntiles = (long long)ncol_tiles * nother * a.nitems;
@@ -350,7 +460,7 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
                            const Chain& ch, bool conj, hipStream_t st) {
     const bool d = dbl(p);
     const long long n = (long long)s.nx * s.ny * s.m;
-    const RadixPlan px = make_radix_plan(s.nx), py = make_radix_plan(s.ny), pt = make_radix_plan(s.m);
+    const RadixPlan px = radix_plan_of(p, s.nx, d), py = radix_plan_of(p, s.ny, d), pt = radix_plan_of(p, s.m, d);
     const size_t cb = cplx_bytes(p);
     auto fx = [&](int j) { return ch.ptr[j]; };
     auto fy = [&](int j) { return (const void*)((const char*)ch.ptr[j] + cb * s.nx); };
@@ -377,8 +487,8 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
     a.conj_tab = conj ? 1 : 0;
     a.px = px;
     a.pt = pt;
-    a.twx = tw_of(p, s.nx, d);
-    a.twt = tw_of(p, s.m, d);
+    a.twx = stage_tw_of(p, px, d);
+    a.twt = stage_tw_of(p, pt, d);
     for (int j = 0; j < ch.ntab; ++j) {
         a.tx[j] = fx(j);
         a.tt[j] = ftt(j);
@@ -408,8 +518,8 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
     if (!d && !generic_only && !two_pass && three_pass_fast_supported(s.nx, s.ny, s.m))
         return enqueue_three_pass_fast(p, s, fa, st);
     if (fast_slab && fast_pencil) {
-        // Fields are processed in chunks whose intermediate (one real plane set per
-        // field) stays resident in the memory-side cache between the two passes.
+        // Fields per launch pair (the whole batch unless SE2CONV_SEP_CHUNK says
+        // otherwise; see sep_chunk_fields).
         const int chunk = sep_chunk_fields(p, s, batch);
         for (int c0 = 0; c0 < batch; c0 += chunk) {
             FastSepArgs ca = fa;
@@ -440,7 +550,7 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
         a.do_t = 1;
         a.scale = 1.0 / ((double)s.nx * s.m);
     } else {
-        a.rows_per_tile = rows_for_xpass(s, sched_of(p, s).xrow_points);
+        a.rows_per_tile = rows_for_xpass(s, d, sched_of(p, s).xrow_points);
         a.ntile_t = (s.m + a.rows_per_tile - 1) / a.rows_per_tile;
         a.do_t = 0;
         a.scale = 1.0 / (double)s.nx;
@@ -472,7 +582,7 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
         b.conj_tab = conj ? 1 : 0;
         b.scale = 1.0 / (double)L;
         b.p = axis == 1 ? py : pt;
-        b.tw = tw_of(p, L, d);
+        b.tw = stage_tw_of(p, b.p, d);
         HIPCHK(run_pencil(b, d, st));
         return SE2CONV_OK;
     };
@@ -534,17 +644,17 @@ se2conv_status enqueue_sep_items(se2conv_plan_s* p, const se2conv_shape& s, cons
         a.mul = 1;
         a.ntab = 0;  // factors come from the items
         a.conj_tab = conj ? 1 : 0;
-        a.px = make_radix_plan(s.nx);
-        a.pt = make_radix_plan(s.m);
-        a.twx = tw_of(p, s.nx, d);
-        a.twt = tw_of(p, s.m, d);
+        a.px = radix_plan_of(p, s.nx, d);
+        a.pt = radix_plan_of(p, s.m, d);
+        a.twx = stage_tw_of(p, a.px, d);
+        a.twt = stage_tw_of(p, a.pt, d);
         if (two_pass) {
             a.rows_per_tile = s.m;
             a.ntile_t = 1;
             a.do_t = 1;
             a.scale = 1.0 / ((double)s.nx * s.m);
         } else {
-            a.rows_per_tile = rows_for_xpass(s, sched_of(p, s).xrow_points);
+            a.rows_per_tile = rows_for_xpass(s, d, sched_of(p, s).xrow_points);
             a.ntile_t = (s.m + a.rows_per_tile - 1) / a.rows_per_tile;
             a.do_t = 0;
             a.scale = 1.0 / (double)s.nx;
@@ -569,8 +679,8 @@ se2conv_status enqueue_sep_items(se2conv_plan_s* p, const se2conv_shape& s, cons
         b.ntab = 0;
         b.conj_tab = conj ? 1 : 0;
         b.scale = 1.0 / (double)L;
-        b.p = make_radix_plan(L);
-        b.tw = tw_of(p, L, d);
+        b.p = radix_plan_of(p, L, d);
+        b.tw = stage_tw_of(p, b.p, d);
         return run_pencil(b, d, st);
     };
     if (fast_pencil) {
@@ -590,7 +700,7 @@ se2conv_status enqueue_sep_items(se2conv_plan_s* p, const se2conv_shape& s, cons
 hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int dir, const void* in0,
                         const void* in1, void* out0, void* out1, const void* lone_in1, void* lone_out1,
                         long long stride_in, long long stride_out, int nitems, hipStream_t st, int cplx = 0) {
-    const RadixPlan px = make_radix_plan(s.nx), pt = make_radix_plan(s.m);
+    const RadixPlan px = radix_plan_of(p, s.nx, d), pt = radix_plan_of(p, s.m, d);
     SlabArgs a{};
     a.cplx = cplx;
     a.in0 = in0;
@@ -614,8 +724,8 @@ hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int d
     a.mul = 0;
     a.px = px;
     a.pt = pt;
-    a.twx = tw_of(p, s.nx, d);
-    a.twt = tw_of(p, s.m, d);
+    a.twx = stage_tw_of(p, px, d);
+    a.twt = stage_tw_of(p, pt, d);
     if (slab_fits(s, d)) {
         a.rows_per_tile = s.m;
         a.ntile_t = 1;
@@ -623,7 +733,7 @@ hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int d
         return run_slab(a, d, st);
     }
     // split: x rows and theta pencils (planes mode), in the right order
-    a.rows_per_tile = rows_for_xpass(s, sched_of(p, s).xrow_points);
+    a.rows_per_tile = rows_for_xpass(s, d, sched_of(p, s).xrow_points);
     a.ntile_t = (s.m + a.rows_per_tile - 1) / a.rows_per_tile;
     a.do_t = 0;
     PencilArgs b{};
@@ -640,7 +750,7 @@ hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int d
     b.inv = dir == 1;
     b.mul = 0;
     b.p = pt;
-    b.tw = tw_of(p, s.m, d);
+    b.tw = stage_tw_of(p, pt, d);
     b.nitems = nitems;
     hipError_t e;
     if (dir == 0) {
@@ -695,8 +805,8 @@ hipError_t y_pass(se2conv_plan_s* p, const se2conv_shape& s, bool d, void* re, v
     b.fwd = fwd;
     b.inv = inv;
     b.mul = mul;
-    b.p = make_radix_plan(s.ny);
-    b.tw = tw_of(p, s.ny, d);
+    b.p = radix_plan_of(p, s.ny, d);
+    b.tw = stage_tw_of(p, b.p, d);
     b.conj_tab = conj ? 1 : 0;
     b.scale = scale;
     if (mul && ch) {
@@ -740,8 +850,8 @@ hipError_t y_pass_io(se2conv_plan_s* p, const se2conv_shape& s, bool d, const vo
     b.fwd = fwd;
     b.inv = inv;
     b.mul = mul;
-    b.p = make_radix_plan(s.ny);
-    b.tw = tw_of(p, s.ny, d);
+    b.p = radix_plan_of(p, s.ny, d);
+    b.tw = stage_tw_of(p, b.p, d);
     b.conj_tab = conj ? 1 : 0;
     b.scale = scale;
     if (mul && ch) {
@@ -1107,6 +1217,21 @@ se2conv_status se2conv_plan(const se2conv_shape* shapes, int32_t n_shapes, se2co
         p->tw32[L] = t32;
         if (launch_twiddles((double2*)t64, (float2*)t32, L, nullptr) != hipSuccess)
             return cleanup(fail(SE2CONV_ERR_DEVICE, "twiddle generation launch failed"));
+        if (make_radix_plan(L).rader) {
+            std::vector<unsigned char> h64, h32;
+            rader_tables(L, h64, h32);
+            void* r64 = nullptr;
+            void* r32 = nullptr;
+            if (hipMalloc(&r64, h64.size()) != hipSuccess)
+                return cleanup(fail(SE2CONV_ERR_OUT_OF_MEMORY, "Rader table allocation"));
+            p->rader64[L] = r64;
+            if (hipMalloc(&r32, h32.size()) != hipSuccess)
+                return cleanup(fail(SE2CONV_ERR_OUT_OF_MEMORY, "Rader table allocation"));
+            p->rader32[L] = r32;
+            if (hipMemcpy(r64, h64.data(), h64.size(), hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(r32, h32.data(), h32.size(), hipMemcpyHostToDevice) != hipSuccess)
+                return cleanup(fail(SE2CONV_ERR_DEVICE, "Rader table upload failed"));
+        }
     }
     if (prepare_kernels() != hipSuccess) return cleanup(fail(SE2CONV_ERR_DEVICE, "kernel attribute setup failed"));
     p->ws_bytes = maxn * real_bytes(p);
@@ -1136,6 +1261,8 @@ se2conv_status se2conv_plan_destroy(se2conv_plan_t p) {
         for (auto ev : p->ev_rec) (void)hipEventDestroy(ev);
         for (auto& kv : p->tw32) (void)hipFree(kv.second);
         for (auto& kv : p->tw64) (void)hipFree(kv.second);
+        for (auto& kv : p->rader32) (void)hipFree(kv.second);
+        for (auto& kv : p->rader64) (void)hipFree(kv.second);
         if (p->ws) (void)hipFree(p->ws);
         if (p->ws2) (void)hipFree(p->ws2);
         if (p->ws4) (void)hipFree(p->ws4);

@@ -211,20 +211,22 @@ __device__ __forceinline__ int pad_source(int g, int G, int L, bool* half) {
     return -1;
 }
 
-// Division by a small runtime divisor d (1 <= d, n < 2^21) via a 32x32->64
-// multiply by ceil(2^42/d): exact for all n < 2^21 because n*d < 2^42.
+// Division by a runtime divisor 1 <= d < 2^16 of n < 2^16 (every index of a tile:
+// tiles hold at most 16384 points): q = mulhi(n, m) with m = ceil(2^32 / d).  With
+// m d = 2^32 + r, 0 <= r < d, n m / 2^32 = n/d + n r / (d 2^32) and the second term
+// is below 2^-16 < 1/d, so the floor is exact.  d = 1 is m = 0.  Building m takes one
+// 32-bit division (a 64-bit magic number would take a software 64-bit division on
+// the scalar unit per stage).
 struct FastDiv {
-    uint32_t d;
-    uint64_t m;
+    uint32_t m;
 };
 __host__ __device__ inline FastDiv make_fastdiv(uint32_t d) {
     FastDiv f;
-    f.d = d;
-    f.m = ((uint64_t(1) << 42) + d - 1) / d;
+    f.m = d > 1 ? 0xFFFFFFFFu / d + 1u : 0u;
     return f;
 }
 __device__ __forceinline__ uint32_t fdiv(uint32_t n, FastDiv f) {
-    return (uint32_t)((uint64_t(n) * f.m) >> 42);
+    return f.m ? __umulhi(n, f.m) : n;
 }
 
 // One radix-R stage over 'nlines' lines of length L in LDS.
@@ -349,31 +351,40 @@ __device__ __forceinline__ void direct_stage(C<T>* buf, const C<T>* tw, const St
     __syncthreads();
 }
 
-// Radix plan for one transform length: up to 8 stages.
+// Radix plan for one transform length: up to 8 stages.  For a prime length L above
+// 7 (rader = 1) the stages are those of L - 1: the DFT runs as Rader's cyclic
+// convolution of length L - 1, with its tables at rtab (device, the kernel's type):
+// the twiddles w_{L-1}^j, the forward and inverse kernel spectra (each L - 1 complex
+// values), then the index maps g^q mod L and g^-q mod L (L - 1 ints each).
 struct RadixPlan {
     int L;
     int nst;
     int r[8];
+    int rader;
+    const void* rtab;
 };
 
-// Transform 'nlines' lines of length p.L (forward or inverse) in LDS.
-template <typename T, int MAXV, bool INV, bool ODD = false>
-__device__ void line_fft(C<T>* buf, const C<T>* tw, const RadixPlan& p, int es, int ls, int nlines,
-                         bool line_fast, int tid, int nthr) {
+// Entries of the twiddle table a plan's stages read: L, or L - 1 under Rader.
+__host__ __device__ __forceinline__ int stage_tw_len(const RadixPlan& p) { return p.rader ? p.L - 1 : p.L; }
+
+// The Stockham stages r[0..nst) of a length-L transform over 'nlines' lines in LDS.
+template <typename T, int MAXV, bool INV, bool ODD>
+__device__ __forceinline__ void run_stages(C<T>* buf, const C<T>* tw, const RadixPlan& p, int L, int es, int ls,
+                                           int nlines, bool line_fast, int tid, int nthr) {
     int Ns = 1;
     for (int s = 0; s < p.nst; ++s) {
         const int R = p.r[s];
         StageGeom g;
-        g.L = p.L;
+        g.L = L;
         g.Ns = Ns;
         g.es = es;
         g.ls = ls;
         g.nlines = nlines;
-        g.div_nbl = make_fastdiv((uint32_t)(p.L / R));
+        g.div_nbl = make_fastdiv((uint32_t)(L / R));
         g.div_ns = make_fastdiv((uint32_t)Ns);
         g.div_nl = make_fastdiv((uint32_t)nlines);
-        g.div_l = make_fastdiv((uint32_t)p.L);
-        g.tw_step = p.L / (Ns * R);
+        g.div_l = make_fastdiv((uint32_t)L);
+        g.tw_step = L / (Ns * R);
         switch (R) {
             case 16: stockham_stage<T, 16, MAXV, INV>(buf, tw, g, line_fast, tid, nthr); break;
             case 8: stockham_stage<T, 8, MAXV, INV>(buf, tw, g, line_fast, tid, nthr); break;
@@ -390,6 +401,122 @@ __device__ void line_fft(C<T>* buf, const C<T>* tw, const RadixPlan& p, int es, 
                 break;
         }
         Ns *= R;
+    }
+}
+
+// Work item e of the n * nlines items of a line-wise step -> (line, q < n).
+__device__ __forceinline__ void split_item(int e, int n, int nlines, FastDiv div_n, FastDiv div_nl, bool line_fast,
+                                           int& line, int& q) {
+    if (line_fast) {
+        q = (int)fdiv((uint32_t)e, div_nl);
+        line = e - q * nlines;
+    } else {
+        line = (int)fdiv((uint32_t)e, div_n);
+        q = e - line * n;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ C<T> conj_if(C<T> v, bool c) {
+    if (c) v.y = -v.y;
+    return v;
+}
+
+// Rader's reindexing of a prime-length line: GATHER moves x[g^q] to slot 1 + q (and
+// conjugates it when CONJ), otherwise slot 1 + q (conjugated when CONJ) moves to
+// g^-q.  Slot 0 stays.  Every value passes through registers between two barriers,
+// so the permutation is in place.
+template <typename T, int MAXV, bool GATHER, bool CONJ>
+__device__ __forceinline__ void rader_permute(C<T>* buf, const int* perm, int n, int es, int ls, int nlines,
+                                              FastDiv div_n, FastDiv div_nl, bool line_fast, int tid, int nthr) {
+    const int total = n * nlines;
+    C<T> v[MAXV];
+#pragma unroll
+    for (int u = 0; u < MAXV; ++u) {
+        const int e = tid + u * nthr;
+        if (e < total) {
+            int line, q;
+            split_item(e, n, nlines, div_n, div_nl, line_fast, line, q);
+            const int src = GATHER ? perm[q] : 1 + q;
+            v[u] = conj_if<T>(buf[line * ls + src * es], CONJ);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < MAXV; ++u) {
+        const int e = tid + u * nthr;
+        if (e < total) {
+            int line, q;
+            split_item(e, n, nlines, div_n, div_nl, line_fast, line, q);
+            const int dst = GATHER ? 1 + q : perm[q];
+            buf[line * ls + dst * es] = v[u];
+        }
+    }
+    __syncthreads();
+}
+
+// Transform 'nlines' lines of length p.L (forward or inverse) in LDS.  'tw' holds
+// the plan's stage twiddles (stage_tw_len entries).
+//
+// A prime length above 7 (ODD kernels) runs by Rader's algorithm.  With a generator
+// g of the units mod L, X[g^-m] = x[0] + sum_q x[g^q] w^{g^(q-m)}: a cyclic
+// convolution of length n = L - 1 of a_q = x[g^q] with b_j = w^{g^-j} (w = w_L,
+// conjugated for the inverse transform).  It is computed as A = DFT_n(a), the product
+// with B = DFT_n(b) / n (tabulated in FP64), and an unnormalised inverse DFT_n; x[0]
+// enters as a constant added to the zero frequency of the product, and
+// X[0] = x[0] + A[0].  Both length-n transforms run through the one stage loop of
+// this direction: the opposite direction is its conjugate, conj(DFT(conj(v))), and
+// those conjugations ride on the permutations and the product step.
+template <typename T, int MAXV, bool INV, bool ODD = false>
+__device__ __forceinline__ void line_fft(C<T>* buf, const C<T>* tw, const RadixPlan& p, int es, int ls, int nlines,
+                                         bool line_fast, int tid, int nthr) {
+    bool rad = false;
+    if constexpr (ODD) rad = p.rader != 0;
+    const int n = rad ? p.L - 1 : p.L;
+    C<T>* sub = rad ? buf + es : buf;
+    const C<T>* bh = nullptr;
+    const int* pin = nullptr;
+    FastDiv div_n{}, div_nl{};
+    if constexpr (ODD) {
+        if (rad) {
+            const C<T>* tab = reinterpret_cast<const C<T>*>(p.rtab);
+            bh = tab + (INV ? 2 : 1) * n;
+            pin = reinterpret_cast<const int*>(tab + 3 * n);
+            div_n = make_fastdiv((uint32_t)n);
+            div_nl = make_fastdiv((uint32_t)nlines);
+            // the forward DFT_n of an inverse transform runs as conj(DFT_n^-1(conj a))
+            rader_permute<T, MAXV, true, INV>(buf, pin, n, es, ls, nlines, div_n, div_nl, line_fast, tid, nthr);
+        }
+    }
+    const int npass = rad ? 2 : 1;
+#pragma unroll 1
+    for (int pass = 0; pass < npass; ++pass) {
+        run_stages<T, MAXV, INV, ODD>(sub, tw, p, n, es, ls, nlines, line_fast, tid, nthr);
+        if constexpr (ODD) {
+            if (rad && pass == 0) {
+                const int total = n * nlines;
+                for (int e = tid; e < total; e += nthr) {
+                    int line, k;
+                    split_item(e, n, nlines, div_n, div_nl, line_fast, line, k);
+                    C<T>* row = buf + line * ls;
+                    const C<T> a = conj_if<T>(row[(1 + k) * es], INV);  // A[k]
+                    C<T> v = mul<T>(a, bh[k]);
+                    if (k == 0) {  // the only work item that touches slot 0 of this line
+                        const C<T> x0 = row[0];
+                        row[0] = add<T>(x0, a);
+                        v = add<T>(v, x0);
+                    }
+                    // the inverse DFT_n of a forward transform runs as conj(DFT_n(conj v))
+                    row[(1 + k) * es] = conj_if<T>(v, !INV);
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if constexpr (ODD) {
+        if (rad)
+            rader_permute<T, MAXV, false, !INV>(buf, pin + n, n, es, ls, nlines, div_n, div_nl, line_fast, tid,
+                                                nthr);
     }
 }
 

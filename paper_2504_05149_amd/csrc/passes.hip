@@ -43,9 +43,12 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) slab_kernel(S
     C<T>* fx = twt + a.m;                           // separable factors (scaled)
     C<T>* ft = fx + a.nx;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    // elements per thread staged through registers by tile loads and stores (one in
+    // the kernels with odd stages, where staging measured slower)
+    constexpr int STG = ODD ? 1 : SE2C_STAGE;
 
-    load_tw<T>(twx, a.twx, a.nx, tid, nthr);
-    if (a.do_t) load_tw<T>(twt, a.twt, a.m, tid, nthr);
+    load_tw<T>(twx, a.twx, stage_tw_len(a.px), tid, nthr);
+    if (a.do_t) load_tw<T>(twt, a.twt, stage_tw_len(a.pt), tid, nthr);
     if (a.mul) {
         const T sc = (T)a.scale;
         for (int i = tid; i < a.nx; i += nthr) {
@@ -113,14 +116,29 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) slab_kernel(S
         }
         __syncthreads();
         const int P = nrow * a.nx;
-        for (int i = tid; i < P; i += nthr) {
-            const int r = i / a.nx;
-            const int x = i - r * a.nx;
-            const long long off = ((long long)(t0 + r) * plane + x) * es;
-            C<T> v;
-            v.x = in0[off];
-            v.y = in1 ? in1[off] : (T)0;
-            tile[r * pitch + x] = v;
+        // Tile loads and stores move STG elements per thread at a time, reads first,
+        // so that that many HBM reads are in flight together.
+#pragma unroll 1
+        for (int i0 = tid; i0 < P; i0 += STG * nthr) {
+            C<T> v[STG];
+#pragma unroll
+            for (int k = 0; k < STG; ++k) {
+                const int i = i0 + k * nthr;
+                if (i < P) {
+                    const int r = i / a.nx;
+                    const long long off = ((long long)(t0 + r) * plane + (i - r * a.nx)) * es;
+                    v[k].x = in0[off];
+                    v[k].y = in1 ? in1[off] : (T)0;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < STG; ++k) {
+                const int i = i0 + k * nthr;
+                if (i < P) {
+                    const int r = i / a.nx;
+                    tile[r * pitch + (i - r * a.nx)] = v[k];
+                }
+            }
         }
         __syncthreads();
 
@@ -158,13 +176,27 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) slab_kernel(S
                             : (a.out1 ? reinterpret_cast<T*>(a.out1) + (long long)item * a.item_stride_out : nullptr);
             if (out1) out1 += (long long)slab * a.nx * es;
         }
-        for (int i = tid; i < P; i += nthr) {
-            const int r = i / a.nx;
-            const int x = i - r * a.nx;
-            const long long off = ((long long)(t0 + r) * plane + x) * es;
-            const C<T> v = tile[r * pitch + x];
-            out0[off] = v.x;
-            if (out1) out1[off] = v.y;
+#pragma unroll 1
+        for (int i0 = tid; i0 < P; i0 += STG * nthr) {
+            C<T> v[STG];
+#pragma unroll
+            for (int k = 0; k < STG; ++k) {
+                const int i = i0 + k * nthr;
+                if (i < P) {
+                    const int r = i / a.nx;
+                    v[k] = tile[r * pitch + (i - r * a.nx)];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < STG; ++k) {
+                const int i = i0 + k * nthr;
+                if (i < P) {
+                    const int r = i / a.nx;
+                    const long long off = ((long long)(t0 + r) * plane + (i - r * a.nx)) * es;
+                    out0[off] = v[k].x;
+                    if (out1) out1[off] = v[k].y;
+                }
+            }
         }
     }
 }
@@ -179,8 +211,9 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) pencil_kernel
     C<T>* tw = tile + L * pitch;
     C<T>* f1 = tw + L;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    constexpr int STG = ODD ? 1 : SE2C_STAGE;  // as in the slab pass
 
-    load_tw<T>(tw, a.tw, L, tid, nthr);
+    load_tw<T>(tw, a.tw, stage_tw_len(a.p), tid, nthr);
     if (a.mul == 1) {
         const T sc = (T)a.scale;
         for (int i = tid; i < L; i += nthr) {
@@ -229,28 +262,50 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) pencil_kernel
             const T* ibase = a.items ? reinterpret_cast<const T*>(a.items[item].out)
                                      : reinterpret_cast<const T*>(a.in0) + (long long)item * a.item_stride_in;
             const C<T>* in = reinterpret_cast<const C<T>*>(ibase + obase);
-            for (int i = tid; i < P; i += nthr) {
-                const int e = i / a.W;
-                const int c = i - e * a.W;
-                C<T> v = mk<T>((T)0, (T)0);
-                if (c0 + c < a.ncols) v = in[(e * astride) / 2 + c0 + c];
-                tile[e * pitch + c] = v;
+#pragma unroll 1
+            for (int i0 = tid; i0 < P; i0 += STG * nthr) {
+                C<T> v[STG];
+#pragma unroll
+                for (int k = 0; k < STG; ++k) {
+                    const int i = i0 + k * nthr;
+                    const int e = i / a.W;
+                    const int c = i - e * a.W;
+                    v[k] = mk<T>((T)0, (T)0);
+                    if (i < P && c0 + c < a.ncols) v[k] = in[(e * astride) / 2 + c0 + c];
+                }
+#pragma unroll
+                for (int k = 0; k < STG; ++k) {
+                    const int i = i0 + k * nthr;
+                    const int e = i / a.W;
+                    if (i < P) tile[e * pitch + (i - e * a.W)] = v[k];
+                }
             }
         } else {
             const T* in0 = reinterpret_cast<const T*>(a.in0) + (long long)item * a.item_stride_in + obase * es;
             const T* in1 = last_odd ? reinterpret_cast<const T*>(a.lone_in1)
                                     : (a.in1 ? reinterpret_cast<const T*>(a.in1) + (long long)item * a.item_stride_in : nullptr);
             if (in1) in1 += obase * es;
-            for (int i = tid; i < P; i += nthr) {
-                const int e = i / a.W;
-                const int c = i - e * a.W;
-                C<T> v = mk<T>((T)0, (T)0);
-                if (c0 + c < a.ncols) {
-                    const long long off = (e * astride + c0 + c) * es;
-                    v.x = in0[off];
-                    v.y = in1 ? in1[off] : (T)0;
+#pragma unroll 1
+            for (int i0 = tid; i0 < P; i0 += STG * nthr) {
+                C<T> v[STG];
+#pragma unroll
+                for (int k = 0; k < STG; ++k) {
+                    const int i = i0 + k * nthr;
+                    const int e = i / a.W;
+                    const int c = i - e * a.W;
+                    v[k] = mk<T>((T)0, (T)0);
+                    if (i < P && c0 + c < a.ncols) {
+                        const long long off = (e * astride + c0 + c) * es;
+                        v[k].x = in0[off];
+                        v[k].y = in1 ? in1[off] : (T)0;
+                    }
                 }
-                tile[e * pitch + c] = v;
+#pragma unroll
+                for (int k = 0; k < STG; ++k) {
+                    const int i = i0 + k * nthr;
+                    const int e = i / a.W;
+                    if (i < P) tile[e * pitch + (i - e * a.W)] = v[k];
+                }
             }
         }
         __syncthreads();
@@ -294,24 +349,47 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) pencil_kernel
             T* obase_ptr = a.items ? reinterpret_cast<T*>(a.items[item].out)
                                    : reinterpret_cast<T*>(a.out0) + (long long)item * a.item_stride_out;
             C<T>* out = reinterpret_cast<C<T>*>(obase_ptr + obase);
-            for (int i = tid; i < P; i += nthr) {
-                const int e = i / a.W;
-                const int c = i - e * a.W;
-                if (c0 + c < a.ncols) out[(e * astride) / 2 + c0 + c] = tile[e * pitch + c];
+#pragma unroll 1
+            for (int i0 = tid; i0 < P; i0 += STG * nthr) {
+                C<T> v[STG];
+#pragma unroll
+                for (int k = 0; k < STG; ++k) {
+                    const int i = i0 + k * nthr;
+                    const int e = i / a.W;
+                    if (i < P) v[k] = tile[e * pitch + (i - e * a.W)];
+                }
+#pragma unroll
+                for (int k = 0; k < STG; ++k) {
+                    const int i = i0 + k * nthr;
+                    const int e = i / a.W;
+                    const int c = i - e * a.W;
+                    if (i < P && c0 + c < a.ncols) out[(e * astride) / 2 + c0 + c] = v[k];
+                }
             }
         } else {
             T* out0 = reinterpret_cast<T*>(a.out0) + (long long)item * a.item_stride_out + obase * es;
             T* out1 = last_odd ? reinterpret_cast<T*>(a.lone_out1)
                                : (a.out1 ? reinterpret_cast<T*>(a.out1) + (long long)item * a.item_stride_out : nullptr);
             if (out1) out1 += obase * es;
-            for (int i = tid; i < P; i += nthr) {
-                const int e = i / a.W;
-                const int c = i - e * a.W;
-                if (c0 + c < a.ncols) {
-                    const long long off = (e * astride + c0 + c) * es;
-                    const C<T> v = tile[e * pitch + c];
-                    out0[off] = v.x;
-                    if (out1) out1[off] = v.y;
+#pragma unroll 1
+            for (int i0 = tid; i0 < P; i0 += STG * nthr) {
+                C<T> v[STG];
+#pragma unroll
+                for (int k = 0; k < STG; ++k) {
+                    const int i = i0 + k * nthr;
+                    const int e = i / a.W;
+                    if (i < P) v[k] = tile[e * pitch + (i - e * a.W)];
+                }
+#pragma unroll
+                for (int k = 0; k < STG; ++k) {
+                    const int i = i0 + k * nthr;
+                    const int e = i / a.W;
+                    const int c = i - e * a.W;
+                    if (i < P && c0 + c < a.ncols) {
+                        const long long off = (e * astride + c0 + c) * es;
+                        out0[off] = v[k].x;
+                        if (out1) out1[off] = v[k].y;
+                    }
                 }
             }
         }
@@ -335,6 +413,7 @@ static hipError_t launch_pencil_t(const PencilArgs& a, int nthr, int nblocks, si
 // codelets and the direct stage (kept out of the 2^a 3^b kernels, whose register
 // allocation they would raise).  Those kernels take at most 512 threads.
 static bool needs_odd_stages(const RadixPlan& p) {
+    if (p.rader) return true;
     for (int i = 0; i < p.nst; ++i)
         if (p.r[i] != 2 && p.r[i] != 3 && p.r[i] != 4 && p.r[i] != 8 && p.r[i] != 16) return true;
     return false;
@@ -347,10 +426,10 @@ hipError_t prepare_generic_kernels() {
                          reinterpret_cast<const void*>(slab_kernel<double, SE2C_MAXV, false>),
                          reinterpret_cast<const void*>(pencil_kernel<float, SE2C_MAXV, false>),
                          reinterpret_cast<const void*>(pencil_kernel<double, SE2C_MAXV, false>),
-                         reinterpret_cast<const void*>(slab_kernel<float, SE2C_MAXV, true>),
-                         reinterpret_cast<const void*>(slab_kernel<double, SE2C_MAXV, true>),
-                         reinterpret_cast<const void*>(pencil_kernel<float, SE2C_MAXV, true>),
-                         reinterpret_cast<const void*>(pencil_kernel<double, SE2C_MAXV, true>)};
+                         reinterpret_cast<const void*>(slab_kernel<float, SE2C_MAXV_ODD, true>),
+                         reinterpret_cast<const void*>(slab_kernel<double, SE2C_MAXV_ODD, true>),
+                         reinterpret_cast<const void*>(pencil_kernel<float, SE2C_MAXV_ODD, true>),
+                         reinterpret_cast<const void*>(pencil_kernel<double, SE2C_MAXV_ODD, true>)};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
@@ -372,8 +451,8 @@ hipError_t launch_slab(const SlabArgs& a, bool dbl, int nthr, int nblocks, hipSt
     const size_t lds = slab_lds_bytes(a, dbl);
     const bool odd = needs_odd_stages(a.px) || (a.do_t && needs_odd_stages(a.pt));
     if (odd) {
-        if (dbl) return launch_slab_t<double, SE2C_MAXV, true>(a, nthr, nblocks, lds, s);
-        return launch_slab_t<float, SE2C_MAXV, true>(a, nthr, nblocks, lds, s);
+        if (dbl) return launch_slab_t<double, SE2C_MAXV_ODD, true>(a, nthr, nblocks, lds, s);
+        return launch_slab_t<float, SE2C_MAXV_ODD, true>(a, nthr, nblocks, lds, s);
     }
     if (dbl) return launch_slab_t<double, SE2C_MAXV, false>(a, nthr, nblocks, lds, s);
     return launch_slab_t<float, SE2C_MAXV, false>(a, nthr, nblocks, lds, s);
@@ -382,8 +461,8 @@ hipError_t launch_slab(const SlabArgs& a, bool dbl, int nthr, int nblocks, hipSt
 hipError_t launch_pencil(const PencilArgs& a, bool dbl, int nthr, int nblocks, hipStream_t s) {
     const size_t lds = pencil_lds_bytes(a, dbl);
     if (needs_odd_stages(a.p)) {
-        if (dbl) return launch_pencil_t<double, SE2C_MAXV, true>(a, nthr, nblocks, lds, s);
-        return launch_pencil_t<float, SE2C_MAXV, true>(a, nthr, nblocks, lds, s);
+        if (dbl) return launch_pencil_t<double, SE2C_MAXV_ODD, true>(a, nthr, nblocks, lds, s);
+        return launch_pencil_t<float, SE2C_MAXV_ODD, true>(a, nthr, nblocks, lds, s);
     }
     if (dbl) return launch_pencil_t<double, SE2C_MAXV, false>(a, nthr, nblocks, lds, s);
     return launch_pencil_t<float, SE2C_MAXV, false>(a, nthr, nblocks, lds, s);

@@ -6,6 +6,16 @@
 #include "fft_device.hpp"
 
 #define SE2C_MAXV 16          // complex values held per thread during a stage
+// The same for the kernels with radix-5/7, direct and Rader stages: a smaller budget
+// keeps their register allocation low enough for several workgroups per CU.
+#ifndef SE2C_MAXV_ODD
+#define SE2C_MAXV_ODD 8
+#endif
+// Tile elements per thread whose HBM reads are in flight together when a tile is
+// loaded or stored.
+#ifndef SE2C_STAGE
+#define SE2C_STAGE 4
+#endif
 #define SE2C_MAX_TABLES 8     // kernels multiplied at run time in one pass
 // Threads per workgroup: FP32 tiles use up to 1024 (128 VGPRs each), FP64 tiles
 // up to 512 so that the doubled register footprint does not spill.

@@ -1,5 +1,6 @@
 """GPU parity on general grid sizes: the paper's odd grids L = 2K+1 (Sec. 3.2) and
-lengths with prime factors above 3 (radix-5/7 codelets, direct-summation stages).
+lengths with prime factors above 3 (radix-5/7 codelets, Rader's algorithm for prime
+lengths above 7, direct-summation stages for other prime factors).
 
 Same bars as the other parity tests: FP32 rel-L2 <= 2e-6 log2(N^2 M), FP64 <= 1e-12,
 against the FP64 oracle (signed frequencies, |k| <= K on odd axes).
@@ -175,3 +176,37 @@ def test_general_size_powers_and_gradients(dt):
     err = rel_l2(kg, ref)
     print(f"kernel gradient: rel-L2 {err:.2e}", flush=True)
     assert err <= tol
+
+
+RADER_CASES = [
+    # (nx, ny, m, dtype): prime axes above 7 run by Rader's algorithm on the stages of L - 1
+    (11, 13, 17, "f64"),   # smallest: inner lengths 10 = 2*5, 12 = 4*3, 16
+    (47, 23, 97, "f32"),   # inner 46 = 2*23 and 22 = 2*11 (direct stages), 96 = 16*2*3
+    (509, 16, 8, "f32"),   # largest prime length, along x: inner 508 = 4*127
+    (16, 509, 8, "f64"),   # along y
+    (40, 34, 37, "f32"),   # even x and y: pair passes with a prime theta axis
+]
+
+
+@pytest.mark.parametrize("nx,ny,m,dt", RADER_CASES)
+def test_prime_lengths_field_coeffs_and_apply(nx, ny, m, dt):
+    case(f"prime lengths (Rader) {nx}x{ny}x{m} {dt}: field coefficients and a chain")
+    plan = se2.Plan([(nx, ny, m)], dtype=dt)
+    f = sample_fields(11, 2, 8, nx, ny, m)
+    fd = _dev(f, _tdt(dt))
+    ft = plan.field_coeffs(0, fd)
+    chain = [(0.05, 6.0, 0.4), (0.03, 2.0, 1.9)]
+    table = plan.coeffs(0, [se2.GaussVM(*c) for c in chain])
+    out = plan.apply(0, fd, table)
+    adj = plan.apply(0, fd, table, adjoint=True)
+    torch.cuda.synchronize()
+    tol = _tol(dt, nx * ny * m)
+    ref_t = oracle_table_gauss(nx, ny, m, chain)
+    for b in range(2):
+        gpu = ft[b].complex_view().cpu().numpy()
+        ref = ffc(f[b])
+        err = np.linalg.norm(gpu - ref) / np.linalg.norm(ref)
+        e1 = rel_l2(out[b].cpu().numpy().astype(np.float64), oc.conv_with_coeffs(f[b], ref_t))
+        e2 = rel_l2(adj[b].cpu().numpy().astype(np.float64), oc.conv_with_coeffs(f[b], np.conj(ref_t)))
+        print(f"field {b}: coefficients {err:.2e}, apply {e1:.2e}, adjoint {e2:.2e} (tol {tol:.1e})", flush=True)
+        assert max(err, e1, e2) <= tol
