@@ -123,13 +123,13 @@ bool odd_len(int L) {
 int max_threads(bool d, bool odd = false) { return (d || odd) ? 512 : 1024; }
 
 // Complex values per thread per stage of the generic kernels.
-int maxv(bool odd) { return odd ? SE2C_MAXV_ODD : SE2C_MAXV; }
+int maxv(bool d, bool odd) { return odd ? SE2C_MAXV_ODD : (d ? SE2C_MAXV_F64 : SE2C_MAXV); }
 
 // Points one generic tile can hold.
-long long tile_capacity(bool d, bool odd) { return (long long)maxv(odd) * max_threads(d, odd); }
+long long tile_capacity(bool d, bool odd) { return (long long)maxv(d, odd) * max_threads(d, odd); }
 
 int threads_for(long long P, bool d, bool odd) {
-    long long t = (P + maxv(odd) - 1) / maxv(odd);
+    long long t = (P + maxv(d, odd) - 1) / maxv(d, odd);
     t = ((t + 63) / 64) * 64;
     if (t < 64) t = 64;
     if (t > max_threads(d, odd)) t = max_threads(d, odd);
@@ -411,7 +411,7 @@ hipError_t run_slab(SlabArgs a, bool d, hipStream_t st) {
     const long long P = (long long)a.rows_per_tile * a.nx;
     const bool odd = odd_len(a.nx) || (a.do_t && odd_len(a.m));
     const int nthr = threads_for(P, d, odd);
-    if (P > (long long)maxv(odd) * nthr) return hipErrorInvalidConfiguration;  // tile larger than the workgroup covers
+    if (P > (long long)maxv(d, odd) * nthr) return hipErrorInvalidConfiguration;  // tile larger than the workgroup covers
     const long long ntiles = (long long)a.nslab * a.ntile_t * a.nitems;
     const int nb = (int)std::min<long long>(ntiles, 1 << 20);
     hipError_t e = launch_slab(a, d, nthr, nb, st);
@@ -422,7 +422,7 @@ hipError_t run_slab(SlabArgs a, bool d, hipStream_t st) {
 hipError_t run_pencil(PencilArgs a, bool d, hipStream_t st) {
     const long long P = (long long)a.p.L * a.W;
     const int nthr = threads_for(P, d, odd_len(a.p.L));
-    if (P > (long long)maxv(odd_len(a.p.L)) * nthr) return hipErrorInvalidConfiguration;
+    if (P > (long long)maxv(d, odd_len(a.p.L)) * nthr) return hipErrorInvalidConfiguration;
     const int ncol_tiles = (a.ncols + a.W - 1) / a.W;
     const int nother = a.axis == 1 ? a.m : a.ny;
     const long long ntiles = (long long)ncol_tiles * nother * a.nitems;

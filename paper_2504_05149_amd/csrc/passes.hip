@@ -423,9 +423,9 @@ static bool needs_odd_stages(const RadixPlan& p) {
 hipError_t prepare_generic_kernels() {
     const int lds = 160 * 1024;
     const void* fns[] = {reinterpret_cast<const void*>(slab_kernel<float, SE2C_MAXV, false>),
-                         reinterpret_cast<const void*>(slab_kernel<double, SE2C_MAXV, false>),
+                         reinterpret_cast<const void*>(slab_kernel<double, SE2C_MAXV_F64, false>),
                          reinterpret_cast<const void*>(pencil_kernel<float, SE2C_MAXV, false>),
-                         reinterpret_cast<const void*>(pencil_kernel<double, SE2C_MAXV, false>),
+                         reinterpret_cast<const void*>(pencil_kernel<double, SE2C_MAXV_F64, false>),
                          reinterpret_cast<const void*>(slab_kernel<float, SE2C_MAXV_ODD, true>),
                          reinterpret_cast<const void*>(slab_kernel<double, SE2C_MAXV_ODD, true>),
                          reinterpret_cast<const void*>(pencil_kernel<float, SE2C_MAXV_ODD, true>),
@@ -454,7 +454,7 @@ hipError_t launch_slab(const SlabArgs& a, bool dbl, int nthr, int nblocks, hipSt
         if (dbl) return launch_slab_t<double, SE2C_MAXV_ODD, true>(a, nthr, nblocks, lds, s);
         return launch_slab_t<float, SE2C_MAXV_ODD, true>(a, nthr, nblocks, lds, s);
     }
-    if (dbl) return launch_slab_t<double, SE2C_MAXV, false>(a, nthr, nblocks, lds, s);
+    if (dbl) return launch_slab_t<double, SE2C_MAXV_F64, false>(a, nthr, nblocks, lds, s);
     return launch_slab_t<float, SE2C_MAXV, false>(a, nthr, nblocks, lds, s);
 }
 
@@ -464,7 +464,7 @@ hipError_t launch_pencil(const PencilArgs& a, bool dbl, int nthr, int nblocks, h
         if (dbl) return launch_pencil_t<double, SE2C_MAXV_ODD, true>(a, nthr, nblocks, lds, s);
         return launch_pencil_t<float, SE2C_MAXV_ODD, true>(a, nthr, nblocks, lds, s);
     }
-    if (dbl) return launch_pencil_t<double, SE2C_MAXV, false>(a, nthr, nblocks, lds, s);
+    if (dbl) return launch_pencil_t<double, SE2C_MAXV_F64, false>(a, nthr, nblocks, lds, s);
     return launch_pencil_t<float, SE2C_MAXV, false>(a, nthr, nblocks, lds, s);
 }
 
