@@ -358,6 +358,8 @@ bool slab_fits(const se2conv_shape& s, bool d) {
     a.m = s.m;
     a.rows_per_tile = s.m;
     a.pad = 0;
+    a.px = make_radix_plan(s.nx);  // their LDS tables count
+    a.pt = make_radix_plan(s.m);
     const long long P = (long long)s.nx * s.m;
     const bool odd = odd_len(s.nx) || odd_len(s.m);
     return P <= tile_capacity(d, odd) && slab_lds_bytes(a, d) <= kMaxLds;

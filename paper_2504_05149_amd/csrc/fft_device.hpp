@@ -367,6 +367,15 @@ struct RadixPlan {
 // Entries of the twiddle table a plan's stages read: L, or L - 1 under Rader.
 __host__ __device__ __forceinline__ int stage_tw_len(const RadixPlan& p) { return p.rader ? p.L - 1 : p.L; }
 
+// Complex slots of the LDS copy of a plan's tables, for complex values of cb bytes:
+// the twiddles, and under Rader the whole table block (3 (L - 1) complex values and
+// 2 (L - 1) ints), rounded up to whole slots.
+__host__ __device__ __forceinline__ int tables_slots(const RadixPlan& p, int cb) {
+    if (!p.rader) return p.L;
+    const int n = p.L - 1;
+    return 3 * n + (8 * n + cb - 1) / cb;
+}
+
 // The Stockham stages r[0..nst) of a length-L transform over 'nlines' lines in LDS.
 template <typename T, int MAXV, bool INV, bool ODD>
 __device__ __forceinline__ void run_stages(C<T>* buf, const C<T>* tw, const RadixPlan& p, int L, int es, int ls,
@@ -455,8 +464,9 @@ __device__ __forceinline__ void rader_permute(C<T>* buf, const int* perm, int n,
     __syncthreads();
 }
 
-// Transform 'nlines' lines of length p.L (forward or inverse) in LDS.  'tw' holds
-// the plan's stage twiddles (stage_tw_len entries).
+// Transform 'nlines' lines of length p.L (forward or inverse) in LDS.  'tw' is the
+// LDS copy of the plan's tables (tables_slots): the stage twiddles, and under Rader
+// the rest of its table block after them.
 //
 // A prime length above 7 (ODD kernels) runs by Rader's algorithm.  With a generator
 // g of the units mod L, X[g^-m] = x[0] + sum_q x[g^q] w^{g^(q-m)}: a cyclic
@@ -479,7 +489,7 @@ __device__ __forceinline__ void line_fft(C<T>* buf, const C<T>* tw, const RadixP
     FastDiv div_n{}, div_nl{};
     if constexpr (ODD) {
         if (rad) {
-            const C<T>* tab = reinterpret_cast<const C<T>*>(p.rtab);
+            const C<T>* tab = tw;
             bh = tab + (INV ? 2 : 1) * n;
             pin = reinterpret_cast<const int*>(tab + 3 * n);
             div_n = make_fastdiv((uint32_t)n);

@@ -24,10 +24,20 @@
 
 namespace se2c {
 
+// LDS copy of a plan's tables (tables_slots complex slots; src holds at least the
+// bytes they cover, see stage_tw_of on the host).
 template <typename T>
-__device__ __forceinline__ void load_tw(C<T>* dst, const void* src, int L, int tid, int nthr) {
-    const C<T>* s = reinterpret_cast<const C<T>*>(src);
-    for (int i = tid; i < L; i += nthr) dst[i] = s[i];
+__device__ __forceinline__ void load_tables(C<T>* dst, const void* src, const RadixPlan& p, int tid, int nthr) {
+    if (!p.rader) {
+        const C<T>* s = reinterpret_cast<const C<T>*>(src);
+        for (int i = tid; i < p.L; i += nthr) dst[i] = s[i];
+        return;
+    }
+    const int n = p.L - 1;
+    const int words = (3 * n * (int)sizeof(C<T>) + 8 * n) / 4;
+    const uint32_t* s = reinterpret_cast<const uint32_t*>(src);
+    uint32_t* d = reinterpret_cast<uint32_t*>(dst);
+    for (int i = tid; i < words; i += nthr) d[i] = s[i];
 }
 
 // ---------------------------------------------------------------- slab pass
@@ -38,17 +48,17 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) slab_kernel(S
     const int pitch = a.nx + a.pad;                 // row pitch (complex) in LDS
     const int rows = a.rows_per_tile;
     const int es = a.cplx ? 2 : 1;                  // element stride of the planes (interleaved complex: 2)
-    C<T>* twx = tile + rows * pitch;
-    C<T>* twt = twx + a.nx;
-    C<T>* fx = twt + a.m;                           // separable factors (scaled)
+    C<T>* twx = tile + rows * pitch;                // plan tables of x, then of theta
+    C<T>* twt = twx + tables_slots(a.px, (int)sizeof(C<T>));
+    C<T>* fx = twt + tables_slots(a.pt, (int)sizeof(C<T>));  // separable factors (scaled)
     C<T>* ft = fx + a.nx;
     const int tid = threadIdx.x, nthr = blockDim.x;
     // elements per thread staged through registers by tile loads and stores (one in
     // the kernels with odd stages, where staging measured slower)
     constexpr int STG = ODD ? 1 : SE2C_STAGE;
 
-    load_tw<T>(twx, a.twx, stage_tw_len(a.px), tid, nthr);
-    if (a.do_t) load_tw<T>(twt, a.twt, stage_tw_len(a.pt), tid, nthr);
+    load_tables<T>(twx, a.twx, a.px, tid, nthr);
+    if (a.do_t) load_tables<T>(twt, a.twt, a.pt, tid, nthr);
     if (a.mul) {
         const T sc = (T)a.scale;
         for (int i = tid; i < a.nx; i += nthr) {
@@ -208,12 +218,12 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) pencil_kernel
     C<T>* tile = reinterpret_cast<C<T>*>(smem_raw);
     const int L = a.p.L;
     const int pitch = a.W + a.pad;                  // LDS pitch between consecutive axis points
-    C<T>* tw = tile + L * pitch;
-    C<T>* f1 = tw + L;
+    C<T>* tw = tile + L * pitch;                    // plan tables
+    C<T>* f1 = tw + tables_slots(a.p, (int)sizeof(C<T>));
     const int tid = threadIdx.x, nthr = blockDim.x;
     constexpr int STG = ODD ? 1 : SE2C_STAGE;  // as in the slab pass
 
-    load_tw<T>(tw, a.tw, stage_tw_len(a.p), tid, nthr);
+    load_tables<T>(tw, a.tw, a.p, tid, nthr);
     if (a.mul == 1) {
         const T sc = (T)a.scale;
         for (int i = tid; i < L; i += nthr) {
@@ -438,13 +448,14 @@ hipError_t prepare_generic_kernels() {
 }
 
 size_t slab_lds_bytes(const SlabArgs& a, bool dbl) {
-    const size_t cb = dbl ? 16 : 8;
-    return cb * ((size_t)a.rows_per_tile * (a.nx + a.pad) + 2 * (size_t)a.nx + 2 * (size_t)a.m);
+    const int cb = dbl ? 16 : 8;
+    return (size_t)cb * ((size_t)a.rows_per_tile * (a.nx + a.pad) + tables_slots(a.px, cb) + tables_slots(a.pt, cb) +
+                         (size_t)a.nx + (size_t)a.m);
 }
 
 size_t pencil_lds_bytes(const PencilArgs& a, bool dbl) {
-    const size_t cb = dbl ? 16 : 8;
-    return cb * ((size_t)a.p.L * (a.W + a.pad) + 2 * (size_t)a.p.L);
+    const int cb = dbl ? 16 : 8;
+    return (size_t)cb * ((size_t)a.p.L * (a.W + a.pad) + tables_slots(a.p, cb) + (size_t)a.p.L);
 }
 
 hipError_t launch_slab(const SlabArgs& a, bool dbl, int nthr, int nblocks, hipStream_t s) {
