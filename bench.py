@@ -228,7 +228,7 @@ def cpu_baseline_padded(f_host, out_host, ks, L, N, budget_s):
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     return {"value": done / el, "unit": "conv/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{done} of {f_host.shape[0]} fields, FP64 route 1 with synthesis on the finer grid; "
-                      f"{el:.1f} s"}, errs
+                      f"{el:.1f} s; {host_cpu()}"}, errs
 
 
 def run_powers(steps, warmup, cpu_budget=None):
@@ -281,7 +281,8 @@ def run_powers(steps, warmup, cpu_budget=None):
         errs = [rel_l2(out_host[k].astype(np.float64), ref[k]) for k in range(q)]
         threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
         line["cpu_baseline"] = {"value": q / el, "unit": "conv/s", "cores": int(threads), "kind": "oracle",
-                                "sample": f"field 0, all {q} powers by the oracle's Alg. 7 (FP64); {el:.1f} s"}
+                                "sample": f"field 0, all {q} powers by the oracle's Alg. 7 (FP64); {el:.1f} s; "
+                                          f"{host_cpu()}"}
         line["rel_l2_vs_oracle"] = float(max(errs))
         line["rel_l2_tol"] = float(2e-6 * np.log2(n))
     return line
@@ -378,6 +379,18 @@ def traffic_for(kernel: str, workload: str, src_hash: str):
     return rec.get("bytes_per_launch")
 
 
+def host_cpu() -> str:
+    """The host CPU model (Linux /proc/cpuinfo), for the CPU baseline's record."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.lower().startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def cpu_baseline(res, budget_s: float):
     """The FP64 oracle (route 1, table precomputed) on the host cores, bounded sample."""
     from threadpoolctl import threadpool_info
@@ -409,7 +422,8 @@ def cpu_baseline(res, budget_s: float):
     return {"value": done / el, "unit": "conv/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{done} of {res['batch']} fields, FP64 naive separable DFT route with the "
                       f"chain table precomputed (table build excluded, as on the GPU); {el:.1f} s; "
-                      f"BLAS: {', '.join(sorted(set(i.get('internal_api', '?') for i in info))) or 'none'}"}, errs
+                      f"BLAS: {', '.join(sorted(set(i.get('internal_api', '?') for i in info))) or 'none'}; "
+                      f"{host_cpu()}"}, errs
 
 
 def main():
