@@ -73,8 +73,9 @@ typedef struct {
  *   out               receives the plan handle (owned by the caller, released with
  *                     se2conv_plan_destroy).
  * The plan allocates twiddle tables (generated in FP64 on the device, eq. (3DFT)
- * roots e^{-2 pi i j/L}) and a workspace of one real plane of the largest shape,
- * on the current HIP device.  Returns ERR_UNSUPPORTED_SIZE for a bad shape,
+ * roots e^{-2 pi i j/L}), the tables of Rader's algorithm for every prime length
+ * above 7 (computed in FP64 on the host and copied), and a workspace of one real
+ * plane of the largest shape, on the current HIP device.  Returns ERR_UNSUPPORTED_SIZE for a bad shape,
  * ERR_DEVICE when no device is usable.
  */
 se2conv_status se2conv_plan(const se2conv_shape* shapes, int32_t n_shapes, se2conv_dtype dtype, uint32_t flags,
