@@ -305,13 +305,14 @@ typedef struct {
  * se2conv_chain: run n_probs problems (different shapes and kernel chains allowed),
  * ordered after earlier work on the stream; the call's work is complete when the stream
  * reaches the point after it.  Problems whose tables are all SEPARABLE are grouped by
- * shape into one launch per pass per shape class; the classes are independent and run
- * concurrently on the plan's auxiliary streams (forked from and joined back into
- * `stream`; sequentially on `stream` with SE2CONV_TIMING).  Problems with FULL tables
- * follow one at a time.  A problem's output must therefore not overlap another
- * problem's input or output.  With SE2CONV_GRAPH the submission (forks included) is
- * captured into a HIP graph on first use and replayed on later calls with the same
- * problem list (same pointers and sizes).  SE2CONV_ADJOINT applies to every problem.
+ * shape into one launch per pass per shape class; the classes run one after another on
+ * `stream` (the environment variable SE2CONV_CHAIN_STREAMS = 2..4 forks them over that
+ * many of the plan's auxiliary streams, joined back into `stream`; not with
+ * SE2CONV_TIMING).  Problems with FULL tables follow one at a time.  A problem's output
+ * must not overlap another problem's input or output.  With SE2CONV_GRAPH the
+ * submission (forks included) is captured into a HIP graph on first use and replayed
+ * on later calls with the same problem list (same pointers and sizes).
+ * SE2CONV_ADJOINT applies to every problem.
  */
 se2conv_status se2conv_chain(se2conv_plan_t plan, const se2conv_problem* probs, int32_t n_probs, uint32_t flags,
                              hipStream_t stream);

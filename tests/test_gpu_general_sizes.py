@@ -112,8 +112,12 @@ def test_general_size_full_table_apply(nx, ny, m, batch, dt):
     assert worst <= _tol(dt, nx * ny * m)
 
 
-def test_general_sizes_in_one_chain_submission():
-    case("heterogeneous submission: odd, non-2^a3^b and 2^a3^b shapes, eager and graph")
+@pytest.mark.parametrize("streams", ["1", "4"])
+def test_general_sizes_in_one_chain_submission(streams, monkeypatch):
+    # the shape classes in sequence on the caller's stream (default), or forked over four
+    # auxiliary streams (SE2CONV_CHAIN_STREAMS, read at each call)
+    monkeypatch.setenv("SE2CONV_CHAIN_STREAMS", streams)
+    case(f"heterogeneous submission on {streams} stream(s): odd, non-2^a3^b and 2^a3^b shapes, eager and graph")
     shapes = [(31, 31, 31), (32, 32, 16), (40, 50, 35), (45, 35, 49)]
     plan = se2.Plan(shapes, dtype="f32")
     items, host = [], []
