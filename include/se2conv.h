@@ -143,6 +143,22 @@ typedef struct {
 se2conv_status se2conv_coeffs(se2conv_plan_t plan, int32_t shape_idx, const se2conv_kernel_desc* kernels,
                               int32_t n_kernels, void* d_table, size_t* table_bytes, hipStream_t stream);
 
+/*
+ * se2conv_coeffs_sum: coefficients of a weighted sum of kernels, rho = sum_k w_k rho_k
+ * (the paper's outlook of Sec. 1: a general kernel approximated by a sum of radial
+ * ones), rho^[k; L] = sum_k w_k rho_k^[k; L] by linearity of eq. (FkLv).  Each term is one
+ * kernel descriptor (validated as in se2conv_coeffs, normalised by its own flags); the
+ * terms' tables are formed in FP64 on the device, accumulated in FP64 and rounded once.
+ * The result is a FULL table (M*Ny*Nx complex of the plan dtype).
+ *   kernels[n_terms], weights[n_terms]  host arrays, 1 <= n_terms <= 64, finite weights.
+ *   d_table, table_bytes                as in se2conv_coeffs (NULL d_table: size query).
+ * Uses the plan's FP64 scratch and an FP64 accumulator of M*Ny*Nx complex values
+ * (allocated on first use).
+ */
+se2conv_status se2conv_coeffs_sum(se2conv_plan_t plan, int32_t shape_idx, const se2conv_kernel_desc* kernels,
+                                  const double* weights, int32_t n_terms, void* d_table, size_t* table_bytes,
+                                  hipStream_t stream);
+
 /* Kind (SE2CONV_TABLE_*) and byte size of a table produced by this plan. */
 se2conv_status se2conv_table_info(se2conv_plan_t plan, const void* d_table, int32_t* kind, int32_t* shape_idx,
                                   size_t* bytes);

@@ -139,6 +139,19 @@ class Plan:
         t = Table(self, shape_idx, buf, kind.value)
         return t
 
+    def coeffs_sum(self, shape_idx: int, terms, stream=None) -> Table:
+        """FULL table of a weighted sum of kernels: terms = [(weight, kernel), ...]
+        (se2conv_coeffs_sum)."""
+        descs = (L.KernelDesc * len(terms))(*[_desc(k) for _, k in terms])
+        w = (ctypes.c_double * len(terms))(*[float(a) for a, _ in terms])
+        nbytes = ctypes.c_size_t(0)
+        L.check(self._lib.se2conv_coeffs_sum(self.handle, shape_idx, descs, w, len(terms), None,
+                                             ctypes.byref(nbytes), None))
+        buf = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        L.check(self._lib.se2conv_coeffs_sum(self.handle, shape_idx, descs, w, len(terms), buf.data_ptr(),
+                                             ctypes.byref(nbytes), _stream_handle(stream)))
+        return Table(self, shape_idx, buf, L.TABLE_FULL)
+
     def apply(self, shape_idx: int, f: torch.Tensor, table: Table, out: torch.Tensor | None = None,
               adjoint: bool = False, stream=None, timing: bool = False) -> torch.Tensor:
         _require(f, self.tdtype)

@@ -190,6 +190,8 @@ struct se2conv_plan_s {
     void* ws4 = nullptr;               // four more planes (kernel gradient), allocated on first use
     void* scratch64 = nullptr;         // FP64 scratch for se2conv_coeffs
     size_t scratch64_bytes = 0;
+    void* sum64 = nullptr;             // FP64 accumulator of se2conv_coeffs_sum, allocated on first use
+    size_t sum64_bytes = 0;
     void* pad_ws = nullptr;            // sampling-grid product spectra of se2conv_apply_padded
     size_t pad_ws_bytes = 0;
     // hat basis of the last radial-profile geometry used by se2conv_profile_grad
@@ -1269,6 +1271,7 @@ se2conv_status se2conv_plan_destroy(se2conv_plan_t p) {
         if (p->ws2) (void)hipFree(p->ws2);
         if (p->ws4) (void)hipFree(p->ws4);
         if (p->scratch64) (void)hipFree(p->scratch64);
+        if (p->sum64) (void)hipFree(p->sum64);
         if (p->basis) (void)hipFree(p->basis);
         if (p->basis_hat) (void)hipFree(p->basis_hat);
         if (p->pad_ws) (void)hipFree(p->pad_ws);
@@ -1278,14 +1281,10 @@ se2conv_status se2conv_plan_destroy(se2conv_plan_t p) {
     return SE2CONV_OK;  // keeps the thread's last error (plan creation cleans up through here)
 }
 
-se2conv_status se2conv_coeffs(se2conv_plan_t p, int32_t shape_idx, const se2conv_kernel_desc* kernels,
-                              int32_t n_kernels, void* d_table, size_t* table_bytes, hipStream_t stream) {
-    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
-    if (shape_idx < 0 || shape_idx >= (int)p->shapes.size())
-        return fail(SE2CONV_ERR_INVALID_ARG, "shape_idx %d out of range", shape_idx);
-    if (!kernels || n_kernels < 1 || n_kernels > 64) return fail(SE2CONV_ERR_INVALID_ARG, "need 1..64 kernels");
-    if (!table_bytes) return fail(SE2CONV_ERR_INVALID_ARG, "table_bytes is null");
-    const se2conv_shape& s = p->shapes[shape_idx];
+namespace {
+
+// Checks a kernel list; *sep tells whether every kernel is GAUSS_VM (a SEPARABLE chain).
+se2conv_status validate_kernels(const se2conv_kernel_desc* kernels, int32_t n_kernels, bool* sep_out) {
     bool sep = true;
     for (int j = 0; j < n_kernels; ++j) {
         const se2conv_kernel_desc& k = kernels[j];
@@ -1325,6 +1324,93 @@ se2conv_status se2conv_coeffs(se2conv_plan_t p, int32_t shape_idx, const se2conv
                 return fail(SE2CONV_ERR_INVALID_ARG, "kernel %d: unknown kind %d", j, k.kind);
         }
     }
+    *sep_out = sep;
+    return SE2CONV_OK;
+}
+
+// FP64 scratch of se2conv_coeffs for one shape: separable accumulator | full accumulator
+// n | spectrum re n | im n | samples n (re .. samples also serve as the basis-DFT
+// temporary of a radial profile).
+struct CoeffScratch {
+    double2* sepacc;
+    double2* full;
+    double* re;
+    double* im;
+    double* samp;
+};
+
+se2conv_status coeff_scratch(se2conv_plan_s* p, const se2conv_shape& s, const se2conv_kernel_desc* kernels,
+                             int32_t n_kernels, bool sep, CoeffScratch* cs) {
+    const long long n = (long long)s.nx * s.ny * s.m;
+    const int nsep = s.nx + s.ny + s.m;
+    size_t need = sizeof(double2) * nsep + (sep ? 0 : (sizeof(double2) * n + 3 * sizeof(double) * n));
+    for (int j = 0; j < n_kernels && !sep; ++j)
+        if (kernels[j].kind == SE2CONV_K_RADIAL_PROFILE && profile_by_basis(s, kernels[j].n_knots))
+            need = std::max(need, sizeof(double2) * (nsep + (size_t)n) +
+                                      sizeof(double2) * (size_t)((long long)kernels[j].n_knots * s.ny * (s.nx / 2 + 1)));
+    se2conv_status r = ensure_scratch64(p, need);
+    if (r != SE2CONV_OK) return r;
+    cs->sepacc = reinterpret_cast<double2*>(p->scratch64);
+    cs->full = cs->sepacc + nsep;
+    cs->re = reinterpret_cast<double*>(cs->full + n);
+    cs->im = cs->re + n;
+    cs->samp = cs->im + n;
+    return SE2CONV_OK;
+}
+
+// Multiplies the FULL FP64 accumulator by the coefficients of one kernel (first: sets it).
+se2conv_status fold_kernel_full(se2conv_plan_s* p, int32_t shape_idx, const se2conv_kernel_desc& k,
+                                const CoeffScratch& cs, bool first, hipStream_t stream) {
+    const se2conv_shape& s = p->shapes[shape_idx];
+    const long long n = (long long)s.nx * s.ny * s.m;
+    const int norm = (int)(k.flags & 3u);
+    if (k.kind == SE2CONV_K_GAUSS_VM) {
+        SepKernelParams kp;
+        kp.sigma = k.sigma;
+        kp.kappa = k.kappa;
+        kp.theta0 = k.theta0;
+        kp.ive0 = std::cyl_bessel_i(0.0, k.kappa) * std::exp(-k.kappa);
+        kp.norm = norm;
+        HIPCHK(launch_sep_factor(kp, s.nx, s.ny, s.m, cs.sepacc, 1, stream));
+        HIPCHK(launch_full_fold_sep(cs.sepacc, cs.full, n, s.nx, s.ny, first, stream));
+    } else if (k.kind == SE2CONV_K_RADIAL_PROFILE && profile_by_basis(s, k.n_knots)) {
+        // P^ = sum_q prof^[q] H_q^ with the basis spectrum cached per geometry
+        auto* tmp = reinterpret_cast<double2*>(cs.re);
+        se2conv_status rb = ensure_basis_hat(p, shape_idx, k.n_knots, k.r_max, tmp, stream);
+        if (rb != SE2CONV_OK) return rb;
+        HIPCHK(launch_profile_fold(reinterpret_cast<const double*>(k.data),
+                                   reinterpret_cast<const double2*>(tw_of(p, s.m, true)), p->basis_hat, k.n_knots,
+                                   s.nx, s.ny, s.m, norm == 0 ? 0 : 1, tmp, cs.full, first, stream));
+    } else {
+        const double* src = reinterpret_cast<const double*>(k.data);
+        if (k.kind == SE2CONV_K_RADIAL_PROFILE) {
+            HIPCHK(launch_profile_samples(src, k.n_knots, k.r_max, s.nx, s.ny, s.m, cs.samp, stream));
+            src = cs.samp;
+        } else if (k.kind == SE2CONV_K_EXP_GAUSS) {
+            HIPCHK(launch_exp_gauss_samples(k.sigma, s.nx, s.ny, s.m, cs.samp, stream));
+            src = cs.samp;
+        }
+        // FP64 forward 3-D DFT of the real samples into (re, im) planes
+        HIPCHK(xt_transform(p, s, true, 0, src, nullptr, cs.re, cs.im, nullptr, nullptr, n, n, 1, stream));
+        HIPCHK(y_pass(p, s, true, cs.re, cs.im, nullptr, n, 1, 1, 0, 0, nullptr, false, 1.0, stream));
+        HIPCHK(launch_full_fold(cs.re, cs.im, cs.full, n, s.nx, s.ny, norm == 0 ? 0 : 1, first, stream));
+    }
+    return SE2CONV_OK;
+}
+
+}  // namespace
+
+se2conv_status se2conv_coeffs(se2conv_plan_t p, int32_t shape_idx, const se2conv_kernel_desc* kernels,
+                              int32_t n_kernels, void* d_table, size_t* table_bytes, hipStream_t stream) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (shape_idx < 0 || shape_idx >= (int)p->shapes.size())
+        return fail(SE2CONV_ERR_INVALID_ARG, "shape_idx %d out of range", shape_idx);
+    if (!kernels || n_kernels < 1 || n_kernels > 64) return fail(SE2CONV_ERR_INVALID_ARG, "need 1..64 kernels");
+    if (!table_bytes) return fail(SE2CONV_ERR_INVALID_ARG, "table_bytes is null");
+    const se2conv_shape& s = p->shapes[shape_idx];
+    bool sep = true;
+    se2conv_status vr = validate_kernels(kernels, n_kernels, &sep);
+    if (vr != SE2CONV_OK) return vr;
     const long long n = (long long)s.nx * s.ny * s.m;
     const size_t cb = cplx_bytes(p);
     const size_t bytes = sep ? cb * (size_t)(s.nx + s.ny + s.m) : cb * (size_t)n;
@@ -1338,67 +1424,83 @@ se2conv_status se2conv_coeffs(se2conv_plan_t p, int32_t shape_idx, const se2conv
 
     std::lock_guard<std::mutex> g(p->mu);
     const int nsep = s.nx + s.ny + s.m;
-    // FP64 scratch: sep accumulator | (full) accumulator n | spectrum re n | im n | samples n
-    // (re .. samples also serve as the basis-DFT temporary of a radial profile)
-    size_t need = sizeof(double2) * nsep + (sep ? 0 : (sizeof(double2) * n + 3 * sizeof(double) * n));
-    for (int j = 0; j < n_kernels && !sep; ++j)
-        if (kernels[j].kind == SE2CONV_K_RADIAL_PROFILE && profile_by_basis(s, kernels[j].n_knots))
-            need = std::max(need, sizeof(double2) * (nsep + (size_t)n) +
-                                      sizeof(double2) * (size_t)((long long)kernels[j].n_knots * s.ny * (s.nx / 2 + 1)));
-    se2conv_status r = ensure_scratch64(p, need);
+    CoeffScratch cs;
+    se2conv_status r = coeff_scratch(p, s, kernels, n_kernels, sep, &cs);
     if (r != SE2CONV_OK) return r;
-    auto* sepacc = reinterpret_cast<double2*>(p->scratch64);
-    auto* full = reinterpret_cast<double2*>(sepacc + nsep);
-    auto* re = reinterpret_cast<double*>(full + n);
-    double* im = re + n;
-    double* samp = im + n;
-    bool first_full = true;
     for (int j = 0; j < n_kernels; ++j) {
         const se2conv_kernel_desc& k = kernels[j];
-        const int norm = (int)(k.flags & 3u);
-        if (k.kind == SE2CONV_K_GAUSS_VM) {
+        if (sep) {
             SepKernelParams kp;
             kp.sigma = k.sigma;
             kp.kappa = k.kappa;
             kp.theta0 = k.theta0;
             kp.ive0 = std::cyl_bessel_i(0.0, k.kappa) * std::exp(-k.kappa);
-            kp.norm = norm;
-            if (sep) {
-                HIPCHK(launch_sep_factor(kp, s.nx, s.ny, s.m, sepacc, j == 0, stream));
-            } else {
-                HIPCHK(launch_sep_factor(kp, s.nx, s.ny, s.m, sepacc, 1, stream));
-                HIPCHK(launch_full_fold_sep(sepacc, full, n, s.nx, s.ny, first_full, stream));
-                first_full = false;
-            }
-        } else if (k.kind == SE2CONV_K_RADIAL_PROFILE && profile_by_basis(s, k.n_knots)) {
-            // P^ = sum_q prof^[q] H_q^ with the basis spectrum cached per geometry
-            auto* tmp = reinterpret_cast<double2*>(re);
-            se2conv_status rb = ensure_basis_hat(p, shape_idx, k.n_knots, k.r_max, tmp, stream);
-            if (rb != SE2CONV_OK) return rb;
-            HIPCHK(launch_profile_fold(reinterpret_cast<const double*>(k.data),
-                                       reinterpret_cast<const double2*>(tw_of(p, s.m, true)), p->basis_hat, k.n_knots,
-                                       s.nx, s.ny, s.m, norm == 0 ? 0 : 1, tmp, full, first_full, stream));
-            first_full = false;
+            kp.norm = (int)(k.flags & 3u);
+            HIPCHK(launch_sep_factor(kp, s.nx, s.ny, s.m, cs.sepacc, j == 0, stream));
         } else {
-            const double* src = reinterpret_cast<const double*>(k.data);
-            if (k.kind == SE2CONV_K_RADIAL_PROFILE) {
-                HIPCHK(launch_profile_samples(src, k.n_knots, k.r_max, s.nx, s.ny, s.m, samp, stream));
-                src = samp;
-            } else if (k.kind == SE2CONV_K_EXP_GAUSS) {
-                HIPCHK(launch_exp_gauss_samples(k.sigma, s.nx, s.ny, s.m, samp, stream));
-                src = samp;
-            }
-            // FP64 forward 3-D DFT of the real samples into (re, im) planes
-            HIPCHK(xt_transform(p, s, true, 0, src, nullptr, re, im, nullptr, nullptr, n, n, 1, stream));
-            HIPCHK(y_pass(p, s, true, re, im, nullptr, n, 1, 1, 0, 0, nullptr, false, 1.0, stream));
-            HIPCHK(launch_full_fold(re, im, full, n, s.nx, s.ny, norm == 0 ? 0 : 1, first_full, stream));
-            first_full = false;
+            r = fold_kernel_full(p, shape_idx, k, cs, j == 0, stream);
+            if (r != SE2CONV_OK) return r;
         }
     }
-    HIPCHK(launch_round(sep ? sepacc : full, d_table, sep ? nsep : n, dbl(p) ? 1 : 0, stream));
+    HIPCHK(launch_round(sep ? cs.sepacc : cs.full, d_table, sep ? nsep : n, dbl(p) ? 1 : 0, stream));
     TableRec rec;
     rec.shape_idx = shape_idx;
     rec.kind = sep ? SE2CONV_TABLE_SEPARABLE : SE2CONV_TABLE_FULL;
+    rec.bytes = bytes;
+    p->tables[reinterpret_cast<uintptr_t>(d_table)] = rec;
+    return ok();
+}
+
+se2conv_status se2conv_coeffs_sum(se2conv_plan_t p, int32_t shape_idx, const se2conv_kernel_desc* kernels,
+                                  const double* weights, int32_t n_terms, void* d_table, size_t* table_bytes,
+                                  hipStream_t stream) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (shape_idx < 0 || shape_idx >= (int)p->shapes.size())
+        return fail(SE2CONV_ERR_INVALID_ARG, "shape_idx %d out of range", shape_idx);
+    if (!kernels || !weights || n_terms < 1 || n_terms > 64)
+        return fail(SE2CONV_ERR_INVALID_ARG, "need 1..64 kernels and their weights");
+    if (!table_bytes) return fail(SE2CONV_ERR_INVALID_ARG, "table_bytes is null");
+    for (int j = 0; j < n_terms; ++j)
+        if (!std::isfinite(weights[j])) return fail(SE2CONV_ERR_INVALID_ARG, "weight %d is not finite", j);
+    const se2conv_shape& s = p->shapes[shape_idx];
+    bool sep = true;
+    se2conv_status vr = validate_kernels(kernels, n_terms, &sep);
+    if (vr != SE2CONV_OK) return vr;
+    const long long n = (long long)s.nx * s.ny * s.m;
+    const size_t bytes = cplx_bytes(p) * (size_t)n;  // a sum of kernels is FULL
+    if (!d_table) {
+        *table_bytes = bytes;
+        return ok();
+    }
+    if (*table_bytes < bytes) return fail(SE2CONV_ERR_INVALID_ARG, "table buffer too small (%zu < %zu)", *table_bytes, bytes);
+    if (!aligned16(d_table)) return fail(SE2CONV_ERR_INVALID_ARG, "table must be 16-byte aligned");
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+
+    std::lock_guard<std::mutex> g(p->mu);
+    CoeffScratch cs;
+    se2conv_status r = coeff_scratch(p, s, kernels, n_terms, false, &cs);
+    if (r != SE2CONV_OK) return r;
+    if (p->sum64_bytes < sizeof(double2) * (size_t)n) {
+        if (p->sum64) {
+            hipError_t e = hipFree(p->sum64);
+            p->sum64 = nullptr;
+            p->sum64_bytes = 0;
+            if (e != hipSuccess) return fail(SE2CONV_ERR_DEVICE, "hipFree: %s", hipGetErrorString(e));
+        }
+        if (hipMalloc(&p->sum64, sizeof(double2) * (size_t)n) != hipSuccess)
+            return fail(SE2CONV_ERR_OUT_OF_MEMORY, "FP64 sum accumulator (%zu bytes)", sizeof(double2) * (size_t)n);
+        p->sum64_bytes = sizeof(double2) * (size_t)n;
+    }
+    auto* sum = reinterpret_cast<double2*>(p->sum64);
+    for (int j = 0; j < n_terms; ++j) {
+        r = fold_kernel_full(p, shape_idx, kernels[j], cs, true, stream);
+        if (r != SE2CONV_OK) return r;
+        HIPCHK(launch_axpy64(cs.full, sum, n, weights[j], j == 0 ? 1 : 0, stream));
+    }
+    HIPCHK(launch_round(sum, d_table, n, dbl(p) ? 1 : 0, stream));
+    TableRec rec;
+    rec.shape_idx = shape_idx;
+    rec.kind = SE2CONV_TABLE_FULL;
     rec.bytes = bytes;
     p->tables[reinterpret_cast<uintptr_t>(d_table)] = rec;
     return ok();

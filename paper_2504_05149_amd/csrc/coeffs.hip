@@ -221,6 +221,26 @@ hipError_t launch_round(const double2* src, void* dst, long long n, int dbl, hip
     return hipGetLastError();
 }
 
+// One weighted term of a sum of kernel tables, accumulated in FP64.
+__global__ void axpy64_kernel(const double2* __restrict__ x, double2* __restrict__ y, long long n, double w,
+                              int first) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const double2 v = x[i];
+        double2 acc = first ? make_double2(0.0, 0.0) : y[i];
+        acc.x = fma(w, v.x, acc.x);
+        acc.y = fma(w, v.y, acc.y);
+        y[i] = acc;
+    }
+}
+
+hipError_t launch_axpy64(const double2* x, double2* y, long long n, double w, int first, hipStream_t s) {
+    const int nthr = 256;
+    const long long want = (n + nthr - 1) / nthr;
+    const int nb = (int)(want < 16384 ? want : 16384);
+    hipLaunchKernelGGL(axpy64_kernel, dim3(nb), dim3(nthr), 0, s, x, y, n, w, first);
+    return hipGetLastError();
+}
+
 // Radial-profile kernel samples (FP64):
 // P[l][j][i] = sum_images sum_q prof[q][l] * hat_q(|x_ij + image|),
 // hat_q(r) = max(0, 1 - |r/h - q|), h = r_max/(n_knots-1).

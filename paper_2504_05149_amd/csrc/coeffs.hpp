@@ -20,6 +20,8 @@ hipError_t launch_full_fold(const double* re, const double* im, double2* acc, lo
 hipError_t launch_full_fold_sep(const double2* sep, double2* acc, long long n, int nx, int ny, int first,
                                 hipStream_t s);
 hipError_t launch_round(const double2* src, void* dst, long long n, int dbl, hipStream_t s);
+// y = (first ? 0 : y) + w x over n complex FP64 values (sums of kernel tables)
+hipError_t launch_axpy64(const double2* x, double2* y, long long n, double w, int first, hipStream_t s);
 // Radial-profile tables from the 2-D DFT of the hat basis (cached per geometry):
 // hr[q][k2][k1], 0 <= k1 <= nx/2, 0 <= k2 <= ny/2, the real spectrum of basis[q] (tmp:
 // nq ny (nx/2+1) double2 of scratch), then the FFC table folded into acc for profiles with

@@ -189,3 +189,29 @@ def test_fused_entry_points_validate_on_host():
     assert lib.se2conv_backward(h, 0, 1 << 20, 4096, 1 << 30, 0, 1 << 24, 1 << 28, None) == L.ERR_INVALID_ARG
     assert lib.se2conv_backward(h, 0, 1 << 20, 4096, 1 << 30, 1, 1 << 24, 1 << 28, None) == L.ERR_DEVICE
     assert b"host-only" in lib.se2conv_last_error()
+
+
+def test_coeffs_sum_validation_on_host_only_plan():
+    # a weighted sum of kernels is a FULL table; weights must be finite, 1..64 terms,
+    # every term validated as in se2conv_coeffs; device work is refused on a host-only plan
+    p = se2.Plan([(32, 48, 16)], dtype="f64", host_only=True)
+    lib = L.load()
+    descs = (L.KernelDesc * 2)()
+    for dd, (s, k) in zip(descs, [(0.05, 4.0), (0.03, 9.0)]):
+        dd.kind, dd.sigma, dd.kappa = L.K_GAUSS_VM, s, k
+    w = (ctypes.c_double * 2)(0.7, 0.3)
+    n = ctypes.c_size_t(0)
+    assert lib.se2conv_coeffs_sum(p.handle, 0, descs, w, 2, None, ctypes.byref(n), None) == L.OK
+    assert n.value == 16 * 32 * 48 * 16
+    assert lib.se2conv_coeffs_sum(p.handle, 0, descs, None, 2, None, ctypes.byref(n), None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_coeffs_sum(p.handle, 0, descs, w, 0, None, ctypes.byref(n), None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_coeffs_sum(p.handle, 0, descs, w, 65, None, ctypes.byref(n), None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_coeffs_sum(p.handle, 1, descs, w, 2, None, ctypes.byref(n), None) == L.ERR_INVALID_ARG
+    w[1] = float("inf")
+    assert lib.se2conv_coeffs_sum(p.handle, 0, descs, w, 2, None, ctypes.byref(n), None) == L.ERR_INVALID_ARG
+    w[1] = 0.3
+    descs[1].sigma = -1.0
+    assert lib.se2conv_coeffs_sum(p.handle, 0, descs, w, 2, None, ctypes.byref(n), None) == L.ERR_INVALID_ARG
+    descs[1].sigma = 0.03
+    n = ctypes.c_size_t(16 * 32 * 48 * 16)
+    assert lib.se2conv_coeffs_sum(p.handle, 0, descs, w, 2, 1 << 16, ctypes.byref(n), None) == L.ERR_DEVICE
