@@ -189,6 +189,7 @@ RADER_CASES = [
     (509, 16, 8, "f32"),   # largest prime length, along x: inner 508 = 4*127
     (16, 509, 8, "f64"),   # along y
     (40, 34, 37, "f32"),   # even x and y: pair passes with a prime theta axis
+    (8, 16, 509, "f32"),   # largest prime length along theta (x rows, then theta pencils)
 ]
 
 
