@@ -472,8 +472,9 @@ def main():
                          "byte counters and gives the achievable streaming bandwidth)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus above 1 is not supported "
-                                   "(the batch shards across GPUs with no communication, see DESIGN.md)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus above 1 is not supported "
+                                   "(the fields of a batch are independent: a batch would be split across "
+                                   "GPUs with no communication)"}))
         sys.exit(2)
 
     if args.copy_calibration:
