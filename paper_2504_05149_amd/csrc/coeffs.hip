@@ -403,12 +403,15 @@ __global__ void profile_theta_dft_kernel(const double* prof, const double2* twm,
 
 // acc[k3][k2][k1] (*)= (-1)^{k1+k2} / norm * sum_q prof^[k3][q] hr[q][|k2|][|k1|], norm = P^[0]
 // (the sample sum, discrete mass) or n.  One lane per quadrant frequency (|k1|, |k2|); the
-// four waves of a block split k3 (wave g: k3 = g + 4 i), each lane keeping 16 complex sums
-// while hr[q] streams through; the wave-uniform prof^ values come through scalar loads.
-// Each result goes to the up to four mirrored frequencies.  Requires m, n_knots <= 64.
+// four waves of a block and the four blocks along y split k3 (wave g of block y:
+// k3 = g + 4 (4 y + i), i < 4), each lane keeping 4 complex sums while hr[q] streams through
+// (four blocks per 64 frequencies: a quarter of the sums per lane measured faster than one
+// block holding 16); the wave-uniform prof^ values come through scalar loads.  Each result
+// goes to the up to four mirrored frequencies.  Requires m, n_knots <= 64.
 __global__ void __launch_bounds__(256) profile_fold_kernel(const double* hr, const double2* pht, int nq, int nx,
                                                            int ny, int m, int norm_mode, double2* acc, int first) {
-    constexpr int KI = kProfileFoldMaxM / 4;
+    constexpr int KT = kProfileFoldMaxM / 4;  // k3 values per wave over the whole grid
+    constexpr int KI = KT / 4;                // of them in this block (blockIdx.y picks the quarter)
     const int hx = nx / 2 + 1, hy = ny / 2 + 1;
     const long long quad = (long long)hx * hy;
     const long long nxy = (long long)nx * ny;
@@ -418,13 +421,13 @@ __global__ void __launch_bounds__(256) profile_fold_kernel(const double* hr, con
     double2 sum[KI];
 #pragma unroll
     for (int i = 0; i < KI; ++i) sum[i] = make_double2(0.0, 0.0);
-    const double2* pw = pht + (long long)g * nq * KI;
+    const double2* pw = pht + (long long)g * nq * KT + blockIdx.y * KI;
     double h = hr[kq];
     for (int q = 0; q < nq; ++q) {
         const double hn = hr[(long long)(q + 1 < nq ? q + 1 : q) * quad + kq];
 #pragma unroll
         for (int i = 0; i < KI; ++i) {
-            const double2 a = pw[q * KI + i];
+            const double2 a = pw[q * KT + i];
             sum[i].x += a.x * h;
             sum[i].y += a.y * h;
         }
@@ -434,7 +437,7 @@ __global__ void __launch_bounds__(256) profile_fold_kernel(const double* hr, con
     double inv = 1.0 / (double)(nxy * m);
     if (norm_mode == 0) {
         double s0 = 0.0;  // P^[0,0,0]: the sum of the (real) samples
-        for (int q = 0; q < nq; ++q) s0 += pht[(long long)q * KI].x * hr[(long long)q * quad];
+        for (int q = 0; q < nq; ++q) s0 += pht[(long long)q * KT].x * hr[(long long)q * quad];
         inv = 1.0 / s0;
     }
     const int a1 = (int)(kq % hx), a2 = (int)(kq / hx);
@@ -445,7 +448,7 @@ __global__ void __launch_bounds__(256) profile_fold_kernel(const double* hr, con
     const bool use[4] = {true, m1 != a1, m2 != a2, m1 != a1 && m2 != a2};
 #pragma unroll
     for (int i = 0; i < KI; ++i) {
-        const int k3 = g + 4 * i;
+        const int k3 = g + 4 * (blockIdx.y * KI + i);
         if (k3 < m) {
             const double2 v = make_double2(sum[i].x * sg, sum[i].y * sg);
 #pragma unroll
@@ -479,7 +482,7 @@ hipError_t launch_profile_fold(const double* prof, const double2* twm, const dou
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long quad = (long long)(nx / 2 + 1) * (ny / 2 + 1);
-    hipLaunchKernelGGL(profile_fold_kernel, dim3((unsigned)((quad + 63) / 64)), dim3(256), 0, s, hr, pht, nq, nx, ny,
+    hipLaunchKernelGGL(profile_fold_kernel, dim3((unsigned)((quad + 63) / 64), 4), dim3(256), 0, s, hr, pht, nq, nx, ny,
                        m, norm_mode, acc, first);
     return hipGetLastError();
 }
