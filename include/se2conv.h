@@ -216,11 +216,14 @@ se2conv_status se2conv_profile_grad(se2conv_plan_t plan, int32_t shape_idx, cons
  * se2conv_apply: out[b] = Re S_K[f[b], chain] for b = 0 .. batch-1.
  *   d_f, d_out  device arrays [batch][M][Ny][Nx] of the plan dtype, 16-byte aligned;
  *               d_out == d_f (in place) is allowed, other overlaps are not.
- *   d_table     a table produced by se2conv_coeffs for this plan and shape.
+ *   d_table     a table produced for this plan and shape (se2conv_coeffs,
+ *               se2conv_coeffs_sum or se2conv_field_coeffs).
  * Separable tables run two passes (x-theta slabs, then y pencils) when a slab fits
  * in LDS, three otherwise; full tables run forward / product / inverse passes on
  * pairs of fields.  Uses the plan workspace when batch is odd and the table is
- * FULL: calls on one plan must not overlap on different streams.
+ * FULL: calls on one plan must not overlap on different streams.  The environment
+ * variable SE2CONV_SEP_CHUNK = k splits the separable two-pass schedule into launches
+ * of k fields (tuning only; the default is the whole batch).
  */
 se2conv_status se2conv_apply(se2conv_plan_t plan, int32_t shape_idx, const void* d_f, const void* d_table,
                              void* d_out, int32_t batch, uint32_t flags, hipStream_t stream);
@@ -233,7 +236,7 @@ se2conv_status se2conv_apply(se2conv_plan_t plan, int32_t shape_idx, const void*
  *   d_f, d_out  device arrays [batch][M][Ny][Nx] of complex values (re, im adjacent;
  *               complex64 for F32 plans, complex128 for F64), 16-byte aligned;
  *               d_out == d_f (in place) is allowed, other overlaps are not.
- *   d_table     a table produced by se2conv_coeffs for this plan and shape.
+ *   d_table     a table produced for this plan and shape (as for se2conv_apply).
  * Runs on the generic passes (every size).  Flags: SE2CONV_ADJOINT, SE2CONV_TIMING.
  */
 se2conv_status se2conv_apply_complex(se2conv_plan_t plan, int32_t shape_idx, const void* d_f, const void* d_table,
