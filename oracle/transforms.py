@@ -48,6 +48,14 @@ def _dft_axis(a: np.ndarray, axis: int, sign: int) -> np.ndarray:
     return np.fft.ifft(a, axis=axis) * float(length)
 
 
+def axis_routes(shape) -> dict:
+    """Which evaluation _dft_axis takes along each axis of a [theta][y][x] array."""
+    size = int(np.prod(shape))
+    m, ny, nx = shape[-3:]
+    return {name: ("dense" if size * length < DENSE_LIMIT else "fft")
+            for name, length in (("x", nx), ("y", ny), ("theta", m))}
+
+
 def dft3(a: np.ndarray) -> np.ndarray:
     """Un-normalised 3-D DFT (3DFT) of an array laid out [theta][y][x]."""
     a = np.asarray(a, dtype=np.complex128)

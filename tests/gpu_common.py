@@ -1,7 +1,7 @@
 """Helpers shared by the GPU parity tests (oracle side and HIP side kept apart)."""
 import numpy as np
 
-from inputs import rel_l2  # noqa: F401
+from inputs import rel_l2
 from oracle import conv as oc
 from oracle import kernels as ok
 
@@ -12,6 +12,21 @@ def tol32(n_points: int) -> float:
 
 
 TOL64 = 1e-12
+
+
+def parity_err(a, b) -> float:
+    """Parity error of a HIP result a against a reference b.
+
+    The larger of ||a - b||_2 / ||b||_2 and max|a - b| / (10 max|b|).  A test that
+    asserts parity_err <= tol therefore bounds the relative L2 error by tol and every
+    element by 10 tol max|b|, so a local fault (one wrong tile of a few hundred points)
+    cannot hide inside the norm.
+    """
+    a = np.asarray(a)
+    b = np.asarray(b)
+    scale = float(np.max(np.abs(b))) if b.size else 0.0
+    elem = float(np.max(np.abs(a - b))) / (10.0 * scale) if scale > 0 else float(np.max(np.abs(a - b), initial=0.0))
+    return max(rel_l2(a, b), elem)
 
 
 def case(msg: str) -> None:

@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import paper_2504_05149_amd as se2
-from gpu_common import TOL64, case, rel_l2, tol32
+from gpu_common import TOL64, case, parity_err, tol32
 from inputs import chain_kernel_params, sample_fields
 from oracle import conv as oc
 from oracle import kernels as ok
@@ -39,7 +39,7 @@ def test_complex_fields_separable_chain(shape, batch, lc, dt, adjoint):
     out = out.cpu().numpy().astype(np.complex128)
     ps = [ok.gauss_vm(*shape, *c) for c in chain]
     tol = tol32(shape[0] * shape[1] * shape[2]) if dt == "f32" else TOL64
-    worst = max(rel_l2(out[b], oc.conv_chain(f[b], ps, return_complex=True, adjoint=adjoint))
+    worst = max(parity_err(out[b], oc.conv_chain(f[b], ps, return_complex=True, adjoint=adjoint))
                 for b in range(batch))
     print(f"rel-L2 {worst:.2e} (tol {tol:.1e})", flush=True)
     assert worst <= tol
@@ -62,9 +62,9 @@ def test_complex_fields_full_table_in_place_and_real_consistency():
     p = ok.radial_profile(*shape, prof, 0.4)
     tol = tol32(shape[0] * shape[1] * shape[2])
     for b in range(batch):
-        err = rel_l2(out[b], oc.conv_chain(f[b], [p], return_complex=True))
+        err = parity_err(out[b], oc.conv_chain(f[b], [p], return_complex=True))
         assert err <= tol, (b, err)
     both = (re + 1j * im).cpu().numpy().astype(np.complex128)
-    d = rel_l2(out, both)
+    d = parity_err(out, both)
     print(f"complex path against two real applies: rel-L2 {d:.2e}", flush=True)
     assert d <= tol

@@ -9,7 +9,7 @@ import pytest
 import torch
 
 import paper_2504_05149_amd as se2
-from gpu_common import TOL64, case, oracle_table_gauss, rel_l2, tol32
+from gpu_common import TOL64, case, oracle_table_gauss, parity_err, tol32
 from inputs import chain_kernel_params, sample_field, sample_fields, uneven_problem_list
 from oracle import adjoint as OA
 from oracle import conv as oc
@@ -58,7 +58,7 @@ def test_c2_uneven_batch_graph():
         if i % 8 == 0:  # every 8th problem against the oracle
             n, m = p["n"], p["m"]
             ref_t = oracle_table_gauss(n, n, m, [(k.sigma, k.kappa, k.theta0) for k in p["chain"]])
-            err = rel_l2(out, oc.conv_with_coeffs(f, ref_t))
+            err = parity_err(out, oc.conv_with_coeffs(f, ref_t))
             assert err <= tol32(n * n * m), (i, n, m, err)
 
 
@@ -93,7 +93,7 @@ def test_c3_512x512x128_subsampled(dt, c3_data):
     del fd
     out0 = out[0].cpu().numpy().astype(np.float64)
     sub = out0[np.ix_(pts[2], pts[1], pts[0])]
-    err = rel_l2(sub, ref)
+    err = parity_err(sub, ref)
     tol = tol32(nx * ny * m) if dt == "f32" else TOL64
     print(f"  subsampled rel-L2 {err:.2e} (tol {tol:.1e})", flush=True)
     assert err <= tol
@@ -137,11 +137,11 @@ def test_c4_gradients_256x256x64_batch8():
     gP = np.stack([OA.grad_kernel_samples(f[b], g[b]) for b in range(f.shape[0])])
     ref_gprof = OA.grad_profile(gP, nk, rmax)
     e_loss = abs(loss.item() - ref_loss) / ref_loss
-    e_gp = rel_l2(pd.grad.cpu().numpy(), ref_gprof)
+    e_gp = parity_err(pd.grad.cpu().numpy(), ref_gprof)
     print(f"  loss {e_loss:.2e} grad_prof {e_gp:.2e}", flush=True)
     assert e_loss <= 1e-4 and e_gp <= 1e-4
     gf = fd.grad.cpu().numpy()
     for b in (0, 5):
-        e_gf = rel_l2(gf[b], oc.conv_with_coeffs(g[b], np.conj(table)))
+        e_gf = parity_err(gf[b], oc.conv_with_coeffs(g[b], np.conj(table)))
         print(f"  grad_f field {b}: {e_gf:.2e}", flush=True)
         assert e_gf <= 1e-4

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import paper_2504_05149_amd as se2
-from gpu_common import TOL64, case, oracle_table_gauss, rel_l2, tol32
+from gpu_common import TOL64, case, oracle_table_gauss, parity_err, tol32
 from inputs import chain_kernel_params, sample_fields
 from oracle import conv as oc
 from oracle import kernels as ok
@@ -44,8 +44,8 @@ def test_smallest_and_longest_axes(shape, batch, dt):
     ref_sep = oracle_table_gauss(*shape, chain)
     ref_full = ffc(ok.radial_profile(*shape, prof, 0.45))
     for b in range(batch):
-        e1 = rel_l2(o_sep[b], oc.conv_with_coeffs(f[b], ref_sep))
-        e2 = rel_l2(o_full[b], oc.conv_with_coeffs(f[b], ref_full))
+        e1 = parity_err(o_sep[b], oc.conv_with_coeffs(f[b], ref_sep))
+        e2 = parity_err(o_full[b], oc.conv_with_coeffs(f[b], ref_full))
         print(f"  field {b}: separable {e1:.2e}, full {e2:.2e}", flush=True)
         assert e1 <= _tol(dt, shape) and e2 <= _tol(dt, shape)
 
@@ -71,7 +71,7 @@ def test_longest_runtime_chain_mixed_tables(shape, dt):
     for p in profs:
         c = ffc(ok.radial_profile(*shape, p, 0.3))
         ref_t = ref_t * c / c[0, 0, 0]
-    worst = max(rel_l2(out[b], oc.conv_with_coeffs(f[b], ref_t)) for b in range(3))
+    worst = max(parity_err(out[b], oc.conv_with_coeffs(f[b], ref_t)) for b in range(3))
     print(f"rel-L2 {worst:.2e}", flush=True)
     assert worst <= _tol(dt, shape)
 
@@ -91,7 +91,7 @@ def test_long_odd_batch(shape, kind):
     f = sample_fields(17, batch, 4, *shape)
     out = plan.apply(0, _dev(f, torch.float32), table).cpu().numpy().astype(np.float64)
     for b in (0, 7, 15, 16):
-        err = rel_l2(out[b], oc.conv_with_coeffs(f[b], ref_t))
+        err = parity_err(out[b], oc.conv_with_coeffs(f[b], ref_t))
         print(f"  field {b}: rel-L2 {err:.2e}", flush=True)
         assert err <= tol32(shape[0] * shape[1] * shape[2])
 

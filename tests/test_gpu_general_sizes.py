@@ -10,7 +10,7 @@ import pytest
 import torch
 
 import paper_2504_05149_amd as se2
-from gpu_common import TOL64, case, oracle_table_gauss, rel_l2, tol32
+from gpu_common import TOL64, case, oracle_table_gauss, parity_err, tol32
 from inputs import chain_kernel_params, sample_fields
 from oracle import adjoint as OA
 from oracle import conv as oc
@@ -62,7 +62,7 @@ def test_general_size_separable_chain(nx, ny, m, batch, lc, dt):
     ref_t = oracle_table_gauss(nx, ny, m, chain)
     worst = 0.0
     for b in range(batch):
-        worst = max(worst, rel_l2(out[b], oc.conv_with_coeffs(f[b], ref_t)))
+        worst = max(worst, parity_err(out[b], oc.conv_with_coeffs(f[b], ref_t)))
     print(f"rel-L2 {worst:.2e} (tol {_tol(dt, nx * ny * m):.1e})", flush=True)
     assert worst <= _tol(dt, nx * ny * m)
 
@@ -106,8 +106,8 @@ def test_general_size_full_table_apply(nx, ny, m, batch, dt):
     p = ok.radial_profile(nx, ny, m, prof, 0.4)  # no normalisation (the descriptor's default)
     worst = 0.0
     for b in range(batch):
-        worst = max(worst, rel_l2(out[b].cpu().numpy().astype(np.float64), oc.conv_chain(f[b], [p])))
-        worst = max(worst, rel_l2(adj[b].cpu().numpy().astype(np.float64), oc.conv_chain(f[b], [p], adjoint=True)))
+        worst = max(worst, parity_err(out[b].cpu().numpy().astype(np.float64), oc.conv_chain(f[b], [p])))
+        worst = max(worst, parity_err(adj[b].cpu().numpy().astype(np.float64), oc.conv_chain(f[b], [p], adjoint=True)))
     print(f"rel-L2 {worst:.2e}", flush=True)
     assert worst <= _tol(dt, nx * ny * m)
 
@@ -145,7 +145,7 @@ def test_general_sizes_in_one_chain_submission(streams, monkeypatch):
     for (nx, ny, m), (f, chain), e in zip(shapes, host, eager):
         ref_t = oracle_table_gauss(nx, ny, m, chain)
         out = e.cpu().numpy().astype(np.float64)
-        err = max(rel_l2(out[b], oc.conv_with_coeffs(f[b], ref_t)) for b in range(f.shape[0]))
+        err = max(parity_err(out[b], oc.conv_with_coeffs(f[b], ref_t)) for b in range(f.shape[0]))
         print(f"{nx}x{ny}x{m}: rel-L2 {err:.2e}", flush=True)
         assert err <= tol32(nx * ny * m)
 
@@ -166,7 +166,7 @@ def test_general_size_powers_and_gradients(dt):
     for q in range(3):
         for b in range(3):
             ref = oc.conv_chain(f[b], [p] * (q + 1))
-            err = rel_l2(pw[q][b].cpu().numpy().astype(np.float64), ref)
+            err = parity_err(pw[q][b].cpu().numpy().astype(np.float64), ref)
             assert err <= tol, (q, b, err)
     for b in range(3):
         gpu = ft[b].complex_view().cpu().numpy()
@@ -177,7 +177,7 @@ def test_general_size_powers_and_gradients(dt):
     g = np.random.default_rng([2504_05149, 79]).standard_normal((3, m, ny, nx))
     kg = plan.kernel_grad(0, _dev(g, _tdt(dt)), ft).cpu().numpy().astype(np.float64)
     ref = sum(OA.grad_kernel_samples(f[b], g[b]) for b in range(3))
-    err = rel_l2(kg, ref)
+    err = parity_err(kg, ref)
     print(f"kernel gradient: rel-L2 {err:.2e}", flush=True)
     assert err <= tol
 
@@ -211,7 +211,7 @@ def test_prime_lengths_field_coeffs_and_apply(nx, ny, m, dt):
         gpu = ft[b].complex_view().cpu().numpy()
         ref = ffc(f[b])
         err = np.linalg.norm(gpu - ref) / np.linalg.norm(ref)
-        e1 = rel_l2(out[b].cpu().numpy().astype(np.float64), oc.conv_with_coeffs(f[b], ref_t))
-        e2 = rel_l2(adj[b].cpu().numpy().astype(np.float64), oc.conv_with_coeffs(f[b], np.conj(ref_t)))
+        e1 = parity_err(out[b].cpu().numpy().astype(np.float64), oc.conv_with_coeffs(f[b], ref_t))
+        e2 = parity_err(adj[b].cpu().numpy().astype(np.float64), oc.conv_with_coeffs(f[b], np.conj(ref_t)))
         print(f"field {b}: coefficients {err:.2e}, apply {e1:.2e}, adjoint {e2:.2e} (tol {tol:.1e})", flush=True)
         assert max(err, e1, e2) <= tol

@@ -4,7 +4,7 @@ import pytest
 import torch
 
 import paper_2504_05149_amd as se2
-from gpu_common import TOL64, case, rel_l2, tol32
+from gpu_common import TOL64, case, parity_err, tol32
 from inputs import sample_fields
 from oracle import adjoint as OA
 from oracle import conv as oc
@@ -85,8 +85,8 @@ def test_autograd_matches_oracle_gradients(dt, checkpoint, rng):
     ref_loss, ref_gf, ref_gprof = _oracle_grads(f, prof, target, nk, rmax)
     tol = TOL64 * 10 if dt == "f64" else 1e-4
     e_loss = abs(loss.item() - ref_loss) / abs(ref_loss)
-    e_gf = rel_l2(fd.grad.cpu().numpy(), ref_gf)
-    e_gp = rel_l2(pd.grad.cpu().numpy(), ref_gprof)
+    e_gf = parity_err(fd.grad.cpu().numpy(), ref_gf)
+    e_gp = parity_err(pd.grad.cpu().numpy(), ref_gprof)
     print(f"  loss {e_loss:.2e} grad_f {e_gf:.2e} grad_prof {e_gp:.2e}", flush=True)
     assert e_loss <= tol and e_gf <= tol and e_gp <= tol
 
@@ -152,7 +152,7 @@ def test_kernel_grad_accumulates_over_batch(dt, batch, rng):
     tabs = plan.field_coeffs(0, _dev(f, tdt))
     out = plan.kernel_grad(0, _dev(g, tdt), tabs).cpu().numpy().astype(np.float64)
     ref = sum(OA.grad_kernel_samples(f[b], g[b]) for b in range(batch))
-    err = rel_l2(out, ref)
+    err = parity_err(out, ref)
     print(f"  rel-L2 {err:.2e}", flush=True)
     assert err <= (TOL64 if dt == "f64" else tol32(nx * ny * m))
 
@@ -209,11 +209,11 @@ def test_fused_backward_matches_oracle(nx, ny, m, batch, rng):
     ref_t = ffc(ok.radial_profile(nx, ny, m, prof, 0.4))
     tol = tol32(nx * ny * m)
     for b in range(batch):
-        e = rel_l2(gf[b], oc.conv_with_coeffs(g[b], np.conj(ref_t)))
+        e = parity_err(gf[b], oc.conv_with_coeffs(g[b], np.conj(ref_t)))
         print(f"  grad_f field {b}: {e:.2e}", flush=True)
         assert e <= tol
     ref_p = sum(OA.grad_kernel_samples(f[b], g[b]) for b in range(batch))
-    e = rel_l2(gp, ref_p)
+    e = parity_err(gp, ref_p)
     print(f"  grad_P (batch sum): {e:.2e}", flush=True)
     assert e <= tol
 
@@ -233,8 +233,8 @@ def test_fused_autograd_matches_oracle(checkpoint, rng):
     loss.backward()
     ref_loss, ref_gf, ref_gprof = _oracle_grads(f, prof, target, nk, rmax)
     e_loss = abs(loss.item() - ref_loss) / abs(ref_loss)
-    e_gf = rel_l2(fd.grad.cpu().numpy(), ref_gf)
-    e_gp = rel_l2(pd.grad.cpu().numpy(), ref_gprof)
+    e_gf = parity_err(fd.grad.cpu().numpy(), ref_gf)
+    e_gp = parity_err(pd.grad.cpu().numpy(), ref_gprof)
     print(f"  loss {e_loss:.2e} grad_f {e_gf:.2e} grad_prof {e_gp:.2e}", flush=True)
     assert e_loss <= 1e-4 and e_gf <= 1e-4 and e_gp <= 1e-4
 

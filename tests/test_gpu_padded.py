@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import paper_2504_05149_amd as se2
-from gpu_common import TOL64, case, rel_l2, tol32
+from gpu_common import TOL64, case, parity_err, tol32
 from inputs import chain_kernel_params, sample_fields
 from oracle import conv as oc
 from oracle import kernels as ok
@@ -46,7 +46,7 @@ def test_padded_evaluation_matches_oracle(L, N, batch, lc, dt):
     assert out.shape == (batch, N[2], N[1], N[0])
     ps = [ok.gauss_vm(*L, k.sigma, k.kappa, 0.4 * j) for j, k in enumerate(ks)]
     tol = tol32(N[0] * N[1] * N[2]) if dt == "f32" else TOL64
-    worst = max(rel_l2(out[b], oc.conv_on_grid(f[b], ps, N)) for b in range(batch))
+    worst = max(parity_err(out[b], oc.conv_on_grid(f[b], ps, N)) for b in range(batch))
     print(f"rel-L2 {worst:.2e} (tol {tol:.1e})", flush=True)
     assert worst <= tol
 
@@ -67,10 +67,10 @@ def test_padded_full_table_adjoint_and_identity_grid():
     p = ok.radial_profile(*L, prof, 0.4)
     tol = tol32(N[0] * N[1] * N[2])
     for b in range(3):
-        err = rel_l2(out[b].cpu().numpy().astype(np.float64), oc.conv_on_grid(f[b], [p], N, adjoint=True))
+        err = parity_err(out[b].cpu().numpy().astype(np.float64), oc.conv_on_grid(f[b], [p], N, adjoint=True))
         print(f"field {b}: adjoint rel-L2 {err:.2e}", flush=True)
         assert err <= tol
-    d = rel_l2(same.cpu().numpy().astype(np.float64), ref_apply.cpu().numpy().astype(np.float64))
+    d = parity_err(same.cpu().numpy().astype(np.float64), ref_apply.cpu().numpy().astype(np.float64))
     print(f"N = L against se2conv_apply: rel-L2 {d:.2e}", flush=True)
     assert d <= tol32(L[0] * L[1] * L[2])
 
@@ -95,9 +95,9 @@ def test_padded_register_kernels(L, N, kind, adjoint):
     out = plan.apply_padded(0, fd, table, 1, adjoint=adjoint).cpu().numpy().astype(np.float64)
     tol = tol32(N[0] * N[1] * N[2])
     for b in range(4):
-        err = rel_l2(out[b], oc.conv_on_grid(f[b], ps, N, adjoint=adjoint))
+        err = parity_err(out[b], oc.conv_on_grid(f[b], ps, N, adjoint=adjoint))
         print(f"  field {b}: rel-L2 {err:.2e}", flush=True)
         assert err <= tol
     if L == N:
         same = plan.apply(0, fd, table, adjoint=adjoint).cpu().numpy().astype(np.float64)
-        assert rel_l2(out, same) <= tol
+        assert parity_err(out, same) <= tol

@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import paper_2504_05149_amd as se2
-from gpu_common import TOL64, case, oracle_conv, oracle_table_gauss, rel_l2, tol32
+from gpu_common import TOL64, case, oracle_conv, oracle_table_gauss, parity_err, tol32
 from inputs import bump_field, chain_kernel_params, sample_field, sample_fields
 from oracle import conv as oc
 from oracle import kernels as ok
@@ -44,9 +44,9 @@ def test_c0_fp64_against_both_oracle_routes():
     out = _run(plan, 0, f[None], table, torch.float64)[0]
     p = ok.gauss_vm(n, n, m, 0.05, 4.0, 0.0, normalize="continuous")
     ref1 = oc.conv_chain(f, [p])
-    e1 = rel_l2(out, ref1)
+    e1 = parity_err(out, ref1)
     ref2 = oq.quadrature_conv(f, ok.gauss_vm_function(0.05, 4.0, 0.0))
-    e2 = rel_l2(out, ref2)
+    e2 = parity_err(out, ref2)
     print(f"C0 rel-L2: vs DFT route {e1:.2e}, vs quadrature {e2:.2e}", flush=True)
     assert e1 <= TOL64 and e2 <= TOL64
 
@@ -118,7 +118,7 @@ def test_separable_path_parity(nx, ny, m, batch, lc, dt):
     ref_t = oracle_table_gauss(nx, ny, m, chain)
     tol = tol32(nx * ny * m) if dt == "f32" else TOL64
     for b in range(batch):
-        err = rel_l2(out[b], oracle_conv(f[b], ref_t))
+        err = parity_err(out[b], oracle_conv(f[b], ref_t))
         print(f"  field {b}: rel-L2 {err:.2e} (tol {tol:.1e})", flush=True)
         assert err <= tol
 
@@ -135,17 +135,16 @@ def test_c1_128x128x64_batch16_chain8():
     out = _run(plan, 0, f, table, torch.float32)
     ref_t = oracle_table_gauss(nx, ny, m, chain)
     tol = tol32(nx * ny * m)
-    for b in (0, 7, 15):
-        err = rel_l2(out[b], oracle_conv(f[b], ref_t))
-        print(f"  field {b}: rel-L2 {err:.2e}", flush=True)
-        assert err <= tol
-    # every field: mass is multiplicative (discrete normalisation => mean preserved)
     for b in range(16):
+        err = parity_err(out[b], oracle_conv(f[b], ref_t))
+        print(f"  field {b}: err {err:.2e}", flush=True)
+        assert err <= tol
+        # mass is multiplicative (discrete normalisation => mean preserved)
         assert abs(out[b].mean() - f[b].mean()) <= 1e-5 * abs(f[b].mean())
 
 
-def test_headline_256x256x64_batch16_chain8_sampled():
-    case("headline 256x256x64 fp32 batch 16, chain of 8: 2 fields vs oracle, mass on all")
+def test_headline_256x256x64_batch16_chain8_all_fields():
+    case("headline 256x256x64 fp32 batch 16, chain of 8: every field vs oracle, mass on all")
     nx = ny = 256
     m = 64
     ks = chain_kernel_params(2, 8)
@@ -156,11 +155,10 @@ def test_headline_256x256x64_batch16_chain8_sampled():
     out = _run(plan, 0, f, table, torch.float32)
     ref_t = oracle_table_gauss(nx, ny, m, chain)
     tol = tol32(nx * ny * m)
-    for b in (0, 13):
-        err = rel_l2(out[b], oracle_conv(f[b], ref_t))
-        print(f"  field {b}: rel-L2 {err:.2e} (tol {tol:.1e})", flush=True)
-        assert err <= tol
     for b in range(16):
+        err = parity_err(out[b], oracle_conv(f[b], ref_t))
+        print(f"  field {b}: err {err:.2e} (tol {tol:.1e})", flush=True)
+        assert err <= tol
         assert abs(out[b].mean() - f[b].mean()) <= 1e-5 * abs(f[b].mean())
 
 
@@ -194,8 +192,8 @@ def test_register_kernels_match_generic_and_oracle(nx, ny, m):
         ref = oracle_conv(f[b], ref_t)
         ref_adj = oc.conv_with_coeffs(f[b], np.conj(ref_t))
         for generic in (False, True):
-            e1 = rel_l2(outs[generic][0][b], ref)
-            e2 = rel_l2(outs[generic][1][b], ref_adj)
+            e1 = parity_err(outs[generic][0][b], ref)
+            e2 = parity_err(outs[generic][1][b], ref_adj)
             print(f"  field {b} generic={generic}: {e1:.2e} adj {e2:.2e}", flush=True)
             assert e1 <= tol and e2 <= tol
 
@@ -216,7 +214,7 @@ def test_full_path_parity(dt, batch, rng):
     ref_t = ffc(p_prof) * ffc(ok.gauss_vm(nx, ny, m, 0.05, 3.0, 0.7))
     tol = tol32(nx * ny * m) if dt == "f32" else TOL64
     for b in range(batch):
-        err = rel_l2(out[b], oracle_conv(f[b], ref_t))
+        err = parity_err(out[b], oracle_conv(f[b], ref_t))
         print(f"  field {b}: rel-L2 {err:.2e}", flush=True)
         assert err <= tol
 
@@ -245,8 +243,8 @@ def test_full_path_register_kernels(nx, ny, m, batch, rng):
         ref = oracle_conv(f[b], ref_t)
         ref_adj = oc.conv_with_coeffs(f[b], np.conj(ref_t))
         for generic in (False, True):
-            e1 = rel_l2(outs[generic][0][b], ref)
-            e2 = rel_l2(outs[generic][1][b], ref_adj)
+            e1 = parity_err(outs[generic][0][b], ref)
+            e2 = parity_err(outs[generic][1][b], ref_adj)
             print(f"  field {b} generic={generic}: {e1:.2e} adj {e2:.2e}", flush=True)
             assert e1 <= tol and e2 <= tol
 
@@ -261,7 +259,7 @@ def test_full_path_large_three_pass_fp64():
     out = _run(plan, 0, f, table, torch.float64)
     ref_t = ffc(p)
     for b in range(3):
-        err = rel_l2(out[b], oracle_conv(f[b], ref_t))
+        err = parity_err(out[b], oracle_conv(f[b], ref_t))
         print(f"  field {b}: rel-L2 {err:.2e}", flush=True)
         assert err <= TOL64
 
@@ -283,7 +281,7 @@ def test_adjoint_matches_oracle(kind):
     out = plan.apply(0, _dev(g, torch.float64), table, adjoint=True).cpu().numpy()
     for b in range(2):
         ref = oc.conv_chain(g[b], [p], adjoint=True)
-        assert rel_l2(out[b], ref) <= TOL64
+        assert parity_err(out[b], ref) <= TOL64
 
 
 def test_in_place_operation():
@@ -298,7 +296,7 @@ def test_in_place_operation():
     out = fd.cpu().numpy().astype(np.float64)
     ref_t = oracle_table_gauss(nx, ny, m, [(0.05, 4.0, 0.0)])
     for b in range(2):
-        assert rel_l2(out[b], oracle_conv(f[b], ref_t)) <= tol32(nx * ny * m)
+        assert parity_err(out[b], oracle_conv(f[b], ref_t)) <= tol32(nx * ny * m)
 
 
 # --------------------------------------------- chain API, graphs, many problems
@@ -326,7 +324,7 @@ def test_chain_runtime_product_and_graph_replay():
         nx, ny, m = shapes[i]
         o = out.cpu().numpy().astype(np.float64)
         for b in range(2):
-            assert rel_l2(o[b], ref[b]) <= tol32(nx * ny * m)
+            assert parity_err(o[b], ref[b]) <= tol32(nx * ny * m)
     for rep in range(4):
         for _, _, out, _ in probs:
             out.zero_()
@@ -403,14 +401,14 @@ def test_all_powers_match_oracle_alg7(nx, ny, m, batch, q, dt, kind, rng):
     for b in range(batch):
         refs = oc.alg7_all_powers(f[b], p, q)
         for k in range(q):
-            err = rel_l2(out[k, b], refs[k])
+            err = parity_err(out[k, b], refs[k])
             print(f"  field {b} power {k + 1}: {err:.2e}", flush=True)
             assert err <= tol
         # the adjoint power p is the correlation with rho p times (conjugated coefficients)
         ref_adj = f[b]
         for k in range(q):
             ref_adj = oc.conv_chain(ref_adj, [p], adjoint=True)
-            assert rel_l2(adj[k, b], ref_adj) <= tol, (b, k)
+            assert parity_err(adj[k, b], ref_adj) <= tol, (b, k)
 
 
 # ------------------------------------------------------------ field sampling
@@ -443,4 +441,4 @@ def test_autotuned_schedules_stay_correct(tmp_path, monkeypatch):
         out = plan.apply(i, _dev(f, torch.float32), table).cpu().numpy().astype(np.float64)
         ref_t = oracle_table_gauss(nx, ny, m, chain)
         for b in range(2):
-            assert rel_l2(out[b], oracle_conv(f[b], ref_t)) <= tol32(nx * ny * m)
+            assert parity_err(out[b], oracle_conv(f[b], ref_t)) <= tol32(nx * ny * m)
