@@ -164,6 +164,21 @@ se2conv_status se2conv_table_info(se2conv_plan_t plan, const void* d_table, int3
                                   size_t* bytes);
 
 /*
+ * se2conv_table_release: the plan forgets a table it recorded (se2conv_coeffs,
+ * se2conv_coeffs_sum, se2conv_field_coeffs), together with every cached se2conv_chain
+ * submission that names it (waiting for that submission's last enqueued use).  Call it
+ * before the table's buffer is freed, so that a later buffer at the same address is not
+ * taken for this table and the plan's record of tables stays bounded in a training loop.
+ * Later calls that pass the address fail with ERR_INVALID_ARG until a table is produced
+ * there again.  Host-side bookkeeping: nothing is enqueued.  ERR_INVALID_ARG when the
+ * address is not a recorded table of this plan.
+ */
+se2conv_status se2conv_table_release(se2conv_plan_t plan, const void* d_table);
+
+/* Diagnostics: number of tables the plan records and of cached se2conv_chain submissions. */
+se2conv_status se2conv_plan_counts(se2conv_plan_t plan, int64_t* n_tables, int64_t* n_submissions);
+
+/*
  * se2conv_field_coeffs: finite Fourier coefficient tables f^[k; L] = (-1)^{k1+k2} F^[k] / n
  * (eq. (FkLv)) of real fields, in the plan dtype, one FULL table per field.  They serve as
  * the checkpointed forward spectra of a field: the gradient of a loss with respect to the
@@ -330,8 +345,13 @@ typedef struct {
  * SE2CONV_TIMING).  Problems with FULL tables follow one at a time.  A problem's output
  * must not overlap another problem's input or output.  With SE2CONV_GRAPH the
  * submission (forks included) is captured into a HIP graph on first use and replayed
- * on later calls with the same problem list (same pointers and sizes).
- * SE2CONV_ADJOINT applies to every problem.
+ * on later calls with the same problem list (same pointers, sizes and table kinds).
+ * SE2CONV_ADJOINT applies to every problem.  The plan caches up to 64 problem lists (their
+ * device item arrays and graphs); the oldest is dropped first, after its last enqueued
+ * use has finished on whatever stream it went to.  A list enqueued on a stream that the
+ * caller is capturing stays cached until the plan is destroyed or one of its tables is
+ * released, since the caller's graph refers to its item array.  Calls may come from
+ * several threads and streams.
  */
 se2conv_status se2conv_chain(se2conv_plan_t plan, const se2conv_problem* probs, int32_t n_probs, uint32_t flags,
                              hipStream_t stream);

@@ -7,6 +7,7 @@ from __future__ import annotations
 
 import ctypes
 import dataclasses
+import weakref
 
 import torch
 
@@ -74,14 +75,25 @@ def _require(t: torch.Tensor, dtype) -> None:
         raise ValueError(f"expected a contiguous {dtype} device tensor")
 
 
+def _release_table(plan: "Plan", ptr: int) -> None:
+    # the buffer is about to be freed: the plan forgets the address, so a later
+    # allocation at the same address is not taken for this table
+    if plan.handle:
+        plan._lib.se2conv_table_release(plan.handle, ptr)
+
+
 class Table:
-    """A coefficient table produced by Plan.coeffs (device buffer + its plan)."""
+    """A coefficient table produced by Plan.coeffs (device buffer + its plan).
+
+    When the Table is garbage-collected its record in the plan is released
+    (se2conv_table_release) before the buffer goes back to the allocator."""
 
     def __init__(self, plan: "Plan", shape_idx: int, buf: torch.Tensor, kind: int):
         self.plan = plan
         self.shape_idx = shape_idx
         self.buf = buf
         self.kind = kind
+        weakref.finalize(self, _release_table, plan, buf.data_ptr())
 
     @property
     def ptr(self) -> int:
@@ -118,6 +130,12 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def counts(self) -> tuple[int, int]:
+        """(tables recorded by the plan, cached chain submissions)."""
+        nt, ns = ctypes.c_int64(0), ctypes.c_int64(0)
+        L.check(self._lib.se2conv_plan_counts(self.handle, ctypes.byref(nt), ctypes.byref(ns)))
+        return int(nt.value), int(ns.value)
 
     def table_bytes(self, shape_idx: int, kernels) -> int:
         descs = (L.KernelDesc * len(kernels))(*[_desc(k) for k in kernels])

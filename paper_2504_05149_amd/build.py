@@ -1,13 +1,17 @@
-"""Build libse2conv.so (HIP, gfx950) in-tree with hipcc."""
+"""Build libse2conv.so (HIP, gfx950) in-tree with hipcc.
+
+Every source is compiled to an object file on its own (in parallel), then linked."""
 from __future__ import annotations
 
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
+OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libse2conv.so")
 SOURCES = ["api.cpp", "passes.hip", "coeffs.hip", "sep_fast.hip", "full_fast.hip", "grad.hip", "sample.hip", "pad.hip"]
 ARCH = os.environ.get("SE2CONV_ARCH", "gfx950")
@@ -20,26 +24,44 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def command(out: str = LIB) -> list[str]:
+def flags() -> list[str]:
     return [
-        hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+        f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
         # keep the compiler from emitting packed-FP32 VALU instructions
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-I", os.path.join(ROOT, "include"),
-        "-x", "hip", *[os.path.join(CSRC, s) for s in SOURCES],
-        "-o", out,
     ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = command(tmp)
+def compile_command(src: str, obj: str) -> list[str]:
+    return [hipcc(), *flags(), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+
+
+def link_command(objs: list[str], out: str) -> list[str]:
+    return [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out]
+
+
+def _run(cmd: list[str], verbose: bool) -> subprocess.CompletedProcess:
     if verbose:
         print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
+    return subprocess.run(cmd, capture_output=True, text=True)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJ, exist_ok=True)
+    objs = [os.path.join(OBJ, os.path.splitext(s)[0] + ".o") for s in SOURCES]
+    jobs = max(1, min(len(SOURCES), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        results = list(ex.map(lambda so: _run(compile_command(*so), verbose), zip(SOURCES, objs)))
+    for src, res in zip(SOURCES, results):
+        if res.returncode != 0:
+            sys.stderr.write(res.stdout + res.stderr)
+            raise RuntimeError(f"hipcc failed compiling {src}")
+    tmp = LIB + ".tmp"
+    res = _run(link_command(objs, tmp), verbose)
     if res.returncode != 0:
         sys.stderr.write(res.stdout + res.stderr)
-        raise RuntimeError("hipcc failed building libse2conv.so")
+        raise RuntimeError("hipcc failed linking libse2conv.so")
     os.replace(tmp, LIB)
     return LIB
 

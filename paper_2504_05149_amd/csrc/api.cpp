@@ -8,7 +8,9 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <list>
 #include <map>
+#include <memory>
 #include <set>
 #include <mutex>
 #include <string>
@@ -163,13 +165,34 @@ struct TableRec {
 
 // A problem list seen by se2conv_chain: its device item arrays (one group of
 // fields per shape with separable chains) and, with SE2CONV_GRAPH, its graph.
+// Records are shared: a call keeps its own reference while it enqueues work, so
+// an eviction by another thread cannot free a record in use.  The device resources
+// are released by the destructor, after the last enqueued use has finished.
 struct SubmissionRec {
     std::vector<uint64_t> key;
+    std::vector<uintptr_t> tabs;                   // every table address the list names
     void* d_items = nullptr;                       // all groups' SepItem arrays
     std::vector<std::pair<int, int>> groups;       // (shape_idx, first item) per group
     std::vector<int> group_counts;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // recorded after every enqueue of the record's work (eager or graph launch) on the
+    // stream it went to; waited on before the record's device resources are freed
+    hipEvent_t done = nullptr;
+    bool used = false;       // done has been recorded at least once
+    // enqueued on a stream under someone else's capture: the captured graph refers to
+    // d_items for as long as that graph lives, so the record is never evicted
+    bool pinned = false;
+    SubmissionRec() = default;
+    SubmissionRec(const SubmissionRec&) = delete;
+    SubmissionRec& operator=(const SubmissionRec&) = delete;
+    ~SubmissionRec() {
+        if (done && used) (void)hipEventSynchronize(done);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (d_items) (void)hipFree(d_items);
+        if (done) (void)hipEventDestroy(done);
+    }
 };
 
 }  // namespace
@@ -206,7 +229,7 @@ struct se2conv_plan_s {
     int bh_shape = -1, bh_knots = 0;
     double bh_rmax = 0.0;
     std::unordered_map<uintptr_t, TableRec> tables;
-    std::vector<SubmissionRec> subs;
+    std::list<std::shared_ptr<SubmissionRec>> subs;  // se2conv_chain's cache, oldest first
     // concurrent shape classes in se2conv_chain: auxiliary streams (default priority)
     // and the fork / join events around them, created on first use
     std::vector<hipStream_t> aux;
@@ -226,6 +249,26 @@ namespace {
 bool dbl(const se2conv_plan_s* p) { return p->dtype == SE2CONV_F64; }
 size_t real_bytes(const se2conv_plan_s* p) { return dbl(p) ? 8 : 4; }
 size_t cplx_bytes(const se2conv_plan_s* p) { return dbl(p) ? 16 : 8; }
+
+// Drops the cached chain submissions whose problem list names a table address: the
+// address is being registered again (possibly as a table of the other kind) or
+// released, so the cached grouping of that list may no longer hold.  A record still
+// in use by another call stays alive through that call's reference.  Caller holds p->mu.
+void purge_subs_naming(se2conv_plan_s* p, uintptr_t addr) {
+    for (auto it = p->subs.begin(); it != p->subs.end();) {
+        const std::vector<uintptr_t>& t = (*it)->tabs;
+        if (std::find(t.begin(), t.end(), addr) != t.end())
+            it = p->subs.erase(it);
+        else
+            ++it;
+    }
+}
+
+// Records a table produced by the plan (caller holds p->mu).
+void register_table(se2conv_plan_s* p, const void* addr, const TableRec& rec) {
+    purge_subs_naming(p, reinterpret_cast<uintptr_t>(addr));
+    p->tables[reinterpret_cast<uintptr_t>(addr)] = rec;
+}
 
 const void* tw_of(se2conv_plan_s* p, int L, bool use64) { return use64 ? p->tw64.at(L) : p->tw32.at(L); }
 
@@ -1253,11 +1296,7 @@ se2conv_status se2conv_plan_destroy(se2conv_plan_t p) {
         (void)hipGetDevice(&cur);
         if (p->device >= 0) (void)hipSetDevice(p->device);
         (void)hipDeviceSynchronize();
-        for (auto& g : p->subs) {
-            if (g.exec) (void)hipGraphExecDestroy(g.exec);
-            if (g.graph) (void)hipGraphDestroy(g.graph);
-            if (g.d_items) (void)hipFree(g.d_items);
-        }
+        p->subs.clear();
         for (auto ev : p->ev_pool) (void)hipEventDestroy(ev);
         for (auto st : p->aux) (void)hipStreamDestroy(st);
         for (auto ev : p->ev_join) (void)hipEventDestroy(ev);
@@ -1447,7 +1486,7 @@ se2conv_status se2conv_coeffs(se2conv_plan_t p, int32_t shape_idx, const se2conv
     rec.shape_idx = shape_idx;
     rec.kind = sep ? SE2CONV_TABLE_SEPARABLE : SE2CONV_TABLE_FULL;
     rec.bytes = bytes;
-    p->tables[reinterpret_cast<uintptr_t>(d_table)] = rec;
+    register_table(p, d_table, rec);
     return ok();
 }
 
@@ -1502,7 +1541,7 @@ se2conv_status se2conv_coeffs_sum(se2conv_plan_t p, int32_t shape_idx, const se2
     rec.shape_idx = shape_idx;
     rec.kind = SE2CONV_TABLE_FULL;
     rec.bytes = bytes;
-    p->tables[reinterpret_cast<uintptr_t>(d_table)] = rec;
+    register_table(p, d_table, rec);
     return ok();
 }
 
@@ -1547,7 +1586,7 @@ se2conv_status se2conv_field_coeffs(se2conv_plan_t p, int32_t shape_idx, const v
         rec.shape_idx = shape_idx;
         rec.kind = SE2CONV_TABLE_FULL;
         rec.bytes = tbytes;
-        p->tables[reinterpret_cast<uintptr_t>((char*)d_tables + table_stride * b)] = rec;
+        register_table(p, (char*)d_tables + table_stride * b, rec);
     }
     return ok();
 }
@@ -1706,6 +1745,7 @@ se2conv_status se2conv_autotune(se2conv_plan_t p, int32_t shape_idx, int32_t bat
     (void)hipEventDestroy(e1);
     {
         std::lock_guard<std::mutex> g(p->mu);
+        purge_subs_naming(p, reinterpret_cast<uintptr_t>(tab));
         p->tables.erase(reinterpret_cast<uintptr_t>(tab));
     }
     release();
@@ -1819,6 +1859,24 @@ se2conv_status se2conv_table_info(se2conv_plan_t p, const void* d_table, int32_t
     if (kind) *kind = it->second.kind;
     if (shape_idx) *shape_idx = it->second.shape_idx;
     if (bytes) *bytes = it->second.bytes;
+    return ok();
+}
+
+se2conv_status se2conv_table_release(se2conv_plan_t p, const void* d_table) {
+    if (!p || !d_table) return fail(SE2CONV_ERR_INVALID_ARG, "null argument");
+    std::lock_guard<std::mutex> g(p->mu);
+    auto it = p->tables.find(reinterpret_cast<uintptr_t>(d_table));
+    if (it == p->tables.end()) return fail(SE2CONV_ERR_INVALID_ARG, "table was not produced by this plan");
+    purge_subs_naming(p, it->first);
+    p->tables.erase(it);
+    return ok();
+}
+
+se2conv_status se2conv_plan_counts(se2conv_plan_t p, int64_t* n_tables, int64_t* n_submissions) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    std::lock_guard<std::mutex> g(p->mu);
+    if (n_tables) *n_tables = (int64_t)p->tables.size();
+    if (n_submissions) *n_submissions = (int64_t)p->subs.size();
     return ok();
 }
 
@@ -2186,17 +2244,21 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
         key.push_back((uint64_t)q.batch);
         key.push_back((uint64_t)(uintptr_t)q.f);
         key.push_back((uint64_t)(uintptr_t)q.out);
-        for (int j = 0; j < q.n_tables; ++j) key.push_back((uint64_t)(uintptr_t)q.tables[j]);
+        key.push_back((uint64_t)q.n_tables);
+        for (int j = 0; j < q.n_tables; ++j) {
+            key.push_back((uint64_t)(uintptr_t)q.tables[j]);
+            key.push_back((uint64_t)chains[i].kind[j]);
+        }
     }
     if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
     const bool conj = (flags & SE2CONV_ADJOINT) != 0;
 
     // find or build the submission record (device item arrays grouped by shape)
-    SubmissionRec* rec = nullptr;
+    std::shared_ptr<SubmissionRec> rec;
     {
         std::lock_guard<std::mutex> g(p->mu);
         for (auto& r : p->subs)
-            if (r.key == key) rec = &r;
+            if (r->key == key) rec = r;
     }
     if (!rec) {
         std::map<int, std::vector<SepItem>> by_shape;
@@ -2214,36 +2276,45 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
                 by_shape[q.shape_idx].push_back(it);
             }
         }
-        SubmissionRec nr;
-        nr.key = key;
+        auto nr = std::make_shared<SubmissionRec>();
+        nr->key = key;
+        for (int i = 0; i < n_probs; ++i)
+            for (int j = 0; j < probs[i].n_tables; ++j)
+                nr->tabs.push_back(reinterpret_cast<uintptr_t>(probs[i].tables[j]));
         std::vector<SepItem> all;
         for (auto& kv : by_shape) {
-            nr.groups.push_back({kv.first, (int)all.size()});
-            nr.group_counts.push_back((int)kv.second.size());
+            nr->groups.push_back({kv.first, (int)all.size()});
+            nr->group_counts.push_back((int)kv.second.size());
             all.insert(all.end(), kv.second.begin(), kv.second.end());
         }
+        if (hipEventCreateWithFlags(&nr->done, hipEventDisableTiming) != hipSuccess) {
+            nr->done = nullptr;
+            return fail(SE2CONV_ERR_DEVICE, "could not create the submission event");
+        }
         if (!all.empty()) {
-            if (hipMalloc(&nr.d_items, sizeof(SepItem) * all.size()) != hipSuccess)
+            if (hipMalloc(&nr->d_items, sizeof(SepItem) * all.size()) != hipSuccess) {
+                nr->d_items = nullptr;
                 return fail(SE2CONV_ERR_OUT_OF_MEMORY, "item list (%zu items)", all.size());
-            hipError_t e = hipMemcpyAsync(nr.d_items, all.data(), sizeof(SepItem) * all.size(),
+            }
+            hipError_t e = hipMemcpyAsync(nr->d_items, all.data(), sizeof(SepItem) * all.size(),
                                           hipMemcpyHostToDevice, stream);
             if (e == hipSuccess) e = hipStreamSynchronize(stream);
-            if (e != hipSuccess) {
-                (void)hipFree(nr.d_items);
-                return fail(SE2CONV_ERR_DEVICE, "item upload failed: %s", hipGetErrorString(e));
-            }
+            if (e != hipSuccess) return fail(SE2CONV_ERR_DEVICE, "item upload failed: %s", hipGetErrorString(e));
         }
+        // bounded cache: drop the oldest record that no captured graph of the caller's
+        // refers to; its destructor waits for its last enqueued use (on whatever stream)
+        std::shared_ptr<SubmissionRec> evicted;
         std::lock_guard<std::mutex> g(p->mu);
-        if (p->subs.size() >= 64) {  // bounded cache: drop the oldest record
-            SubmissionRec& old = p->subs.front();
-            (void)hipStreamSynchronize(stream);
-            if (old.exec) (void)hipGraphExecDestroy(old.exec);
-            if (old.graph) (void)hipGraphDestroy(old.graph);
-            if (old.d_items) (void)hipFree(old.d_items);
-            p->subs.erase(p->subs.begin());
+        if (p->subs.size() >= 64) {
+            for (auto it = p->subs.begin(); it != p->subs.end(); ++it)
+                if (!(*it)->pinned) {
+                    evicted = *it;
+                    p->subs.erase(it);
+                    break;
+                }
         }
         p->subs.push_back(nr);
-        rec = &p->subs.back();
+        rec = nr;
     }
     // Shape classes are independent: with several of them (and no per-pass timing) they run
     // concurrently on the plan's auxiliary streams, forked from and joined back into the
@@ -2307,6 +2378,20 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
         }
         return SE2CONV_OK;
     };
+    // after every enqueue of the record's work: mark where it ends on this stream (or, on
+    // a stream that the caller is capturing, keep the record for the plan's lifetime)
+    auto mark_done = [&]() -> se2conv_status {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        HIPCHK(hipStreamIsCapturing(stream, &cs));
+        std::lock_guard<std::mutex> g(p->mu);
+        if (cs != hipStreamCaptureStatusNone) {
+            rec->pinned = true;
+            return SE2CONV_OK;
+        }
+        HIPCHK(hipEventRecord(rec->done, stream));
+        rec->used = true;
+        return SE2CONV_OK;
+    };
     if (!(flags & SE2CONV_GRAPH)) {
         if (flags & SE2CONV_TIMING) {
             HIPCHK(record_event(p, stream, true));
@@ -2314,11 +2399,19 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
         }
         se2conv_status r = submit();
         g_timing_plan = nullptr;
+        if (r != SE2CONV_OK) return r;
+        r = mark_done();
         return r == SE2CONV_OK ? ok() : r;
     }
-    if (rec->exec) {
-        HIPCHK(hipGraphLaunch(rec->exec, stream));
-        return ok();
+    hipGraphExec_t cached = nullptr;
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        cached = rec->exec;
+    }
+    if (cached) {
+        HIPCHK(hipGraphLaunch(cached, stream));
+        se2conv_status r = mark_done();
+        return r == SE2CONV_OK ? ok() : r;
     }
     HIPCHK(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal));
     se2conv_status r = submit();
@@ -2335,10 +2428,19 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
         (void)hipGraphDestroy(graph);
         return fail(SE2CONV_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
     }
-    rec->graph = graph;
-    rec->exec = exec;
-    HIPCHK(hipGraphLaunch(exec, stream));
-    return ok();
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        if (rec->exec) {  // another call captured the same list meanwhile: keep that one
+            (void)hipGraphExecDestroy(exec);
+            (void)hipGraphDestroy(graph);
+        } else {
+            rec->graph = graph;
+            rec->exec = exec;
+        }
+    }
+    HIPCHK(hipGraphLaunch(rec->exec, stream));
+    r = mark_done();
+    return r == SE2CONV_OK ? ok() : r;
 }
 
 }  // extern "C"

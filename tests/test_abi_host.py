@@ -215,3 +215,15 @@ def test_coeffs_sum_validation_on_host_only_plan():
     descs[1].sigma = 0.03
     n = ctypes.c_size_t(16 * 32 * 48 * 16)
     assert lib.se2conv_coeffs_sum(p.handle, 0, descs, w, 2, 1 << 16, ctypes.byref(n), None) == L.ERR_DEVICE
+
+
+def test_table_release_and_counts_on_host_only_plan():
+    import ctypes
+    plan = se2.Plan([(32, 32, 16)], host_only=True)
+    assert plan.counts() == (0, 0)
+    lib = L.load()
+    # an address the plan never produced
+    assert lib.se2conv_table_release(plan.handle, ctypes.c_void_p(0x1000)) == L.ERR_INVALID_ARG
+    assert lib.se2conv_table_release(plan.handle, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_table_release(None, ctypes.c_void_p(0x1000)) == L.ERR_INVALID_ARG
+    plan.close()
