@@ -27,6 +27,9 @@ Everything here is plain and slow on purpose:
                    with Gaussian x von Mises kernels.
 * ``adjoint``      gradients of the convolution with respect to the field samples
                    and the kernel samples.
+* ``shifted``      kernels that are sums of SE(2)-shifts of one radial kernel (the
+                   outlook of Sec. 1): each shift moved onto the field as a per-slice
+                   translation phase and a theta shift, then the radial product.
 
 Array layout everywhere: [theta][y][x] (x fastest), sizes (M, Ny, Nx).
 """
