@@ -126,6 +126,8 @@ typedef struct {
 #define SE2CONV_TABLE_SEPARABLE 0 /* layout: Tx[Nx] | Ty[Ny] | Tt[M], complex (re, im) of the plan dtype;
                                      rho^[k; L] = Tx[k1] Ty[k2] Tt[k3] */
 #define SE2CONV_TABLE_FULL 1      /* layout: T[M][Ny][Nx] complex of the plan dtype, T[k3][k2][k1] = rho^[k; L] */
+#define SE2CONV_TABLE_SHIFT 2     /* se2conv_shift_table: J plane sets Q_j[M][Ny][Nx] complex of the plan dtype
+                                     (one per distinct roll, in order of first appearance) */
 
 /*
  * se2conv_coeffs: finite Fourier coefficients of a kernel chain (eq. (FkLv)),
@@ -174,6 +176,53 @@ se2conv_status se2conv_table_info(se2conv_plan_t plan, const void* d_table, int3
  * address is not a recorded table of this plan.
  */
 se2conv_status se2conv_table_release(se2conv_plan_t plan, const void* d_table);
+
+/*
+ * Kernels that are sums of SE(2)-shifts of one kernel radial in translations (the outlook of
+ * Sec. 1: a general f2 approximated by sum_k a_k rho_k, the rho_k shifts of one radial rho).
+ * A shift acts on the left (group law eq. (SE2law)): rho_k(g) = rho(s_k^{-1} o g) with
+ * s_k = (t_k, R_phi_k).  Radiality of rho gives f * rho_k = f_k * rho with
+ * f_k(y, alpha) = f(y - R_{alpha - phi_k} t_k, alpha - phi_k): every theta-slice alpha of f
+ * translated by R_alpha t_k, the field shifted by phi_k in theta; after that, Thm. f*gP's
+ * product of coefficients applies.  On the spatial finite Fourier coefficients of a slice
+ * the translation is the phase e^{-2 pi i (k1, k2) . R_alpha t_k} (signed frequencies; for
+ * an even length the Nyquist index holds +-L/2 in halves, phase cos(pi L tau)), exact for
+ * the trigonometric polynomial.  The rotation phi_k must be a grid angle: phi_k = 2 pi roll / M.
+ */
+typedef struct {
+    double tx, ty;  /* translation t_k (any real values, |t| <= 1e6) */
+    double weight;  /* a_k */
+    int32_t roll;   /* phi_k = 2 pi roll / M, 0 <= roll < M */
+} se2conv_shift;
+
+/*
+ * se2conv_shift_table: the translation-phase tables of a shift sum, computed in FP64 on the
+ * device and rounded once: for each distinct roll r_j (at most 8),
+ *   Q_j[alpha][t2][t1] = sum_{k: roll_k = r_j} a_k e^{-2 pi i (k1, k2) . R_alpha t_k}.
+ *   shifts[n_shifts]  host array, 1 <= n_shifts <= 64.
+ *   d_table           device buffer of *table_bytes bytes (J * M*Ny*Nx complex of the plan
+ *                     dtype), 16-byte aligned, or NULL to query the size.
+ * The plan records it as a SE2CONV_TABLE_SHIFT table (usable only with se2conv_apply_shifted).
+ */
+se2conv_status se2conv_shift_table(se2conv_plan_t plan, int32_t shape_idx, const se2conv_shift* shifts,
+                                   int32_t n_shifts, void* d_table, size_t* table_bytes, hipStream_t stream);
+
+/*
+ * se2conv_apply_shifted: out[b] = Re S_K[f[b], sum_k a_k rho_k] with the shifts of d_shift_table
+ * and rho the chain of kernel_tables (SEPARABLE or FULL tables of this plan and shape; for
+ * the result to be the SE(2) convolution rho must be radial in translations):
+ *   f^_shift[k] = sum_j DFT_theta( F2[k1, k2, alpha - r_j] Q_j[alpha - r_j][k2][k1] )[k3],
+ *   out = Re synthesis of f^_shift . prod rho^   (eq. (SKfg)),
+ * F2 the spatial FFCs of the theta-slices.  Five passes on pairs of fields: x and y forward,
+ * theta lines (shift mix, forward transform, product, inverse), y and x inverse.
+ *   d_f, d_out  device [batch][M][Ny][Nx] of the plan dtype, 16-byte aligned; d_out == d_f allowed.
+ * Uses the plan workspace for an odd batch: calls on one plan must not overlap on different
+ * streams.  Flags: SE2CONV_TIMING.
+ */
+se2conv_status se2conv_apply_shifted(se2conv_plan_t plan, int32_t shape_idx, const void* d_f,
+                                     const void* d_shift_table, const void* const* kernel_tables,
+                                     int32_t n_kernel_tables, void* d_out, int32_t batch, uint32_t flags,
+                                     hipStream_t stream);
 
 /* Diagnostics: number of tables the plan records and of cached se2conv_chain submissions. */
 se2conv_status se2conv_plan_counts(se2conv_plan_t plan, int64_t* n_tables, int64_t* n_submissions);

@@ -185,6 +185,35 @@ class Plan:
                                         _stream_handle(stream)))
         return out
 
+    def shift_table(self, shape_idx: int, shifts, stream=None) -> Table:
+        """Translation-phase tables of a sum of SE(2)-shifted kernels (se2conv_shift_table):
+        shifts = [(tx, ty, roll, weight), ...], the rotation of each shift 2 pi roll / M."""
+        arr = (L.Shift * len(shifts))(*[L.Shift(float(tx), float(ty), float(w), int(r)) for tx, ty, r, w in shifts])
+        nbytes = ctypes.c_size_t(0)
+        L.check(self._lib.se2conv_shift_table(self.handle, shape_idx, arr, len(shifts), None, ctypes.byref(nbytes),
+                                              None))
+        buf = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        L.check(self._lib.se2conv_shift_table(self.handle, shape_idx, arr, len(shifts), buf.data_ptr(),
+                                              ctypes.byref(nbytes), _stream_handle(stream)))
+        return Table(self, shape_idx, buf, L.TABLE_SHIFT)
+
+    def apply_shifted(self, shape_idx: int, f: torch.Tensor, shift_table: Table, kernel_tables,
+                      out: torch.Tensor | None = None, stream=None, timing: bool = False) -> torch.Tensor:
+        """Re S_K[f, sum_k a_k rho(s_k^{-1} .)] (se2conv_apply_shifted); kernel_tables: rho's chain."""
+        _require(f, self.tdtype)
+        nx, ny, m = self.shapes[shape_idx]
+        if f.shape[-3:] != (m, ny, nx):
+            raise ValueError(f"field shape {tuple(f.shape)} does not end in {(m, ny, nx)}")
+        batch = f.numel() // (nx * ny * m)
+        if out is None:
+            out = torch.empty_like(f)
+        _require(out, self.tdtype)
+        tp = (ctypes.c_void_p * len(kernel_tables))(*[t.ptr for t in kernel_tables])
+        L.check(self._lib.se2conv_apply_shifted(self.handle, shape_idx, f.data_ptr(), shift_table.ptr, tp,
+                                                len(kernel_tables), out.data_ptr(), batch,
+                                                L.TIMING if timing else 0, _stream_handle(stream)))
+        return out
+
     def apply_complex(self, shape_idx: int, f: torch.Tensor, table: Table, out: torch.Tensor | None = None,
                       adjoint: bool = False, stream=None, timing: bool = False) -> torch.Tensor:
         """S_K[f, chain] for complex-valued fields f (complex64 / complex128 by plan dtype)."""

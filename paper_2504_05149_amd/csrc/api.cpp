@@ -24,6 +24,7 @@
 #include "full_fast.hpp"
 #include "grad.hpp"
 #include "sample.hpp"
+#include "shift.hpp"
 
 using namespace se2c;
 
@@ -161,6 +162,7 @@ struct TableRec {
     int32_t shape_idx;
     int32_t kind;
     size_t bytes;
+    std::vector<int> rolls;  // SE2CONV_TABLE_SHIFT: theta roll of each plane set
 };
 
 // A problem list seen by se2conv_chain: its device item arrays (one group of
@@ -568,8 +570,13 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
         // Fields per launch pair (the whole batch unless SE2CONV_SEP_CHUNK says
         // otherwise; see sep_chunk_fields).
         const int chunk = sep_chunk_fields(p, s, batch);
+        static const int mid_cached = [] {
+            const char* e = std::getenv("SE2CONV_MID_CACHED");
+            return e ? std::atoi(e) : 0;
+        }();
         for (int c0 = 0; c0 < batch; c0 += chunk) {
             FastSepArgs ca = fa;
+            ca.mid_cached = mid_cached;
             ca.in = reinterpret_cast<const float*>(f) + (long long)c0 * n;
             ca.out = reinterpret_cast<float*>(out) + (long long)c0 * n;
             ca.nitems = std::min(chunk, batch - c0);
@@ -987,6 +994,99 @@ se2conv_status enqueue_full(se2conv_plan_s* p, const se2conv_shape& s, const voi
     return SE2CONV_OK;
 }
 
+// x lines only (forward or inverse) on plane pairs, theta chunks as in the x-row pass.
+hipError_t x_pass(se2conv_plan_s* p, const se2conv_shape& s, bool d, int dir, const void* in0, const void* in1,
+                  void* out0, void* out1, const void* lone_in1, void* lone_out1, long long stride, int nitems,
+                  hipStream_t st) {
+    SlabArgs a{};
+    a.in0 = in0;
+    a.in1 = in1;
+    a.out0 = out0;
+    a.out1 = out1;
+    a.lone_in1 = lone_in1;
+    a.lone_out1 = lone_out1;
+    a.item_stride_in = stride;
+    a.item_stride_out = stride;
+    a.nitems = nitems;
+    a.in_mode = 1;
+    a.out_mode = 1;
+    a.nx = s.nx;
+    a.ny = s.ny;
+    a.m = s.m;
+    a.nslab = s.ny;
+    a.fwd = dir == 0;
+    a.inv = dir == 1;
+    a.px = radix_plan_of(p, s.nx, d);
+    a.pt = radix_plan_of(p, s.m, d);
+    a.twx = stage_tw_of(p, a.px, d);
+    a.twt = stage_tw_of(p, a.pt, d);
+    a.rows_per_tile = rows_for_xpass(s, d, sched_of(p, s).xrow_points);
+    a.ntile_t = (s.m + a.rows_per_tile - 1) / a.rows_per_tile;
+    a.do_t = 0;
+    return run_slab(a, d, st);
+}
+
+// Sum of SE(2)-shifted radial kernels on pairs of fields (two real fields as one complex
+// field: every step is real-linear and maps real fields to real fields).  Five passes over
+// plane pairs: x forward, y forward (spatial spectra of every theta-slice), theta lines
+// with the shift mix, forward transform, product with the radial kernel's coefficients
+// (x 1/n) and inverse, y inverse, x inverse.
+se2conv_status enqueue_shifted(se2conv_plan_s* p, const se2conv_shape& s, const void* f, void* out, int batch,
+                               const Chain& ch, const void* qtab, const std::vector<int>& rolls, hipStream_t st) {
+    const bool d = dbl(p);
+    const long long n = (long long)s.nx * s.ny * s.m;
+    const size_t rb = real_bytes(p);
+    const int pairs = (batch + 1) / 2;
+    const bool odd = (batch & 1) != 0;
+    const void* f1 = batch == 1 ? nullptr : (const char*)f + rb * n;
+    void* o1 = batch == 1 ? nullptr : (char*)out + rb * n;
+    void* lone = odd ? p->ws : nullptr;  // the odd field's imaginary plane between the passes
+    HIPCHK(x_pass(p, s, d, 0, f, f1, out, o1, nullptr, lone, 2 * n, pairs, st));
+    HIPCHK(y_pass(p, s, d, out, o1, lone, 2 * n, pairs, 1, 0, 0, nullptr, false, 1.0, st));
+    PencilArgs b{};
+    b.in0 = out;
+    b.in1 = o1;
+    b.out0 = out;
+    b.out1 = o1;
+    b.lone_in1 = lone;
+    b.lone_out1 = lone;
+    b.item_stride_in = 2 * n;
+    b.item_stride_out = 2 * n;
+    b.nitems = pairs;
+    b.mode = 1;
+    b.axis = 2;
+    b.nx = s.nx;
+    b.ny = s.ny;
+    b.m = s.m;
+    b.ncols = s.nx;
+    b.W = pencil_width(b.ncols, s.m, d, sched_of(p, s).pencil_w);
+    b.fwd = 1;
+    b.inv = 1;
+    b.mul = 3;
+    b.p = radix_plan_of(p, s.m, d);
+    b.tw = stage_tw_of(p, b.p, d);
+    b.scale = 1.0 / (double)n;
+    b.qtab = qtab;
+    b.nshift = (int)rolls.size();
+    for (size_t j = 0; j < rolls.size(); ++j) b.rolls[j] = rolls[j];
+    const size_t cb = cplx_bytes(p);
+    b.ntab = ch.ntab;
+    for (int j = 0; j < ch.ntab; ++j) {
+        if (ch.kind[j] == SE2CONV_TABLE_FULL) {
+            b.tab3[j] = ch.ptr[j];
+        } else {
+            b.tab3[j] = nullptr;
+            b.sepx[j] = ch.ptr[j];
+            b.sepy[j] = (const char*)ch.ptr[j] + cb * s.nx;
+            b.sept[j] = (const char*)ch.ptr[j] + cb * (s.nx + s.ny);
+        }
+    }
+    HIPCHK(run_pencil(b, d, st));
+    HIPCHK(y_pass(p, s, d, out, o1, lone, 2 * n, pairs, 0, 1, 0, nullptr, false, 1.0, st));
+    HIPCHK(x_pass(p, s, d, 1, out, o1, out, o1, lone, nullptr, 2 * n, pairs, st));
+    return SE2CONV_OK;
+}
+
 se2conv_status lookup_chain(se2conv_plan_s* p, int shape_idx, const void* const* tables, int ntab, Chain* ch,
                             bool* all_sep) {
     if (ntab < 1 || ntab > SE2C_MAX_TABLES)
@@ -1001,6 +1101,8 @@ se2conv_status lookup_chain(se2conv_plan_s* p, int shape_idx, const void* const*
         if (it->second.shape_idx != shape_idx)
             return fail(SE2CONV_ERR_INVALID_ARG, "table %d belongs to shape %d, not %d", j, it->second.shape_idx,
                         shape_idx);
+        if (it->second.kind == SE2CONV_TABLE_SHIFT)
+            return fail(SE2CONV_ERR_INVALID_ARG, "table %d is a shift table (use se2conv_apply_shifted)", j);
         ch->kind[j] = it->second.kind;
         ch->ptr[j] = tables[j];
         if (it->second.kind != SE2CONV_TABLE_SEPARABLE) *all_sep = false;
@@ -1880,6 +1982,88 @@ se2conv_status se2conv_plan_counts(se2conv_plan_t p, int64_t* n_tables, int64_t*
     return ok();
 }
 
+se2conv_status se2conv_shift_table(se2conv_plan_t p, int32_t shape_idx, const se2conv_shift* shifts,
+                                   int32_t n_shifts, void* d_table, size_t* table_bytes, hipStream_t stream) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (shape_idx < 0 || shape_idx >= (int)p->shapes.size())
+        return fail(SE2CONV_ERR_INVALID_ARG, "shape_idx %d out of range", shape_idx);
+    if (!table_bytes) return fail(SE2CONV_ERR_INVALID_ARG, "table_bytes is null");
+    if (!shifts || n_shifts < 1 || n_shifts > SE2C_MAX_SHIFT_TERMS)
+        return fail(SE2CONV_ERR_INVALID_ARG, "need 1..%d shifts", SE2C_MAX_SHIFT_TERMS);
+    const se2conv_shape& s = p->shapes[shape_idx];
+    std::vector<int> rolls;
+    for (int k = 0; k < n_shifts; ++k) {
+        const se2conv_shift& q = shifts[k];
+        if (!std::isfinite(q.tx) || !std::isfinite(q.ty) || !std::isfinite(q.weight) || std::fabs(q.tx) > 1e6 ||
+            std::fabs(q.ty) > 1e6)
+            return fail(SE2CONV_ERR_INVALID_ARG, "shift %d: translation and weight must be finite (|t| <= 1e6)", k);
+        if (q.roll < 0 || q.roll >= s.m)
+            return fail(SE2CONV_ERR_INVALID_ARG, "shift %d: roll %d outside [0, M = %d)", k, q.roll, s.m);
+        if (std::find(rolls.begin(), rolls.end(), q.roll) == rolls.end()) rolls.push_back(q.roll);
+    }
+    if ((int)rolls.size() > SE2C_MAX_SHIFT_CLASSES)
+        return fail(SE2CONV_ERR_INVALID_ARG, "at most %d distinct rolls per table (got %zu)", SE2C_MAX_SHIFT_CLASSES,
+                    rolls.size());
+    const long long n = (long long)s.nx * s.ny * s.m;
+    const size_t bytes = cplx_bytes(p) * (size_t)n * rolls.size();
+    if (!d_table) {
+        *table_bytes = bytes;
+        return ok();
+    }
+    if (*table_bytes < bytes) return fail(SE2CONV_ERR_INVALID_ARG, "table buffer too small (%zu < %zu)", *table_bytes, bytes);
+    if (!aligned16(d_table)) return fail(SE2CONV_ERR_INVALID_ARG, "table must be 16-byte aligned");
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    for (size_t j = 0; j < rolls.size(); ++j) {
+        ShiftClassArgs a{};
+        a.nx = s.nx;
+        a.ny = s.ny;
+        a.m = s.m;
+        for (int k = 0; k < n_shifts; ++k)
+            if (shifts[k].roll == rolls[j]) a.t[a.nterm++] = ShiftTerm{shifts[k].tx, shifts[k].ty, shifts[k].weight};
+        HIPCHK(launch_shift_table(a, (char*)d_table + cplx_bytes(p) * (size_t)n * j, dbl(p), stream));
+    }
+    TableRec rec;
+    rec.shape_idx = shape_idx;
+    rec.kind = SE2CONV_TABLE_SHIFT;
+    rec.bytes = bytes;
+    rec.rolls = rolls;
+    std::lock_guard<std::mutex> g(p->mu);
+    register_table(p, d_table, rec);
+    return ok();
+}
+
+se2conv_status se2conv_apply_shifted(se2conv_plan_t p, int32_t shape_idx, const void* d_f, const void* d_shift_table,
+                                     const void* const* kernel_tables, int32_t n_kernel_tables, void* d_out,
+                                     int32_t batch, uint32_t flags, hipStream_t stream) {
+    se2conv_status r = validate_io(p, shape_idx, d_f, d_out, batch);
+    if (r != SE2CONV_OK) return r;
+    if (flags & ~SE2CONV_TIMING) return fail(SE2CONV_ERR_INVALID_ARG, "unknown flags 0x%x (only SE2CONV_TIMING)", flags);
+    if (!d_shift_table || !kernel_tables) return fail(SE2CONV_ERR_INVALID_ARG, "null table");
+    std::vector<int> rolls;
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        auto it = p->tables.find(reinterpret_cast<uintptr_t>(d_shift_table));
+        if (it == p->tables.end() || it->second.kind != SE2CONV_TABLE_SHIFT)
+            return fail(SE2CONV_ERR_INVALID_ARG, "d_shift_table is not a shift table of this plan");
+        if (it->second.shape_idx != shape_idx)
+            return fail(SE2CONV_ERR_INVALID_ARG, "shift table belongs to shape %d, not %d", it->second.shape_idx,
+                        shape_idx);
+        rolls = it->second.rolls;
+    }
+    Chain ch;
+    bool all_sep = true;
+    r = lookup_chain(p, shape_idx, kernel_tables, n_kernel_tables, &ch, &all_sep);
+    if (r != SE2CONV_OK) return r;
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    if (flags & SE2CONV_TIMING) {
+        HIPCHK(record_event(p, stream, true));
+        g_timing_plan = p;
+    }
+    r = enqueue_shifted(p, p->shapes[shape_idx], d_f, d_out, batch, ch, d_shift_table, rolls, stream);
+    g_timing_plan = nullptr;
+    return r == SE2CONV_OK ? ok() : r;
+}
+
 se2conv_status se2conv_apply(se2conv_plan_t p, int32_t shape_idx, const void* d_f, const void* d_table, void* d_out,
                              int32_t batch, uint32_t flags, hipStream_t stream) {
     se2conv_status r = validate_io(p, shape_idx, d_f, d_out, batch);
@@ -2442,5 +2626,6 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
     r = mark_done();
     return r == SE2CONV_OK ? ok() : r;
 }
+
 
 }  // extern "C"

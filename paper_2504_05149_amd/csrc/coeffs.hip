@@ -22,15 +22,22 @@ namespace se2c {
 // ------------------------------------------------------------------ twiddles
 __global__ void twiddle_kernel(double2* out64, float2* out32, int L) {
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < L; j += gridDim.x * blockDim.x) {
-        // exp(-2 pi i j / L): use the symmetric quarter-turn reduction so that the
-        // table is exactly symmetric, and sincospi for the reduced angle.
-        double s, c;
-        sincospi(2.0 * (double)j / (double)L, &s, &c);
-        // Snap the exact quarter-turn points.
-        if ((4LL * j) % L == 0) {
-            const int q = (int)((4LL * j) / L) & 3;
-            c = (q == 0) ? 1.0 : (q == 2 ? -1.0 : 0.0);
-            s = (q == 1) ? 1.0 : (q == 3 ? -1.0 : 0.0);
+        // exp(-2 pi i j / L) with the angle reduced exactly to the first quarter turn in
+        // integers: quadrant q = floor(4j / L), remainder r = 4j - q L, so that
+        // 2 pi j / L = q (pi/2) + (pi/2) r / L; sincospi takes the reduced angle and the
+        // quadrant is an exact rotation by q quarter turns (the quarter-turn points come
+        // out exact: r = 0 gives cos = 1, sin = 0).
+        const long long j4 = 4LL * j;
+        const int q = (int)(j4 / L);
+        const long long r = j4 - (long long)q * L;
+        double sr, cr;
+        sincospi(0.5 * (double)r / (double)L, &sr, &cr);
+        double c, s;
+        switch (q & 3) {
+            case 0: c = cr; s = sr; break;
+            case 1: c = -sr; s = cr; break;
+            case 2: c = -cr; s = -sr; break;
+            default: c = sr; s = -cr; break;
         }
         double2 w;
         w.x = c;

@@ -320,6 +320,40 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) pencil_kernel
         }
         __syncthreads();
 
+        if (a.mul == 3) {
+            // shift mix (theta lines: e = alpha, other = k2, column c0 + c = k1):
+            // z'[alpha] = sum_j z[alpha - r_j] Q_j[alpha - r_j][k2][k1], indices mod M
+            const C<T>* q = reinterpret_cast<const C<T>*>(a.qtab);
+            const long long nn = plane * a.m;
+            C<T> g[MAXV];
+#pragma unroll
+            for (int k = 0; k < MAXV; ++k) {
+                const int i = tid + k * nthr;
+                g[k] = mk<T>((T)0, (T)0);
+                if (i < P) {
+                    const int e = i / a.W;
+                    const int c = i - e * a.W;
+                    if (c0 + c < a.ncols) {
+                        for (int j = 0; j < a.nshift; ++j) {
+                            int src = e - a.rolls[j];
+                            if (src < 0) src += L;
+                            const C<T> qv = q[(long long)j * nn + (long long)src * plane + (long long)other * a.nx + c0 + c];
+                            g[k] = add<T>(g[k], mul<T>(tile[src * pitch + c], qv));
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < MAXV; ++k) {
+                const int i = tid + k * nthr;
+                if (i < P) {
+                    const int e = i / a.W;
+                    tile[e * pitch + (i - e * a.W)] = g[k];
+                }
+            }
+            __syncthreads();
+        }
         if (a.fwd) line_fft<T, MAXV, false, ODD>(tile, tw, a.p, pitch, 1, a.W, true, tid, nthr);
         if (a.mul == 1) {
             for (int i = tid; i < P; i += nthr) {
@@ -328,23 +362,26 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) pencil_kernel
                 tile[e * pitch + c] = mul<T>(tile[e * pitch + c], f1[e]);
             }
             __syncthreads();
-        } else if (a.mul == 2) {
-            // full-table product (axis == y): element (kx = c0 + c, ky = e, kt = other);
-            // a separable table contributes Tx[kx] Ty[ky] Tt[kt].
+        } else if (a.mul >= 2) {
+            // full-table product: element (kx = c0 + c, ky, kt) with (ky, kt) = (e, other) on
+            // y lines and (other, e) on theta lines; a separable table contributes
+            // Tx[kx] Ty[ky] Tt[kt].
             const T sc = (T)a.scale;
             for (int i = tid; i < P; i += nthr) {
                 const int e = i / a.W;
                 const int c = i - e * a.W;
                 if (c0 + c < a.ncols) {
                     const int kx = c0 + c;
+                    const int ky = a.axis == 1 ? e : other;
+                    const int kt = a.axis == 1 ? other : e;
                     C<T> w = mk<T>(sc, (T)0);
                     for (int j = 0; j < a.ntab; ++j) {
                         if (a.tab3[j]) {
-                            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.tab3[j])[(long long)other * plane + (long long)e * a.nx + kx]);
+                            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.tab3[j])[(long long)kt * plane + (long long)ky * a.nx + kx]);
                         } else {
                             w = mul<T>(w, reinterpret_cast<const C<T>*>(a.sepx[j])[kx]);
-                            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.sepy[j])[e]);
-                            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.sept[j])[other]);
+                            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.sepy[j])[ky]);
+                            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.sept[j])[kt]);
                         }
                     }
                     if (a.conj_tab) w.y = -w.y;

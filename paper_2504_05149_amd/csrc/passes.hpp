@@ -4,6 +4,7 @@
 #include <stddef.h>
 
 #include "fft_device.hpp"
+#include "shift.hpp"
 
 #define SE2C_MAXV 16          // complex values held per thread during a stage
 // The same for the kernels with radix-5/7, direct and Rader stages: a smaller budget
@@ -90,7 +91,8 @@ struct PencilArgs {
     int W;
     int pad;
     int fwd, inv;
-    int mul;                // 1: 1-D factors (sep tables), 2: full tables / mixed
+    int mul;                // 1: 1-D factors (sep tables), 2: full tables / mixed, 3: as 2 along theta,
+                            // after the shift mix before the forward transform (qtab, rolls)
     int ntab;
     const void* tab1[SE2C_MAX_TABLES];    // 1-D factor along this axis (mul == 1)
     const void* tab3[SE2C_MAX_TABLES];    // full [m][ny][nx] table, or nullptr if separable
@@ -103,6 +105,12 @@ struct PencilArgs {
     const void* tw;
     const SepItem* items;   // device; non-null: item i reads items[i] (x-pair mode, 1-D factor product)
     int cplx;               // plane mode: planes are interleaved (complex fields; in1 = in0 + 1, element stride 2)
+    // mul == 3 (theta lines of spatial spectra): before the forward transform every point
+    // alpha becomes sum_j z[alpha - rolls[j]] Q_j[alpha - rolls[j]][k2][k1] (indices mod M),
+    // Q_j the j-th [M][Ny][Nx] complex plane set of qtab
+    const void* qtab;
+    int nshift;
+    int rolls[SE2C_MAX_SHIFT_CLASSES];
 };
 
 size_t slab_lds_bytes(const SlabArgs& a, bool dbl);

@@ -242,11 +242,20 @@ xt_slab_fast(FastSepArgs a) {
     // 5. store columns
     float* __restrict__ out0 = fout + (long long)(2 * s) * NX;
     float* __restrict__ out1 = out0 + NX;
+    if (a.mid_cached) {
 #pragma unroll
-    for (int l = 0; l < MV; ++l) {
-        const int off = (TPC * l + hh) * pl + xc;
-        __builtin_nontemporal_store(v[l].x, out0 + off);
-        __builtin_nontemporal_store(v[l].y, out1 + off);
+        for (int l = 0; l < MV; ++l) {
+            const int off = (TPC * l + hh) * pl + xc;
+            out0[off] = v[l].x;
+            out1[off] = v[l].y;
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < MV; ++l) {
+            const int off = (TPC * l + hh) * pl + xc;
+            __builtin_nontemporal_store(v[l].x, out0 + off);
+            __builtin_nontemporal_store(v[l].y, out1 + off);
+        }
     }
 }
 

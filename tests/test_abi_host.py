@@ -227,3 +227,28 @@ def test_table_release_and_counts_on_host_only_plan():
     assert lib.se2conv_table_release(plan.handle, None) == L.ERR_INVALID_ARG
     assert lib.se2conv_table_release(None, ctypes.c_void_p(0x1000)) == L.ERR_INVALID_ARG
     plan.close()
+
+
+def test_shift_table_validation_on_host_only_plan():
+    import ctypes
+    plan = se2.Plan([(32, 32, 16)], host_only=True)
+    lib = L.load()
+
+    def size(shifts):
+        arr = (L.Shift * len(shifts))(*[L.Shift(tx, ty, w, r) for tx, ty, r, w in shifts])
+        nb = ctypes.c_size_t(0)
+        st = lib.se2conv_shift_table(plan.handle, 0, arr, len(shifts), None, ctypes.byref(nb), None)
+        return st, nb.value
+
+    st, nb = size([(0.1, 0.2, 0, 1.0), (0.3, -0.1, 0, 0.5), (0.0, 0.1, 3, 2.0)])
+    assert st == L.OK and nb == 2 * 32 * 32 * 16 * 8  # two distinct rolls, FP32 complex
+    assert size([(0.1, 0.2, 16, 1.0)])[0] == L.ERR_INVALID_ARG          # roll outside [0, M)
+    assert size([(0.1, 0.2, -1, 1.0)])[0] == L.ERR_INVALID_ARG
+    assert size([(float("nan"), 0.2, 0, 1.0)])[0] == L.ERR_INVALID_ARG
+    assert size([(0.1, 0.2, r, 1.0) for r in range(9)])[0] == L.ERR_INVALID_ARG   # 9 distinct rolls
+    assert size([(0.1, 0.2, 0, 1.0)] * 65)[0] == L.ERR_INVALID_ARG                # 65 terms
+    # a table the plan never produced is refused by the shifted apply
+    tp = (ctypes.c_void_p * 1)(0x2000)
+    assert lib.se2conv_apply_shifted(plan.handle, 0, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x3000), tp, 1,
+                                     ctypes.c_void_p(0x4000), 1, 0, None) == L.ERR_INVALID_ARG
+    plan.close()

@@ -1,0 +1,94 @@
+"""se2conv_chain_noalloc (the allocation-free variant of se2conv_chain) against
+se2conv_chain on the same problems, through the C ABI: two calls in a row, the
+second with a smaller problem list, plus the size limit and flag checks."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2504_05149_amd as se2
+from paper_2504_05149_amd import _lib as L
+from gpu_common import case, oracle_table_gauss, parity_err, tol32
+from inputs import chain_kernel_params, sample_fields
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+SHAPES = [(32, 32, 16), (48, 48, 32), (64, 64, 64), (128, 128, 64), (96, 64, 16)]
+
+
+def _problems(plan, n_per_shape, seed):
+    probs, host = [], []
+    for si, s in enumerate(SHAPES):
+        for r in range(n_per_shape[si]):
+            ks = chain_kernel_params(seed * 100 + si * 10 + r, 1 + (r % 4))
+            chain = [(k.sigma, k.kappa, k.theta0) for k in ks]
+            tabs = [plan.coeffs(si, [se2.GaussVM(*c)]) for c in chain]
+            batch = 1 + (r % 3)
+            f = sample_fields(seed * 100 + si * 10 + r, batch, 8, *s, dtype=np.float32)
+            fd = torch.from_numpy(f).to(DEV)
+            probs.append((si, fd, tabs))
+            host.append((s, f, chain))
+    return probs, host
+
+
+def _run_both(plan, probs, adjoint):
+    stream = torch.cuda.Stream()
+    ref_out = [torch.full_like(fd, np.nan) for _, fd, _ in probs]
+    new_out = [torch.full_like(fd, np.nan) for _, fd, _ in probs]
+    torch.cuda.synchronize()
+    plan.chain([(si, fd, o, tabs) for (si, fd, tabs), o in zip(probs, ref_out)], adjoint=adjoint, stream=stream)
+    plan.chain_noalloc([(si, fd, o, tabs) for (si, fd, tabs), o in zip(probs, new_out)], adjoint=adjoint,
+                       stream=stream)
+    torch.cuda.synchronize()
+    return ref_out, new_out
+
+
+@pytest.mark.parametrize("adjoint", [False, True])
+def test_noalloc_matches_chain_two_calls(adjoint):
+    plan = se2.Plan(SHAPES, dtype="f32")
+    for call, counts in enumerate(([3, 3, 2, 2, 2], [1, 2, 1, 0, 1])):
+        case(f"chain_noalloc call {call}: problems per shape {counts}, adjoint={adjoint}")
+        probs, host = _problems(plan, counts, 7 + call)
+        ref_out, new_out = _run_both(plan, probs, adjoint)
+        nfields = 0
+        for i, (r, n) in enumerate(zip(ref_out, new_out)):
+            assert torch.equal(r, n), f"problem {i}: differs from se2conv_chain"
+            nfields += r.shape[0]
+        print(f"  {len(probs)} problems, {nfields} fields: identical to se2conv_chain", flush=True)
+        # and the first field of every problem against the oracle
+        from oracle import conv as oc
+        for i, ((s, f, chain), n) in enumerate(zip(host, new_out)):
+            t = oracle_table_gauss(*s, chain)
+            if adjoint:
+                t = np.conj(t)
+            err = parity_err(n[0].cpu().numpy(), oc.conv_with_coeffs(f[0], t))
+            assert err <= tol32(s[0] * s[1] * s[2]), (i, err)
+    plan.close()
+
+
+def test_noalloc_rejects_oversized_and_unsupported_calls():
+    case("chain_noalloc: more than 4096 fields, FULL tables and graph flags are refused")
+    plan = se2.Plan([(8, 8, 2), (32, 32, 16)], dtype="f32")
+    t = plan.coeffs(0, [se2.GaussVM(0.1, 2.0)])
+    f = torch.zeros(4097, 2, 8, 8, device=DEV)
+    out = torch.full_like(f, 7.0)
+    with pytest.raises(L.Se2convError) as e:
+        plan.chain_noalloc([(0, f, out, [t])])
+    assert e.value.status == L.ERR_INVALID_ARG and "4096" in str(e.value)
+    torch.cuda.synchronize()
+    assert bool((out == 7.0).all()), "nothing may be enqueued for a refused call"
+    # exactly the limit runs
+    plan.chain_noalloc([(0, f[:4096], out[:4096], [t])])
+    torch.cuda.synchronize()
+    assert bool((out[:4096] == 0.0).all()) and bool((out[4096] == 7.0).all())
+    # a FULL table is refused
+    g = torch.from_numpy(sample_fields(3, 1, 4, 32, 32, 16, dtype=np.float32)).to(DEV)
+    tf = plan.coeffs(1, [se2.ExpGauss(0.08)])
+    with pytest.raises(L.Se2convError) as e:
+        plan.chain_noalloc([(1, g, torch.empty_like(g), [tf])])
+    assert e.value.status == L.ERR_INVALID_ARG
+    # only SE2CONV_ADJOINT is accepted
+    arr, keep = plan._problem_array([(1, g, torch.empty_like(g), [plan.coeffs(1, [se2.GaussVM(0.1, 2.0)])])])
+    st = int(torch.cuda.current_stream().cuda_stream)
+    assert plan._lib.se2conv_chain_noalloc(plan.handle, arr, 1, L.GRAPH, st) == L.ERR_INVALID_ARG
+    plan.close()
