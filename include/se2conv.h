@@ -406,6 +406,28 @@ se2conv_status se2conv_chain(se2conv_plan_t plan, const se2conv_problem* probs, 
                              hipStream_t stream);
 
 /*
+ * se2conv_chain_noalloc: se2conv_chain for callers that cannot allocate device memory
+ * (code under stream capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same result as se2conv_chain on the same problems (the same pass kernels), but the
+ * per-field item lists (input, output, table chain) go into a fixed device array of the
+ * library instead of a cached allocation: no hipMalloc, hipFree or allocating library
+ * call, no graph, nothing cached.  The items are written by small kernels that carry them
+ * in their arguments, then each shape class runs its passes on them, all on `stream`.
+ *   probs[n_probs]  as for se2conv_chain, restricted to problems whose tables are all
+ *                   SEPARABLE on shapes with even Nx and Ny (others: ERR_INVALID_ARG).
+ *   flags           0 or SE2CONV_ADJOINT.
+ * Limit: at most 4096 fields (the sum of the problems' batches) per call; more gives
+ * ERR_INVALID_ARG and enqueues nothing.  The array (4096 items, about 360 KB) is held by
+ * every device the library runs on until the process ends; its address is looked up at
+ * plan creation with that device current, and the plan's device must be current here.
+ * Every call on one device shares that array and overwrites it: calls that overlap on
+ * one device (different streams, or threads without ordering) race and must not be
+ * issued; calls ordered on one stream are safe.
+ */
+se2conv_status se2conv_chain_noalloc(se2conv_plan_t plan, const se2conv_problem* probs, int32_t n_probs,
+                                     uint32_t flags, hipStream_t stream);
+
+/*
  * se2conv_pass_times: durations of the passes enqueued with SE2CONV_TIMING since the
  * last read, in launch order.  Synchronises on the last recorded event.
  *   ms[cap], kinds[cap]   host arrays; kinds: 0 = x-theta slab pass, 1 = y pencil,

@@ -23,7 +23,7 @@ PASS_KINDS = {0: "xt_slab", 1: "y_pencil", 2: "t_pencil", 3: "x_rows"}
 
 EXPORTED = [
     "se2conv_plan", "se2conv_plan_destroy", "se2conv_coeffs", "se2conv_coeffs_sum", "se2conv_table_info",
-    "se2conv_table_release", "se2conv_plan_counts", "se2conv_shift_table", "se2conv_apply_shifted", "se2conv_apply", "se2conv_apply_padded", "se2conv_apply_complex", "se2conv_chain", "se2conv_pass_times", "se2conv_field_coeffs",
+    "se2conv_table_release", "se2conv_plan_counts", "se2conv_shift_table", "se2conv_apply_shifted", "se2conv_apply", "se2conv_apply_padded", "se2conv_apply_complex", "se2conv_chain", "se2conv_chain_noalloc", "se2conv_pass_times", "se2conv_field_coeffs",
     "se2conv_profile_grad", "se2conv_powers", "se2conv_sample_bumps", "se2conv_autotune", "se2conv_kernel_grad",
     "se2conv_fused_supported", "se2conv_field_spectra", "se2conv_apply_save", "se2conv_backward",
     "se2conv_status_string",
@@ -95,6 +95,7 @@ def load() -> ctypes.CDLL:
     lib.se2conv_apply_padded.argtypes = [vp, i32, vp, vp, i32, vp, i32, u32, vp]
     lib.se2conv_apply_complex.argtypes = [vp, i32, vp, vp, vp, i32, u32, vp]
     lib.se2conv_chain.argtypes = [vp, ctypes.POINTER(Problem), i32, u32, vp]
+    lib.se2conv_chain_noalloc.argtypes = [vp, ctypes.POINTER(Problem), i32, u32, vp]
     lib.se2conv_pass_times.argtypes = [vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(i32), i32,
                                        ctypes.POINTER(i32)]
     lib.se2conv_field_coeffs.argtypes = [vp, i32, vp, i32, vp, sz, vp]
@@ -114,7 +115,7 @@ def load() -> ctypes.CDLL:
     for name in ["se2conv_plan", "se2conv_plan_destroy", "se2conv_coeffs", "se2conv_coeffs_sum", "se2conv_table_info",
                  "se2conv_table_release", "se2conv_plan_counts", "se2conv_shift_table", "se2conv_apply_shifted",
                  "se2conv_apply", "se2conv_apply_padded", "se2conv_apply_complex", "se2conv_chain",
-                 "se2conv_pass_times",
+                 "se2conv_chain_noalloc", "se2conv_pass_times",
                  "se2conv_field_coeffs",
                  "se2conv_profile_grad", "se2conv_powers", "se2conv_sample_bumps", "se2conv_autotune",
                  "se2conv_kernel_grad", "se2conv_fused_supported", "se2conv_field_spectra", "se2conv_apply_save",

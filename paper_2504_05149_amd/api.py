@@ -376,6 +376,28 @@ class Plan:
         L.check(self._lib.se2conv_pass_times(self.handle, ms, kinds, cap, ctypes.byref(n)))
         return [(L.PASS_KINDS.get(kinds[i], str(kinds[i])), float(ms[i])) for i in range(min(n.value, cap))]
 
+    def chain_noalloc(self, problems, adjoint: bool = False, stream=None) -> None:
+        """se2conv_chain_noalloc: problems as for chain(), separable tables only; the item
+        lists go into the library's fixed device array (no device allocation)."""
+        arr, keep = self._problem_array(problems)
+        L.check(self._lib.se2conv_chain_noalloc(self.handle, arr, len(problems), L.ADJOINT if adjoint else 0,
+                                                _stream_handle(stream)))
+
+    def _problem_array(self, problems):
+        keep = []
+        arr = (L.Problem * len(problems))()
+        for i, (sidx, f, out, tabs) in enumerate(problems):
+            nx, ny, m = self.shapes[sidx]
+            tp = (ctypes.c_void_p * len(tabs))(*[t.ptr for t in tabs])
+            keep.append(tp)
+            arr[i].shape_idx = sidx
+            arr[i].batch = f.numel() // (nx * ny * m)
+            arr[i].f = f.data_ptr()
+            arr[i].out = out.data_ptr()
+            arr[i].tables = ctypes.cast(tp, ctypes.POINTER(ctypes.c_void_p))
+            arr[i].n_tables = len(tabs)
+        return arr, keep
+
     def chain(self, problems, adjoint: bool = False, graph: bool = False, stream=None,
               timing: bool = False) -> None:
         """problems: list of (shape_idx, f, out, [tables])."""

@@ -197,6 +197,51 @@ struct SubmissionRec {
     }
 };
 
+// Device scratch of se2conv_chain_noalloc: the per-field item lists (input, output,
+// table chain) of one call, written by fill_items_kernel from kernel arguments.  Every
+// device the library runs on holds one copy until the process ends.  In host code the
+// array's name is not a device address: kernels get the address that
+// hipGetSymbolAddress returned for the current device (noalloc_scratch_of).
+constexpr int kNoAllocMaxItems = 4096;
+static __device__ __align__(256) SepItem scratch[kNoAllocMaxItems];
+
+std::mutex g_scratch_mu;
+std::map<int, SepItem*> g_scratch_ptr;  // device -> address of that device's copy
+
+// Looks up the scratch's device address once per device, with that device current.
+se2conv_status noalloc_scratch_setup(int device) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch_ptr.count(device)) return SE2CONV_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+        return fail(SE2CONV_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", device,
+                    hipGetErrorString(e));
+    g_scratch_ptr[device] = reinterpret_cast<SepItem*>(ptr);
+    return SE2CONV_OK;
+}
+
+SepItem* noalloc_scratch_of(int device) {
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    return it == g_scratch_ptr.end() ? nullptr : it->second;
+}
+
+// Up to kFillBatch items travel by value in the kernel arguments (no host buffer, no
+// copy engine) and are stored at dst[first .. first + n).
+constexpr int kFillBatch = 32;
+struct ItemBatch {
+    SepItem it[kFillBatch];
+    int first;
+    int n;
+};
+static_assert(sizeof(ItemBatch) <= 4000, "kernel argument size");
+
+__global__ void fill_items_kernel(SepItem* dst, ItemBatch b) {
+    const int i = threadIdx.x;
+    if (i < b.n) dst[b.first + i] = b.it[i];
+}
+
 }  // namespace
 
 struct se2conv_plan_s {
@@ -1341,6 +1386,10 @@ se2conv_status se2conv_plan(const se2conv_shape* shapes, int32_t n_shapes, se2co
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
         return cleanup(fail(SE2CONV_ERR_DEVICE, "no HIP device available"));
     if (hipGetDevice(&p->device) != hipSuccess) return cleanup(fail(SE2CONV_ERR_DEVICE, "hipGetDevice failed"));
+    {
+        const se2conv_status sr = noalloc_scratch_setup(p->device);
+        if (sr != SE2CONV_OK) return cleanup(sr);
+    }
     if (hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
         p->num_cus < 1)
         return cleanup(fail(SE2CONV_ERR_DEVICE, "could not query the compute-unit count"));
@@ -2627,5 +2676,73 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
     return r == SE2CONV_OK ? ok() : r;
 }
 
+se2conv_status se2conv_chain_noalloc(se2conv_plan_t p, const se2conv_problem* probs, int32_t n_probs, uint32_t flags,
+                                     hipStream_t stream) {
+    if (!p) return fail(SE2CONV_ERR_INVALID_ARG, "plan is null");
+    if (!probs || n_probs < 1) return fail(SE2CONV_ERR_INVALID_ARG, "need at least one problem");
+    if (flags & ~SE2CONV_ADJOINT)
+        return fail(SE2CONV_ERR_INVALID_ARG, "se2conv_chain_noalloc takes only SE2CONV_ADJOINT (flags 0x%x)", flags);
+    std::map<int, std::vector<SepItem>> by_shape;
+    long long total = 0;
+    for (int i = 0; i < n_probs; ++i) {
+        const se2conv_problem& q = probs[i];
+        se2conv_status r = validate_io(p, q.shape_idx, q.f, q.out, q.batch);
+        if (r != SE2CONV_OK) return fail(r, "problem %d: %s", i, g_last_error.c_str());
+        if (!q.tables) return fail(SE2CONV_ERR_INVALID_ARG, "problem %d: tables is null", i);
+        Chain ch;
+        bool all_sep = true;
+        r = lookup_chain(p, q.shape_idx, q.tables, q.n_tables, &ch, &all_sep);
+        if (r != SE2CONV_OK) return fail(r, "problem %d: %s", i, g_last_error.c_str());
+        const se2conv_shape& s = p->shapes[q.shape_idx];
+        if (!all_sep || !pair_layout(s))
+            return fail(SE2CONV_ERR_INVALID_ARG,
+                        "problem %d: se2conv_chain_noalloc needs SEPARABLE tables on a shape with even Nx and Ny "
+                        "(use se2conv_chain)", i);
+        total += q.batch;
+        if (total > kNoAllocMaxItems)
+            return fail(SE2CONV_ERR_INVALID_ARG,
+                        "se2conv_chain_noalloc holds at most %d fields per call (problem %d brings the total to %lld)",
+                        kNoAllocMaxItems, i, total);
+        const long long n = (long long)s.nx * s.ny * s.m;
+        for (int b = 0; b < q.batch; ++b) {
+            SepItem it{};
+            it.in = (const char*)q.f + real_bytes(p) * n * b;
+            it.out = (char*)q.out + real_bytes(p) * n * b;
+            it.ntab = q.n_tables;
+            for (int j = 0; j < q.n_tables; ++j) it.tab[j] = q.tables[j];
+            by_shape[q.shape_idx].push_back(it);
+        }
+    }
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    int cur = -1;
+    HIPCHK(hipGetDevice(&cur));
+    if (cur != p->device)
+        return fail(SE2CONV_ERR_INVALID_ARG, "the plan's device (%d) must be current (current: %d)", p->device, cur);
+    SepItem* sp = noalloc_scratch_of(p->device);
+    if (!sp) return fail(SE2CONV_ERR_INTERNAL, "no scratch address for device %d", p->device);
+    const bool conj = (flags & SE2CONV_ADJOINT) != 0;
+    // write every group's items into the scratch, then run each group's passes on them
+    int first = 0;
+    for (auto& kv : by_shape) {
+        const std::vector<SepItem>& v = kv.second;
+        for (int k = 0; k < (int)v.size(); k += kFillBatch) {
+            ItemBatch b{};
+            b.first = first + k;
+            b.n = std::min(kFillBatch, (int)v.size() - k);
+            for (int j = 0; j < b.n; ++j) b.it[j] = v[k + j];
+            hipLaunchKernelGGL(fill_items_kernel, dim3(1), dim3(kFillBatch), 0, stream, sp, b);
+            HIPCHK(hipGetLastError());
+        }
+        first += (int)v.size();
+    }
+    first = 0;
+    for (auto& kv : by_shape) {
+        const int cnt = (int)kv.second.size();
+        se2conv_status r = enqueue_sep_items(p, p->shapes[kv.first], sp + first, cnt, conj, stream);
+        if (r != SE2CONV_OK) return r;
+        first += cnt;
+    }
+    return ok();
+}
 
 }  // extern "C"
