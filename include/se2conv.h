@@ -81,7 +81,8 @@ typedef struct {
 se2conv_status se2conv_plan(const se2conv_shape* shapes, int32_t n_shapes, se2conv_dtype dtype, uint32_t flags,
                             se2conv_plan_t* out);
 
-/* Release a plan and its device resources (synchronises the plan's device). */
+/* Release a plan and its device resources (synchronises the plan's device).  Resource
+ * management of this library; it computes nothing of the paper's method. */
 se2conv_status se2conv_plan_destroy(se2conv_plan_t plan);
 
 /* ---- kernels rho (radial in translations, Sec. 5.1 footnote to Thm. f*gP) */
@@ -374,7 +375,9 @@ se2conv_status se2conv_backward(se2conv_plan_t plan, int32_t shape_idx, const vo
                                 const void* d_spectra, int32_t batch, void* d_grad_f, void* d_grad_p,
                                 hipStream_t stream);
 
-/* One problem of a heterogeneous submission: out = Re S_K[f, tables[0] * ... ]. */
+/* One problem of a heterogeneous submission: out = Re S_K[f, tables[0] * ... ], the chain form
+ * f * rho_1 * ... * rho_q of Sec. 6.3 (Algorithm 4, eq. (MatSqKfgG) with distinct kernels: the
+ * coefficients of the kernels multiply, Thm. f*gP (2)). */
 typedef struct {
     int32_t shape_idx;
     int32_t batch;
@@ -476,7 +479,7 @@ se2conv_status se2conv_sample_bumps(se2conv_plan_t plan, int32_t shape_idx, cons
 se2conv_status se2conv_powers(se2conv_plan_t plan, int32_t shape_idx, const void* d_f, const void* d_table,
                               int32_t q, void* d_out, int32_t batch, uint32_t flags, hipStream_t stream);
 
-/* Static description of a status code. */
+/* Static description of a status code (error reporting of this library; no passage of the paper). */
 const char* se2conv_status_string(se2conv_status s);
 /* Message of the last error on the calling thread ("" if none). */
 const char* se2conv_last_error(void);
