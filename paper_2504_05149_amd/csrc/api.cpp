@@ -515,8 +515,13 @@ hipError_t run_slab(SlabArgs a, bool d, hipStream_t st) {
 
 hipError_t run_pencil(PencilArgs a, bool d, hipStream_t st) {
     const long long P = (long long)a.p.L * a.W;
-    const int nthr = threads_for(P, d, odd_len(a.p.L));
-    if (P > (long long)maxv(d, odd_len(a.p.L)) * nthr) return hipErrorInvalidConfiguration;
+    const bool odd = odd_len(a.p.L);
+    // the shift-mix pencils hold fewer values per thread (SE2C_MAXV_SHIFT)
+    const int mv = a.mul == 3 && !odd ? SE2C_MAXV_SHIFT : maxv(d, odd);
+    long long nt = (P + mv - 1) / mv;
+    nt = std::max<long long>(64, (nt + 63) / 64 * 64);
+    const int nthr = (int)std::min<long long>(nt, a.mul == 3 ? 512 : max_threads(d, odd));
+    if (P > (long long)mv * nthr) return hipErrorInvalidConfiguration;
     const int ncol_tiles = (a.ncols + a.W - 1) / a.W;
     const int nother = a.axis == 1 ? a.m : a.ny;
     const long long ntiles = (long long)ncol_tiles * nother * a.nitems;
@@ -615,13 +620,8 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
         // Fields per launch pair (the whole batch unless SE2CONV_SEP_CHUNK says
         // otherwise; see sep_chunk_fields).
         const int chunk = sep_chunk_fields(p, s, batch);
-        static const int mid_cached = [] {
-            const char* e = std::getenv("SE2CONV_MID_CACHED");
-            return e ? std::atoi(e) : 0;
-        }();
         for (int c0 = 0; c0 < batch; c0 += chunk) {
             FastSepArgs ca = fa;
-            ca.mid_cached = mid_cached;
             ca.in = reinterpret_cast<const float*>(f) + (long long)c0 * n;
             ca.out = reinterpret_cast<float*>(out) + (long long)c0 * n;
             ca.nitems = std::min(chunk, batch - c0);
@@ -1105,6 +1105,8 @@ se2conv_status enqueue_shifted(se2conv_plan_s* p, const se2conv_shape& s, const 
     b.m = s.m;
     b.ncols = s.nx;
     b.W = pencil_width(b.ncols, s.m, d, sched_of(p, s).pencil_w);
+    if (!odd_len(s.m))  // the shift-mix pencils hold SE2C_MAXV_SHIFT values per thread
+        while (b.W > 1 && (long long)b.W * s.m > (long long)SE2C_MAXV_SHIFT * 512) b.W /= 2;
     b.fwd = 1;
     b.inv = 1;
     b.mul = 3;

@@ -212,8 +212,10 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) slab_kernel(S
 }
 
 // -------------------------------------------------------------- pencil pass
-template <typename T, int MAXV, bool ODD>
-__global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) pencil_kernel(PencilArgs a) {
+// SHIFT: the instantiation that also carries the shift mix (mul == 3), kept apart so
+// that the other pencils keep their register allocation.
+template <typename T, int MAXV, bool ODD, bool SHIFT = false>
+__global__ void __launch_bounds__((ODD || SHIFT) ? 512 : SE2C_MAX_THREADS(T)) pencil_kernel(PencilArgs a) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C<T>* tile = reinterpret_cast<C<T>*>(smem_raw);
     const int L = a.p.L;
@@ -320,7 +322,7 @@ __global__ void __launch_bounds__(ODD ? 512 : SE2C_MAX_THREADS(T)) pencil_kernel
         }
         __syncthreads();
 
-        if (a.mul == 3) {
+        if (SHIFT && a.mul == 3) {
             // shift mix (theta lines: e = alpha, other = k2, column c0 + c = k1):
             // z'[alpha] = sum_j z[alpha - r_j] Q_j[alpha - r_j][k2][k1], indices mod M
             const C<T>* q = reinterpret_cast<const C<T>*>(a.qtab);
@@ -450,9 +452,9 @@ static hipError_t launch_slab_t(const SlabArgs& a, int nthr, int nblocks, size_t
     return hipGetLastError();
 }
 
-template <typename T, int MAXV, bool ODD>
+template <typename T, int MAXV, bool ODD, bool SHIFT = false>
 static hipError_t launch_pencil_t(const PencilArgs& a, int nthr, int nblocks, size_t lds, hipStream_t s) {
-    hipLaunchKernelGGL((pencil_kernel<T, MAXV, ODD>), dim3(nblocks), dim3(nthr), lds, s, a);
+    hipLaunchKernelGGL((pencil_kernel<T, MAXV, ODD, SHIFT>), dim3(nblocks), dim3(nthr), lds, s, a);
     return hipGetLastError();
 }
 
@@ -476,7 +478,11 @@ hipError_t prepare_generic_kernels() {
                          reinterpret_cast<const void*>(slab_kernel<float, SE2C_MAXV_ODD, true>),
                          reinterpret_cast<const void*>(slab_kernel<double, SE2C_MAXV_ODD, true>),
                          reinterpret_cast<const void*>(pencil_kernel<float, SE2C_MAXV_ODD, true>),
-                         reinterpret_cast<const void*>(pencil_kernel<double, SE2C_MAXV_ODD, true>)};
+                         reinterpret_cast<const void*>(pencil_kernel<double, SE2C_MAXV_ODD, true>),
+                         reinterpret_cast<const void*>(pencil_kernel<float, SE2C_MAXV_SHIFT, false, true>),
+                         reinterpret_cast<const void*>(pencil_kernel<double, SE2C_MAXV_SHIFT, false, true>),
+                         reinterpret_cast<const void*>(pencil_kernel<float, SE2C_MAXV_ODD, true, true>),
+                         reinterpret_cast<const void*>(pencil_kernel<double, SE2C_MAXV_ODD, true, true>)};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
@@ -508,6 +514,14 @@ hipError_t launch_slab(const SlabArgs& a, bool dbl, int nthr, int nblocks, hipSt
 
 hipError_t launch_pencil(const PencilArgs& a, bool dbl, int nthr, int nblocks, hipStream_t s) {
     const size_t lds = pencil_lds_bytes(a, dbl);
+    if (a.mul == 3) {
+        if (needs_odd_stages(a.p)) {
+            if (dbl) return launch_pencil_t<double, SE2C_MAXV_ODD, true, true>(a, nthr, nblocks, lds, s);
+            return launch_pencil_t<float, SE2C_MAXV_ODD, true, true>(a, nthr, nblocks, lds, s);
+        }
+        if (dbl) return launch_pencil_t<double, SE2C_MAXV_SHIFT, false, true>(a, nthr, nblocks, lds, s);
+        return launch_pencil_t<float, SE2C_MAXV_SHIFT, false, true>(a, nthr, nblocks, lds, s);
+    }
     if (needs_odd_stages(a.p)) {
         if (dbl) return launch_pencil_t<double, SE2C_MAXV_ODD, true>(a, nthr, nblocks, lds, s);
         return launch_pencil_t<float, SE2C_MAXV_ODD, true>(a, nthr, nblocks, lds, s);

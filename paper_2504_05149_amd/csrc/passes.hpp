@@ -17,6 +17,11 @@
 #ifndef SE2C_MAXV_F64
 #define SE2C_MAXV_F64 8
 #endif
+// The same for the pencils that carry the shift mix (they hold a second copy of their
+// values while the mix reads rolled neighbours).
+#ifndef SE2C_MAXV_SHIFT
+#define SE2C_MAXV_SHIFT 8
+#endif
 // Tile elements per thread whose HBM reads are in flight together when a tile is
 // loaded or stored.
 #ifndef SE2C_STAGE

@@ -23,7 +23,6 @@ struct FastSepArgs {
     int cus;           // compute units of the device
     int axis;          // pencil kernel: 1 = lines along y, 2 = lines along theta
     const SepItem* items;  // device; non-null: field i is items[i] (own input, output and tables)
-    int mid_cached;    // slab pass: store the intermediate with ordinary (cache-allocating) stores
 };
 
 bool slab_fast_supported(int nx, int m);
