@@ -1039,6 +1039,55 @@ se2conv_status enqueue_full(se2conv_plan_s* p, const se2conv_shape& s, const voi
     return SE2CONV_OK;
 }
 
+// Every shape class of a grouped item list in one launch per pass (the multi-class
+// register kernels), when every class has them; *done tells whether it ran.  Classes go
+// largest first, so that the last workgroups of the grid are the small ones.
+se2conv_status enqueue_multi(se2conv_plan_s* p, const SepItem* d_items, const std::vector<std::pair<int, int>>& groups,
+                             const std::vector<int>& counts, bool conj, hipStream_t st, bool* done) {
+    *done = false;
+    static const bool enabled = [] {
+        const char* e = std::getenv("SE2CONV_CHAIN_MULTI");
+        return !(e && std::atoi(e) == 0);
+    }();
+    const int ng = (int)groups.size();
+    if (!enabled || dbl(p) || (p->flags & SE2CONV_PLAN_GENERIC) || ng < 1 || ng > SE2C_MAX_CLASSES) return SE2CONV_OK;
+    for (int gi = 0; gi < ng; ++gi) {
+        const se2conv_shape& s = p->shapes[groups[gi].first];
+        if (!slab_fits(s, false) || !multi_slab_supported(s.nx, s.m) || !multi_pencil_supported(s.nx, s.ny))
+            return SE2CONV_OK;
+    }
+    std::vector<int> order(ng);
+    for (int gi = 0; gi < ng; ++gi) order[gi] = gi;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        const se2conv_shape& sa = p->shapes[groups[a].first];
+        const se2conv_shape& sb = p->shapes[groups[b].first];
+        return (long long)sa.nx * sa.ny * sa.m * counts[a] > (long long)sb.nx * sb.ny * sb.m * counts[b];
+    });
+    MultiArgs m{};
+    m.items = d_items;
+    m.conj_tab = conj ? 1 : 0;
+    m.nclass = ng;
+    for (int k = 0; k < ng; ++k) {
+        const int gi = order[k];
+        const se2conv_shape& s = p->shapes[groups[gi].first];
+        MultiClass& c = m.c[k];
+        c.nx = s.nx;
+        c.ny = s.ny;
+        c.m = s.m;
+        c.nitems = counts[gi];
+        c.item0 = groups[gi].second;
+        c.twx = reinterpret_cast<const float2*>(tw_of(p, s.nx, false));
+        c.twy = reinterpret_cast<const float2*>(tw_of(p, s.ny, false));
+        c.twt = reinterpret_cast<const float2*>(tw_of(p, s.m, false));
+    }
+    HIPCHK(launch_slab_multi(m, st));
+    HIPCHK(after_pass(0, st));
+    HIPCHK(launch_pencil_multi(m, st));
+    HIPCHK(after_pass(1, st));
+    *done = true;
+    return SE2CONV_OK;
+}
+
 // x lines only (forward or inverse) on plane pairs, theta chunks as in the x-row pass.
 hipError_t x_pass(se2conv_plan_s* p, const se2conv_shape& s, bool d, int dir, const void* in0, const void* in1,
                   void* out0, void* out1, const void* lone_in1, void* lone_out1, long long stride, int nitems,
@@ -2597,10 +2646,14 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
                 HIPCHK(hipStreamWaitEvent(stream, p->ev_join[k], 0));
             }
         } else {
-            for (int gi = 0; gi < ngroups; ++gi) {
+            bool multi = false;
+            se2conv_status r = enqueue_multi(p, reinterpret_cast<const SepItem*>(rec->d_items), rec->groups,
+                                             rec->group_counts, conj, stream, &multi);
+            if (r != SE2CONV_OK) return r;
+            for (int gi = 0; !multi && gi < ngroups; ++gi) {
                 const int sidx = rec->groups[gi].first;
                 const SepItem* items = reinterpret_cast<const SepItem*>(rec->d_items) + rec->groups[gi].second;
-                se2conv_status r = enqueue_sep_items(p, p->shapes[sidx], items, rec->group_counts[gi], conj, stream);
+                r = enqueue_sep_items(p, p->shapes[sidx], items, rec->group_counts[gi], conj, stream);
                 if (r != SE2CONV_OK) return r;
             }
         }
@@ -2737,12 +2790,21 @@ se2conv_status se2conv_chain_noalloc(se2conv_plan_t p, const se2conv_problem* pr
         }
         first += (int)v.size();
     }
+    std::vector<std::pair<int, int>> groups;
+    std::vector<int> counts;
     first = 0;
     for (auto& kv : by_shape) {
-        const int cnt = (int)kv.second.size();
-        se2conv_status r = enqueue_sep_items(p, p->shapes[kv.first], sp + first, cnt, conj, stream);
+        groups.push_back({kv.first, first});
+        counts.push_back((int)kv.second.size());
+        first += (int)kv.second.size();
+    }
+    bool multi = false;
+    se2conv_status mr = enqueue_multi(p, sp, groups, counts, conj, stream, &multi);
+    if (mr != SE2CONV_OK) return mr;
+    for (size_t gi = 0; !multi && gi < groups.size(); ++gi) {
+        se2conv_status r = enqueue_sep_items(p, p->shapes[groups[gi].first], sp + groups[gi].second, counts[gi], conj,
+                                             stream);
         if (r != SE2CONV_OK) return r;
-        first += cnt;
     }
     return ok();
 }

@@ -39,6 +39,16 @@ __device__ __forceinline__ float2 chain_factor(const void* const* tabs, int ntab
     return v;
 }
 
+// The same, with the tables given by an accessor tab(j) -> const float2* (no local array
+// of table pointers, which a dynamic index would place in scratch memory).
+template <typename F>
+__device__ __forceinline__ float2 chain_factor_of(F tab, int ntab, int i, float scale, int conj) {
+    float2 v = make_float2(scale, 0.f);
+    for (int j = 0; j < ntab; ++j) v = mul<float>(v, tab(j)[i]);
+    if (conj) v.y = -v.y;
+    return v;
+}
+
 // Swap a value with the neighbouring lane (lane ^ 1) through DPP quad_perm [1,0,3,2].
 __device__ __forceinline__ float swap_lane1(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));

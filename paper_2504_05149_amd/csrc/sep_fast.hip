@@ -40,13 +40,13 @@ namespace se2c {
 // wavefronts) idle during the x phase.
 constexpr int pow2_floor(int v) { return v >= 32 ? 32 : v >= 16 ? 16 : v >= 8 ? 8 : v >= 4 ? 4 : v >= 2 ? 2 : 1; }
 
-template <int NX, int M> struct SlabGeom {
+template <int NX, int M, int RCX = (M < 32 ? M : 32)> struct SlabGeom {
     static constexpr int TPC = M == 64 ? 2 : 1;
     static constexpr int NT = NX * TPC;
     static constexpr int R1 = (NX % 3 == 0) ? NX / 4 : 16;
     static constexpr int R2 = NX / R1;
     static constexpr int CC = R1 / R2;
-    static constexpr int RC = M < 32 ? M : 32;        // rows per transpose chunk
+    static constexpr int RC = RCX;                     // rows per transpose chunk
     static constexpr int H = M / RC;
     static constexpr int G = pow2_floor(NT / R2 < RC ? NT / R2 : RC);  // rows per x round
     static constexpr int RPT = M / G;                  // theta rows per thread in row layout
@@ -55,93 +55,120 @@ template <int NX, int M> struct SlabGeom {
     // two row groups of a half-wave never share a bank
     static constexpr int P = NX + (R2 == 16 ? 16 : R2 % 16);
     static constexpr int MV = M / TPC;                 // theta values per thread in column layout
-    static_assert(R1 * R2 == NX && CC * R2 == R1 && M % G == 0 && XT <= NT && XT % 32 == 0, "slab geometry");
+    static constexpr size_t LDS = sizeof(float2) * ((size_t)RC * P + 3 * NX + 2 * M);
+    static_assert(R1 * R2 == NX && CC * R2 == R1 && M % G == 0 && M % RC == 0 && XT <= NT && XT % 16 == 0,
+                  "slab geometry");
 };
 
-template <int NX, int M>
-__global__ void __launch_bounds__((SlabGeom<NX, M>::NT))
-__attribute__((amdgpu_waves_per_eu(SlabGeom<NX, M>::NT >= 512 ? 4 : (SlabGeom<NX, M>::NT >= 256 ? 2 : 1))))
-xt_slab_fast(FastSepArgs a) {
-    // Wave priority: high while a wave issues its HBM loads and stores, low during the
-    // arithmetic, so that a workgroup starting its memory phase is not held behind the
-    // other workgroup's arithmetic on the same CU (measured 128 -> 118-122 us at
-    // 256 x 256 x 64 x 16 fields).
-    __builtin_amdgcn_s_setprio(2);
-    using Gm = SlabGeom<NX, M>;
+// One y-pair slab (rows 2s and 2s+1 of field `item`, packed as re/im) by the NT threads
+// tid = 0 .. NT-1 of a workgroup, in the LDS region smem of Gm::LDS bytes.  Threads of a
+// slab that is not `active` (the tail of a multi-class launch, or lanes beyond the last
+// slab of a workgroup) take part in every barrier with the others but read and write no
+// global memory and write no LDS; their LDS reads stay inside smem.
+// ACC: the fields are always items (a.items) and their tables are read through an
+// accessor (the multi-class launches); otherwise a.items may be null (then the launch's
+// fields are a.in / a.out with one chain in the argument block) and the chain's table
+// pointers are copied into a local array.
+template <int NX, int M, int RCX, bool ACC>
+__device__ __forceinline__ void slab_body(const FastSepArgs& a, int ny, int item, int s, bool active, int tid,
+                                          unsigned char* smem) {
+    using Gm = SlabGeom<NX, M, RCX>;
     constexpr int TPC = Gm::TPC, NT = Gm::NT, R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC, G = Gm::G, RPT = Gm::RPT,
                   RC = Gm::RC, H = Gm::H, P = Gm::P, MV = Gm::MV, XT = Gm::XT;
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    float2* buf = reinterpret_cast<float2*>(smem_raw);  // RC x P
+    float2* buf = reinterpret_cast<float2*>(smem);       // RC x P
     float2* tw_f = buf + RC * P;                         // [k1][t] = w_NX^{t k1}
     float2* tw_i = tw_f + NX;                            // [t][k1]
     float2* fx = tw_i + NX;                              // Tx / NX
     float2* ft = fx + NX;                                // Tt / M (TPC == 1)
     float4* cm = reinterpret_cast<float4*>(ft);          // [hh][k] = (S_k, E_hh,k) (TPC == 2)
-    const int tid = threadIdx.x;
 
-    const int nslab = a.ny / 2;
-    const int tile = blockIdx.x;  // one y-pair slab per block
-    const int item = tile / nslab;
-    const int s = tile - item * nslab;
-    const long long plane = (long long)NX * a.ny;
+    const long long plane = (long long)NX * ny;
     const int pl = (int)plane;
     // the field's input, output and table chain (shared by the launch, or per item)
-    const float* fin;
-    float* fout;
+    const float* fin = nullptr;
+    float* fout = nullptr;
+    const SepItem* it = a.items + item;
+    // the chain's x and theta factors (a SEPARABLE table is Tx | Ty | Tt)
     const void* tx[SE2C_MAX_TABLES];
     const void* tt[SE2C_MAX_TABLES];
-    int ntab;
-    if (a.items) {
-        const SepItem& it = a.items[item];
-        fin = reinterpret_cast<const float*>(it.in);
-        fout = reinterpret_cast<float*>(it.out);
-        ntab = it.ntab;
-        for (int j = 0; j < ntab; ++j) {
-            tx[j] = it.tab[j];
-            tt[j] = reinterpret_cast<const float2*>(it.tab[j]) + NX + a.ny;
+    int ntab = 0;
+    if constexpr (!ACC) {
+        if (!active) {
+        } else if (a.items) {
+            fin = reinterpret_cast<const float*>(it->in);
+            fout = reinterpret_cast<float*>(it->out);
+            ntab = it->ntab;
+            for (int j = 0; j < ntab; ++j) {
+                tx[j] = it->tab[j];
+                tt[j] = reinterpret_cast<const float2*>(it->tab[j]) + NX + ny;
+            }
+        } else {
+            fin = a.in + (long long)item * a.n;
+            fout = a.out + (long long)item * a.n;
+            ntab = a.ntab;
+            for (int j = 0; j < ntab; ++j) {
+                tx[j] = a.tx[j];
+                tt[j] = a.tt[j];
+            }
         }
-    } else {
-        fin = a.in + (long long)item * a.n;
-        fout = a.out + (long long)item * a.n;
-        ntab = a.ntab;
-        for (int j = 0; j < ntab; ++j) {
-            tx[j] = a.tx[j];
-            tt[j] = a.tt[j];
+    } else if (active) {
+        fin = reinterpret_cast<const float*>(it->in);
+        fout = reinterpret_cast<float*>(it->out);
+    }
+    auto chain_x = [&](int i, float sc) {
+        if constexpr (ACC)
+            return chain_factor_of([&](int j) { return reinterpret_cast<const float2*>(it->tab[j]); }, it->ntab, i, sc,
+                                   a.conj_tab);
+        else
+            return chain_factor(tx, ntab, i, sc, a.conj_tab);
+    };
+    auto chain_t = [&](int i, float sc) {
+        if constexpr (ACC)
+            return chain_factor_of([&](int j) { return reinterpret_cast<const float2*>(it->tab[j]) + NX + ny; },
+                                   it->ntab, i, sc, a.conj_tab);
+        else
+            return chain_factor(tt, ntab, i, sc, a.conj_tab);
+    };
+    if (active) {
+        for (int i = tid; i < NX; i += NT) {
+            const int k1 = i / R2, t = i - k1 * R2;
+            const float2 w = a.tw[t * k1];
+            tw_f[k1 * R2 + t] = w;
+            tw_i[t * R1 + k1] = w;
         }
-    }
-    for (int i = tid; i < NX; i += NT) {
-        const int k1 = i / R2, t = i - k1 * R2;
-        const float2 w = a.tw[t * k1];
-        tw_f[k1 * R2 + t] = w;
-        tw_i[t * R1 + k1] = w;
-    }
-    for (int i = tid; i < NX; i += NT) fx[i] = chain_factor(tx, ntab, i, 1.0f / NX, a.conj_tab);
-    if constexpr (TPC == 1) {
-        for (int i = tid; i < M; i += NT) ft[i] = chain_factor(tt, ntab, i, 1.0f / M, a.conj_tab);
-    } else {
-        // the radix-2 step across the lane pair, the product with Tt and the inverse
-        // radix-2 step fold into one 2 x 2 matrix per k < M/2 (see the column phase)
-        for (int k = tid; k < MV; k += NT) {
-            const float2 f0 = chain_factor(tt, ntab, k, 1.0f / M, a.conj_tab);
-            const float2 f1 = chain_factor(tt, ntab, k + MV, 1.0f / M, a.conj_tab);
-            const float2 sk = add<float>(f0, f1), dk = sub<float>(f0, f1);
-            const float2 b = a.twt[k];  // w_M^k
-            const float2 e0 = mul<float>(b, dk), e1 = mulc<float>(dk, b);
-            cm[k] = make_float4(sk.x, sk.y, e0.x, e0.y);
-            cm[MV + k] = make_float4(sk.x, sk.y, e1.x, e1.y);
+        for (int i = tid; i < NX; i += NT) fx[i] = chain_x(i, 1.0f / NX);
+        if constexpr (TPC == 1) {
+            for (int i = tid; i < M; i += NT) ft[i] = chain_t(i, 1.0f / M);
+        } else {
+            // the radix-2 step across the lane pair, the product with Tt and the inverse
+            // radix-2 step fold into one 2 x 2 matrix per k < M/2 (see the column phase)
+            for (int k = tid; k < MV; k += NT) {
+                const float2 f0 = chain_t(k, 1.0f / M);
+                const float2 f1 = chain_t(k + MV, 1.0f / M);
+                const float2 sk = add<float>(f0, f1), dk = sub<float>(f0, f1);
+                const float2 b = a.twt[k];  // w_M^k
+                const float2 e0 = mul<float>(b, dk), e1 = mulc<float>(dk, b);
+                cm[k] = make_float4(sk.x, sk.y, e0.x, e0.y);
+                cm[MV + k] = make_float4(sk.x, sk.y, e1.x, e1.y);
+            }
         }
     }
     __syncthreads();
 
     const int t = tid % R2, g = tid / R2;
     const bool xlane = XT == NT || tid < XT;   // takes part in the x phase (lanes from XT on idle)
+    const bool xw = xlane && active;           // ... and writes
     // uniform tile base; per-lane offsets stay 32-bit (Nx Ny M < 2^30 is checked on the host)
     const float* __restrict__ in0 = fin + (long long)(2 * s) * NX;
     const float* __restrict__ in1 = in0 + NX;
 
     // 1. row-layout loads: rows theta = g + G i, columns x = t + R2 r
     float2 w[RPT][R1];
-    if (xlane) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i)
+#pragma unroll
+        for (int r = 0; r < R1; ++r) w[i][r] = make_float2(0.f, 0.f);
+    if (xw) {
 #pragma unroll
         for (int i = 0; i < RPT; ++i) {
 #pragma unroll
@@ -165,7 +192,7 @@ xt_slab_fast(FastSepArgs a) {
 #pragma unroll
     for (int i = 0; i < RPT; ++i) {
         if (i > 0) __syncthreads();
-        if (xlane) {
+        if (xw) {
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) row[xpos_line<R1, R2>(k1, t)] = w[i][k1];
         }
@@ -186,7 +213,7 @@ xt_slab_fast(FastSepArgs a) {
             }
         }
         __syncthreads();
-        if (xlane) {
+        if (xw) {
 #pragma unroll
             for (int j = 0; j < CC; ++j) {
 #pragma unroll
@@ -207,7 +234,7 @@ xt_slab_fast(FastSepArgs a) {
 #pragma unroll
     for (int h = 0; h < H; ++h) {
         __syncthreads();
-        if (xlane) {
+        if (xw) {
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
                 if (G * i >= h * RC && G * i < (h + 1) * RC) {
@@ -246,6 +273,7 @@ xt_slab_fast(FastSepArgs a) {
         RegDFT<MV, true, float>::run(v);
     }
     // 5. store columns
+    if (!active) return;
     float* __restrict__ out0 = fout + (long long)(2 * s) * NX;
     float* __restrict__ out1 = out0 + NX;
     __builtin_amdgcn_s_setprio(2);
@@ -255,6 +283,21 @@ xt_slab_fast(FastSepArgs a) {
         __builtin_nontemporal_store(v[l].x, out0 + off);
         __builtin_nontemporal_store(v[l].y, out1 + off);
     }
+}
+
+template <int NX, int M>
+__global__ void __launch_bounds__((SlabGeom<NX, M>::NT))
+__attribute__((amdgpu_waves_per_eu(SlabGeom<NX, M>::NT >= 512 ? 4 : (SlabGeom<NX, M>::NT >= 256 ? 2 : 1))))
+xt_slab_fast(FastSepArgs a) {
+    // Wave priority: high while a wave issues its HBM loads and stores, low during the
+    // arithmetic, so that a workgroup starting its memory phase is not held behind the
+    // other workgroup's arithmetic on the same CU (measured 128 -> 118-122 us at
+    // 256 x 256 x 64 x 16 fields).
+    __builtin_amdgcn_s_setprio(2);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int nslab = a.ny / 2;
+    const int item = blockIdx.x / nslab;  // one y-pair slab per block
+    slab_body<NX, M, SlabGeom<NX, M>::RC, false>(a, a.ny, item, blockIdx.x - item * nslab, true, threadIdx.x, smem_raw);
 }
 
 // Line pencils: W = 16 adjacent x-pairs (float2 columns) x L points along y
@@ -502,11 +545,291 @@ __global__ void __launch_bounds__(RowGeom<NX>::NT) x_rows_fast(FastSepArgs a) {
     }
 }
 
+// ------------------------------------------------- multi-class launches (uneven batches)
+// One launch per pass covers every shape class of a heterogeneous submission: a
+// workgroup of 256 threads takes S = 256 / NT slabs (or pencil tiles) of one class side
+// by side, each in its own LDS region; the classes are laid end to end over the grid, so
+// small classes no longer run alone.  The transpose chunk is 16 rows wherever the x
+// rounds need no more, which keeps every class within about 45 KB of LDS per workgroup.
+template <int NX, int M> struct MultiSlab {
+    static constexpr int NT0 = NX * (M == 64 ? 2 : 1);
+    static constexpr int R20 = NX / ((NX % 3 == 0) ? NX / 4 : 16);
+    static constexpr int RC = (M < 32 || NT0 / R20 <= 16) ? 16 : 32;
+    using Gm = SlabGeom<NX, M, RC>;
+    static constexpr int S = SE2C_MULTI_THREADS / Gm::NT;
+    static constexpr size_t REGION = (Gm::LDS + 15) / 16 * 16;
+    static constexpr size_t LDS = REGION * S;
+};
+
+template <int NX, int M>
+__device__ __forceinline__ void slab_class(const MultiArgs& m, const MultiClass& c, int lb, unsigned char* smem) {
+    using MS = MultiSlab<NX, M>;
+    constexpr int NT = MS::Gm::NT, S = MS::S;
+    const int sub_raw = threadIdx.x / NT;
+    const int sub = sub_raw < S ? sub_raw : S - 1;   // lanes beyond S shadow the last slab
+    const int tid = threadIdx.x - sub_raw * NT;
+    const int nslab = c.ny / 2;
+    const int unit = lb * S + sub;
+    const bool active = sub_raw < S && unit < c.nitems * nslab;
+    const int item = active ? unit / nslab : 0;
+    FastSepArgs a{};
+    a.items = m.items + c.item0;
+    a.tw = c.tw;
+    a.twt = c.twt;
+    a.conj_tab = m.conj_tab;
+    slab_body<NX, M, MS::RC, true>(a, c.ny, item, unit - item * nslab, active, tid, smem + (size_t)sub * MS::REGION);
+}
+
+#ifndef SE2C_MULTI_SLABS
+#define SE2C_MULTI_SLABS(X) \
+    X(32, 16) X(32, 32) X(32, 64) X(48, 16) X(48, 32) X(48, 64) X(64, 16) X(64, 32) X(64, 64) \
+    X(96, 16) X(96, 32) X(96, 64) X(128, 16) X(128, 32) X(128, 64) X(256, 16) X(256, 32)
+#endif
+
+__global__ void __launch_bounds__(SE2C_MULTI_THREADS) xt_slab_multi(MultiArgs m) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __builtin_amdgcn_s_setprio(2);
+    int ci = 0;
+    for (int k = 1; k < m.nclass; ++k)
+        if ((int)blockIdx.x >= m.c[k].first_block) ci = k;
+    const MultiClass& c = m.c[ci];
+    const int lb = blockIdx.x - c.first_block;
+    switch (c.code) {
+#define SE2C_X(NX_, M_) \
+    case NX_ * 1024 + M_: slab_class<NX_, M_>(m, c, lb, smem_raw); break;
+        SE2C_MULTI_SLABS(SE2C_X)
+#undef SE2C_X
+        default: break;
+    }
+}
+
+// One pencil tile (W adjacent x-pairs x L points along y at theta = o, columns from
+// ct * W) of field `item`, in place on the item's output, by threads tid < NT.
+template <int L, int WW>
+__device__ __forceinline__ void pencil_tile(const FastSepArgs& a, int nx, int ny, int item, int o, int ct, bool active,
+                                            int tid, unsigned char* smem) {
+    using Gm = LineGeom<L, WW>;
+    constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC, W = Gm::W;
+    float2* buf = reinterpret_cast<float2*>(smem);  // [k1*R2 + t][W]
+    float2* tw_f = buf + L * W;                      // [k1][t] = w_L^{t k1}
+    float2* tw_i = tw_f + L;                         // [t][k1]
+    float2* fl = tw_i + L;                           // line factor / L
+    const int ncols = nx / 2;
+    const int q = tid % W, t = tid / W;
+    float2* base = nullptr;
+    if (active) {
+        const SepItem& it = a.items[item];
+        base = reinterpret_cast<float2*>(it.out) + (long long)o * ncols * ny + ct * W;
+        auto ty = [&](int j) { return reinterpret_cast<const float2*>(it.tab[j]) + nx; };
+        for (int i = tid; i < L; i += Gm::NT) {
+            const int k1 = i / R2, tt = i - k1 * R2;
+            const float2 w = a.tw[tt * k1];
+            tw_f[k1 * R2 + tt] = w;
+            tw_i[tt * R1 + k1] = w;
+            fl[i] = chain_factor_of(ty, it.ntab, i, 1.0f / L, a.conj_tab);
+        }
+    }
+    const int lane_off = q + t * ncols;
+    const int rstride = R2 * ncols;
+    float2 w[R1];
+#pragma unroll
+    for (int r = 0; r < R1; ++r) w[r] = make_float2(0.f, 0.f);
+    if (active) {
+#pragma unroll
+        for (int r = 0; r < R1; ++r) w[r] = (base + r * rstride)[lane_off];
+    }
+    __builtin_amdgcn_s_setprio(0);
+    __syncthreads();
+    RegDFT<R1, false, float>::run(w);
+#pragma unroll
+    for (int k1 = 1; k1 < R1; ++k1) w[k1] = mul<float>(w[k1], tw_f[k1 * R2 + t]);
+    if (active) {
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) buf[(k1 * R2 + t) * W + q] = w[k1];
+    }
+    __syncthreads();
+    float2 u[CC][R2];
+#pragma unroll
+    for (int j = 0; j < CC; ++j) {
+        const int k1 = CC * t + j;
+#pragma unroll
+        for (int tt = 0; tt < R2; ++tt) u[j][tt] = buf[(k1 * R2 + tt) * W + q];
+        RegDFT<R2, false, float>::run(u[j]);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = mul<float>(u[j][k2], fl[k1 + R1 * k2]);
+        RegDFT<R2, true, float>::run(u[j]);
+#pragma unroll
+        for (int tt = 1; tt < R2; ++tt) u[j][tt] = mulc<float>(u[j][tt], tw_i[tt * R1 + k1]);
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int j = 0; j < CC; ++j) {
+#pragma unroll
+            for (int tt = 0; tt < R2; ++tt) buf[((CC * t + j) * R2 + tt) * W + q] = u[j][tt];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) w[k1] = buf[(k1 * R2 + t) * W + q];
+    RegDFT<R1, true, float>::run(w);
+    if (!active) return;
+    __builtin_amdgcn_s_setprio(2);
+#pragma unroll
+    for (int r = 0; r < R1; ++r) (base + r * rstride)[lane_off] = w[r];
+}
+
+template <int L, int WW> struct MultiPencil {
+    using Gm = LineGeom<L, WW>;
+    static constexpr int S = SE2C_MULTI_THREADS / Gm::NT;
+    static constexpr size_t REGION = (sizeof(float2) * ((size_t)L * WW + 3 * L) + 15) / 16 * 16;
+    static constexpr size_t LDS = REGION * S;
+};
+
+template <int L, int WW>
+__device__ __forceinline__ void pencil_class(const MultiArgs& m, const MultiClass& c, int lb, unsigned char* smem) {
+    using MP = MultiPencil<L, WW>;
+    constexpr int NT = MP::Gm::NT, S = MP::S;
+    const int sub_raw = threadIdx.x / NT;
+    const int sub = sub_raw < S ? sub_raw : S - 1;
+    const int tid = threadIdx.x - sub_raw * NT;
+    const int ctiles = (c.nx / 2) / WW;
+    const int per_item = ctiles * c.m;
+    const int unit = lb * S + sub;
+    const bool active = sub_raw < S && unit < c.nitems * per_item;
+    const int item = active ? unit / per_item : 0;
+    const int rem = unit - item * per_item;
+    const int o = rem / ctiles;
+    FastSepArgs a{};
+    a.items = m.items + c.item0;
+    a.tw = c.tw;
+    a.conj_tab = m.conj_tab;
+    pencil_tile<L, WW>(a, c.nx, c.ny, item, o, rem - o * ctiles, active, tid, smem + (size_t)sub * MP::REGION);
+}
+
+#define SE2C_MULTI_PENCILS(X) \
+    X(32, 16) X(32, 8) X(48, 16) X(48, 8) X(64, 16) X(64, 8) X(96, 16) X(96, 8) X(128, 16) X(128, 8) X(256, 16) X(256, 8)
+
+__global__ void __launch_bounds__(SE2C_MULTI_THREADS) y_pencil_multi(MultiArgs m) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __builtin_amdgcn_s_setprio(2);
+    int ci = 0;
+    for (int k = 1; k < m.nclass; ++k)
+        if ((int)blockIdx.x >= m.c[k].first_block) ci = k;
+    const MultiClass& c = m.c[ci];
+    const int lb = blockIdx.x - c.first_block;
+    switch (c.code) {
+#define SE2C_X(L_, W_) \
+    case L_ * 1024 + W_: pencil_class<L_, W_>(m, c, lb, smem_raw); break;
+        SE2C_MULTI_PENCILS(SE2C_X)
+#undef SE2C_X
+        default: break;
+    }
+}
+
+// Host side of the multi-class launches: shape support, class codes, units per
+// workgroup and LDS.
+bool multi_slab_supported(int nx, int m) {
+#define SE2C_X(NX_, M_) if (nx == NX_ && m == M_) return true;
+    SE2C_MULTI_SLABS(SE2C_X)
+#undef SE2C_X
+    return false;
+}
+
+static int multi_slab_per_block(int nx, int m) {
+#define SE2C_X(NX_, M_) if (nx == NX_ && m == M_) return MultiSlab<NX_, M_>::S;
+    SE2C_MULTI_SLABS(SE2C_X)
+#undef SE2C_X
+    return 0;
+}
+
+static size_t multi_slab_lds(int nx, int m) {
+#define SE2C_X(NX_, M_) if (nx == NX_ && m == M_) return MultiSlab<NX_, M_>::LDS;
+    SE2C_MULTI_SLABS(SE2C_X)
+#undef SE2C_X
+    return 0;
+}
+
+static int pencil_w_for(int nx) { return (nx / 2) % 16 == 0 ? 16 : 8; }
+
+bool multi_pencil_supported(int nx, int ny) {
+    const int w = pencil_w_for(nx);
+    if (nx % 16) return false;
+#define SE2C_X(L_, W_) if (ny == L_ && w == W_) return true;
+    SE2C_MULTI_PENCILS(SE2C_X)
+#undef SE2C_X
+    return false;
+}
+
+static int multi_pencil_per_block(int ny, int w) {
+#define SE2C_X(L_, W_) if (ny == L_ && w == W_) return MultiPencil<L_, W_>::S;
+    SE2C_MULTI_PENCILS(SE2C_X)
+#undef SE2C_X
+    return 0;
+}
+
+static size_t multi_pencil_lds(int ny, int w) {
+#define SE2C_X(L_, W_) if (ny == L_ && w == W_) return MultiPencil<L_, W_>::LDS;
+    SE2C_MULTI_PENCILS(SE2C_X)
+#undef SE2C_X
+    return 0;
+}
+
+// Fills the per-class launch fields (code, first workgroup) of one pass and returns the
+// grid size and LDS; classes keep the caller's order.
+static hipError_t plan_multi(MultiArgs& m, bool pencil, int* blocks, size_t* lds) {
+    int first = 0;
+    size_t l = 0;
+    for (int k = 0; k < m.nclass; ++k) {
+        MultiClass& c = m.c[k];
+        int per, units;
+        size_t cl;
+        if (pencil) {
+            const int w = pencil_w_for(c.nx);
+            per = multi_pencil_per_block(c.ny, w);
+            cl = multi_pencil_lds(c.ny, w);
+            c.code = c.ny * 1024 + w;
+            units = c.nitems * ((c.nx / 2) / w) * c.m;
+            c.tw = c.twy;
+        } else {
+            per = multi_slab_per_block(c.nx, c.m);
+            cl = multi_slab_lds(c.nx, c.m);
+            c.code = c.nx * 1024 + c.m;
+            units = c.nitems * (c.ny / 2);
+            c.tw = c.twx;
+        }
+        if (per < 1) return hipErrorInvalidValue;
+        c.first_block = first;
+        first += (units + per - 1) / per;
+        l = l > cl ? l : cl;
+    }
+    *blocks = first;
+    *lds = l;
+    return hipSuccess;
+}
+
+hipError_t launch_slab_multi(MultiArgs m, hipStream_t s) {
+    int blocks = 0;
+    size_t lds = 0;
+    hipError_t e = plan_multi(m, false, &blocks, &lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(xt_slab_multi, dim3(blocks), dim3(SE2C_MULTI_THREADS), lds, s, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_pencil_multi(MultiArgs m, hipStream_t s) {
+    int blocks = 0;
+    size_t lds = 0;
+    hipError_t e = plan_multi(m, true, &blocks, &lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(y_pencil_multi, dim3(blocks), dim3(SE2C_MULTI_THREADS), lds, s, m);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ dispatch
 template <int NX, int M>
 static size_t slab_fast_lds() {
-    using Gm = SlabGeom<NX, M>;
-    return sizeof(float2) * ((size_t)Gm::RC * Gm::P + 3 * NX + 2 * M);
+    return SlabGeom<NX, M>::LDS;
 }
 
 template <int L, int W>
@@ -627,6 +950,12 @@ hipError_t launch_rows_fast(const FastSepArgs& a, hipStream_t s) {
 
 hipError_t prepare_fast_kernels() {
     hipError_t e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(xt_slab_multi), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_pencil_multi), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+    if (e != hipSuccess) return e;
     SE2C_SLAB_ATTR(32, 16) SE2C_SLAB_ATTR(32, 32) SE2C_SLAB_ATTR(32, 64)
     SE2C_SLAB_ATTR(48, 16) SE2C_SLAB_ATTR(48, 32) SE2C_SLAB_ATTR(48, 64)
     SE2C_SLAB_ATTR(96, 16) SE2C_SLAB_ATTR(96, 32) SE2C_SLAB_ATTR(96, 64)

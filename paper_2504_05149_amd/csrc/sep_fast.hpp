@@ -25,6 +25,31 @@ struct FastSepArgs {
     const SepItem* items;  // device; non-null: field i is items[i] (own input, output and tables)
 };
 
+// Multi-class launches: every shape class of a submission in one launch per pass.
+#define SE2C_MULTI_THREADS 256
+#define SE2C_MAX_CLASSES 16
+struct MultiClass {
+    int nx, ny, m;
+    int nitems;          // fields of the class
+    int item0;           // first of them in MultiArgs::items
+    int code;            // kernel body (filled by the launcher)
+    int first_block;     // first workgroup of the class (filled by the launcher)
+    const float2* twx;   // FP64-generated twiddles of Nx, Ny, M (rounded)
+    const float2* twy;
+    const float2* twt;
+    const float2* tw;    // the pass's line twiddles (filled by the launcher)
+};
+struct MultiArgs {
+    const SepItem* items;  // device
+    int conj_tab;
+    int nclass;
+    MultiClass c[SE2C_MAX_CLASSES];
+};
+bool multi_slab_supported(int nx, int m);
+bool multi_pencil_supported(int nx, int ny);
+hipError_t launch_slab_multi(MultiArgs m, hipStream_t s);
+hipError_t launch_pencil_multi(MultiArgs m, hipStream_t s);
+
 bool slab_fast_supported(int nx, int m);
 bool pencil_fast_supported(int nx, int ny);
 bool three_pass_fast_supported(int nx, int ny, int m);
