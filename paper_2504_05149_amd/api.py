@@ -401,17 +401,25 @@ class Plan:
     def chain(self, problems, adjoint: bool = False, graph: bool = False, stream=None,
               timing: bool = False) -> None:
         """problems: list of (shape_idx, f, out, [tables])."""
-        keep = []
-        arr = (L.Problem * len(problems))()
-        for i, (sidx, f, out, tabs) in enumerate(problems):
-            nx, ny, m = self.shapes[sidx]
-            tp = (ctypes.c_void_p * len(tabs))(*[t.ptr for t in tabs])
-            keep.append(tp)
-            arr[i].shape_idx = sidx
-            arr[i].batch = f.numel() // (nx * ny * m)
-            arr[i].f = f.data_ptr()
-            arr[i].out = out.data_ptr()
-            arr[i].tables = ctypes.cast(tp, ctypes.POINTER(ctypes.c_void_p))
-            arr[i].n_tables = len(tabs)
+        arr, keep = self._problem_array(problems)
         flags = (L.ADJOINT if adjoint else 0) | (L.GRAPH if graph else 0) | (L.TIMING if timing else 0)
         L.check(self._lib.se2conv_chain(self.handle, arr, len(problems), flags, _stream_handle(stream)))
+
+    def chain_submission(self, problems, adjoint: bool = False, graph: bool = True) -> "ChainSubmission":
+        """A problem list marshalled once, for repeated se2conv_chain calls (a serving loop)."""
+        return ChainSubmission(self, problems, adjoint, graph)
+
+
+class ChainSubmission:
+    """A se2conv_chain problem list marshalled once (the argument arrays are built here and
+    reused by every run; the tensors and tables stay referenced)."""
+
+    def __init__(self, plan: Plan, problems, adjoint: bool = False, graph: bool = True):
+        self.plan = plan
+        self.problems = list(problems)
+        self.arr, self._keep = plan._problem_array(self.problems)
+        self.flags = (L.ADJOINT if adjoint else 0) | (L.GRAPH if graph else 0)
+
+    def run(self, stream=None) -> None:
+        L.check(self.plan._lib.se2conv_chain(self.plan.handle, self.arr, len(self.problems), self.flags,
+                                             _stream_handle(stream)))

@@ -172,6 +172,7 @@ struct TableRec {
 // are released by the destructor, after the last enqueued use has finished.
 struct SubmissionRec {
     std::vector<uint64_t> key;
+    uint64_t key_hash = 0;                         // FNV-1a of key, compared first
     std::vector<uintptr_t> tabs;                   // every table address the list names
     void* d_items = nullptr;                       // all groups' SepItem arrays
     std::vector<std::pair<int, int>> groups;       // (shape_idx, first item) per group
@@ -2538,11 +2539,13 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
     const bool conj = (flags & SE2CONV_ADJOINT) != 0;
 
     // find or build the submission record (device item arrays grouped by shape)
+    uint64_t key_hash = 1469598103934665603ull;
+    for (uint64_t v : key) key_hash = (key_hash ^ v) * 1099511628211ull;
     std::shared_ptr<SubmissionRec> rec;
     {
         std::lock_guard<std::mutex> g(p->mu);
         for (auto& r : p->subs)
-            if (r->key == key) rec = r;
+            if (r->key_hash == key_hash && r->key == key) rec = r;
     }
     if (!rec) {
         std::map<int, std::vector<SepItem>> by_shape;
@@ -2562,6 +2565,7 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
         }
         auto nr = std::make_shared<SubmissionRec>();
         nr->key = key;
+        nr->key_hash = key_hash;
         for (int i = 0; i < n_probs; ++i)
             for (int j = 0; j < probs[i].n_tables; ++j)
                 nr->tabs.push_back(reinterpret_cast<uintptr_t>(probs[i].tables[j]));
