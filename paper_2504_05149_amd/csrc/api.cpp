@@ -25,6 +25,7 @@
 #include "grad.hpp"
 #include "sample.hpp"
 #include "shift.hpp"
+#include "sep_fast64.hpp"
 
 using namespace se2c;
 
@@ -617,6 +618,35 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
     const bool fast_pencil = !d && !generic_only && two_pass && pencil_fast_supported(s.nx, s.ny);
     if (!d && !generic_only && !two_pass && three_pass_fast_supported(s.nx, s.ny, s.m))
         return enqueue_three_pass_fast(p, s, fa, st);
+    if (d && !generic_only && !two_pass && fast64_supported(s.nx, s.ny, s.m)) {
+        // FP64 register kernels: x rows, then y and theta pencils in place
+        Fast64Args g{};
+        g.in = reinterpret_cast<const double*>(f);
+        g.out = reinterpret_cast<double*>(out);
+        g.n = n;
+        g.nitems = batch;
+        g.nx = s.nx;
+        g.ny = s.ny;
+        g.m = s.m;
+        g.ntab = ch.ntab;
+        g.conj_tab = conj ? 1 : 0;
+        for (int j = 0; j < ch.ntab; ++j) g.tab[j] = fx(j);
+        g.tw = reinterpret_cast<const double2*>(tw_of(p, s.nx, true));
+        HIPCHK(launch_rows_f64(g, st));
+        HIPCHK(after_pass(3, st));
+        g.in = g.out;
+        g.axis = 1;
+        for (int j = 0; j < ch.ntab; ++j) g.tab[j] = fy(j);
+        g.tw = reinterpret_cast<const double2*>(tw_of(p, s.ny, true));
+        HIPCHK(launch_pencil_f64(g, st));
+        HIPCHK(after_pass(1, st));
+        g.axis = 2;
+        for (int j = 0; j < ch.ntab; ++j) g.tab[j] = ftt(j);
+        g.tw = reinterpret_cast<const double2*>(tw_of(p, s.m, true));
+        HIPCHK(launch_pencil_f64(g, st));
+        HIPCHK(after_pass(2, st));
+        return SE2CONV_OK;
+    }
     if (fast_slab && fast_pencil) {
         // Fields per launch pair (the whole batch unless SE2CONV_SEP_CHUNK says
         // otherwise; see sep_chunk_fields).

@@ -534,10 +534,12 @@ hipError_t launch_pencil(const PencilArgs& a, bool dbl, int nthr, int nblocks, h
 
 namespace se2c {
 hipError_t prepare_fast_kernels();
+hipError_t prepare_fast64_kernels();
 hipError_t prepare_kernels() {
     static hipError_t once = [] {
         hipError_t e = prepare_generic_kernels();
         if (e == hipSuccess) e = prepare_fast_kernels();
+        if (e == hipSuccess) e = prepare_fast64_kernels();
         return e != hipSuccess ? e : prepare_full_fast_kernels();
     }();
     return once;

@@ -442,3 +442,28 @@ def test_autotuned_schedules_stay_correct(tmp_path, monkeypatch):
         ref_t = oracle_table_gauss(nx, ny, m, chain)
         for b in range(2):
             assert parity_err(out[b], oracle_conv(f[b], ref_t)) <= tol32(nx * ny * m)
+
+
+@pytest.mark.parametrize("nx,ny,m", [(128, 64, 64), (512, 64, 32), (64, 128, 128), (256, 256, 32), (64, 512, 64)])
+def test_fp64_register_kernels_match_generic_and_oracle(nx, ny, m):
+    batch = 2 if nx * ny * m >= (1 << 20) else 3
+    case(f"FP64 register vs generic kernels {nx}x{ny}x{m} batch {batch}, chain of 2, adjoint too")
+    ks = chain_kernel_params(10, 2)
+    chain = [(k.sigma, k.kappa, 0.6 * j) for j, k in enumerate(ks)]
+    f = _fields(10, batch, 16, nx, ny, m)
+    ref_t = oracle_table_gauss(nx, ny, m, chain)
+    outs = {}
+    for generic in (False, True):
+        plan = se2.Plan([(nx, ny, m)], dtype="f64", generic=generic)
+        table = plan.coeffs(0, [se2.GaussVM(s, k, th) for s, k, th in chain])
+        fd = _dev(f, torch.float64)
+        outs[generic] = (plan.apply(0, fd, table).cpu().numpy(), plan.apply(0, fd, table, adjoint=True).cpu().numpy())
+        print(f"  GPU generic={generic} done", flush=True)
+    for b in range(batch):
+        ref = oracle_conv(f[b], ref_t)
+        ref_adj = oc.conv_with_coeffs(f[b], np.conj(ref_t))
+        for generic in (False, True):
+            e1 = parity_err(outs[generic][0][b], ref)
+            e2 = parity_err(outs[generic][1][b], ref_adj)
+            print(f"  field {b} generic={generic}: {e1:.2e} adj {e2:.2e}", flush=True)
+            assert e1 <= TOL64 and e2 <= TOL64
