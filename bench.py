@@ -47,7 +47,7 @@ WORKLOADS = {
 }
 # workloads whose kernel is not a chain of Gauss-vM kernels: (kind, sigma)
 EXP_GAUSS_SIGMA = {"expgauss": 0.05}
-SPECIAL = ("c2", "c4", "padded", "powers")
+SPECIAL = ("c2", "c4", "padded", "powers", "shifted")
 
 
 def lib_source_hash() -> str:
@@ -332,6 +332,87 @@ def run_powers(steps, warmup, cpu_budget=None):
     return line
 
 
+def shifted_params(m, n_terms=8, rolls=(0, 5)):
+    """Seeded shifts (tx, ty, roll, weight) of the shifted-kernel workload."""
+    rng = np.random.default_rng([2504_05149, 6, 2000])
+    return [(float(rng.uniform(-0.3, 0.3)), float(rng.uniform(-0.3, 0.3)), int(rolls[k % len(rolls)]),
+             float(rng.uniform(-1.0, 1.0))) for k in range(n_terms)]
+
+
+def run_shifted(steps, warmup, cpu_budget=None):
+    """Sums of SE(2)-shifted radial kernels: 8 shifts of a Gauss-vM kernel (sigma 0.04, kappa 6)
+    in two theta rolls, 256x256x64 FP32, batch 8 (se2conv_apply_shifted, five passes)."""
+    import torch
+
+    import paper_2504_05149_amd as se2
+    from inputs import sample_fields
+
+    shape, batch = (256, 256, 64), 8
+    shifts = shifted_params(shape[2])
+    plan = se2.Plan([shape], dtype="f32")
+    q = plan.shift_table(0, shifts)
+    rho = plan.coeffs(0, [se2.GaussVM(0.04, 6.0, 0.0)])
+    f_host = sample_fields(6, batch, 32, *shape, dtype=np.float32)
+    f = torch.from_numpy(f_host).to("cuda")
+    out = torch.empty_like(f)
+    for _ in range(warmup):
+        plan.apply_shifted(0, f, q, [rho], out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.apply_shifted(0, f, q, [rho], out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    med_ms, _, reps = replay_median(lambda st: plan.apply_shifted(0, f, q, [rho], out=out, stream=st))
+    for _ in range(steps):
+        plan.apply_shifted(0, f, q, [rho], out=out, timing=True)
+    per_kind = {}
+    for kind, t in plan.pass_times():
+        per_kind.setdefault(kind, []).append(t)
+    out_host = out.cpu().numpy()
+    plan.close()
+    n = shape[0] * shape[1] * shape[2]
+    alg = 8 * n * batch
+    gbps = alg / (med_ms * 1e-3) / 1e9
+    line = {"metric": "SE(2) convolutions/sec with a sum of 8 SE(2)-shifted Gauss-vM kernels",
+            "value": round(batch / (ms * 1e-3), 1), "unit": "conv/s", "n_gpus": 1, "steps": steps,
+            "warmup": warmup, "ms_per_step": round(ms, 4), "replay_median_ms": round(med_ms, 4), "replays": reps,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{shape[0]}x{shape[1]}x{shape[2]} fp32, batch {batch} fields of 32 Gauss-vM bumps, "
+                                   "kernel = sum of 8 SE(2)-shifts (translations U[-0.3,0.3]^2, theta rolls 0 and 5 "
+                                   "grid angles, weights U[-1,1]) of a Gauss-vM kernel sigma=0.04 kappa=6"},
+            "pass_ms_total_per_step": {k: round(float(np.sum(v)) / steps, 4) for k, v in per_kind.items()},
+            "roofline": {"bound": "hbm", "kernel": "whole path", "achieved": round(gbps, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbps / HBM_PEAK_GBS, 4), "traffic": None,
+                         "alg_bytes_per_step": alg}}
+    if cpu_budget is not None:
+        from threadpoolctl import threadpool_info
+
+        from inputs import rel_l2
+        from oracle import kernels as ok
+        from oracle import shifted as osh
+
+        p = ok.gauss_vm(*shape, 0.04, 6.0, 0.0)
+        sh = [(tx, ty, 2 * np.pi * r / shape[2]) for tx, ty, r, _ in shifts]
+        w = [a for *_, a in shifts]
+        done, errs = 0, []
+        t0 = time.perf_counter()
+        while done < batch:
+            ref = osh.shifted_sum_conv(f_host[done].astype(np.float64), p, sh, w)
+            errs.append(rel_l2(out_host[done].astype(np.float64), ref))
+            done += 1
+            if time.perf_counter() - t0 > cpu_budget:
+                break
+        el = time.perf_counter() - t0
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        line["cpu_baseline"] = {"value": done / el, "unit": "conv/s", "cores": int(threads), "kind": "oracle",
+                                "sample": f"{done} of {batch} fields, FP64 oracle (spatial FFCs per slice, shift "
+                                          f"phases, theta FFC, product, dense synthesis); {el:.1f} s; {host_cpu()}"}
+        line["rel_l2_vs_oracle"] = float(max(errs))
+        line["rel_l2_tol"] = float(2e-6 * np.log2(n))
+    return line
+
+
 def run_c4(steps, warmup):
     """Loss + gradients w.r.t. the field and a 64 x 64 radial profile, 256x256x64 FP32 batch 8."""
     import torch
@@ -549,6 +630,9 @@ def main():
     if args.workload == "powers":
         print(json.dumps(run_powers(args.steps, args.warmup, None if args.no_cpu else args.cpu_budget)), flush=True)
         return
+    if args.workload == "shifted":
+        print(json.dumps(run_shifted(args.steps, args.warmup, None if args.no_cpu else args.cpu_budget)), flush=True)
+        return
     if args.workload == "padded":
         print(json.dumps(run_padded(args.steps, args.warmup, None if args.no_cpu else args.cpu_budget)), flush=True)
         return
@@ -618,8 +702,9 @@ def main():
 
 
 def secondary(steps, warmup, tune=True):
-    """The plain single-kernel convolution at the headline shape, the uneven batch (C2) and
-    the differentiated form (C4), measured in the same invocation."""
+    """The plain single-kernel convolution at the headline shape, the uneven batch (C2), the
+    differentiated form (C4) and a sum of SE(2)-shifted kernels, measured in the same
+    invocation."""
     out = {}
     r = run_gpu("headline_plain", steps, warmup, tune=tune)
     nx, ny, m = r["shape"]
@@ -638,6 +723,10 @@ def secondary(steps, warmup, tune=True):
     out["differentiated_c4"] = {k: c4[k] for k in ("value", "unit", "ms_per_step", "ms_fwd_bwd",
                                                    "ms_fwd_bwd_event_median", "ms_forward_full_table")}
     out["differentiated_c4"]["workload"] = c4["config"]["workload"]
+    sh = run_shifted(steps, warmup)
+    out["shifted_kernel_sum"] = {k: sh[k] for k in ("value", "unit", "ms_per_step", "replay_median_ms",
+                                                    "pass_ms_total_per_step")}
+    out["shifted_kernel_sum"]["workload"] = sh["config"]["workload"]
     return out
 
 

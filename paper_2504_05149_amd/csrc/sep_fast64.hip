@@ -40,13 +40,16 @@ __device__ __forceinline__ int xpos64(int k1, int t) {
 // One line exchange: v[R1] (first stage done, in the thread's registers) -> second stage,
 // product with f (the line factor, L entries), inverse second stage -> v (ready for the
 // inverse first stage).  line points to the line's LDS slots (stride `ls` between slots).
-template <int L>
-__device__ __forceinline__ void line_middle64(D2* v, D2* line, int ls, const D2* f, const D2* tw_f, const D2* tw_i,
-                                              int t) {
+// twf(t, k1) and twi(tt, k1) give the twiddle w_L^{t k1} (t k1 < L): from the plan's table
+// in global memory (the x rows, where LDS is kept for the exchange so that two workgroups
+// fit per CU at 512 points) or from LDS copies laid out for conflict-free reads (pencils,
+// measured faster there).
+template <int L, typename TF, typename TI>
+__device__ __forceinline__ void line_middle64(D2* v, D2* line, int ls, const D2* f, TF twf, TI twi, int t) {
     using Gm = Geom64<L>;
     constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC;
 #pragma unroll
-    for (int k1 = 1; k1 < R1; ++k1) v[k1] = mul<double>(v[k1], tw_f[k1 * R2 + t]);
+    for (int k1 = 1; k1 < R1; ++k1) v[k1] = mul<double>(v[k1], twf(t, k1));
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) line[xpos64<R1, R2>(k1, t) * ls] = v[k1];
     __syncthreads();
@@ -62,7 +65,7 @@ __device__ __forceinline__ void line_middle64(D2* v, D2* line, int ls, const D2*
         for (int k2 = 0; k2 < R2; ++k2) u[k2] = mul<double>(u[k2], f[k1 + R1 * k2]);
         RegDFT<R2, true, double>::run(u);
 #pragma unroll
-        for (int tt = 1; tt < R2; ++tt) u[tt] = mulc<double>(u[tt], tw_i[tt * R1 + k1]);
+        for (int tt = 1; tt < R2; ++tt) u[tt] = mulc<double>(u[tt], twi(tt, k1));
 #pragma unroll
         for (int tt = 0; tt < R2; ++tt) line[xpos64<R1, R2>(k1, tt) * ls] = u[tt];
     }
@@ -72,16 +75,9 @@ __device__ __forceinline__ void line_middle64(D2* v, D2* line, int ls, const D2*
 }
 
 template <int L>
-__device__ __forceinline__ void load_line_tables64(D2* tw_f, D2* tw_i, D2* f, const D2* tw, const void* const* tabs,
-                                                   int ntab, int conj, int tid, int nthr) {
-    using Gm = Geom64<L>;
-    for (int i = tid; i < L; i += nthr) {
-        const int k1 = i / Gm::R2, t = i - k1 * Gm::R2;
-        const D2 w = tw[t * k1];
-        tw_f[k1 * Gm::R2 + t] = w;
-        tw_i[t * Gm::R1 + k1] = w;
-        f[i] = chain_factor64(tabs, ntab, i, 1.0 / L, conj);
-    }
+__device__ __forceinline__ void load_line_factor64(D2* f, const void* const* tabs, int ntab, int conj, int tid,
+                                                   int nthr) {
+    for (int i = tid; i < L; i += nthr) f[i] = chain_factor64(tabs, ntab, i, 1.0 / L, conj);
 }
 
 // x rows: one workgroup per (y-pair, G theta rows); rows 2s and 2s+1 as re/im.
@@ -98,9 +94,7 @@ __global__ void __launch_bounds__(RowGeom64<NX>::NT) x_rows_f64(Fast64Args a) {
     constexpr int R1 = Gm::R1, R2 = Gm::R2, G = RG::G, P = RG::P;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     D2* buf = reinterpret_cast<D2*>(smem_raw);  // G x P
-    D2* tw_f = buf + G * P;
-    D2* tw_i = tw_f + NX;
-    D2* fx = tw_i + NX;
+    D2* fx = buf + G * P;
     const int tid = threadIdx.x;
     const int nslab = a.ny / 2;
     const int trows = a.m / G;
@@ -109,7 +103,7 @@ __global__ void __launch_bounds__(RowGeom64<NX>::NT) x_rows_f64(Fast64Args a) {
     const int rem = blockIdx.x - item * per_item;
     const int tr = rem / nslab;
     const int s = rem - tr * nslab;
-    load_line_tables64<NX>(tw_f, tw_i, fx, a.tw, a.tab, a.ntab, a.conj_tab, tid, RG::NT);
+    load_line_factor64<NX>(fx, a.tab, a.ntab, a.conj_tab, tid, RG::NT);
     const int t = tid % R2, g = tid / R2;
     const int pl = NX * a.ny;
     const long long base = (long long)item * a.n + (long long)(tr * G + g) * pl + (long long)(2 * s) * NX;
@@ -121,7 +115,9 @@ __global__ void __launch_bounds__(RowGeom64<NX>::NT) x_rows_f64(Fast64Args a) {
         v[r] = make_double2(__builtin_nontemporal_load(in0 + t + R2 * r), __builtin_nontemporal_load(in1 + t + R2 * r));
     __syncthreads();
     RegDFT<R1, false, double>::run(v);
-    line_middle64<NX>(v, buf + g * P, 1, fx, tw_f, tw_i, t);
+    const D2* tw = a.tw;
+    line_middle64<NX>(v, buf + g * P, 1, fx, [tw](int t_, int k_) { return tw[t_ * k_]; },
+                      [tw](int t_, int k_) { return tw[t_ * k_]; }, t);
     RegDFT<R1, true, double>::run(v);
     double* out0 = a.out + base;
     double* out1 = out0 + NX;
@@ -147,11 +143,17 @@ __global__ void __launch_bounds__(PencilGeom64<L>::NT) pencil_f64(Fast64Args a) 
     constexpr int R1 = Gm::R1, R2 = Gm::R2, W = PG::W, P = PG::P;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     D2* buf = reinterpret_cast<D2*>(smem_raw);  // [slot][W] with pitch P
-    D2* tw_f = buf + L * P;
-    D2* tw_i = tw_f + L;
+    D2* tw_f = buf + L * P;                      // [k1][t] = w_L^{t k1}
+    D2* tw_i = tw_f + L;                         // [t][k1]
     D2* fl = tw_i + L;
     const int tid = threadIdx.x;
-    load_line_tables64<L>(tw_f, tw_i, fl, a.tw, a.tab, a.ntab, a.conj_tab, tid, PG::NT);
+    load_line_factor64<L>(fl, a.tab, a.ntab, a.conj_tab, tid, PG::NT);
+    for (int i = tid; i < L; i += PG::NT) {
+        const int k1 = i / R2, tt = i - k1 * R2;
+        const D2 w = a.tw[tt * k1];
+        tw_f[k1 * R2 + tt] = w;
+        tw_i[tt * R1 + k1] = w;
+    }
     const int q = tid % W, t = tid / W;
     const int ncols = a.nx / 2;
     const int ctiles = ncols / W;
@@ -169,7 +171,8 @@ __global__ void __launch_bounds__(PencilGeom64<L>::NT) pencil_f64(Fast64Args a) 
     for (int r = 0; r < R1; ++r) v[r] = base[(long long)(t + R2 * r) * lstride];
     __syncthreads();
     RegDFT<R1, false, double>::run(v);
-    line_middle64<L>(v, buf + q, P, fl, tw_f, tw_i, t);
+    line_middle64<L>(v, buf + q, P, fl, [tw_f](int t_, int k_) { return tw_f[k_ * R2 + t_]; },
+                     [tw_i](int t_, int k_) { return tw_i[t_ * R1 + k_]; }, t);
     RegDFT<R1, true, double>::run(v);
 #pragma unroll
     for (int r = 0; r < R1; ++r) base[(long long)(t + R2 * r) * lstride] = v[r];
@@ -177,7 +180,7 @@ __global__ void __launch_bounds__(PencilGeom64<L>::NT) pencil_f64(Fast64Args a) 
 
 template <int NX>
 static size_t rows64_lds() {
-    return sizeof(D2) * ((size_t)RowGeom64<NX>::G * RowGeom64<NX>::P + 3 * NX);
+    return sizeof(D2) * ((size_t)RowGeom64<NX>::G * RowGeom64<NX>::P + NX);
 }
 template <int L>
 static size_t pencil64_lds() {
@@ -187,7 +190,7 @@ static size_t pencil64_lds() {
 static bool len64_ok(int l) { return l == 32 || l == 64 || l == 128 || l == 256 || l == 512; }
 
 bool fast64_supported(int nx, int ny, int m) {
-    return (nx == 64 || nx == 128 || nx == 256 || nx == 512) && (nx / 2) % PencilGeom64<32>::W == 0 && len64_ok(ny) &&
+    return (nx == 64 || nx == 128 || nx == 256 || nx == 512) && (nx / 2) % 8 == 0 && len64_ok(ny) &&
            len64_ok(m) && m % RowGeom64<64>::G == 0;
 }
 
