@@ -530,4 +530,17 @@ __device__ __forceinline__ void line_fft(C<T>* buf, const C<T>* tw, const RadixP
     }
 }
 
+// Workgroups are handed to the chip's 8 XCDs in turn (workgroup b to XCD b mod 8), each
+// XCD with its own L2.  xcd_contiguous(b, G) renumbers the G workgroups of a launch so
+// that every XCD receives one contiguous range of the new indices, in its own dispatch
+// order: workgroups with neighbouring indices (tiles that share table entries, or halves
+// of the same cache lines) run on one XCD close together in time, and what they share is
+// fetched from HBM once.  A bijection of [0, G) for every G >= 1; a grid-stride loop over
+// G tiles keeps the property when its grid is a multiple of 8.
+__device__ __forceinline__ int xcd_contiguous(int b, int G) {
+    const int x = b & 7, i = b >> 3;
+    const int per = G >> 3, rem = G & 7;
+    return (x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per) + i;
+}
+
 }  // namespace se2c

@@ -245,7 +245,7 @@ xt_full(FullFastArgs a) {
 }
 
 // y pass: W = 16 adjacent x frequencies (columns of the re and im planes) x NY points
-// at one theta frequency; every pair of the batch in turn, the table loaded once.
+// at one theta frequency, for one pair of the batch (the backward: every pair in turn).
 // Columns per workgroup: 32 (128-byte row segments per plane, one workgroup round at
 // 256^2 x 64) where the LDS allows; the backward keeps 16 (its accumulator and table
 // registers limit occupancy either way).
@@ -312,16 +312,24 @@ __global__ void __launch_bounds__((FullLineGeom<NY, MODE>::NT)) y_full(FullFastA
     __syncthreads();
 
     const int ctiles = a.nx / W;
-    const int kt = blockIdx.x / ctiles;
     const int pl = a.nx * NY;
     const int npairs = (a.batch + 1) / 2;
+    // MODE 0 and 1: one pair per workgroup, the workgroups of one column tile (its pairs)
+    // back to back on one XCD, so that the tile's table entries come from HBM once and are
+    // then L2 hits (the backward's accumulator needs every pair in one workgroup)
+    const int bid = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int tb = MODE == 2 ? bid : bid / npairs;
+    const int p_lo = MODE == 2 ? 0 : bid - tb * npairs;
+    const int p_hi = MODE == 2 ? npairs : p_lo + 1;
+    const int kt = tb / ctiles;
+    const int ct = tb - kt * ctiles;
     // table factor for (kt, ky = k1 + R1 k2, kx), k1 = CC t + j: held in registers across
-    // the pair loop by the backward; the convolution re-reads it per pair (cache hits after
-    // the first pair), which keeps it within 128 registers (four waves per SIMD)
+    // the pair loop by the backward; the convolution reads it once per workgroup, in the
+    // product, which keeps it within 128 registers (four waves per SIMD)
     float2 tv[CC][R2];
     if constexpr (MODE == 2) {
         const int q = tid % W, t = tid / W;
-        const int kx = (blockIdx.x - kt * ctiles) * W + q;
+        const int kx = ct * W + q;
 #pragma unroll
         for (int j = 0; j < CC; ++j)
 #pragma unroll
@@ -336,13 +344,13 @@ __global__ void __launch_bounds__((FullLineGeom<NY, MODE>::NT)) y_full(FullFastA
             for (int k2 = 0; k2 < R2; ++k2) acc[j][k2] = make_float2(0.f, 0.f);
     }
     const int rstride = R2 * a.nx;
-    for (int pair = 0; pair < npairs; ++pair) {
+    for (int pair = p_lo; pair < p_hi; ++pair) {
         // per-lane offsets are recomputed for every pair rather than hoisted out of the
         // loop (hoisting them would hold dozens of registers across the loop)
         int lt = tid;
         asm volatile("" : "+v"(lt));
         const int q = lt % W, t = lt / W;
-        const int base = kt * pl + (blockIdx.x - kt * ctiles) * W + q;  // element (kt, y, kx) at base + y nx
+        const int base = kt * pl + ct * W + q;  // element (kt, y, kx) at base + y nx
         const int lane_off = base + t * a.nx;
         float* __restrict__ re = a.out + (long long)(2 * pair) * a.n;
         float* __restrict__ im = 2 * pair + 1 < a.batch ? re + a.n : a.lone;
@@ -435,7 +443,7 @@ __global__ void __launch_bounds__((FullLineGeom<NY, MODE>::NT)) y_full(FullFastA
     if constexpr (MODE == 2) {
         // W[k] = (-1)^(kx + ky) and 1/n^2, then the inverse DFT along y of the accumulator
         const int q = tid % W, t = tid / W;
-        const int kx = (blockIdx.x - kt * ctiles) * W + q;
+        const int kx = ct * W + q;
         const int base = kt * pl + kx;
         const float s2 = a.acc_scale;
 #pragma unroll
@@ -505,18 +513,30 @@ hipError_t launch_xt_full_inv(const FullFastArgs& a, hipStream_t s) { return lau
 // All powers (Alg. 7) along y, MODE 3 geometry: each workgroup (theta frequency, 16 x
 // frequencies) walks the pairs; a pair's y spectrum Z (forward DFT of the x-theta spectrum
 // planes in the last output slot) stays in registers while, for p = 1..q, the running
-// product H_p = H_{p-1} T (scale 1/n folded in at p = 1, conjugated for the adjoint) is
-// inverted along y into slot p - 1.  The last slot is read before it is written (same
-// workgroup, same pair).  The table factor is re-read for every power (cache hits): held in
-// registers across the powers it would cost a third of the occupancy.
+// product H_p = H_{p-1} T (H_0 = Z / n, conjugated for the adjoint) is inverted along y
+// into slot p - 1.  The last slot is read before it is written (same workgroup, same
+// pair).  Up to NY = 256 the workgroup's table tile (NY x 16 factors, the chain's product)
+// sits in LDS, read from HBM once for all pairs and powers; at NY = 512 it would leave one
+// workgroup per CU, and the factor is read from memory for every power.
+template <int NY> struct PowersGeom {
+    static constexpr bool TAB_LDS = NY <= 256;
+};
+template <int NY>
+static constexpr size_t powers_lds() {
+    return full_line_lds<NY, 3>() +
+           (PowersGeom<NY>::TAB_LDS ? sizeof(float2) * (size_t)NY * FullLineGeom<NY, 3>::W : 0);
+}
+
 template <int NY>
 __global__ void __launch_bounds__((FullLineGeom<NY, 3>::NT)) y_full_powers(FullFastArgs a) {
     using Gm = FullLineGeom<NY, 3>;
     constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC, W = Gm::W, NT = Gm::NT;
+    constexpr bool TL = PowersGeom<NY>::TAB_LDS;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     float2* buf = reinterpret_cast<float2*>(smem_raw);  // [k1*R2 + t][W]
     float2* tw_f = buf + NY * W;                        // [k1][t] = w_NY^{t k1}
     float2* tw_i = tw_f + NY;                           // [t][k1]
+    float2* tabl = tw_i + NY;                           // [ky][W] (TL)
     const int tid = threadIdx.x;
     for (int i = tid; i < NY; i += NT) {
         const int k1 = i / R2, t = i - k1 * R2;
@@ -524,10 +544,18 @@ __global__ void __launch_bounds__((FullLineGeom<NY, 3>::NT)) y_full_powers(FullF
         tw_f[k1 * R2 + t] = w;
         tw_i[t * R1 + k1] = w;
     }
+    const int ctiles = a.nx / W;
+    const int bid = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int kt = bid / ctiles;
+    const int ct = bid - kt * ctiles;
+    if constexpr (TL) {
+        for (int i = tid; i < NY * W; i += NT) {
+            const int ky = i / W;
+            tabl[i] = full_table_factor(a, NY, kt, ky, ct * W + (i - ky * W), 1.0f);
+        }
+    }
     __syncthreads();
 
-    const int ctiles = a.nx / W;
-    const int kt = blockIdx.x / ctiles;
     const int pl = a.nx * NY;
     const int npairs = a.batch / 2;
     const int rstride = R2 * a.nx;
@@ -536,7 +564,7 @@ __global__ void __launch_bounds__((FullLineGeom<NY, 3>::NT)) y_full_powers(FullF
         int lt = tid;
         asm volatile("" : "+v"(lt));
         const int q = lt % W, t = lt / W;
-        const int base = kt * pl + (blockIdx.x - kt * ctiles) * W + q;
+        const int base = kt * pl + ct * W + q;
         const int lane_off = base + t * a.nx;
         const float* __restrict__ sre = spec + (long long)(2 * pair) * a.n;
         const float* __restrict__ sim = sre + a.n;
@@ -557,18 +585,22 @@ __global__ void __launch_bounds__((FullLineGeom<NY, 3>::NT)) y_full_powers(FullF
 #pragma unroll
             for (int tt = 0; tt < R2; ++tt) h[j][tt] = buf[(k1 * R2 + tt) * W + q];
             RegDFT<R2, false, float>::run(h[j]);
+#pragma unroll
+            for (int tt = 0; tt < R2; ++tt) h[j][tt] = make_float2(h[j][tt].x * a.scale, h[j][tt].y * a.scale);
         }
 #pragma unroll 1
         for (int pw = 0; pw < a.q; ++pw) {
-            const float sc = pw == 0 ? a.scale : 1.0f;
             float2 u[CC][R2];
 #pragma unroll
             for (int j = 0; j < CC; ++j) {
                 const int k1 = CC * t + j;
                 const int kx = base - kt * pl;
 #pragma unroll
-                for (int k2 = 0; k2 < R2; ++k2)
-                    h[j][k2] = mul<float>(h[j][k2], full_table_factor(a, NY, kt, k1 + R1 * k2, kx, sc));
+                for (int k2 = 0; k2 < R2; ++k2) {
+                    const float2 tf = TL ? tabl[(k1 + R1 * k2) * W + q]
+                                         : full_table_factor(a, NY, kt, k1 + R1 * k2, kx, 1.0f);
+                    h[j][k2] = mul<float>(h[j][k2], tf);
+                }
 #pragma unroll
                 for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = h[j][k2];
                 RegDFT<R2, true, float>::run(u[j]);
@@ -635,7 +667,9 @@ __global__ void __launch_bounds__((FullLineGeom<NY, 3>::NT)) y_full_pad_inv(Full
     __syncthreads();
 
     const int ctiles = a.nx / W;
-    const int kt = blockIdx.x / ctiles;
+    const int bid = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int kt = bid / ctiles;
+    const int ct = bid - kt * ctiles;
     const int pl = a.nx * NY;
     const int npairs = a.batch / 2;
     const int rstride = R2 * a.nx;
@@ -645,7 +679,7 @@ __global__ void __launch_bounds__((FullLineGeom<NY, 3>::NT)) y_full_pad_inv(Full
         int lt = tid;
         asm volatile("" : "+v"(lt));
         const int q = lt % W, t = lt / W;
-        const int kx = (blockIdx.x - kt * ctiles) * W + q;
+        const int kx = ct * W + q;
         const int lane_off = kt * pl + kx + t * a.nx;
         bool hx;
         const int sx = pad_source(kx, a.nx, a.lx, &hx);
@@ -697,7 +731,7 @@ __global__ void __launch_bounds__((FullLineGeom<NY, 3>::NT)) y_full_pad_inv(Full
 
 template <int NY, int MODE>
 static hipError_t launch_y_full_t(const FullFastArgs& a, hipStream_t s) {
-    const int nblocks = (a.nx / FullLineGeom<NY, MODE>::W) * a.m;
+    const int nblocks = (a.nx / FullLineGeom<NY, MODE>::W) * a.m * (MODE == 2 ? 1 : (a.batch + 1) / 2);
     const int nthr = FullLineGeom<NY, MODE>::NT;
     const size_t lds = full_line_lds<NY, MODE>();
     if (MODE == 0 && a.ntab == 1 && a.tab_full[0])
@@ -725,7 +759,7 @@ template <int NY>
 static hipError_t launch_y_full_powers_t(const FullFastArgs& a, hipStream_t s) {
     const int nblocks = (a.nx / FullLineGeom<NY, 3>::W) * a.m;
     const int nthr = FullLineGeom<NY, 3>::NT;
-    const size_t lds = full_line_lds<NY, 3>();
+    const size_t lds = powers_lds<NY>();
     hipLaunchKernelGGL((y_full_powers<NY>), dim3(nblocks), dim3(nthr), lds, s, a);
     return hipGetLastError();
 }
@@ -779,7 +813,7 @@ hipError_t launch_y_full_powers(const FullFastArgs& a, hipStream_t s) {
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_, 3>());       \
     if (e != hipSuccess) return e;                                                                          \
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full_powers<NY_>),                               \
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_, 3>());       \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)powers_lds<NY_>());             \
     if (e != hipSuccess) return e;
 
 hipError_t prepare_full_fast_kernels() {
