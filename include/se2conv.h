@@ -129,6 +129,8 @@ typedef struct {
 #define SE2CONV_TABLE_FULL 1      /* layout: T[M][Ny][Nx] complex of the plan dtype, T[k3][k2][k1] = rho^[k; L] */
 #define SE2CONV_TABLE_SHIFT 2     /* se2conv_shift_table: J plane sets Q_j[M][Ny][Nx] complex of the plan dtype
                                      (one per distinct roll, in order of first appearance) */
+#define SE2CONV_TABLE_QUARTER 3   /* se2conv_table_quarter: T[M][Ny/2+1][Nx/2+1] complex of the plan dtype,
+                                     T[k3][|k2|][|k1|] = rho^[k; L] (signed frequencies, integer halves) */
 
 /*
  * se2conv_coeffs: finite Fourier coefficients of a kernel chain (eq. (FkLv)),
@@ -161,6 +163,29 @@ se2conv_status se2conv_coeffs(se2conv_plan_t plan, int32_t shape_idx, const se2c
 se2conv_status se2conv_coeffs_sum(se2conv_plan_t plan, int32_t shape_idx, const se2conv_kernel_desc* kernels,
                                   const double* weights, int32_t n_terms, void* d_table, size_t* table_bytes,
                                   hipStream_t stream);
+
+/*
+ * se2conv_table_quarter: a FULL table folded by the symmetries of a radial kernel.
+ * A kernel radial in translations (Sec. 5.1, the footnote to Thm. f*gP) sampled on the
+ * lattice of Omega_L is unchanged by x1 -> -x1 and by x2 -> -x2 (the grid is symmetric
+ * modulo the period), so its coefficients satisfy rho^[k1, k2, k3] = rho^[-k1, k2, k3] =
+ * rho^[k1, -k2, k3]: the table is fixed by its entries at nonnegative signed frequencies
+ * 0 <= k1 <= Nx/2, 0 <= k2 <= Ny/2 (every k3), about a quarter of the FULL table.  (On a
+ * square grid the diagonal reflection k1 <-> k2 of the same symmetry group holds as well;
+ * it is not used for storage, as the y pass would read half of such a table across
+ * columns.)  The result is usable wherever a FULL table is (apply, chain, powers, padded,
+ * complex, save/backward, shifted sums).
+ *   d_full      a FULL table this plan produced for shape_idx's shape.
+ *   d_quarter   device buffer of *quarter_bytes bytes (M (Ny/2+1) (Nx/2+1) complex values
+ *               of the plan dtype), 16-byte aligned, or NULL to query the size; it must
+ *               not overlap d_full.
+ * The symmetry is checked on the device: ERR_INVALID_ARG (nothing recorded) when some
+ * |T[k] - T[|k1|, |k2|, k3]| exceeds 1e-5 max |T| (FP32 plan) or 1e-12 max |T| (FP64), the
+ * rounding level of a table generated in FP64 and rounded once, as for a kernel that is not
+ * radial.  Synchronises the stream for that check (not for graph capture).
+ */
+se2conv_status se2conv_table_quarter(se2conv_plan_t plan, const void* d_full, void* d_quarter, size_t* quarter_bytes,
+                                     hipStream_t stream);
 
 /* Kind (SE2CONV_TABLE_*) and byte size of a table produced by this plan. */
 se2conv_status se2conv_table_info(se2conv_plan_t plan, const void* d_table, int32_t* kind, int32_t* shape_idx,

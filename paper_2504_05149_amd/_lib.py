@@ -17,13 +17,13 @@ PLAN_HOST_ONLY = 0x1
 PLAN_GENERIC = 0x2
 K_GAUSS_VM, K_SAMPLES, K_RADIAL_PROFILE, K_EXP_GAUSS = 0, 1, 2, 3
 KNORM_DISCRETE, KNORM_CONTINUOUS, KNORM_NONE = 0, 1, 2
-TABLE_SEPARABLE, TABLE_FULL, TABLE_SHIFT = 0, 1, 2
+TABLE_SEPARABLE, TABLE_FULL, TABLE_SHIFT, TABLE_QUARTER = 0, 1, 2, 3
 ADJOINT, GRAPH, TIMING = 0x1, 0x2, 0x4
 PASS_KINDS = {0: "xt_slab", 1: "y_pencil", 2: "t_pencil", 3: "x_rows"}
 
 EXPORTED = [
     "se2conv_plan", "se2conv_plan_destroy", "se2conv_coeffs", "se2conv_coeffs_sum", "se2conv_table_info",
-    "se2conv_table_release", "se2conv_plan_counts", "se2conv_shift_table", "se2conv_apply_shifted", "se2conv_apply", "se2conv_apply_padded", "se2conv_apply_complex", "se2conv_chain", "se2conv_chain_noalloc", "se2conv_pass_times", "se2conv_field_coeffs",
+    "se2conv_table_release", "se2conv_table_quarter", "se2conv_plan_counts", "se2conv_shift_table", "se2conv_apply_shifted", "se2conv_apply", "se2conv_apply_padded", "se2conv_apply_complex", "se2conv_chain", "se2conv_chain_noalloc", "se2conv_pass_times", "se2conv_field_coeffs",
     "se2conv_profile_grad", "se2conv_powers", "se2conv_sample_bumps", "se2conv_autotune", "se2conv_kernel_grad",
     "se2conv_fused_supported", "se2conv_field_spectra", "se2conv_apply_save", "se2conv_backward",
     "se2conv_status_string",
@@ -88,6 +88,7 @@ def load() -> ctypes.CDLL:
                                        ctypes.POINTER(sz), vp]
     lib.se2conv_table_info.argtypes = [vp, vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(sz)]
     lib.se2conv_table_release.argtypes = [vp, vp]
+    lib.se2conv_table_quarter.argtypes = [vp, vp, vp, ctypes.POINTER(sz), vp]
     lib.se2conv_shift_table.argtypes = [vp, i32, ctypes.POINTER(Shift), i32, vp, ctypes.POINTER(sz), vp]
     lib.se2conv_apply_shifted.argtypes = [vp, i32, vp, vp, ctypes.POINTER(ctypes.c_void_p), i32, vp, i32, u32, vp]
     lib.se2conv_plan_counts.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -113,7 +114,8 @@ def load() -> ctypes.CDLL:
     lib.se2conv_last_error.argtypes = []
     lib.se2conv_last_error.restype = ctypes.c_char_p
     for name in ["se2conv_plan", "se2conv_plan_destroy", "se2conv_coeffs", "se2conv_coeffs_sum", "se2conv_table_info",
-                 "se2conv_table_release", "se2conv_plan_counts", "se2conv_shift_table", "se2conv_apply_shifted",
+                 "se2conv_table_release", "se2conv_table_quarter", "se2conv_plan_counts", "se2conv_shift_table",
+                 "se2conv_apply_shifted",
                  "se2conv_apply", "se2conv_apply_padded", "se2conv_apply_complex", "se2conv_chain",
                  "se2conv_chain_noalloc", "se2conv_pass_times",
                  "se2conv_field_coeffs",

@@ -100,11 +100,16 @@ class Table:
         return self.buf.data_ptr()
 
     def complex_view(self) -> torch.Tensor:
-        """The table as a complex tensor (SEPARABLE: [Nx+Ny+M]; FULL: [M][Ny][Nx])."""
+        """The table as a complex tensor (SEPARABLE: [Nx+Ny+M]; FULL: [M][Ny][Nx];
+        QUARTER: [M][Ny/2+1][Nx/2+1])."""
         nx, ny, m = self.plan.shapes[self.shape_idx]
         cdt = torch.complex64 if self.plan.dtype == L.F32 else torch.complex128
         v = self.buf.view(cdt)
-        return v if self.kind == L.TABLE_SEPARABLE else v.view(m, ny, nx)
+        if self.kind == L.TABLE_SEPARABLE:
+            return v
+        if self.kind == L.TABLE_QUARTER:
+            return v.view(m, ny // 2 + 1, nx // 2 + 1)
+        return v.view(m, ny, nx)
 
 
 class Plan:
@@ -169,6 +174,17 @@ class Plan:
         L.check(self._lib.se2conv_coeffs_sum(self.handle, shape_idx, descs, w, len(terms), buf.data_ptr(),
                                              ctypes.byref(nbytes), _stream_handle(stream)))
         return Table(self, shape_idx, buf, L.TABLE_FULL)
+
+    def quarter(self, table: Table, stream=None) -> Table:
+        """The FULL table folded by the reflection symmetries of a radial kernel
+        (se2conv_table_quarter): M (Ny/2+1) (Nx/2+1) coefficients, usable wherever the FULL
+        table is.  Raises if the table is not symmetric (a kernel not radial in translations)."""
+        nbytes = ctypes.c_size_t(0)
+        L.check(self._lib.se2conv_table_quarter(self.handle, table.ptr, None, ctypes.byref(nbytes), None))
+        buf = torch.empty(nbytes.value, dtype=torch.uint8, device="cuda")
+        L.check(self._lib.se2conv_table_quarter(self.handle, table.ptr, buf.data_ptr(), ctypes.byref(nbytes),
+                                                _stream_handle(stream)))
+        return Table(self, table.shape_idx, buf, L.TABLE_QUARTER)
 
     def apply(self, shape_idx: int, f: torch.Tensor, table: Table, out: torch.Tensor | None = None,
               adjoint: bool = False, stream=None, timing: bool = False) -> torch.Tensor:

@@ -262,6 +262,7 @@ struct se2conv_plan_s {
     void* ws4 = nullptr;               // four more planes (kernel gradient), allocated on first use
     void* scratch64 = nullptr;         // FP64 scratch for se2conv_coeffs
     size_t scratch64_bytes = 0;
+    void* qstat = nullptr;             // two u64 of se2conv_table_quarter's symmetry check, on first use
     void* sum64 = nullptr;             // FP64 accumulator of se2conv_coeffs_sum, allocated on first use
     size_t sum64_bytes = 0;
     void* pad_ws = nullptr;            // sampling-grid product spectra of se2conv_apply_padded
@@ -943,8 +944,9 @@ hipError_t y_pass(se2conv_plan_s* p, const se2conv_shape& s, bool d, void* re, v
         const size_t cb = cplx_bytes(p);
         b.ntab = ch->ntab;
         for (int j = 0; j < ch->ntab; ++j) {
-            if (ch->kind[j] == SE2CONV_TABLE_FULL) {
+            if (ch->kind[j] == SE2CONV_TABLE_FULL || ch->kind[j] == SE2CONV_TABLE_QUARTER) {
                 b.tab3[j] = ch->ptr[j];
+                if (ch->kind[j] == SE2CONV_TABLE_QUARTER) b.tab3_quarter |= 1u << j;
             } else {
                 b.tab3[j] = nullptr;
                 b.sepx[j] = ch->ptr[j];
@@ -988,8 +990,9 @@ hipError_t y_pass_io(se2conv_plan_s* p, const se2conv_shape& s, bool d, const vo
         const size_t cb = cplx_bytes(p);
         b.ntab = ch->ntab;
         for (int j = 0; j < ch->ntab; ++j) {
-            if (ch->kind[j] == SE2CONV_TABLE_FULL) {
+            if (ch->kind[j] == SE2CONV_TABLE_FULL || ch->kind[j] == SE2CONV_TABLE_QUARTER) {
                 b.tab3[j] = ch->ptr[j];
+                if (ch->kind[j] == SE2CONV_TABLE_QUARTER) b.tab3_quarter |= 1u << j;
             } else {
                 b.tab3[j] = nullptr;
                 b.sepx[j] = ch->ptr[j];
@@ -1022,7 +1025,7 @@ void set_chain(FullFastArgs* a, const Chain& ch, bool conj, double scale) {
     a->ntab = ch.ntab;
     for (int j = 0; j < ch.ntab; ++j) {
         a->tab[j] = ch.ptr[j];
-        a->tab_full[j] = ch.kind[j] == SE2CONV_TABLE_FULL ? 1 : 0;
+        a->tab_full[j] = ch.kind[j] == SE2CONV_TABLE_FULL ? 1 : ch.kind[j] == SE2CONV_TABLE_QUARTER ? 2 : 0;
     }
     a->conj_tab = conj ? 1 : 0;
     a->scale = (float)scale;
@@ -1199,8 +1202,9 @@ se2conv_status enqueue_shifted(se2conv_plan_s* p, const se2conv_shape& s, const 
     const size_t cb = cplx_bytes(p);
     b.ntab = ch.ntab;
     for (int j = 0; j < ch.ntab; ++j) {
-        if (ch.kind[j] == SE2CONV_TABLE_FULL) {
+        if (ch.kind[j] == SE2CONV_TABLE_FULL || ch.kind[j] == SE2CONV_TABLE_QUARTER) {
             b.tab3[j] = ch.ptr[j];
+            if (ch.kind[j] == SE2CONV_TABLE_QUARTER) b.tab3_quarter |= 1u << j;
         } else {
             b.tab3[j] = nullptr;
             b.sepx[j] = ch.ptr[j];
@@ -1544,6 +1548,7 @@ se2conv_status se2conv_plan_destroy(se2conv_plan_t p) {
         if (p->ws4) (void)hipFree(p->ws4);
         if (p->scratch64) (void)hipFree(p->scratch64);
         if (p->sum64) (void)hipFree(p->sum64);
+        if (p->qstat) (void)hipFree(p->qstat);
         if (p->basis) (void)hipFree(p->basis);
         if (p->basis_hat) (void)hipFree(p->basis_hat);
         if (p->pad_ws) (void)hipFree(p->pad_ws);
@@ -2092,6 +2097,59 @@ se2conv_status se2conv_table_info(se2conv_plan_t p, const void* d_table, int32_t
     if (kind) *kind = it->second.kind;
     if (shape_idx) *shape_idx = it->second.shape_idx;
     if (bytes) *bytes = it->second.bytes;
+    return ok();
+}
+
+se2conv_status se2conv_table_quarter(se2conv_plan_t p, const void* d_full, void* d_quarter, size_t* quarter_bytes,
+                                     hipStream_t stream) {
+    if (!p || !d_full || !quarter_bytes) return fail(SE2CONV_ERR_INVALID_ARG, "null argument");
+    int shape_idx = -1;
+    size_t full_bytes = 0;
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        auto it = p->tables.find(reinterpret_cast<uintptr_t>(d_full));
+        if (it == p->tables.end()) return fail(SE2CONV_ERR_INVALID_ARG, "table was not produced by this plan");
+        if (it->second.kind != SE2CONV_TABLE_FULL)
+            return fail(SE2CONV_ERR_INVALID_ARG, "only a FULL table can be folded (kind %d)", it->second.kind);
+        shape_idx = it->second.shape_idx;
+        full_bytes = it->second.bytes;
+    }
+    const se2conv_shape& s = p->shapes[shape_idx];
+    const size_t bytes = cplx_bytes(p) * (size_t)s.m * (size_t)(s.ny / 2 + 1) * (size_t)(s.nx / 2 + 1);
+    if (!d_quarter) {
+        *quarter_bytes = bytes;
+        return ok();
+    }
+    if (*quarter_bytes < bytes)
+        return fail(SE2CONV_ERR_INVALID_ARG, "quarter buffer too small (%zu < %zu)", *quarter_bytes, bytes);
+    if (!aligned16(d_quarter)) return fail(SE2CONV_ERR_INVALID_ARG, "quarter table must be 16-byte aligned");
+    const uintptr_t f0 = reinterpret_cast<uintptr_t>(d_full), q0 = reinterpret_cast<uintptr_t>(d_quarter);
+    if (q0 < f0 + full_bytes && f0 < q0 + bytes)
+        return fail(SE2CONV_ERR_INVALID_ARG, "the quarter table must not overlap the FULL table");
+    if (p->host_only) return fail(SE2CONV_ERR_DEVICE, "host-only plan cannot run device work");
+    std::lock_guard<std::mutex> g(p->mu);
+    if (!p->qstat && hipMalloc(&p->qstat, 2 * sizeof(unsigned long long)) != hipSuccess)
+        return fail(SE2CONV_ERR_OUT_OF_MEMORY, "symmetry-check buffer (16 bytes)");
+    auto* st = reinterpret_cast<unsigned long long*>(p->qstat);
+    HIPCHK(launch_quarter(d_full, d_quarter, s.nx, s.ny, s.m, dbl(p) ? 1 : 0, st, stream));
+    unsigned long long h[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(h, st, sizeof(h), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    double dev, big;
+    std::memcpy(&dev, &h[0], sizeof(double));
+    std::memcpy(&big, &h[1], sizeof(double));
+    // rounding level of a table generated in FP64 and rounded once to the plan dtype
+    const double tol = (dbl(p) ? 1e-12 : 1e-5) * big;
+    if (!(dev <= tol))
+        return fail(SE2CONV_ERR_INVALID_ARG,
+                    "table is not symmetric under k1 -> -k1, k2 -> -k2: max deviation %.3g against %.3g "
+                    "(max |T| %.3g); the kernel is not radial in translations",
+                    dev, tol, big);
+    TableRec rec;
+    rec.shape_idx = shape_idx;
+    rec.kind = SE2CONV_TABLE_QUARTER;
+    rec.bytes = bytes;
+    register_table(p, d_quarter, rec);
     return ok();
 }
 

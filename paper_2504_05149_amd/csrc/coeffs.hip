@@ -228,6 +228,58 @@ hipError_t launch_round(const double2* src, void* dst, long long n, int dbl, hip
     return hipGetLastError();
 }
 
+// Quarter table of a FULL table T[m][ny][nx] (complex, float2 or double2):
+// q[k3][b][a] = T[k3][b][a] for 0 <= a <= nx/2, 0 <= b <= ny/2, and the statistics of the
+// reflection symmetry max_k |T[k3][k2][k1] - T[k3][|k2|][|k1|]| (|k| = min(k, L - k), the
+// nonnegative signed frequency) and max_k |T[k]|, FP64, as the bit patterns of nonnegative
+// doubles (which order like the values) under atomicMax: stats[0], stats[1].
+template <typename CT>
+__global__ void quarter_kernel(const CT* __restrict__ full, CT* __restrict__ q, int nx, int ny, int m,
+                               unsigned long long* stats) {
+    const int hx = nx / 2 + 1, hy = ny / 2 + 1;
+    const long long n = (long long)nx * ny * m;
+    double dev = 0.0, big = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+        const int kx = (int)(i % nx);
+        const long long r = i / nx;
+        const int ky = (int)(r % ny);
+        const int kt = (int)(r / ny);
+        const int ax = min(kx, nx - kx), ay = min(ky, ny - ky);
+        const CT v = full[i];
+        const CT w = full[((long long)kt * ny + ay) * nx + ax];
+        dev = fmax(dev, hypot((double)v.x - (double)w.x, (double)v.y - (double)w.y));
+        big = fmax(big, hypot((double)v.x, (double)v.y));
+        if (kx == ax && ky == ay) q[((long long)kt * hy + ay) * hx + ax] = v;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        dev = fmax(dev, __shfl_xor(dev, o));
+        big = fmax(big, __shfl_xor(big, o));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&stats[0], (unsigned long long)__double_as_longlong(dev));
+        atomicMax(&stats[1], (unsigned long long)__double_as_longlong(big));
+    }
+}
+
+__global__ void zero_u64_kernel(unsigned long long* p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
+}
+
+hipError_t launch_quarter(const void* full, void* q, int nx, int ny, int m, int dbl, unsigned long long* stats,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, s, stats, 2);
+    const long long n = (long long)nx * ny * m;
+    long long nb = (n + 255) / 256;
+    if (nb > 8192) nb = 8192;
+    if (dbl)
+        hipLaunchKernelGGL(quarter_kernel<double2>, dim3((unsigned)nb), dim3(256), 0, s,
+                           reinterpret_cast<const double2*>(full), reinterpret_cast<double2*>(q), nx, ny, m, stats);
+    else
+        hipLaunchKernelGGL(quarter_kernel<float2>, dim3((unsigned)nb), dim3(256), 0, s,
+                           reinterpret_cast<const float2*>(full), reinterpret_cast<float2*>(q), nx, ny, m, stats);
+    return hipGetLastError();
+}
+
 // One weighted term of a sum of kernel tables, accumulated in FP64.
 __global__ void axpy64_kernel(const double2* __restrict__ x, double2* __restrict__ y, long long n, double w,
                               int first) {

@@ -20,6 +20,10 @@ hipError_t launch_full_fold(const double* re, const double* im, double2* acc, lo
 hipError_t launch_full_fold_sep(const double2* sep, double2* acc, long long n, int nx, int ny, int first,
                                 hipStream_t s);
 hipError_t launch_round(const double2* src, void* dst, long long n, int dbl, hipStream_t s);
+// Quarter table q[m][ny/2+1][nx/2+1] of a FULL table (plan dtype: dbl selects double2),
+// with stats[0] = max |T[k] - T[|k1|, |k2|, k3]| and stats[1] = max |T[k]| (FP64 bit patterns)
+hipError_t launch_quarter(const void* full, void* q, int nx, int ny, int m, int dbl, unsigned long long* stats,
+                          hipStream_t s);
 // y = (first ? 0 : y) + w x over n complex FP64 values (sums of kernel tables)
 hipError_t launch_axpy64(const double2* x, double2* y, long long n, double w, int first, hipStream_t s);
 // Radial-profile tables from the 2-D DFT of the hat basis (cached per geometry):

@@ -530,6 +530,14 @@ __device__ __forceinline__ void line_fft(C<T>* buf, const C<T>* tw, const RadixP
     }
 }
 
+// Offset of the coefficient at array indices (k3, k2, k1) in a quarter table
+// [m][ny/2+1][nx/2+1]: the entry at the nonnegative signed frequencies |k1|, |k2|
+// (k -> min(k, L - k); the Nyquist index of an even length maps to itself).
+__device__ __forceinline__ long long quarter_offset(int kt, int ky, int kx, int nx, int ny) {
+    const int ax = min(kx, nx - kx), ay = min(ky, ny - ky);
+    return ((long long)kt * (ny / 2 + 1) + ay) * (nx / 2 + 1) + ax;
+}
+
 // Workgroups are handed to the chip's 8 XCDs in turn (workgroup b to XCD b mod 8), each
 // XCD with its own L2.  xcd_contiguous(b, G) renumbers the G workgroups of a launch so
 // that every XCD receives one contiguous range of the new indices, in its own dispatch

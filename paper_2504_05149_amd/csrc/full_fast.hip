@@ -273,8 +273,10 @@ __device__ __forceinline__ float2 full_table_factor(const FullFastArgs& a, int N
     float2 f = make_float2(scale, 0.f);
     for (int e = 0; e < a.ntab; ++e) {
         const float2* T = reinterpret_cast<const float2*>(a.tab[e]);
-        if (a.tab_full[e]) {
+        if (a.tab_full[e] == 1) {
             f = mul<float>(f, T[(long long)kt * pl + ky * a.nx + kx]);
+        } else if (a.tab_full[e] == 2) {
+            f = mul<float>(f, T[quarter_offset(kt, ky, kx, a.nx, NYv)]);
         } else {
             f = mul<float>(f, T[kx]);
             f = mul<float>(f, T[a.nx + ky]);
@@ -292,9 +294,10 @@ __device__ __forceinline__ float2 full_table_factor(const FullFastArgs& a, int N
 //   in the same sweep A[k] = sum_pairs Z_g[k] conj(Z_f[k]) with the field spectra Z_f
 //   (zf); at the end W[k] A[k] / n^2 goes through the inverse DFT along y to acc (two
 //   planes).  Its x-theta inverse has real part dL/dP summed over the batch.
-// T1: the chain is one FULL table (read with 32-bit offsets; the general product loop,
-// compiled in, would cost the registers of a fourth wave per SIMD).
-template <int NY, int MODE, bool T1 = false>
+// TK: the chain is one FULL table (1) or one quarter table (2), read with 32-bit offsets
+// (the general product loop, compiled in, would cost the registers of a fourth wave per
+// SIMD); 0: any chain.
+template <int NY, int MODE, int TK = 0>
 __global__ void __launch_bounds__((FullLineGeom<NY, MODE>::NT)) y_full(FullFastArgs a) {
     using Gm = FullLineGeom<NY, MODE>;
     constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC, W = Gm::W, NT = Gm::NT;
@@ -404,7 +407,7 @@ __global__ void __launch_bounds__((FullLineGeom<NY, MODE>::NT)) y_full(FullFastA
             if constexpr (MODE == 2) {
 #pragma unroll
                 for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = mul<float>(u[j][k2], tv[j][k2]);
-            } else if constexpr (T1) {
+            } else if constexpr (TK == 1) {
                 // one FULL table: 32-bit byte offsets from the uniform table base
                 const char* T = reinterpret_cast<const char*>(a.tab[0]);
                 const unsigned o0 = (unsigned)(base + k1 * a.nx) * 8u;
@@ -413,6 +416,20 @@ __global__ void __launch_bounds__((FullLineGeom<NY, MODE>::NT)) y_full(FullFastA
 #pragma unroll
                 for (int k2 = 0; k2 < R2; ++k2) {
                     const float2 tf = *reinterpret_cast<const float2*>(T + (o0 + (unsigned)k2 * ostep));
+                    u[j][k2] = mul<float>(u[j][k2], make_float2(tf.x * sc, tf.y * sg));
+                }
+            } else if constexpr (TK == 2) {
+                // one quarter table: row |ky| of plane kt, column |kx|
+                const float2* T = reinterpret_cast<const float2*>(a.tab[0]);
+                const int kx = ct * W + q;
+                const int hx = a.nx / 2 + 1;
+                const int col = min(kx, a.nx - kx);
+                const int row0 = kt * (NY / 2 + 1);
+                const float sc = a.scale, sg = a.conj_tab ? -a.scale : a.scale;
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) {
+                    const int ky = k1 + R1 * k2;
+                    const float2 tf = T[(row0 + min(ky, NY - ky)) * hx + col];
                     u[j][k2] = mul<float>(u[j][k2], make_float2(tf.x * sc, tf.y * sg));
                 }
             } else {
@@ -633,8 +650,10 @@ __device__ __forceinline__ float2 grid_table_factor(const FullFastArgs& a, int l
     float2 f = make_float2(1.f, 0.f);
     for (int e = 0; e < a.ntab; ++e) {
         const float2* T = reinterpret_cast<const float2*>(a.tab[e]);
-        if (a.tab_full[e]) {
+        if (a.tab_full[e] == 1) {
             f = mul<float>(f, T[((long long)kt * ly + ky) * lx + kx]);
+        } else if (a.tab_full[e] == 2) {
+            f = mul<float>(f, T[quarter_offset(kt, ky, kx, lx, ly)]);
         } else {
             f = mul<float>(f, T[kx]);
             f = mul<float>(f, T[lx + ky]);
@@ -734,10 +753,12 @@ static hipError_t launch_y_full_t(const FullFastArgs& a, hipStream_t s) {
     const int nblocks = (a.nx / FullLineGeom<NY, MODE>::W) * a.m * (MODE == 2 ? 1 : (a.batch + 1) / 2);
     const int nthr = FullLineGeom<NY, MODE>::NT;
     const size_t lds = full_line_lds<NY, MODE>();
-    if (MODE == 0 && a.ntab == 1 && a.tab_full[0])
-        hipLaunchKernelGGL((y_full<NY, MODE, true>), dim3(nblocks), dim3(nthr), lds, s, a);
+    if (MODE == 0 && a.ntab == 1 && a.tab_full[0] == 1)
+        hipLaunchKernelGGL((y_full<NY, MODE, 1>), dim3(nblocks), dim3(nthr), lds, s, a);
+    else if (MODE == 0 && a.ntab == 1 && a.tab_full[0] == 2)
+        hipLaunchKernelGGL((y_full<NY, MODE, 2>), dim3(nblocks), dim3(nthr), lds, s, a);
     else
-        hipLaunchKernelGGL((y_full<NY, MODE, false>), dim3(nblocks), dim3(nthr), lds, s, a);
+        hipLaunchKernelGGL((y_full<NY, MODE, 0>), dim3(nblocks), dim3(nthr), lds, s, a);
     return hipGetLastError();
 }
 
@@ -806,7 +827,10 @@ hipError_t launch_y_full_powers(const FullFastArgs& a, hipStream_t s) {
     if (e != hipSuccess) return e;
 #define SE2C_Y_FULL_ATTR(NY_)                                                                               \
     SE2C_Y_FULL_ATTR1(NY_, 0) SE2C_Y_FULL_ATTR1(NY_, 1) SE2C_Y_FULL_ATTR1(NY_, 2)                            \
-    e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full<NY_, 0, true>),                             \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full<NY_, 0, 1>),                                \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_, 0>());       \
+    if (e != hipSuccess) return e;                                                                          \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full<NY_, 0, 2>),                                \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_, 0>());       \
     if (e != hipSuccess) return e;                                                                          \
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full_pad_inv<NY_>),                              \

@@ -23,7 +23,7 @@ struct FullFastArgs {
     // y pass: product with scale * prod_j T_j (FULL: [m][ny][nx]; SEPARABLE: Tx Ty Tt)
     int ntab;
     const void* tab[SE2C_MAX_TABLES];
-    int tab_full[SE2C_MAX_TABLES];
+    int tab_full[SE2C_MAX_TABLES];  // 1 FULL [m][ny][nx], 2 quarter [m][ny/2+1][nx/2+1], 0 SEPARABLE
     float scale;
     int conj_tab;
     float* save;            // y pass: if non-null, the spectrum before the product goes to

@@ -391,7 +391,13 @@ __global__ void __launch_bounds__((ODD || SHIFT) ? 512 : SE2C_MAX_THREADS(T)) pe
                     C<T> w = mk<T>(sc, (T)0);
                     for (int j = 0; j < a.ntab; ++j) {
                         if (a.tab3[j]) {
-                            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.tab3[j])[(long long)kt * plane + (long long)ky * a.nx + kx]);
+                            // FULL [m][ny][nx], or quarter [m][ny/2+1][nx/2+1] at |ky|, |kx|
+                            const bool qj = (a.tab3_quarter >> j) & 1u;
+                            const int ax = qj ? min(kx, a.nx - kx) : kx;
+                            const int ay = qj ? min(ky, a.ny - ky) : ky;
+                            const long long off = ((long long)kt * (qj ? a.ny / 2 + 1 : a.ny) + ay) *
+                                                      (qj ? a.nx / 2 + 1 : a.nx) + ax;
+                            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.tab3[j])[off]);
                         } else {
                             w = mul<T>(w, reinterpret_cast<const C<T>*>(a.sepx[j])[kx]);
                             w = mul<T>(w, reinterpret_cast<const C<T>*>(a.sepy[j])[ky]);

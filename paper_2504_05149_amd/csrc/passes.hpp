@@ -101,6 +101,7 @@ struct PencilArgs {
     int ntab;
     const void* tab1[SE2C_MAX_TABLES];    // 1-D factor along this axis (mul == 1)
     const void* tab3[SE2C_MAX_TABLES];    // full [m][ny][nx] table, or nullptr if separable
+    unsigned tab3_quarter;                // bit j: tab3[j] is a quarter table [m][ny/2+1][nx/2+1]
     const void* sepx[SE2C_MAX_TABLES];    // separable factors for mul == 2 with sep tables
     const void* sepy[SE2C_MAX_TABLES];
     const void* sept[SE2C_MAX_TABLES];

@@ -252,3 +252,18 @@ def test_shift_table_validation_on_host_only_plan():
     assert lib.se2conv_apply_shifted(plan.handle, 0, ctypes.c_void_p(0x1000), ctypes.c_void_p(0x3000), tp, 1,
                                      ctypes.c_void_p(0x4000), 1, 0, None) == L.ERR_INVALID_ARG
     plan.close()
+
+
+def test_table_quarter_validation_on_host_only_plan():
+    plan = se2.Plan([(32, 32, 16)], host_only=True)
+    lib = L.load()
+    nb = ctypes.c_size_t(0)
+    # only a FULL table this plan recorded can be folded
+    assert lib.se2conv_table_quarter(plan.handle, ctypes.c_void_p(0x1000), None, ctypes.byref(nb),
+                                     None) == L.ERR_INVALID_ARG
+    assert "not produced by this plan" in lib.se2conv_last_error().decode()
+    assert lib.se2conv_table_quarter(plan.handle, None, None, ctypes.byref(nb), None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_table_quarter(plan.handle, ctypes.c_void_p(0x1000), None, None, None) == L.ERR_INVALID_ARG
+    assert lib.se2conv_table_quarter(None, ctypes.c_void_p(0x1000), None, ctypes.byref(nb),
+                                     None) == L.ERR_INVALID_ARG
+    plan.close()

@@ -71,3 +71,23 @@ def test_power_form_equals_repeated_convolution():
         for _ in range(q):
             rep = C.conv_chain(rep, [p])
         assert rel_l2(C.alg4_power(f, p, q), rep) < 1e-13
+
+
+def test_reflection_symmetry_on_rectangular_and_odd_grids():
+    # the quarter tables keep the coefficients at nonnegative k1, k2: a kernel radial in
+    # translations sampled on any grid (odd, even, rectangular) is even in x and in y, so
+    # its coefficients are fixed by k1 -> -k1 and k2 -> -k2 separately
+    for nx, ny, m in [(12, 20, 8), (15, 9, 7), (11, 16, 6)]:
+        c = ffc(K.sample_function(K.exp_gauss_function(0.2), nx, ny, m))
+        big = np.max(np.abs(c))
+        assert np.max(np.abs(c - c[:, :, (-np.arange(nx)) % nx])) < 1e-15 * big * 8
+        assert np.max(np.abs(c - c[:, (-np.arange(ny)) % ny, :])) < 1e-15 * big * 8
+    # a Gaussian stretched along a 30-degree axis is not radial: its table is not fixed
+    cs, sn = np.cos(np.pi / 6), np.sin(np.pi / 6)
+
+    def tilted(x, y, t):
+        u, v = cs * x + sn * y, -sn * x + cs * y
+        return np.exp(-u * u / (2 * 0.05 ** 2) - v * v / (2 * 0.15 ** 2)) * np.exp(np.cos(t))
+
+    c = ffc(K.sample_function(tilted, 12, 20, 8))
+    assert np.max(np.abs(c - c[:, :, (-np.arange(12)) % 12])) > 1e-3 * np.max(np.abs(c))
