@@ -1169,8 +1169,25 @@ se2conv_status enqueue_shifted(se2conv_plan_s* p, const se2conv_shape& s, const 
     const void* f1 = batch == 1 ? nullptr : (const char*)f + rb * n;
     void* o1 = batch == 1 ? nullptr : (char*)out + rb * n;
     void* lone = odd ? p->ws : nullptr;  // the odd field's imaginary plane between the passes
-    HIPCHK(x_pass(p, s, d, 0, f, f1, out, o1, nullptr, lone, 2 * n, pairs, st));
-    HIPCHK(y_pass(p, s, d, out, o1, lone, 2 * n, pairs, 1, 0, 0, nullptr, false, 1.0, st));
+    // FP32 register kernels where the full-table path has them: x forward (theta in space),
+    // y forward, [shift mix, theta forward, product] in the pencils, y inverse, then the
+    // x-theta inverse; else the generic passes with the theta inverse in the pencils
+    const bool fast = use_full_fast(p, s);
+    if (fast) {
+        FullFastArgs a = full_fast_args(p, s, batch);
+        a.in = reinterpret_cast<const float*>(f);
+        a.out = reinterpret_cast<float*>(out);
+        HIPCHK(launch_x_full_fwd(a, st));
+        HIPCHK(after_pass(3, st));
+        a.in = a.out;
+        a.save = a.out;  // the y spectra in place (a lone last field's im plane in lone)
+        a.save_lone = a.lone;
+        HIPCHK(launch_y_full_spectra(a, st));
+        HIPCHK(after_pass(1, st));
+    } else {
+        HIPCHK(x_pass(p, s, d, 0, f, f1, out, o1, nullptr, lone, 2 * n, pairs, st));
+        HIPCHK(y_pass(p, s, d, out, o1, lone, 2 * n, pairs, 1, 0, 0, nullptr, false, 1.0, st));
+    }
     PencilArgs b{};
     b.in0 = out;
     b.in1 = o1;
@@ -1191,7 +1208,7 @@ se2conv_status enqueue_shifted(se2conv_plan_s* p, const se2conv_shape& s, const 
     if (!odd_len(s.m))  // the shift-mix pencils hold SE2C_MAXV_SHIFT values per thread
         while (b.W > 1 && (long long)b.W * s.m > (long long)SE2C_MAXV_SHIFT * 512) b.W /= 2;
     b.fwd = 1;
-    b.inv = 1;
+    b.inv = fast ? 0 : 1;
     b.mul = 3;
     b.p = radix_plan_of(p, s.m, d);
     b.tw = stage_tw_of(p, b.p, d);
@@ -1213,6 +1230,16 @@ se2conv_status enqueue_shifted(se2conv_plan_s* p, const se2conv_shape& s, const 
         }
     }
     HIPCHK(run_pencil(b, d, st));
+    if (fast) {
+        FullFastArgs a = full_fast_args(p, s, batch);
+        a.in = reinterpret_cast<const float*>(out);
+        a.out = reinterpret_cast<float*>(out);
+        HIPCHK(launch_y_full_inverse(a, st));
+        HIPCHK(after_pass(1, st));
+        HIPCHK(launch_xt_full_inv(a, st));
+        HIPCHK(after_pass(0, st));
+        return SE2CONV_OK;
+    }
     HIPCHK(y_pass(p, s, d, out, o1, lone, 2 * n, pairs, 0, 1, 0, nullptr, false, 1.0, st));
     HIPCHK(x_pass(p, s, d, 1, out, o1, out, o1, lone, nullptr, 2 * n, pairs, st));
     return SE2CONV_OK;

@@ -10,12 +10,15 @@
 //   register decomposition, one XOR-swizzled LDS exchange), rows -> columns through
 //   LDS, forward DFT along theta in registers (TPC = 2: the last radix-2 step across
 //   neighbouring lanes via DPP); stores the x-theta spectrum as re/im planes.
-// y_full<NY, MODE>  one block per (theta frequency, 16 x frequencies), all pairs in
-//   turn: forward DFT along y, [copy of the spectrum], product with the table (loaded
-//   once per block for every pair), inverse DFT along y, in place; MODE 2 also
-//   accumulates the kernel-sample gradient of the batch (see below).
+// y_full<NY, MODE>  one block per (theta frequency, 16 or 32 x frequencies, pair), the
+//   blocks of one tile back to back on one XCD: forward DFT along y, [copy of the
+//   spectrum], product with the table, inverse DFT along y, in place; MODE 2 walks the
+//   pairs in one block and accumulates the kernel-sample gradient of the batch (see below).
 // xt_full<NX, M, DIR = 1>  the mirror image of the first pass: inverse DFT along
 //   theta (columns), columns -> rows, inverse DFT along x, stores the two real fields.
+// xt_full<NX, M, DIR = 2>  the first pass without the theta DFT (x spectrum at every
+//   theta row), and y_full MODE 1 / MODE 4 (forward / inverse along y only): the passes
+//   around a theta pass that needs theta in space (sums of SE(2)-shifted kernels).
 #include "fast_common.hpp"
 #include "full_fast.hpp"
 #include "regfft.hpp"
@@ -75,7 +78,7 @@ xt_full(FullFastArgs a) {
     float2 w[RPT][16];
     float2 v[MV];
 
-    if constexpr (DIR == 0) {
+    if constexpr (DIR == 0 || DIR == 2) {
         // a lone last field is paired with zero (its row is read twice and masked, which
         // keeps the loads free of per-load branches)
         const float* __restrict__ in0 = a.in + (long long)(2 * pair) * a.n + (long long)y * NX;
@@ -130,8 +133,9 @@ xt_full(FullFastArgs a) {
 #pragma unroll
             for (int l = h * RC / TPC; l < (h + 1) * RC / TPC; ++l) v[l] = buf[(TPC * l + hh - h * RC) * P + xc];
         }
-        // forward DFT along theta
-        if constexpr (TPC == 1) {
+        // forward DFT along theta (DIR 2: x only, theta stays spatial)
+        if constexpr (DIR == 2) {
+        } else if constexpr (TPC == 1) {
             RegDFT<M, false, float>::run(v);
         } else {
             // theta = hh + 2 s: Y_hh = DFT over s; X[k] = Y_0 + w^k Y_1, X[k + M/2] = Y_0 - w^k Y_1
@@ -151,7 +155,8 @@ xt_full(FullFastArgs a) {
         float* __restrict__ o_im = (has_b ? a.out + (long long)(2 * pair + 1) * a.n : a.lone) + (long long)y * NX;
 #pragma unroll
         for (int l = 0; l < MV; ++l) {
-            const int kt = TPC == 1 ? l : l + hh * MV;
+            // theta frequency (after the split of TPC == 2), or theta row TPC l + hh (DIR 2)
+            const int kt = DIR == 2 ? TPC * l + hh : (TPC == 1 ? l : l + hh * MV);
             const int off = kt * pl + xc;
             __builtin_nontemporal_store(v[l].x, o_re + off);
             __builtin_nontemporal_store(v[l].y, o_im + off);
@@ -250,7 +255,7 @@ xt_full(FullFastArgs a) {
 // 256^2 x 64) where the LDS allows; the backward keeps 16 (its accumulator and table
 // registers limit occupancy either way).
 template <int NY, int MODE> struct YFullW {
-    static constexpr int W = (MODE <= 1 && NY <= 256) ? 32 : 16;
+    static constexpr int W = ((MODE <= 1 || MODE == 4) && NY <= 256) ? 32 : 16;
 };
 
 template <int NY, int MODE> struct FullLineGeom {
@@ -358,26 +363,37 @@ __global__ void __launch_bounds__((FullLineGeom<NY, MODE>::NT)) y_full(FullFastA
         float* __restrict__ re = a.out + (long long)(2 * pair) * a.n;
         float* __restrict__ im = 2 * pair + 1 < a.batch ? re + a.n : a.lone;
         float2 w[R1];
-#pragma unroll
-        for (int r = 0; r < R1; ++r) w[r] = make_float2(re[lane_off + r * rstride], im[lane_off + r * rstride]);
-        RegDFT<R1, false, float>::run(w);
-#pragma unroll
-        for (int k1 = 1; k1 < R1; ++k1) w[k1] = mul<float>(w[k1], tw_f[k1 * R2 + t]);
-        __syncthreads();
-#pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1) buf[(k1 * R2 + t) * W + q] = w[k1];
-        __syncthreads();
         float2 u[CC][R2];
+        if constexpr (MODE == 4) {
+            // the y spectrum at ky = CC t + j + R1 k2, as the forward pass leaves it
 #pragma unroll
-        for (int j = 0; j < CC; ++j) {
-            const int k1 = CC * t + j;
+            for (int j = 0; j < CC; ++j)
 #pragma unroll
-            for (int tt = 0; tt < R2; ++tt) u[j][tt] = buf[(k1 * R2 + tt) * W + q];
-            RegDFT<R2, false, float>::run(u[j]);
+                for (int k2 = 0; k2 < R2; ++k2) {
+                    const int off = base + (CC * t + j + R1 * k2) * a.nx;
+                    u[j][k2] = make_float2(re[off], im[off]);
+                }
+        } else {
+#pragma unroll
+            for (int r = 0; r < R1; ++r) w[r] = make_float2(re[lane_off + r * rstride], im[lane_off + r * rstride]);
+            RegDFT<R1, false, float>::run(w);
+#pragma unroll
+            for (int k1 = 1; k1 < R1; ++k1) w[k1] = mul<float>(w[k1], tw_f[k1 * R2 + t]);
+            __syncthreads();
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) buf[(k1 * R2 + t) * W + q] = w[k1];
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < CC; ++j) {
+                const int k1 = CC * t + j;
+#pragma unroll
+                for (int tt = 0; tt < R2; ++tt) u[j][tt] = buf[(k1 * R2 + tt) * W + q];
+                RegDFT<R2, false, float>::run(u[j]);
+            }
         }
-        if (MODE == 1 || a.save) {
+        if (MODE == 1 || (MODE != 4 && a.save)) {
             float* s_re = a.save + (long long)(2 * pair) * a.n;
-            float* s_im = s_re + a.n;
+            float* s_im = (2 * pair + 1 < a.batch || !a.save_lone) ? s_re + a.n : a.save_lone;
 #pragma unroll
             for (int j = 0; j < CC; ++j)
 #pragma unroll
@@ -404,7 +420,9 @@ __global__ void __launch_bounds__((FullLineGeom<NY, MODE>::NT)) y_full(FullFastA
 #pragma unroll
         for (int j = 0; j < CC; ++j) {
             const int k1 = CC * t + j;
-            if constexpr (MODE == 2) {
+            if constexpr (MODE == 4) {
+                // inverse only: no product
+            } else if constexpr (MODE == 2) {
 #pragma unroll
                 for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = mul<float>(u[j][k2], tv[j][k2]);
             } else if constexpr (TK == 1) {
@@ -513,7 +531,7 @@ static hipError_t launch_xt_full_t(const FullFastArgs& a, hipStream_t s) {
 }
 
 #define SE2C_XT_FULL_CASE(NX_, M_) \
-    if (a.nx == NX_ && a.m == M_) return DIR ? launch_xt_full_t<NX_, M_, 1>(a, s) : launch_xt_full_t<NX_, M_, 0>(a, s);
+    if (a.nx == NX_ && a.m == M_) return launch_xt_full_t<NX_, M_, DIR>(a, s);
 
 template <int DIR>
 static hipError_t launch_xt_full(const FullFastArgs& a, hipStream_t s) {
@@ -526,6 +544,7 @@ static hipError_t launch_xt_full(const FullFastArgs& a, hipStream_t s) {
 
 hipError_t launch_xt_full_fwd(const FullFastArgs& a, hipStream_t s) { return launch_xt_full<0>(a, s); }
 hipError_t launch_xt_full_inv(const FullFastArgs& a, hipStream_t s) { return launch_xt_full<1>(a, s); }
+hipError_t launch_x_full_fwd(const FullFastArgs& a, hipStream_t s) { return launch_xt_full<2>(a, s); }
 
 // All powers (Alg. 7) along y, MODE 3 geometry: each workgroup (theta frequency, 16 x
 // frequencies) walks the pairs; a pair's y spectrum Z (forward DFT of the x-theta spectrum
@@ -775,6 +794,7 @@ static hipError_t launch_y_full_mode(const FullFastArgs& a, hipStream_t s) {
 hipError_t launch_y_full(const FullFastArgs& a, hipStream_t s) { return launch_y_full_mode<0>(a, s); }
 hipError_t launch_y_full_spectra(const FullFastArgs& a, hipStream_t s) { return launch_y_full_mode<1>(a, s); }
 hipError_t launch_y_full_backward(const FullFastArgs& a, hipStream_t s) { return launch_y_full_mode<2>(a, s); }
+hipError_t launch_y_full_inverse(const FullFastArgs& a, hipStream_t s) { return launch_y_full_mode<4>(a, s); }
 
 template <int NY>
 static hipError_t launch_y_full_powers_t(const FullFastArgs& a, hipStream_t s) {
@@ -820,13 +840,16 @@ hipError_t launch_y_full_powers(const FullFastArgs& a, hipStream_t s) {
     if (e != hipSuccess) return e;                                                                          \
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(xt_full<NX_, M_, 1>),                              \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_slab_lds<NX_, M_>());      \
+    if (e != hipSuccess) return e;                                                                          \
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(xt_full<NX_, M_, 2>),                              \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_slab_lds<NX_, M_>());      \
     if (e != hipSuccess) return e;
 #define SE2C_Y_FULL_ATTR1(NY_, MODE_)                                                                       \
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full<NY_, MODE_>),                               \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_, MODE_>());   \
     if (e != hipSuccess) return e;
 #define SE2C_Y_FULL_ATTR(NY_)                                                                               \
-    SE2C_Y_FULL_ATTR1(NY_, 0) SE2C_Y_FULL_ATTR1(NY_, 1) SE2C_Y_FULL_ATTR1(NY_, 2)                            \
+    SE2C_Y_FULL_ATTR1(NY_, 0) SE2C_Y_FULL_ATTR1(NY_, 1) SE2C_Y_FULL_ATTR1(NY_, 2) SE2C_Y_FULL_ATTR1(NY_, 4)   \
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_full<NY_, 0, 1>),                                \
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)full_line_lds<NY_, 0>());       \
     if (e != hipSuccess) return e;                                                                          \

@@ -28,6 +28,8 @@ struct FullFastArgs {
     int conj_tab;
     float* save;            // y pass: if non-null, the spectrum before the product goes to
                             // save (slots 2p, 2p + 1 per pair, planes as above)
+    float* save_lone;       // if non-null, slot 2p + 1 of a lone last field goes here instead
+                            // (save == out in place: the lone field's im plane, as lone)
     // backward y pass
     const float* zf;        // field spectra (slots 2p, 2p + 1 per pair)
     float* acc;             // two planes: W A / n^2 after the inverse DFT along y
@@ -48,10 +50,15 @@ bool full_fast_supported(int nx, int ny, int m);
 hipError_t launch_xt_full_fwd(const FullFastArgs& a, hipStream_t s);
 // x-theta inverse DFT (in: spectrum planes, out: fields; may alias), no scaling
 hipError_t launch_xt_full_inv(const FullFastArgs& a, hipStream_t s);
+// forward DFT along x only (in: fields, out: re/im planes of each pair, theta in space)
+hipError_t launch_x_full_fwd(const FullFastArgs& a, hipStream_t s);
 // y pass in place on the spectrum planes of every pair: forward DFT, [save], product, inverse
 hipError_t launch_y_full(const FullFastArgs& a, hipStream_t s);
 // y pass: forward DFT only, written to save
 hipError_t launch_y_full_spectra(const FullFastArgs& a, hipStream_t s);
+// y pass: inverse DFT along y only, in place on the planes (the inverse of the spectra pass
+// with save = out)
+hipError_t launch_y_full_inverse(const FullFastArgs& a, hipStream_t s);
 // y pass of the backward: adjoint product in place, kernel-sample gradient accumulated to acc
 hipError_t launch_y_full_backward(const FullFastArgs& a, hipStream_t s);
 // y pass of all powers (Alg. 7): forward DFT of the spectrum planes in the last slot, then

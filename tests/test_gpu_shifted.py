@@ -40,6 +40,9 @@ CASES = [
     (24, 20, 12, 3, 5, 3, "f32"),
     (48, 36, 10, 1, 6, 4, "f32"),
     (64, 64, 64, 2, 8, 8, "f32"),
+    # register kernels around the shift-mix pass: odd batch, a single field, rectangular grids
+    (64, 32, 32, 3, 5, 3, "f32"),
+    (128, 64, 16, 1, 4, 2, "f32"),
 ]
 
 
