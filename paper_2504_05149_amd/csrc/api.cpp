@@ -1229,7 +1229,20 @@ se2conv_status enqueue_shifted(se2conv_plan_s* p, const se2conv_shape& s, const 
             b.sept[j] = (const char*)ch.ptr[j] + cb * (s.nx + s.ny);
         }
     }
-    HIPCHK(run_pencil(b, d, st));
+    if (fast && t_shift_supported(s.nx, s.m, (int)rolls.size())) {
+        // the theta pass on register kernels: the shift-phase tiles in LDS for every pair
+        FullFastArgs a = full_fast_args(p, s, batch);
+        a.in = reinterpret_cast<const float*>(out);
+        a.out = reinterpret_cast<float*>(out);
+        set_chain(&a, ch, false, 1.0 / (double)n);
+        a.qtab = reinterpret_cast<const float2*>(qtab);
+        a.nshift = (int)rolls.size();
+        for (size_t j = 0; j < rolls.size(); ++j) a.rolls[j] = rolls[j];
+        HIPCHK(launch_t_shift(a, st));
+        HIPCHK(after_pass(2, st));
+    } else {
+        HIPCHK(run_pencil(b, d, st));
+    }
     if (fast) {
         FullFastArgs a = full_fast_args(p, s, batch);
         a.in = reinterpret_cast<const float*>(out);

@@ -767,6 +767,151 @@ __global__ void __launch_bounds__((FullLineGeom<NY, 3>::NT)) y_full_pad_inv(Full
     }
 }
 
+// Shift-mix theta pass of a sum of SE(2)-shifted kernels, on the x-y spectrum planes with
+// theta still in space: one block per (y frequency ky, 16 x frequencies), PG groups of
+// threads taking PG pairs of the batch at a time (every pair of a batch of 8 at once at
+// M = 64); the block's shift-phase tiles Q_j[alpha][ky][kx0 .. kx0 + 15] are loaded into
+// LDS with the first pairs' tiles and serve every pair.  Per pair:
+// z'[alpha] = sum_j z[alpha - r_j] Q_j[alpha - r_j] (indices mod M) from the pair's tile in
+// LDS, the forward DFT along theta in registers (M = R1 x R2, one LDS exchange in the same
+// tile), the product with the chain's factor at (kx, ky, kt) (scale 1/n, conjugated for the
+// adjoint), stored in place; the x-theta inverse pass follows.  Blocks of neighbouring
+// column tiles run back to back on one XCD (64-byte rows: halves of the same cache lines).
+template <int M> struct ShiftGeom {
+    static constexpr int R1 = M == 16 ? 8 : 16;
+    static constexpr int R2 = M / R1;
+    static constexpr int CC = R1 / R2;
+    static constexpr int W = 16;
+    static constexpr int LT = W * R2;  // threads per pair group
+    static constexpr int PG = 256 / LT;
+    static constexpr int NT = LT * PG;
+    static_assert(R1 * R2 == M && CC * R2 == R1 && NT == 256, "shift pass geometry");
+};
+
+template <int M>
+static size_t t_shift_lds(int nshift) {
+    using Gm = ShiftGeom<M>;
+    return sizeof(float2) * ((size_t)2 * M + (size_t)(nshift + Gm::PG) * M * Gm::W);
+}
+
+template <int M>
+__global__ void __launch_bounds__(256) t_shift_full(FullFastArgs a) {
+    using Gm = ShiftGeom<M>;
+    constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC, W = Gm::W, LT = Gm::LT, PG = Gm::PG, NT = Gm::NT;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    float2* tw_f = reinterpret_cast<float2*>(smem_raw);  // [k1][t] = w_M^{t k1}
+    float2* tw_i = tw_f + M;                             // [t][k1]
+    float2* qt = tw_i + M;                               // [j][alpha][W]
+    float2* tiles = qt + (size_t)a.nshift * M * W;       // PG x [alpha][W], then the exchange
+    const int tid = threadIdx.x;
+    for (int i = tid; i < M; i += NT) {
+        const int k1 = i / R2, t = i - k1 * R2;
+        const float2 w = a.twt[t * k1];
+        tw_f[k1 * R2 + t] = w;
+        tw_i[t * R1 + k1] = w;
+    }
+    const int ctiles = a.nx / W;
+    const int bid = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int ky = bid / ctiles;
+    const int kx0 = (bid - ky * ctiles) * W;
+    const long long plane = (long long)a.nx * a.ny;
+    const long long col0 = (long long)ky * a.nx + kx0;
+    for (int i = tid; i < a.nshift * M * W; i += NT) {
+        const int j = i / (M * W);
+        const int rem = i - j * (M * W);
+        const int al = rem / W;
+        qt[i] = a.qtab[(long long)j * a.n + al * plane + col0 + (rem - al * W)];
+    }
+
+    const int g = tid / LT, lt = tid - g * LT;
+    const int q = lt % W, t = lt / W;
+    float2* tile = tiles + (size_t)g * M * W;
+    const int npairs = (a.batch + 1) / 2;
+    for (int p0 = 0; p0 < npairs; p0 += PG) {
+        const int pair = p0 + g;
+        const bool active = pair < npairs;
+        float* __restrict__ re = a.out + (long long)(2 * pair) * a.n;
+        float* __restrict__ im = 2 * pair + 1 < a.batch ? re + a.n : a.lone;
+        if (p0 > 0) __syncthreads();  // the previous pairs' exchange reads are done
+        if (active) {
+#pragma unroll
+            for (int r = 0; r < R1; ++r) {
+                const int al = t + R2 * r;
+                const long long off = al * plane + col0 + q;
+                tile[al * W + q] = make_float2(re[off], im[off]);
+            }
+        }
+        __syncthreads();  // tiles (and, the first time, the twiddles and Q tiles) in LDS
+        float2 w[R1];
+#pragma unroll
+        for (int r = 0; r < R1; ++r) {
+            const int al = t + R2 * r;
+            float2 acc = make_float2(0.f, 0.f);
+            for (int j = 0; j < a.nshift; ++j) {
+                int src = al - a.rolls[j];
+                if (src < 0) src += M;
+                const float2 z = tile[src * W + q];
+                const float2 f = qt[(j * M + src) * W + q];
+                acc.x = fmaf(z.x, f.x, fmaf(-z.y, f.y, acc.x));
+                acc.y = fmaf(z.x, f.y, fmaf(z.y, f.x, acc.y));
+            }
+            w[r] = acc;
+        }
+        RegDFT<R1, false, float>::run(w);
+#pragma unroll
+        for (int k1 = 1; k1 < R1; ++k1) w[k1] = mul<float>(w[k1], tw_f[k1 * R2 + t]);
+        __syncthreads();  // every mix read of the tiles is done: they become the exchange buffers
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) tile[(k1 * R2 + t) * W + q] = w[k1];
+        __syncthreads();
+        if (active) {
+            const int kx = kx0 + q;
+            // one first-stage frequency at a time (the chain's factor loop, unrolled over
+            // every value, would hold its loads in a few hundred registers)
+#pragma unroll 1
+            for (int j = 0; j < CC; ++j) {
+                const int k1 = CC * t + j;
+                float2 u[R2];
+#pragma unroll
+                for (int tt = 0; tt < R2; ++tt) u[tt] = tile[(k1 * R2 + tt) * W + q];
+                RegDFT<R2, false, float>::run(u);
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) {
+                    const int kt = k1 + R1 * k2;
+                    const float2 v = mul<float>(u[k2], full_table_factor(a, a.ny, kt, ky, kx, a.scale));
+                    const long long off = kt * plane + col0 + q;
+                    re[off] = v.x;
+                    im[off] = v.y;
+                }
+            }
+        }
+    }
+}
+
+bool t_shift_supported(int nx, int m, int nshift) {
+    if (nx % ShiftGeom<16>::W != 0 || nshift < 1 || nshift > SE2C_MAX_SHIFT_CLASSES) return false;
+    size_t lds = 0;
+    if (m == 16) lds = t_shift_lds<16>(nshift);
+    else if (m == 32) lds = t_shift_lds<32>(nshift);
+    else if (m == 64) lds = t_shift_lds<64>(nshift);
+    else return false;
+    return lds <= 128 * 1024;
+}
+
+template <int M>
+static hipError_t launch_t_shift_t(const FullFastArgs& a, hipStream_t s) {
+    const int nblocks = a.ny * (a.nx / ShiftGeom<M>::W);
+    hipLaunchKernelGGL((t_shift_full<M>), dim3(nblocks), dim3(256), t_shift_lds<M>(a.nshift), s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_t_shift(const FullFastArgs& a, hipStream_t s) {
+    if (!t_shift_supported(a.nx, a.m, a.nshift)) return hipErrorInvalidValue;
+    if (a.m == 16) return launch_t_shift_t<16>(a, s);
+    if (a.m == 32) return launch_t_shift_t<32>(a, s);
+    return launch_t_shift_t<64>(a, s);
+}
+
 template <int NY, int MODE>
 static hipError_t launch_y_full_t(const FullFastArgs& a, hipStream_t s) {
     const int nblocks = (a.nx / FullLineGeom<NY, MODE>::W) * a.m * (MODE == 2 ? 1 : (a.batch + 1) / 2);
@@ -865,6 +1010,15 @@ hipError_t launch_y_full_powers(const FullFastArgs& a, hipStream_t s) {
 
 hipError_t prepare_full_fast_kernels() {
     hipError_t e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(t_shift_full<16>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(t_shift_full<32>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(t_shift_full<64>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    if (e != hipSuccess) return e;
     SE2C_XT_FULL_ATTR(32, 16) SE2C_XT_FULL_ATTR(32, 32) SE2C_XT_FULL_ATTR(32, 64)
     SE2C_XT_FULL_ATTR(64, 16) SE2C_XT_FULL_ATTR(64, 32) SE2C_XT_FULL_ATTR(64, 64)
     SE2C_XT_FULL_ATTR(128, 16) SE2C_XT_FULL_ATTR(128, 32) SE2C_XT_FULL_ATTR(128, 64)

@@ -43,6 +43,11 @@ struct FullFastArgs {
     const float* zsrc;
     int lx, ly, lm;
     long long nl;
+    // shift-mix theta pass: alpha becomes sum_j z[alpha - rolls[j]] Q_j[alpha - rolls[j]][ky][kx]
+    // (indices mod m), Q_j the j-th [m][ny][nx] complex plane set of qtab
+    const float2* qtab;
+    int nshift;
+    int rolls[SE2C_MAX_SHIFT_CLASSES];
 };
 
 bool full_fast_supported(int nx, int ny, int m);
@@ -59,6 +64,11 @@ hipError_t launch_y_full_spectra(const FullFastArgs& a, hipStream_t s);
 // y pass: inverse DFT along y only, in place on the planes (the inverse of the spectra pass
 // with save = out)
 hipError_t launch_y_full_inverse(const FullFastArgs& a, hipStream_t s);
+// theta pass of a shifted-kernel sum on the x-y spectrum planes (theta in space), in place:
+// shift mix, forward DFT along theta, product with the chain; false when this (m, nshift) is
+// not supported (the caller takes the generic pencils)
+bool t_shift_supported(int nx, int m, int nshift);
+hipError_t launch_t_shift(const FullFastArgs& a, hipStream_t s);
 // y pass of the backward: adjoint product in place, kernel-sample gradient accumulated to acc
 hipError_t launch_y_full_backward(const FullFastArgs& a, hipStream_t s);
 // y pass of all powers (Alg. 7): forward DFT of the spectrum planes in the last slot, then
