@@ -791,7 +791,7 @@ template <int M> struct ShiftGeom {
 template <int M>
 static size_t t_shift_lds(int nshift) {
     using Gm = ShiftGeom<M>;
-    return sizeof(float2) * ((size_t)2 * M + (size_t)(nshift + Gm::PG) * M * Gm::W);
+    return sizeof(float2) * ((size_t)3 * M + (size_t)(nshift + Gm::PG) * M * Gm::W);
 }
 
 template <int M>
@@ -803,6 +803,7 @@ __global__ void __launch_bounds__(256) t_shift_full(FullFastArgs a) {
     float2* tw_i = tw_f + M;                             // [t][k1]
     float2* qt = tw_i + M;                               // [j][alpha][W]
     float2* tiles = qt + (size_t)a.nshift * M * W;       // PG x [alpha][W], then the exchange
+    float2* ftt = tiles + (size_t)PG * M * W;            // separable chains: scale prod_e Tt_e[kt]
     const int tid = threadIdx.x;
     for (int i = tid; i < M; i += NT) {
         const int k1 = i / R2, t = i - k1 * R2;
@@ -810,6 +811,16 @@ __global__ void __launch_bounds__(256) t_shift_full(FullFastArgs a) {
         tw_f[k1 * R2 + t] = w;
         tw_i[t * R1 + k1] = w;
     }
+    bool sep = true;
+    for (int e = 0; e < a.ntab; ++e) sep = sep && a.tab_full[e] == 0;
+    if (sep)
+        for (int i = tid; i < M; i += NT) {
+            float2 f = make_float2(a.scale, 0.f);
+            for (int e = 0; e < a.ntab; ++e)
+                f = mul<float>(f, reinterpret_cast<const float2*>(a.tab[e])[a.nx + a.ny + i]);
+            if (a.conj_tab) f.y = -f.y;
+            ftt[i] = f;
+        }
     const int ctiles = a.nx / W;
     const int bid = xcd_contiguous(blockIdx.x, gridDim.x);
     const int ky = bid / ctiles;
@@ -866,6 +877,15 @@ __global__ void __launch_bounds__(256) t_shift_full(FullFastArgs a) {
         __syncthreads();
         if (active) {
             const int kx = kx0 + q;
+            // separable chains: the x-y part of the factor once, the theta part from LDS
+            float2 fxy = make_float2(1.f, 0.f);
+            if (sep) {
+                for (int e = 0; e < a.ntab; ++e) {
+                    const float2* T = reinterpret_cast<const float2*>(a.tab[e]);
+                    fxy = mul<float>(fxy, mul<float>(T[kx], T[a.nx + ky]));
+                }
+                if (a.conj_tab) fxy.y = -fxy.y;
+            }
             // one first-stage frequency at a time (the chain's factor loop, unrolled over
             // every value, would hold its loads in a few hundred registers)
 #pragma unroll 1
@@ -878,7 +898,8 @@ __global__ void __launch_bounds__(256) t_shift_full(FullFastArgs a) {
 #pragma unroll
                 for (int k2 = 0; k2 < R2; ++k2) {
                     const int kt = k1 + R1 * k2;
-                    const float2 v = mul<float>(u[k2], full_table_factor(a, a.ny, kt, ky, kx, a.scale));
+                    const float2 fac = sep ? mul<float>(fxy, ftt[kt]) : full_table_factor(a, a.ny, kt, ky, kx, a.scale);
+                    const float2 v = mul<float>(u[k2], fac);
                     const long long off = kt * plane + col0 + q;
                     re[off] = v.x;
                     im[off] = v.y;
