@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libse2conv.so")
 SOURCES = ["api.cpp", "passes.hip", "coeffs.hip", "sep_fast.hip", "full_fast.hip", "grad.hip", "sample.hip", "pad.hip",
-           "shift.hip", "sep_fast64.hip"]
+           "shift.hip", "sep_fast64.hip", "rader_fast.hip"]
 ARCH = os.environ.get("SE2CONV_ARCH", "gfx950")
 
 

@@ -504,7 +504,36 @@ int pencil_width(int ncols, int L, bool d, int want = 16) {
     return W;
 }
 
-hipError_t run_slab(SlabArgs a, bool d, hipStream_t st) {
+hipError_t run_slab(const se2conv_plan_s* p, SlabArgs a, bool d, hipStream_t st) {
+    // x rows of a prime length with register kernels (one direction, planes, no product):
+    // Rader's algorithm in registers (FP32), unless the plan asks for the generic kernels
+    if (!d && !(p->flags & SE2CONV_PLAN_GENERIC) && !a.do_t && a.mul == 0 && a.in_mode == 1 && a.out_mode == 1 &&
+        !a.items && a.px.rader && rader_fast_supported(a.px.L) && a.fwd != a.inv) {
+        PencilArgs r{};
+        r.in0 = a.in0;
+        r.in1 = a.in1;
+        r.out0 = a.out0;
+        r.out1 = a.out1;
+        r.lone_in1 = a.lone_in1;
+        r.lone_out1 = a.lone_out1;
+        r.item_stride_in = a.item_stride_in;
+        r.item_stride_out = a.item_stride_out;
+        r.nitems = a.nitems;
+        r.mode = 1;
+        r.axis = 0;
+        r.nx = a.nx;
+        r.ny = a.ny;
+        r.m = a.m;
+        r.ncols = a.ny;
+        r.fwd = a.fwd;
+        r.inv = a.inv;
+        r.mul = 0;
+        r.p = a.px;
+        r.cplx = a.cplx;
+        hipError_t e = launch_rader_pencil(r, st);
+        if (e != hipSuccess) return e;
+        return after_pass(3, st);
+    }
     const long long P = (long long)a.rows_per_tile * a.nx;
     const bool odd = odd_len(a.nx) || (a.do_t && odd_len(a.m));
     const int nthr = threads_for(P, d, odd);
@@ -516,7 +545,16 @@ hipError_t run_slab(SlabArgs a, bool d, hipStream_t st) {
     return after_pass(a.do_t ? 0 : 3, st);
 }
 
-hipError_t run_pencil(PencilArgs a, bool d, hipStream_t st) {
+hipError_t run_pencil(const se2conv_plan_s* p, PencilArgs a, bool d, hipStream_t st) {
+    // prime lengths with register kernels: Rader's algorithm in registers (FP32), unless
+    // the plan asks for the generic kernels
+    if (!d && !(p->flags & SE2CONV_PLAN_GENERIC) && a.p.rader && rader_fast_supported(a.p.L) && a.mode == 1 &&
+        !a.items &&
+        ((a.fwd && a.inv && a.mul == 2) || (a.fwd != a.inv && a.mul == 0))) {
+        hipError_t e = launch_rader_pencil(a, st);
+        if (e != hipSuccess) return e;
+        return after_pass(a.axis == 1 ? 1 : 2, st);
+    }
     const long long P = (long long)a.p.L * a.W;
     const bool odd = odd_len(a.p.L);
     // the shift-mix pencils hold fewer values per thread (SE2C_MAXV_SHIFT)
@@ -686,7 +724,7 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
         a.do_t = 0;
         a.scale = 1.0 / (double)s.nx;
     }
-    if (!fast_slab) HIPCHK(run_slab(a, d, st));
+    if (!fast_slab) HIPCHK(run_slab(p, a, d, st));
 
     // pass 2 (and 3): y pencils (and theta pencils) on x-pairs, in place on out
     auto pencil = [&](int axis) -> se2conv_status {
@@ -714,7 +752,7 @@ se2conv_status enqueue_sep(se2conv_plan_s* p, const se2conv_shape& s, const void
         b.scale = 1.0 / (double)L;
         b.p = axis == 1 ? py : pt;
         b.tw = stage_tw_of(p, b.p, d);
-        HIPCHK(run_pencil(b, d, st));
+        HIPCHK(run_pencil(p, b, d, st));
         return SE2CONV_OK;
     };
     se2conv_status r = SE2CONV_OK;
@@ -790,7 +828,7 @@ se2conv_status enqueue_sep_items(se2conv_plan_s* p, const se2conv_shape& s, cons
             a.do_t = 0;
             a.scale = 1.0 / (double)s.nx;
         }
-        HIPCHK(run_slab(a, d, st));
+        HIPCHK(run_slab(p, a, d, st));
     }
     auto pencil = [&](int axis) -> hipError_t {
         PencilArgs b{};
@@ -812,7 +850,7 @@ se2conv_status enqueue_sep_items(se2conv_plan_s* p, const se2conv_shape& s, cons
         b.scale = 1.0 / (double)L;
         b.p = radix_plan_of(p, L, d);
         b.tw = stage_tw_of(p, b.p, d);
-        return run_pencil(b, d, st);
+        return run_pencil(p, b, d, st);
     };
     if (fast_pencil) {
         FastSepArgs fb = fa;
@@ -861,7 +899,7 @@ hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int d
         a.rows_per_tile = s.m;
         a.ntile_t = 1;
         a.do_t = 1;
-        return run_slab(a, d, st);
+        return run_slab(p, a, d, st);
     }
     // split: x rows and theta pencils (planes mode), in the right order
     a.rows_per_tile = rows_for_xpass(s, d, sched_of(p, s).xrow_points);
@@ -885,7 +923,7 @@ hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int d
     b.nitems = nitems;
     hipError_t e;
     if (dir == 0) {
-        e = run_slab(a, d, st);  // in -> out
+        e = run_slab(p, a, d, st);  // in -> out
         if (e != hipSuccess) return e;
         b.in0 = out0;
         b.in1 = out1;
@@ -895,7 +933,7 @@ hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int d
         b.lone_out1 = lone_out1;
         b.item_stride_in = stride_out;
         b.item_stride_out = stride_out;
-        return run_pencil(b, d, st);
+        return run_pencil(p, b, d, st);
     }
     b.in0 = in0;
     b.in1 = in1;
@@ -905,9 +943,9 @@ hipError_t xt_transform(se2conv_plan_s* p, const se2conv_shape& s, bool d, int d
     b.lone_out1 = const_cast<void*>(lone_in1);
     b.item_stride_in = stride_in;
     b.item_stride_out = stride_in;
-    e = run_pencil(b, d, st);  // in place on the input planes
+    e = run_pencil(p, b, d, st);  // in place on the input planes
     if (e != hipSuccess) return e;
-    return run_slab(a, d, st);
+    return run_slab(p, a, d, st);
 }
 
 // y pencils on complex plane pairs: forward, optional product, inverse.
@@ -955,7 +993,7 @@ hipError_t y_pass(se2conv_plan_s* p, const se2conv_shape& s, bool d, void* re, v
             }
         }
     }
-    return run_pencil(b, d, st);
+    return run_pencil(p, b, d, st);
 }
 
 // y pencils on complex plane pairs, input planes -> output planes (may coincide).
@@ -1001,7 +1039,7 @@ hipError_t y_pass_io(se2conv_plan_s* p, const se2conv_shape& s, bool d, const vo
             }
         }
     }
-    return run_pencil(b, d, st);
+    return run_pencil(p, b, d, st);
 }
 
 // Full (non-separable) chain on pairs of fields.
@@ -1151,7 +1189,7 @@ hipError_t x_pass(se2conv_plan_s* p, const se2conv_shape& s, bool d, int dir, co
     a.rows_per_tile = rows_for_xpass(s, d, sched_of(p, s).xrow_points);
     a.ntile_t = (s.m + a.rows_per_tile - 1) / a.rows_per_tile;
     a.do_t = 0;
-    return run_slab(a, d, st);
+    return run_slab(p, a, d, st);
 }
 
 // Sum of SE(2)-shifted radial kernels on pairs of fields (two real fields as one complex
@@ -1241,7 +1279,7 @@ se2conv_status enqueue_shifted(se2conv_plan_s* p, const se2conv_shape& s, const 
         HIPCHK(launch_t_shift(a, st));
         HIPCHK(after_pass(2, st));
     } else {
-        HIPCHK(run_pencil(b, d, st));
+        HIPCHK(run_pencil(p, b, d, st));
     }
     if (fast) {
         FullFastArgs a = full_fast_args(p, s, batch);

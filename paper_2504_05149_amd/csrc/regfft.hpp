@@ -1,7 +1,7 @@
 // In-register DFT codelets with compile-time twiddles (FP32/FP64).
 //
 // RegDFT<N, INV>(v): natural-order in, natural-order out, v[0..N-1] held in
-// registers (every index is a compile-time constant after unrolling).  N = 2, 3, 4,
+// registers (every index is a compile-time constant after unrolling).  N = 2, 3, 4, 5,
 // 8, 16 use the hand-written butterflies of fft_device.hpp; composite N = A * B
 // (A = 16, 8, 4 or 2; B = N / A, e.g. 32 = 16 x 2, 96 = 16 x 6, 6 = 2 x 3) is composed
 // as B A-point DFTs on the stride-B subsequences, twiddles w_N^{b k1}, then A B-point
@@ -115,6 +115,9 @@ template <bool INV, typename T> struct RegDFT<8, INV, T> {
 };
 template <bool INV, typename T> struct RegDFT<16, INV, T> {
     static __device__ __forceinline__ void run(C<T>* v) { dft16<T, INV>(v); }
+};
+template <bool INV, typename T> struct RegDFT<5, INV, T> {
+    static __device__ __forceinline__ void run(C<T>* v) { dft5<T, INV>(v); }
 };
 
 }  // namespace se2c

@@ -1,0 +1,98 @@
+"""GPU parity of the register kernels for prime line lengths (Rader's algorithm in
+registers, FP32): the y pass (forward, product, inverse), the theta passes and the x rows
+(forward or inverse alone) of odd grids with a length 13, 17, 37, 97 or 101, against the
+FP64 oracle; separable, FULL and quarter tables, the adjoint, odd batches and complex
+fields.  The generic FP32 kernels of the same plan (SE2CONV_PLAN_GENERIC) must agree too."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2504_05149_amd as se2
+from gpu_common import case, parity_err, tol32
+from inputs import chain_kernel_params, sample_fields
+from oracle import conv as oc
+from oracle import kernels as ok
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+CASES = [
+    # (nx, ny, m, batch): odd grids (the field-pair passes) with a prime y and / or theta
+    (33, 101, 17, 3),     # y: forward + product + inverse at 101; theta 17
+    (45, 13, 37, 2),      # y 13, theta 37
+    (101, 101, 101, 4),   # the prime-length workload's grid
+    (24, 97, 13, 1),      # even x, prime y: a single field (the lone plane)
+    (31, 17, 97, 3),
+    (37, 30, 509, 2),     # x rows of 37 (the x-theta slab does not fit: split x / theta passes)
+    (101, 24, 101, 3),    # x rows and theta pencils of 101
+]
+
+
+@pytest.mark.parametrize("nx,ny,m,batch", CASES)
+def test_separable_chain_on_prime_axes(nx, ny, m, batch):
+    case(f"register Rader pencils {nx}x{ny}x{m} batch {batch}: separable chain of 2, and its adjoint")
+    ks = chain_kernel_params(7, 2)
+    chain = [(k.sigma, k.kappa, 0.4 + 0.5 * j) for j, k in enumerate(ks)]
+    f = sample_fields(41, batch, 8, nx, ny, m)
+    fd = torch.from_numpy(f).to(DEV, torch.float32)
+    plan = se2.Plan([(nx, ny, m)], dtype="f32")
+    gen = se2.Plan([(nx, ny, m)], dtype="f32", generic=True)
+    ps = [ok.gauss_vm(nx, ny, m, *c) for c in chain]
+    tol = tol32(nx * ny * m)
+    for adjoint in (False, True):
+        out = plan.apply(0, fd, plan.coeffs(0, [se2.GaussVM(*c) for c in chain]), adjoint=adjoint)
+        ref_gen = gen.apply(0, fd, gen.coeffs(0, [se2.GaussVM(*c) for c in chain]), adjoint=adjoint)
+        torch.cuda.synchronize()
+        out = out.cpu().numpy().astype(np.float64)
+        agree = parity_err(out, ref_gen.cpu().numpy().astype(np.float64))
+        for b in sorted({0, batch - 1}):
+            err = parity_err(out[b], oc.conv_chain(f[b], ps, adjoint=adjoint))
+            print(f"  adjoint={adjoint} field {b}: oracle {err:.2e}, generic kernels {agree:.2e} (tol {tol:.1e})",
+                  flush=True)
+            assert err <= tol
+        assert agree <= tol
+    plan.close()
+    gen.close()
+
+
+@pytest.mark.parametrize("quarter", [False, True])
+def test_full_and_quarter_tables_on_prime_axes(quarter):
+    nx, ny, m = 33, 37, 17
+    case(f"register Rader pencils {nx}x{ny}x{m}: exponential-coordinates Gaussian, quarter={quarter}")
+    plan = se2.Plan([(nx, ny, m)], dtype="f32")
+    t = plan.coeffs(0, [se2.ExpGauss(0.09)])
+    if quarter:
+        t = plan.quarter(t)
+    f = sample_fields(42, 3, 8, nx, ny, m)
+    out = plan.apply(0, torch.from_numpy(f).to(DEV, torch.float32), t)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy().astype(np.float64)
+    p = ok.sample_function(ok.exp_gauss_function(0.09), nx, ny, m, images=3)
+    tol = tol32(nx * ny * m)
+    for b in range(3):
+        err = parity_err(out[b], oc.conv_chain(f[b], [p / p.mean()]))
+        print(f"  field {b}: {err:.2e} (tol {tol:.1e})", flush=True)
+        assert err <= tol
+    plan.close()
+
+
+@pytest.mark.parametrize("shape", [(17, 13, 37), (101, 13, 101)])
+def test_complex_fields_on_prime_axes(shape):
+    case(f"register Rader pencils, complex fields {shape} (interleaved planes), chain of 2")
+    nx, ny, m = shape
+    ks = chain_kernel_params(8, 2)
+    chain = [(k.sigma, k.kappa, 0.7 * j) for j, k in enumerate(ks)]
+    a = sample_fields(43, 4, 8, *shape)
+    f = a[:2] + 1j * a[2:]
+    plan = se2.Plan([shape], dtype="f32")
+    out = plan.apply_complex(0, torch.from_numpy(f).to(DEV, torch.complex64),
+                             plan.coeffs(0, [se2.GaussVM(*c) for c in chain]))
+    torch.cuda.synchronize()
+    out = out.cpu().numpy().astype(np.complex128)
+    ps = [ok.gauss_vm(*shape, *c) for c in chain]
+    tol = tol32(nx * ny * m)
+    for b in range(2):
+        err = parity_err(out[b], oc.conv_chain(f[b], ps, return_complex=True))
+        print(f"  field {b}: {err:.2e} (tol {tol:.1e})", flush=True)
+        assert err <= tol
+    plan.close()
