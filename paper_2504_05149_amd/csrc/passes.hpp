@@ -123,11 +123,12 @@ size_t slab_lds_bytes(const SlabArgs& a, bool dbl);
 size_t pencil_lds_bytes(const PencilArgs& a, bool dbl);
 hipError_t launch_slab(const SlabArgs& a, bool dbl, int nthr, int nblocks, hipStream_t s);
 hipError_t launch_pencil(const PencilArgs& a, bool dbl, int nthr, int nblocks, hipStream_t s);
-// FP32 register pencils for the prime lengths rader_fast_supported lists (rader_fast.hip):
-// planes of field pairs (mode 1, no per-item tables); forward + product (mul 2) + inverse,
-// or one direction alone (mul 0).  hipErrorInvalidValue for anything else.
+// Register pencils (FP32 / FP64) for the prime lengths rader_fast_supported lists
+// (rader_fast.hip): planes of field pairs (mode 1, no per-item tables); forward + product
+// (mul 2) + inverse along y or theta, or one direction alone (mul 0, also x rows: axis 0).
+// hipErrorInvalidValue for anything else.
 bool rader_fast_supported(int L);
-hipError_t launch_rader_pencil(const PencilArgs& a, hipStream_t s);
+hipError_t launch_rader_pencil(const PencilArgs& a, bool dbl, hipStream_t s);
 
 // Raise the dynamic-LDS limit of the pass kernels (call once before any capture).
 hipError_t prepare_generic_kernels();

@@ -1,5 +1,5 @@
-// Register-resident FP32 pencils for a prime line length P (the paper's odd grids
-// L = 2K+1 with L prime), by Rader's algorithm.
+// Register-resident pencils (FP32 and FP64) for a prime line length P (the paper's odd
+// grids L = 2K+1 with L prime), by Rader's algorithm.
 //
 // With a generator g of the units mod P and N = P - 1:
 //   X[0]       = sum_n x[n],
@@ -37,27 +37,28 @@ template <> struct RaderGeom<101> { static constexpr int R1 = 10, R2 = 10; };
 
 constexpr int kRaderW = 32;  // columns per tile: 128-byte rows of each plane
 
-template <int P, bool ROWS>
+template <typename T, int P, bool ROWS>
 static constexpr size_t rader_lds() {
     constexpr int N = P - 1;
-    return sizeof(float2) * ((size_t)P * (kRaderW + (ROWS ? 1 : 0)) + 3 * N + P) + sizeof(int) * 2 * N;
+    return sizeof(C<T>) * ((size_t)P * (kRaderW + (ROWS ? 1 : 0)) + 3 * N + P) + sizeof(int) * 2 * N;
 }
 
 // The chain's factor at (kx, ky, kt) (FULL, quarter or separable tables), x scale,
 // conjugated for the adjoint.
-__device__ __forceinline__ float2 rader_chain_factor(const PencilArgs& a, int kx, int ky, int kt) {
-    float2 w = make_float2((float)a.scale, 0.f);
+template <typename T>
+__device__ __forceinline__ C<T> rader_chain_factor(const PencilArgs& a, int kx, int ky, int kt) {
+    C<T> w = mk<T>((T)a.scale, (T)0);
     for (int j = 0; j < a.ntab; ++j) {
         if (a.tab3[j]) {
             const bool qj = (a.tab3_quarter >> j) & 1u;
             const int ax = qj ? min(kx, a.nx - kx) : kx;
             const int ay = qj ? min(ky, a.ny - ky) : ky;
             const long long off = ((long long)kt * (qj ? a.ny / 2 + 1 : a.ny) + ay) * (qj ? a.nx / 2 + 1 : a.nx) + ax;
-            w = mul<float>(w, reinterpret_cast<const float2*>(a.tab3[j])[off]);
+            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.tab3[j])[off]);
         } else {
-            w = mul<float>(w, reinterpret_cast<const float2*>(a.sepx[j])[kx]);
-            w = mul<float>(w, reinterpret_cast<const float2*>(a.sepy[j])[ky]);
-            w = mul<float>(w, reinterpret_cast<const float2*>(a.sept[j])[kt]);
+            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.sepx[j])[kx]);
+            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.sepy[j])[ky]);
+            w = mul<T>(w, reinterpret_cast<const C<T>*>(a.sept[j])[kt]);
         }
     }
     if (a.conj_tab) w.y = -w.y;
@@ -69,35 +70,35 @@ __device__ __forceinline__ float2 rader_chain_factor(const PencilArgs& a, int kx
 // (thread t = 0), inverse DFT_N.  *a0 receives the DFT's zero frequency (thread t = 0).
 // ex: the tile's LDS (row pitch W complex), free to be overwritten (every earlier read is
 // before the barrier).
-template <int R1, int R2, int W, bool CONJB>
-__device__ __forceinline__ void rader_conv(float2 (&x)[R1], const float2* bh, const float2* tw_f, const float2* tw_i,
-                                           float2* ex, int q, int t, float2 add0, float2* a0) {
+template <typename T, int R1, int R2, int W, bool CONJB>
+__device__ __forceinline__ void rader_conv(C<T> (&x)[R1], const C<T>* bh, const C<T>* tw_f, const C<T>* tw_i, C<T>* ex,
+                                           int q, int t, C<T> add0, C<T>* a0) {
     constexpr int CC = R1 / R2;
-    RegDFT<R1, false, float>::run(x);
+    RegDFT<R1, false, T>::run(x);
 #pragma unroll
-    for (int k1 = 1; k1 < R1; ++k1) x[k1] = mul<float>(x[k1], tw_f[k1 * R2 + t]);
+    for (int k1 = 1; k1 < R1; ++k1) x[k1] = mul<T>(x[k1], tw_f[k1 * R2 + t]);
     __syncthreads();
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) ex[(k1 * R2 + t) * W + q] = x[k1];
     __syncthreads();
-    float2 v[CC][R2];
+    C<T> v[CC][R2];
 #pragma unroll
     for (int j = 0; j < CC; ++j) {
         const int k1 = CC * t + j;
 #pragma unroll
         for (int tt = 0; tt < R2; ++tt) v[j][tt] = ex[(k1 * R2 + tt) * W + q];
-        RegDFT<R2, false, float>::run(v[j]);
+        RegDFT<R2, false, T>::run(v[j]);
         if (j == 0 && t == 0) *a0 = v[0][0];
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) {
-            float2 b = bh[k1 + R1 * k2];
+            C<T> b = bh[k1 + R1 * k2];
             if (CONJB) b.y = -b.y;
-            v[j][k2] = mul<float>(v[j][k2], b);
+            v[j][k2] = mul<T>(v[j][k2], b);
         }
-        if (j == 0 && t == 0) v[0][0] = make_float2(v[0][0].x + add0.x, v[0][0].y + add0.y);
-        RegDFT<R2, true, float>::run(v[j]);
+        if (j == 0 && t == 0) v[0][0] = add<T>(v[0][0], add0);
+        RegDFT<R2, true, T>::run(v[j]);
 #pragma unroll
-        for (int tt = 1; tt < R2; ++tt) v[j][tt] = mulc<float>(v[j][tt], tw_i[tt * R1 + k1]);
+        for (int tt = 1; tt < R2; ++tt) v[j][tt] = mulc<T>(v[j][tt], tw_i[tt * R1 + k1]);
     }
     __syncthreads();
 #pragma unroll
@@ -107,10 +108,10 @@ __device__ __forceinline__ void rader_conv(float2 (&x)[R1], const float2* bh, co
     __syncthreads();
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) x[k1] = ex[(k1 * R2 + t) * W + q];
-    RegDFT<R1, true, float>::run(x);
+    RegDFT<R1, true, T>::run(x);
 }
 
-template <int P, int MODE, bool ROWS>
+template <typename T, int P, int MODE, bool ROWS>
 __global__ void __launch_bounds__(kRaderW * RaderGeom<P>::R2) rader_pencil(PencilArgs a) {
     constexpr int R1 = RaderGeom<P>::R1, R2 = RaderGeom<P>::R2, N = P - 1, W = kRaderW, NT = W * R2;
     // LDS row pitch: rows (lines along x) are loaded point-fastest, so their tile rows are
@@ -118,11 +119,11 @@ __global__ void __launch_bounds__(kRaderW * RaderGeom<P>::R2) rader_pencil(Penci
     constexpr int WP = ROWS ? W + 1 : W;
     static_assert(R1 * R2 == N && R1 % R2 == 0, "Rader geometry");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    float2* tile = reinterpret_cast<float2*>(smem_raw);  // [P][WP], then the exchange buffer
-    float2* tw_f = tile + P * WP;                         // [k1][t] = w_N^{t k1}
-    float2* tw_i = tw_f + N;                              // [t][k1]
-    float2* bh = tw_i + N;                                // B[k] = DFT_N(b)[k] / N
-    float2* fl = bh + N;                                  // separable chains: prod_e T_e[k] along the line
+    C<T>* tile = reinterpret_cast<C<T>*>(smem_raw);  // [P][WP], then the exchange buffer
+    C<T>* tw_f = tile + P * WP;                         // [k1][t] = w_N^{t k1}
+    C<T>* tw_i = tw_f + N;                              // [t][k1]
+    C<T>* bh = tw_i + N;                                // B[k] = DFT_N(b)[k] / N
+    C<T>* fl = bh + N;                                  // separable chains: prod_e T_e[k] along the line
     int* pin = reinterpret_cast<int*>(fl + P);            // g^q mod P
     int* pout = pin + N;                                  // g^-q mod P
     const int tid = threadIdx.x;
@@ -131,18 +132,18 @@ __global__ void __launch_bounds__(kRaderW * RaderGeom<P>::R2) rader_pencil(Penci
     if (sep) {
         const void* const* lt = a.axis == 1 ? a.sepy : a.sept;
         for (int i = tid; i < P; i += NT) {
-            float2 v = make_float2(1.f, 0.f);
-            for (int j = 0; j < a.ntab; ++j) v = mul<float>(v, reinterpret_cast<const float2*>(lt[j])[i]);
+            C<T> v = mk<T>((T)1, (T)0);
+            for (int j = 0; j < a.ntab; ++j) v = mul<T>(v, reinterpret_cast<const C<T>*>(lt[j])[i]);
             fl[i] = v;
         }
     }
     {
         // the plan's Rader block: w_N^j | B (forward) | B (inverse) | g^q | g^-q
-        const float2* rt = reinterpret_cast<const float2*>(a.p.rtab);
+        const C<T>* rt = reinterpret_cast<const C<T>*>(a.p.rtab);
         const int* ri = reinterpret_cast<const int*>(rt + 3 * N);
         for (int i = tid; i < N; i += NT) {
             const int k1 = i / R2, t = i - k1 * R2;
-            const float2 w = rt[t * k1];
+            const C<T> w = rt[t * k1];
             tw_f[k1 * R2 + t] = w;
             tw_i[t * R1 + k1] = w;
             bh[i] = rt[N + i];
@@ -171,9 +172,9 @@ __global__ void __launch_bounds__(kRaderW * RaderGeom<P>::R2) rader_pencil(Penci
         const bool last_odd = (a.lone_in1 != nullptr || a.lone_out1 != nullptr) && item == a.nitems - 1;
         const long long obase =
             (ROWS || a.axis == 1 ? (long long)other * plane : (long long)other * a.nx) + (long long)c0 * cstride;
-        const float* in0 = reinterpret_cast<const float*>(a.in0) + (long long)item * a.item_stride_in + obase * es;
-        const float* in1 = last_odd ? reinterpret_cast<const float*>(a.lone_in1)
-                                    : (a.in1 ? reinterpret_cast<const float*>(a.in1) + (long long)item * a.item_stride_in
+        const T* in0 = reinterpret_cast<const T*>(a.in0) + (long long)item * a.item_stride_in + obase * es;
+        const T* in1 = last_odd ? reinterpret_cast<const T*>(a.lone_in1)
+                                    : (a.in1 ? reinterpret_cast<const T*>(a.in1) + (long long)item * a.item_stride_in
                                              : nullptr);
         if (in1) in1 += obase * es;
         const int ncols = min(W, a.ncols - c0);
@@ -182,52 +183,52 @@ __global__ void __launch_bounds__(kRaderW * RaderGeom<P>::R2) rader_pencil(Penci
             // rows: consecutive threads along the points of a row (contiguous in memory)
             const int c = ROWS ? i / P : i % W;
             const int e = ROWS ? i - c * P : i / W;
-            float2 v = make_float2(0.f, 0.f);
+            C<T> v = mk<T>((T)0, (T)0);
             if (c < ncols) {
                 const long long off = (e * astride + c * cstride) * es;
                 v.x = in0[off];
-                v.y = in1 ? in1[off] : 0.f;
+                v.y = in1 ? in1[off] : (T)0;
             }
             tile[e * WP + c] = v;
         }
         __syncthreads();
-        float2 x[R1];
-        float2 h0 = make_float2(0.f, 0.f);  // X[0] or Y[0] (valid in thread t = 0)
-        float2 a0 = make_float2(0.f, 0.f);
+        C<T> x[R1];
+        C<T> h0 = mk<T>((T)0, (T)0);  // X[0] or Y[0] (valid in thread t = 0)
+        C<T> a0 = mk<T>((T)0, (T)0);
         if constexpr (MODE != 2) {
-            const float2 x0 = tile[q];
+            const C<T> x0 = tile[q];
 #pragma unroll
             for (int r = 0; r < R1; ++r) x[r] = tile[pin[t + R2 * r] * WP + q];
-            rader_conv<R1, R2, WP, false>(x, bh, tw_f, tw_i, tile, q, t, x0, &a0);
-            h0 = make_float2(x0.x + a0.x, x0.y + a0.y);  // X[0] = x[0] + sum_q a_q
+            rader_conv<T, R1, R2, WP, false>(x, bh, tw_f, tw_i, tile, q, t, x0, &a0);
+            h0 = add<T>(x0, a0);  // X[0] = x[0] + sum_q a_q
             if constexpr (MODE == 0) {
                 const int kx = min(c0 + q, a.ncols - 1);  // columns past the edge compute, unstored
                 if (sep) {
                     // scale x the factors of x and of the outer coordinate, then the line's from LDS
-                    float2 c = make_float2((float)a.scale, 0.f);
+                    C<T> c = mk<T>((T)a.scale, (T)0);
                     const void* const* ot = a.axis == 1 ? a.sept : a.sepy;
                     for (int j = 0; j < a.ntab; ++j) {
-                        c = mul<float>(c, reinterpret_cast<const float2*>(a.sepx[j])[kx]);
-                        c = mul<float>(c, reinterpret_cast<const float2*>(ot[j])[other]);
+                        c = mul<T>(c, reinterpret_cast<const C<T>*>(a.sepx[j])[kx]);
+                        c = mul<T>(c, reinterpret_cast<const C<T>*>(ot[j])[other]);
                     }
-                    const float sg = a.conj_tab ? -1.f : 1.f;
+                    const T sg = a.conj_tab ? (T)-1 : (T)1;
 #pragma unroll
                     for (int r = 0; r < R1; ++r) {
-                        float2 f = mul<float>(c, fl[pout[t + R2 * r]]);
+                        C<T> f = mul<T>(c, fl[pout[t + R2 * r]]);
                         f.y *= sg;
-                        x[r] = mul<float>(x[r], f);
+                        x[r] = mul<T>(x[r], f);
                     }
-                    float2 f0 = mul<float>(c, fl[0]);
+                    C<T> f0 = mul<T>(c, fl[0]);
                     f0.y *= sg;
-                    h0 = mul<float>(h0, f0);
+                    h0 = mul<T>(h0, f0);
                 } else {
 #pragma unroll
                     for (int r = 0; r < R1; ++r) {
                         const int k = pout[t + R2 * r];
-                        x[r] = mul<float>(x[r],
-                                          rader_chain_factor(a, kx, a.axis == 1 ? k : other, a.axis == 1 ? other : k));
+                        x[r] = mul<T>(x[r],
+                                          rader_chain_factor<T>(a, kx, a.axis == 1 ? k : other, a.axis == 1 ? other : k));
                     }
-                    h0 = mul<float>(h0, rader_chain_factor(a, kx, a.axis == 1 ? 0 : other, a.axis == 1 ? other : 0));
+                    h0 = mul<T>(h0, rader_chain_factor<T>(a, kx, a.axis == 1 ? 0 : other, a.axis == 1 ? other : 0));
                 }
             }
         } else {
@@ -236,8 +237,8 @@ __global__ void __launch_bounds__(kRaderW * RaderGeom<P>::R2) rader_pencil(Penci
             for (int r = 0; r < R1; ++r) x[r] = tile[pout[t + R2 * r] * WP + q];
         }
         if constexpr (MODE != 1) {
-            rader_conv<R1, R2, WP, true>(x, bh, tw_f, tw_i, tile, q, t, h0, &a0);
-            h0 = make_float2(h0.x + a0.x, h0.y + a0.y);  // y[0] = Y[0] + sum_m Y'[m]
+            rader_conv<T, R1, R2, WP, true>(x, bh, tw_f, tw_i, tile, q, t, h0, &a0);
+            h0 = add<T>(h0, a0);  // y[0] = Y[0] + sum_m Y'[m]
         }
         __syncthreads();  // every exchange read is done: the tile takes the natural order
         const int* dst = MODE == 1 ? pout : pin;
@@ -245,9 +246,9 @@ __global__ void __launch_bounds__(kRaderW * RaderGeom<P>::R2) rader_pencil(Penci
         for (int r = 0; r < R1; ++r) tile[dst[t + R2 * r] * WP + q] = x[r];
         if (t == 0) tile[q] = h0;
         __syncthreads();
-        float* out0 = reinterpret_cast<float*>(a.out0) + (long long)item * a.item_stride_out + obase * es;
-        float* out1 = last_odd ? reinterpret_cast<float*>(a.lone_out1)
-                               : (a.out1 ? reinterpret_cast<float*>(a.out1) + (long long)item * a.item_stride_out
+        T* out0 = reinterpret_cast<T*>(a.out0) + (long long)item * a.item_stride_out + obase * es;
+        T* out1 = last_odd ? reinterpret_cast<T*>(a.lone_out1)
+                               : (a.out1 ? reinterpret_cast<T*>(a.out1) + (long long)item * a.item_stride_out
                                          : nullptr);
         if (out1) out1 += obase * es;
         for (int i = tid; i < P * W; i += NT) {
@@ -255,7 +256,7 @@ __global__ void __launch_bounds__(kRaderW * RaderGeom<P>::R2) rader_pencil(Penci
             const int e = ROWS ? i - c * P : i / W;
             if (c < ncols) {
                 const long long off = (e * astride + c * cstride) * es;
-                const float2 v = tile[e * WP + c];
+                const C<T> v = tile[e * WP + c];
                 out0[off] = v.x;
                 if (out1) out1[off] = v.y;
             }
@@ -265,43 +266,48 @@ __global__ void __launch_bounds__(kRaderW * RaderGeom<P>::R2) rader_pencil(Penci
 
 bool rader_fast_supported(int L) { return L == 13 || L == 17 || L == 37 || L == 97 || L == 101; }
 
-template <int P, int MODE, bool ROWS>
+template <typename T, int P, int MODE, bool ROWS>
 static hipError_t launch_rader_t(const PencilArgs& a, hipStream_t s) {
     const int ncol_tiles = (a.ncols + kRaderW - 1) / kRaderW;
     const long long ntiles = (long long)ncol_tiles * (ROWS || a.axis == 1 ? a.m : a.ny) * a.nitems;
     const int nb = (int)(ntiles < (1 << 20) ? ntiles : (1 << 20));
-    constexpr size_t lds = rader_lds<P, ROWS>();
-    hipLaunchKernelGGL((rader_pencil<P, MODE, ROWS>), dim3(nb), dim3(kRaderW * RaderGeom<P>::R2), lds, s, a);
+    constexpr size_t lds = rader_lds<T, P, ROWS>();
+    hipLaunchKernelGGL((rader_pencil<T, P, MODE, ROWS>), dim3(nb), dim3(kRaderW * RaderGeom<P>::R2), lds, s, a);
     return hipGetLastError();
 }
 
-template <int P>
+template <typename T, int P>
 static hipError_t launch_rader_p(const PencilArgs& a, int mode, hipStream_t s) {
     if (a.axis == 0) {  // x rows: one direction at a time
-        if (mode == 1) return launch_rader_t<P, 1, true>(a, s);
-        if (mode == 2) return launch_rader_t<P, 2, true>(a, s);
+        if (mode == 1) return launch_rader_t<T, P, 1, true>(a, s);
+        if (mode == 2) return launch_rader_t<T, P, 2, true>(a, s);
         return hipErrorInvalidValue;
     }
-    if (mode == 0) return launch_rader_t<P, 0, false>(a, s);
-    if (mode == 1) return launch_rader_t<P, 1, false>(a, s);
-    return launch_rader_t<P, 2, false>(a, s);
+    if (mode == 0) return launch_rader_t<T, P, 0, false>(a, s);
+    if (mode == 1) return launch_rader_t<T, P, 1, false>(a, s);
+    return launch_rader_t<T, P, 2, false>(a, s);
 }
 
-hipError_t launch_rader_pencil(const PencilArgs& a, hipStream_t s) {
+template <typename T>
+static hipError_t launch_rader_typed(const PencilArgs& a, int mode, hipStream_t s) {
+    switch (a.p.L) {
+        case 13: return launch_rader_p<T, 13>(a, mode, s);
+        case 17: return launch_rader_p<T, 17>(a, mode, s);
+        case 37: return launch_rader_p<T, 37>(a, mode, s);
+        case 97: return launch_rader_p<T, 97>(a, mode, s);
+        case 101: return launch_rader_p<T, 101>(a, mode, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_rader_pencil(const PencilArgs& a, bool dbl, hipStream_t s) {
     int mode;
     if (a.fwd && a.inv && a.mul == 2) mode = 0;
     else if (a.fwd && !a.inv && a.mul == 0) mode = 1;
     else if (!a.fwd && a.inv && a.mul == 0) mode = 2;
     else return hipErrorInvalidValue;
     if (a.mode != 1 || a.items) return hipErrorInvalidValue;
-    switch (a.p.L) {
-        case 13: return launch_rader_p<13>(a, mode, s);
-        case 17: return launch_rader_p<17>(a, mode, s);
-        case 37: return launch_rader_p<37>(a, mode, s);
-        case 97: return launch_rader_p<97>(a, mode, s);
-        case 101: return launch_rader_p<101>(a, mode, s);
-        default: return hipErrorInvalidValue;
-    }
+    return dbl ? launch_rader_typed<double>(a, mode, s) : launch_rader_typed<float>(a, mode, s);
 }
 
 }  // namespace se2c

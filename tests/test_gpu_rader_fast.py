@@ -1,5 +1,5 @@
 """GPU parity of the register kernels for prime line lengths (Rader's algorithm in
-registers, FP32): the y pass (forward, product, inverse), the theta passes and the x rows
+registers, FP32 and FP64): the y pass (forward, product, inverse), the theta passes and the x rows
 (forward or inverse alone) of odd grids with a length 13, 17, 37, 97 or 101, against the
 FP64 oracle; separable, FULL and quarter tables, the adjoint, odd batches and complex
 fields.  The generic FP32 kernels of the same plan (SE2CONV_PLAN_GENERIC) must agree too."""
@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import paper_2504_05149_amd as se2
-from gpu_common import case, parity_err, tol32
+from gpu_common import TOL64, case, parity_err, tol32
 from inputs import chain_kernel_params, sample_fields
 from oracle import conv as oc
 from oracle import kernels as ok
@@ -17,28 +17,33 @@ pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 
 CASES = [
-    # (nx, ny, m, batch): odd grids (the field-pair passes) with a prime y and / or theta
-    (33, 101, 17, 3),     # y: forward + product + inverse at 101; theta 17
-    (45, 13, 37, 2),      # y 13, theta 37
-    (101, 101, 101, 4),   # the prime-length workload's grid
-    (24, 97, 13, 1),      # even x, prime y: a single field (the lone plane)
-    (31, 17, 97, 3),
-    (37, 30, 509, 2),     # x rows of 37 (the x-theta slab does not fit: split x / theta passes)
-    (101, 24, 101, 3),    # x rows and theta pencils of 101
+    # (nx, ny, m, batch, dtype): odd grids (the field-pair passes) with a prime y and / or theta
+    (33, 101, 17, 3, "f32"),     # y: forward + product + inverse at 101; theta 17
+    (45, 13, 37, 2, "f32"),      # y 13, theta 37
+    (101, 101, 101, 4, "f32"),   # the prime-length workload's grid
+    (24, 97, 13, 1, "f32"),      # even x, prime y: a single field (the lone plane)
+    (31, 17, 97, 3, "f32"),
+    (37, 30, 509, 2, "f32"),     # x rows of 37 (the x-theta slab does not fit: split x / theta passes)
+    (101, 24, 101, 3, "f32"),    # x rows and theta pencils of 101
+    (33, 101, 17, 3, "f64"),
+    (101, 101, 101, 2, "f64"),
+    (24, 97, 13, 1, "f64"),
+    (37, 30, 509, 1, "f64"),
 ]
 
 
-@pytest.mark.parametrize("nx,ny,m,batch", CASES)
-def test_separable_chain_on_prime_axes(nx, ny, m, batch):
-    case(f"register Rader pencils {nx}x{ny}x{m} batch {batch}: separable chain of 2, and its adjoint")
+@pytest.mark.parametrize("nx,ny,m,batch,dt", CASES)
+def test_separable_chain_on_prime_axes(nx, ny, m, batch, dt):
+    case(f"register Rader pencils {nx}x{ny}x{m} batch {batch} {dt}: separable chain of 2, and its adjoint")
     ks = chain_kernel_params(7, 2)
     chain = [(k.sigma, k.kappa, 0.4 + 0.5 * j) for j, k in enumerate(ks)]
     f = sample_fields(41, batch, 8, nx, ny, m)
-    fd = torch.from_numpy(f).to(DEV, torch.float32)
-    plan = se2.Plan([(nx, ny, m)], dtype="f32")
-    gen = se2.Plan([(nx, ny, m)], dtype="f32", generic=True)
+    tdt = torch.float32 if dt == "f32" else torch.float64
+    fd = torch.from_numpy(f).to(DEV, tdt)
+    plan = se2.Plan([(nx, ny, m)], dtype=dt)
+    gen = se2.Plan([(nx, ny, m)], dtype=dt, generic=True)
     ps = [ok.gauss_vm(nx, ny, m, *c) for c in chain]
-    tol = tol32(nx * ny * m)
+    tol = tol32(nx * ny * m) if dt == "f32" else TOL64
     for adjoint in (False, True):
         out = plan.apply(0, fd, plan.coeffs(0, [se2.GaussVM(*c) for c in chain]), adjoint=adjoint)
         ref_gen = gen.apply(0, fd, gen.coeffs(0, [se2.GaussVM(*c) for c in chain]), adjoint=adjoint)
