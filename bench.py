@@ -150,7 +150,7 @@ def run_gpu(name, steps, warmup, tune=True):
                 replay_median_ms=med_ms, replay_mean_ms=mean_ms, replays=reps, replay_identical=replay_identical)
 
 
-def run_c2(steps, warmup):
+def run_c2(steps, warmup, cpu_budget=None):
     """256 independent problems (mixed N, M, chain lengths) replayed as one HIP graph."""
     import torch
 
@@ -189,6 +189,33 @@ def run_c2(steps, warmup):
     # device time of one submission: the eager submission captured in a graph, replays
     # timed with HIP events
     med_ms, mean_ms, reps = replay_median(lambda st: plan.chain(items, stream=st))
+    line_cpu = {}
+    if cpu_budget:
+        # the FP64 oracle (route 1) problem by problem in list order, within the budget, and
+        # each of those problems' GPU output against it
+        from threadpoolctl import threadpool_info
+
+        from inputs import rel_l2
+        from oracle import conv as oc
+        from oracle import kernels as ok
+
+        torch.cuda.synchronize()
+        done, errs = 0, []
+        t0 = time.perf_counter()
+        for p, (si, f, o, _) in zip(probs, items):
+            n_, m_ = p["n"], p["m"]
+            table = oc.coeff_product([ok.gauss_vm(n_, n_, m_, k.sigma, k.kappa, k.theta0) for k in p["chain"]])
+            ref = oc.conv_with_coeffs(f[0].cpu().numpy().astype(np.float64), table)
+            errs.append(rel_l2(o[0].cpu().numpy().astype(np.float64), ref))
+            done += 1
+            if time.perf_counter() - t0 > cpu_budget:
+                break
+        el = time.perf_counter() - t0
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        line_cpu = {"cpu_baseline": {"value": done / el, "unit": "conv/s", "cores": int(threads), "kind": "oracle",
+                                     "sample": f"the first {done} of 256 problems in list order, FP64 route 1 "
+                                               f"(chain table built per problem, included); {el:.1f} s; {host_cpu()}"},
+                    "rel_l2_vs_oracle": float(max(errs)), "rel_l2_tol": 2e-6 * float(np.log2(128 * 128 * 64))}
     return {"metric": "SE(2) convolutions/sec, 256 uneven problems in one graph", "value": round(256 / (ms * 1e-3), 1),
             "unit": "conv/s", "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(ms, 4),
             "higher_is_better": True, "dtype": "f32", "data": "synthetic",
@@ -198,7 +225,7 @@ def run_c2(steps, warmup):
             "path_alg_GBps": round(8 * npts / (ms * 1e-3) / 1e9, 1), "autotune_s": round(t_tune, 2),
             "replay_median_ms": round(med_ms, 4), "replay_mean_ms": round(mean_ms, 4), "replays": reps,
             "conv_per_s_replay_median": round(256 / (med_ms * 1e-3), 1),
-            "replay_alg_GBps": round(8 * npts / (med_ms * 1e-3) / 1e9, 1)}
+            "replay_alg_GBps": round(8 * npts / (med_ms * 1e-3) / 1e9, 1), **line_cpu}
 
 
 def run_padded(steps, warmup, cpu_budget=None):
@@ -413,7 +440,7 @@ def run_shifted(steps, warmup, cpu_budget=None):
     return line
 
 
-def run_c4(steps, warmup):
+def run_c4(steps, warmup, cpu_budget=None):
     """Loss + gradients w.r.t. the field and a 64 x 64 radial profile, 256x256x64 FP32 batch 8."""
     import torch
 
@@ -459,6 +486,44 @@ def run_c4(steps, warmup):
             e1.record()
         torch.cuda.synchronize()
         med["checkpoint" if ck else "recompute"] = float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+    line_cpu = {}
+    if cpu_budget:
+        # the FP64 oracle's differentiated step field by field within the budget: forward,
+        # dL/dout, dL/df (the adjoint convolution), dL/dP and its contraction with the hat
+        # basis; each sampled field's GPU dL/df against it
+        from threadpoolctl import threadpool_info
+
+        from inputs import rel_l2
+        from oracle import adjoint as oa
+        from oracle import conv as oc
+        from oracle import kernels as ok
+        from oracle.ffc import ffc
+
+        fd = f.detach().requires_grad_(True)
+        pd = prof.detach().requires_grad_(True)
+        out = radial_profile_conv(fd, pd, plan, 0, rmax, checkpoint=True)
+        torch.nn.functional.mse_loss(out, target, reduction="sum").backward()
+        gf = fd.grad.cpu().numpy().astype(np.float64)
+        fh = f.cpu().numpy().astype(np.float64)
+        th = target.cpu().numpy().astype(np.float64)
+        done, errs = 0, []
+        t0 = time.perf_counter()
+        table = ffc(ok.radial_profile(nx, ny, m, prof.cpu().numpy(), rmax))
+        for b in range(batch):
+            o = oc.conv_with_coeffs(fh[b], table)
+            g = 2.0 * (o - th[b])
+            errs.append(rel_l2(gf[b], oc.conv_with_coeffs(g, np.conj(table))))
+            oa.grad_profile(oa.grad_kernel_samples(fh[b], g), nk, rmax)
+            done += 1
+            if time.perf_counter() - t0 > cpu_budget:
+                break
+        el = time.perf_counter() - t0
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+        line_cpu = {"cpu_baseline": {"value": done / el, "unit": "conv/s", "cores": int(threads), "kind": "oracle",
+                                     "sample": f"{done} of {batch} fields, FP64 oracle: profile table, forward, "
+                                               f"dL/df, dL/dP and the profile contraction per field; {el:.1f} s; "
+                                               f"{host_cpu()}"},
+                    "rel_l2_grad_f_vs_oracle": float(max(errs))}
     # forward alone, for reference
     table = plan.coeffs(0, [se2.RadialProfile(prof.contiguous(), rmax, norm=2)])
     torch.cuda.synchronize()
@@ -476,7 +541,7 @@ def run_c4(steps, warmup):
                                    "target sigma*=0.04 kappa*=8 + 1% noise"},
             "ms_fwd_bwd": {k: round(v, 4) for k, v in res.items()},
             "ms_fwd_bwd_event_median": {k: round(v, 4) for k, v in med.items()},
-            "ms_forward_full_table": round(fwd_ms, 4)}
+            "ms_forward_full_table": round(fwd_ms, 4), **line_cpu}
 
 
 def copy_calibration(name, steps, warmup):
@@ -622,10 +687,10 @@ def main():
         print(json.dumps(copy_calibration(args.workload, args.steps, args.warmup)), flush=True)
         return
     if args.workload == "c2":
-        print(json.dumps(run_c2(args.steps, args.warmup)), flush=True)
+        print(json.dumps(run_c2(args.steps, args.warmup, None if args.no_cpu else args.cpu_budget)), flush=True)
         return
     if args.workload == "c4":
-        print(json.dumps(run_c4(args.steps, args.warmup)), flush=True)
+        print(json.dumps(run_c4(args.steps, args.warmup, None if args.no_cpu else args.cpu_budget)), flush=True)
         return
     if args.workload == "powers":
         print(json.dumps(run_powers(args.steps, args.warmup, None if args.no_cpu else args.cpu_budget)), flush=True)
