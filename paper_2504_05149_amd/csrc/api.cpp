@@ -508,7 +508,7 @@ hipError_t run_slab(const se2conv_plan_s* p, SlabArgs a, bool d, hipStream_t st)
     // x rows of a prime length with register kernels (one direction, planes, no product):
     // Rader's algorithm in registers, unless the plan asks for the generic kernels
     if (!(p->flags & SE2CONV_PLAN_GENERIC) && !a.do_t && a.mul == 0 && a.in_mode == 1 && a.out_mode == 1 &&
-        !a.items && a.px.rader && rader_fast_supported(a.px.L) && a.fwd != a.inv) {
+        !a.items && a.px.rader && rader_fast_supported(a.px.L, d) && a.fwd != a.inv) {
         PencilArgs r{};
         r.in0 = a.in0;
         r.in1 = a.in1;
@@ -548,7 +548,7 @@ hipError_t run_slab(const se2conv_plan_s* p, SlabArgs a, bool d, hipStream_t st)
 hipError_t run_pencil(const se2conv_plan_s* p, PencilArgs a, bool d, hipStream_t st) {
     // prime lengths with register kernels: Rader's algorithm in registers, unless the plan
     // asks for the generic kernels
-    if (!(p->flags & SE2CONV_PLAN_GENERIC) && a.p.rader && rader_fast_supported(a.p.L) && a.mode == 1 &&
+    if (!(p->flags & SE2CONV_PLAN_GENERIC) && a.p.rader && rader_fast_supported(a.p.L, d) && a.mode == 1 &&
         !a.items &&
         ((a.fwd && a.inv && a.mul == 2) || (a.fwd != a.inv && a.mul == 0))) {
         hipError_t e = launch_rader_pencil(a, d, st);

@@ -127,7 +127,7 @@ hipError_t launch_pencil(const PencilArgs& a, bool dbl, int nthr, int nblocks, h
 // (rader_fast.hip): planes of field pairs (mode 1, no per-item tables); forward + product
 // (mul 2) + inverse along y or theta, or one direction alone (mul 0, also x rows: axis 0).
 // hipErrorInvalidValue for anything else.
-bool rader_fast_supported(int L);
+bool rader_fast_supported(int L, bool dbl);
 hipError_t launch_rader_pencil(const PencilArgs& a, bool dbl, hipStream_t s);
 
 // Raise the dynamic-LDS limit of the pass kernels (call once before any capture).

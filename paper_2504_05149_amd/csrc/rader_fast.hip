@@ -29,11 +29,20 @@ namespace se2c {
 template <int P> struct RaderGeom {
     static constexpr int R1 = 0, R2 = 0;
 };
+// P - 1 = R1 x R2 with R2 dividing R1 (the exchange) and R1, R2 register codelets; the
+// primes whose P - 1 has no such split (31, 43, 53, ...) stay on the generic kernels
 template <> struct RaderGeom<13> { static constexpr int R1 = 6, R2 = 2; };
 template <> struct RaderGeom<17> { static constexpr int R1 = 8, R2 = 2; };
+template <> struct RaderGeom<19> { static constexpr int R1 = 6, R2 = 3; };
+template <> struct RaderGeom<29> { static constexpr int R1 = 14, R2 = 2; };
 template <> struct RaderGeom<37> { static constexpr int R1 = 12, R2 = 3; };
+template <> struct RaderGeom<41> { static constexpr int R1 = 20, R2 = 2; };
+template <> struct RaderGeom<61> { static constexpr int R1 = 30, R2 = 2; };
+template <> struct RaderGeom<73> { static constexpr int R1 = 24, R2 = 3; };
 template <> struct RaderGeom<97> { static constexpr int R1 = 24, R2 = 4; };
 template <> struct RaderGeom<101> { static constexpr int R1 = 10, R2 = 10; };
+template <> struct RaderGeom<109> { static constexpr int R1 = 36, R2 = 3; };
+template <> struct RaderGeom<113> { static constexpr int R1 = 28, R2 = 4; };
 
 constexpr int kRaderW = 32;  // columns per tile: 128-byte rows of each plane
 
@@ -264,7 +273,16 @@ __global__ void __launch_bounds__(kRaderW * RaderGeom<P>::R2) rader_pencil(Penci
     }
 }
 
-bool rader_fast_supported(int L) { return L == 13 || L == 17 || L == 37 || L == 97 || L == 101; }
+bool rader_fast_supported(int L, bool dbl) {
+    switch (L) {
+        case 13: case 17: case 19: case 29: case 37: case 41: case 101:
+            return true;
+        case 61: case 73: case 97: case 109: case 113:
+            return !dbl;
+        default:
+            return false;
+    }
+}
 
 template <typename T, int P, int MODE, bool ROWS>
 static hipError_t launch_rader_t(const PencilArgs& a, hipStream_t s) {
@@ -293,11 +311,25 @@ static hipError_t launch_rader_typed(const PencilArgs& a, int mode, hipStream_t 
     switch (a.p.L) {
         case 13: return launch_rader_p<T, 13>(a, mode, s);
         case 17: return launch_rader_p<T, 17>(a, mode, s);
+        case 19: return launch_rader_p<T, 19>(a, mode, s);
+        case 29: return launch_rader_p<T, 29>(a, mode, s);
         case 37: return launch_rader_p<T, 37>(a, mode, s);
-        case 97: return launch_rader_p<T, 97>(a, mode, s);
+        case 41: return launch_rader_p<T, 41>(a, mode, s);
         case 101: return launch_rader_p<T, 101>(a, mode, s);
-        default: return hipErrorInvalidValue;
+        default: break;
     }
+    if constexpr (std::is_same<T, float>::value) {
+        // FP32 only: in FP64 the R1 = 24..36 values per thread of these need 260-370 VGPRs
+        switch (a.p.L) {
+            case 61: return launch_rader_p<T, 61>(a, mode, s);
+            case 73: return launch_rader_p<T, 73>(a, mode, s);
+            case 97: return launch_rader_p<T, 97>(a, mode, s);
+            case 109: return launch_rader_p<T, 109>(a, mode, s);
+            case 113: return launch_rader_p<T, 113>(a, mode, s);
+            default: break;
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_rader_pencil(const PencilArgs& a, bool dbl, hipStream_t s) {

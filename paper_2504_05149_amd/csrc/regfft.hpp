@@ -2,8 +2,9 @@
 //
 // RegDFT<N, INV>(v): natural-order in, natural-order out, v[0..N-1] held in
 // registers (every index is a compile-time constant after unrolling).  N = 2, 3, 4, 5,
-// 8, 16 use the hand-written butterflies of fft_device.hpp; composite N = A * B
-// (A = 16, 8, 4 or 2; B = N / A, e.g. 32 = 16 x 2, 96 = 16 x 6, 6 = 2 x 3) is composed
+// 7, 8, 16 use the hand-written butterflies of fft_device.hpp; composite N = A * B
+// (A = 16, 8, 4 or 2, or for odd N 3, 5 or 7; B = N / A, e.g. 32 = 16 x 2, 96 = 16 x 6,
+// 6 = 2 x 3, 15 = 3 x 5) is composed
 // as B A-point DFTs on the stride-B subsequences, twiddles w_N^{b k1}, then A B-point
 // DFTs.  The codelet twiddles are evaluated at compile
 // time in double (Taylor series on a quarter turn) and rounded to T.
@@ -65,7 +66,13 @@ __device__ __forceinline__ void static_for(F&& f) {
 // w_N^{b k1}, then A B-point DFTs (decimation in time).  A is 16 when 16 divides N,
 // else the largest of 8, 4, 2 dividing N; sizes 3 * 2^k end in the radix-3 codelet.
 template <int N> struct RegSplit {
-    static constexpr int A = (N % 16 == 0) ? 16 : (N % 8 == 0) ? 8 : (N % 4 == 0) ? 4 : 2;
+    static constexpr int A = (N % 16 == 0) ? 16
+                             : (N % 8 == 0) ? 8
+                             : (N % 4 == 0) ? 4
+                             : (N % 2 == 0) ? 2
+                             : (N % 3 == 0) ? 3   // odd composites: 9 = 3 x 3, 15 = 3 x 5, 21 = 3 x 7
+                             : (N % 5 == 0) ? 5
+                                            : 7;
     static constexpr int B = N / A;
 };
 
@@ -118,6 +125,9 @@ template <bool INV, typename T> struct RegDFT<16, INV, T> {
 };
 template <bool INV, typename T> struct RegDFT<5, INV, T> {
     static __device__ __forceinline__ void run(C<T>* v) { dft5<T, INV>(v); }
+};
+template <bool INV, typename T> struct RegDFT<7, INV, T> {
+    static __device__ __forceinline__ void run(C<T>* v) { dft7<T, INV>(v); }
 };
 
 }  // namespace se2c

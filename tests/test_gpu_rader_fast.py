@@ -1,6 +1,6 @@
 """GPU parity of the register kernels for prime line lengths (Rader's algorithm in
 registers, FP32 and FP64): the y pass (forward, product, inverse), the theta passes and the x rows
-(forward or inverse alone) of odd grids with a length 13, 17, 37, 97 or 101, against the
+(forward or inverse alone) of odd grids with prime lengths (13 ... 113), against the
 FP64 oracle; separable, FULL and quarter tables, the adjoint, odd batches and complex
 fields.  The generic FP32 kernels of the same plan (SE2CONV_PLAN_GENERIC) must agree too."""
 import numpy as np
@@ -25,6 +25,10 @@ CASES = [
     (31, 17, 97, 3, "f32"),
     (37, 30, 509, 2, "f32"),     # x rows of 37 (the x-theta slab does not fit: split x / theta passes)
     (101, 24, 101, 3, "f32"),    # x rows and theta pencils of 101
+    (41, 61, 19, 2, "f32"),      # y 61 (30 x 2 with a 2 x 3 x 5 register DFT), theta 19
+    (109, 24, 41, 2, "f32"),     # x rows of 109, theta 41
+    (29, 113, 73, 1, "f32"),
+    (41, 29, 19, 2, "f64"),
     (33, 101, 17, 3, "f64"),
     (101, 101, 101, 2, "f64"),
     (24, 97, 13, 1, "f64"),
