@@ -5,10 +5,14 @@
 // The FP32 kernels of sep_fast.hip with complex values in double: a line of L points is
 // split R1 x R2 (R1 values per thread, R2 threads per line, R1 >= R2); first-stage
 // radix-R1 DFTs in registers, twiddles w_L^{t k1}, an LDS exchange, radix-R2 DFTs of the
-// CC = R1 / R2 columns a thread owns (one column at a time, so that at most R1 values
-// and one column are live), the product, and the mirror-image inverse.  Two real lines
+// CC = R1 / R2 columns a thread owns (one column at a time), the product, and the
+// mirror-image inverse.  Two real lines
 // are packed as one complex line: rows 2s and 2s+1 (x rows) or columns 2c and 2c+1 (a
-// double2 load, pencils).  One tile per workgroup.
+// double2 load, pencils).  One tile per workgroup.  The exchange buffer holds doubles (the
+// real parts cross, then the imaginary parts), and the pencils keep one twiddle table for
+// both stages: at 512 points that is 54 KB of LDS per workgroup and three workgroups per
+// CU, where complex slots and two twiddle layouts (98 KB) left one (512 x 512 x 128 x 4
+// FP64: y pass 715 -> 431 us, x rows 610 -> 416 us).
 #include "fast_common.hpp"
 #include "regfft.hpp"
 #include "sep_fast64.hpp"
@@ -39,39 +43,59 @@ __device__ __forceinline__ int xpos64(int k1, int t) {
 
 // One line exchange: v[R1] (first stage done, in the thread's registers) -> second stage,
 // product with f (the line factor, L entries), inverse second stage -> v (ready for the
-// inverse first stage).  line points to the line's LDS slots (stride `ls` between slots).
-// twf(t, k1) and twi(tt, k1) give the twiddle w_L^{t k1} (t k1 < L): from the plan's table
-// in global memory (the x rows, where LDS is kept for the exchange so that two workgroups
-// fit per CU at 512 points) or from LDS copies laid out for conflict-free reads (pencils,
-// measured faster there).
+// inverse first stage).  line points to the line's LDS slots (one double each, stride `ls`
+// between slots): the real parts cross first, then the imaginary parts, so the exchange
+// buffer holds doubles, half the LDS of complex slots.  That is what lets two or three
+// workgroups share a CU at 512 points, where one workgroup with complex slots had the CU to
+// itself.  While the columns are transformed the thread's R1 first-stage values are dead
+// (they are in LDS and in its CC columns), so the split costs no registers.
+// twf(t, k1) and twi(tt, k1) give the twiddle w_L^{t k1} (t k1 < L).
 template <int L, typename TF, typename TI>
-__device__ __forceinline__ void line_middle64(D2* v, D2* line, int ls, const D2* f, TF twf, TI twi, int t) {
+__device__ __forceinline__ void line_middle64(D2* v, double* line, int ls, const D2* f, TF twf, TI twi, int t) {
     using Gm = Geom64<L>;
     constexpr int R1 = Gm::R1, R2 = Gm::R2, CC = Gm::CC;
 #pragma unroll
     for (int k1 = 1; k1 < R1; ++k1) v[k1] = mul<double>(v[k1], twf(t, k1));
+    D2 u[CC][R2];
 #pragma unroll
-    for (int k1 = 0; k1 < R1; ++k1) line[xpos64<R1, R2>(k1, t) * ls] = v[k1];
+    for (int k1 = 0; k1 < R1; ++k1) line[xpos64<R1, R2>(k1, t) * ls] = v[k1].x;
     __syncthreads();
-    // each thread reads and writes back only its own CC columns
+#pragma unroll
+    for (int j = 0; j < CC; ++j)
+#pragma unroll
+        for (int tt = 0; tt < R2; ++tt) u[j][tt].x = line[xpos64<R1, R2>(CC * t + j, tt) * ls];
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) line[xpos64<R1, R2>(k1, t) * ls] = v[k1].y;
+    __syncthreads();
+    // each thread reads and writes back only its own CC columns; a finished column's
+    // imaginary parts go straight back to its slots, so one column's values and the real
+    // parts of the others are what is live
 #pragma unroll
     for (int j = 0; j < CC; ++j) {
         const int k1 = CC * t + j;
-        D2 u[R2];
 #pragma unroll
-        for (int tt = 0; tt < R2; ++tt) u[tt] = line[xpos64<R1, R2>(k1, tt) * ls];
-        RegDFT<R2, false, double>::run(u);
+        for (int tt = 0; tt < R2; ++tt) u[j][tt].y = line[xpos64<R1, R2>(k1, tt) * ls];
+        RegDFT<R2, false, double>::run(u[j]);
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) u[k2] = mul<double>(u[k2], f[k1 + R1 * k2]);
-        RegDFT<R2, true, double>::run(u);
+        for (int k2 = 0; k2 < R2; ++k2) u[j][k2] = mul<double>(u[j][k2], f[k1 + R1 * k2]);
+        RegDFT<R2, true, double>::run(u[j]);
 #pragma unroll
-        for (int tt = 1; tt < R2; ++tt) u[tt] = mulc<double>(u[tt], twi(tt, k1));
+        for (int tt = 1; tt < R2; ++tt) u[j][tt] = mulc<double>(u[j][tt], twi(tt, k1));
 #pragma unroll
-        for (int tt = 0; tt < R2; ++tt) line[xpos64<R1, R2>(k1, tt) * ls] = u[tt];
+        for (int tt = 0; tt < R2; ++tt) line[xpos64<R1, R2>(k1, tt) * ls] = u[j][tt].y;
     }
     __syncthreads();
 #pragma unroll
-    for (int k1 = 0; k1 < R1; ++k1) v[k1] = line[xpos64<R1, R2>(k1, t) * ls];
+    for (int k1 = 0; k1 < R1; ++k1) v[k1].y = line[xpos64<R1, R2>(k1, t) * ls];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < CC; ++j)
+#pragma unroll
+        for (int tt = 0; tt < R2; ++tt) line[xpos64<R1, R2>(CC * t + j, tt) * ls] = u[j][tt].x;
+    __syncthreads();
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) v[k1].x = line[xpos64<R1, R2>(k1, t) * ls];
 }
 
 template <int L>
@@ -84,7 +108,7 @@ __device__ __forceinline__ void load_line_factor64(D2* f, const void* const* tab
 template <int NX> struct RowGeom64 {
     static constexpr int G = 8;
     static constexpr int NT = G * Geom64<NX>::R2;
-    static constexpr int P = NX + 1;  // LDS pitch between rows (complex)
+    static constexpr int P = NX + 1;  // LDS pitch between rows (doubles)
 };
 
 template <int NX>
@@ -93,8 +117,8 @@ __global__ void __launch_bounds__(RowGeom64<NX>::NT) x_rows_f64(Fast64Args a) {
     using RG = RowGeom64<NX>;
     constexpr int R1 = Gm::R1, R2 = Gm::R2, G = RG::G, P = RG::P;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    D2* buf = reinterpret_cast<D2*>(smem_raw);  // G x P
-    D2* fx = buf + G * P;
+    D2* fx = reinterpret_cast<D2*>(smem_raw);  // NX
+    double* buf = reinterpret_cast<double*>(fx + NX);  // G x P
     const int tid = threadIdx.x;
     const int nslab = a.ny / 2;
     const int trows = a.m / G;
@@ -131,9 +155,15 @@ __global__ void __launch_bounds__(RowGeom64<NX>::NT) x_rows_f64(Fast64Args a) {
 // Pencils: W adjacent x-pairs (double2 columns) x L points along y (axis 1) or theta
 // (axis 2), in place on a.out.
 template <int L> struct PencilGeom64 {
-    static constexpr int W = 8;
+    // 16 columns (256-byte row segments) up to 128 points: 415 against 483-503 us for the
+    // theta pass of 512 x 512 x 128 x 4; 8 at 256 and 512, where LDS holds the lines
+    static constexpr int W = L <= 128 ? 16 : 8;
     static constexpr int NT = W * Geom64<L>::R2;
-    static constexpr int P = W + 1;  // LDS pitch between line slots (complex)
+    static constexpr int P = W + 1;  // LDS pitch between line slots (doubles)
+    // twiddles w_L^{t k1} in LDS as [k1][t] with pitch R2 + 1: the first stage reads
+    // consecutive t at one k1, the column phase one t at the k1 = CC t + j of each thread
+    // (stride CC (R2 + 1) slots), both without bank conflicts; one table for both reads
+    static constexpr int TP = Geom64<L>::R2 + 1;
 };
 
 template <int L>
@@ -142,17 +172,15 @@ __global__ void __launch_bounds__(PencilGeom64<L>::NT) pencil_f64(Fast64Args a) 
     using PG = PencilGeom64<L>;
     constexpr int R1 = Gm::R1, R2 = Gm::R2, W = PG::W, P = PG::P;
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    D2* buf = reinterpret_cast<D2*>(smem_raw);  // [slot][W] with pitch P
-    D2* tw_f = buf + L * P;                      // [k1][t] = w_L^{t k1}
-    D2* tw_i = tw_f + L;                         // [t][k1]
-    D2* fl = tw_i + L;
+    constexpr int TP = PG::TP;
+    D2* fl = reinterpret_cast<D2*>(smem_raw);
+    D2* tw2 = fl + L;                                         // [k1][t], pitch TP
+    double* buf = reinterpret_cast<double*>(tw2 + R1 * TP);  // [slot][W] with pitch P
     const int tid = threadIdx.x;
     load_line_factor64<L>(fl, a.tab, a.ntab, a.conj_tab, tid, PG::NT);
     for (int i = tid; i < L; i += PG::NT) {
         const int k1 = i / R2, tt = i - k1 * R2;
-        const D2 w = a.tw[tt * k1];
-        tw_f[k1 * R2 + tt] = w;
-        tw_i[tt * R1 + k1] = w;
+        tw2[k1 * TP + tt] = a.tw[tt * k1];
     }
     const int q = tid % W, t = tid / W;
     const int ncols = a.nx / 2;
@@ -171,8 +199,8 @@ __global__ void __launch_bounds__(PencilGeom64<L>::NT) pencil_f64(Fast64Args a) 
     for (int r = 0; r < R1; ++r) v[r] = base[(long long)(t + R2 * r) * lstride];
     __syncthreads();
     RegDFT<R1, false, double>::run(v);
-    line_middle64<L>(v, buf + q, P, fl, [tw_f](int t_, int k_) { return tw_f[k_ * R2 + t_]; },
-                     [tw_i](int t_, int k_) { return tw_i[t_ * R1 + k_]; }, t);
+    const auto twl = [tw2](int t_, int k_) { return tw2[k_ * TP + t_]; };
+    line_middle64<L>(v, buf + q, P, fl, twl, twl, t);
     RegDFT<R1, true, double>::run(v);
 #pragma unroll
     for (int r = 0; r < R1; ++r) base[(long long)(t + R2 * r) * lstride] = v[r];
@@ -180,17 +208,18 @@ __global__ void __launch_bounds__(PencilGeom64<L>::NT) pencil_f64(Fast64Args a) 
 
 template <int NX>
 static size_t rows64_lds() {
-    return sizeof(D2) * ((size_t)RowGeom64<NX>::G * RowGeom64<NX>::P + NX);
+    return sizeof(double) * (size_t)RowGeom64<NX>::G * RowGeom64<NX>::P + sizeof(D2) * NX;
 }
 template <int L>
 static size_t pencil64_lds() {
-    return sizeof(D2) * ((size_t)L * PencilGeom64<L>::P + 3 * L);
+    using PG = PencilGeom64<L>;
+    return sizeof(double) * (size_t)L * PG::P + sizeof(D2) * ((size_t)L + (size_t)Geom64<L>::R1 * PG::TP);
 }
 
 static bool len64_ok(int l) { return l == 32 || l == 64 || l == 128 || l == 256 || l == 512; }
 
 bool fast64_supported(int nx, int ny, int m) {
-    return (nx == 64 || nx == 128 || nx == 256 || nx == 512) && (nx / 2) % 8 == 0 && len64_ok(ny) &&
+    return (nx == 64 || nx == 128 || nx == 256 || nx == 512) && (nx / 2) % 16 == 0 && len64_ok(ny) &&
            len64_ok(m) && m % RowGeom64<64>::G == 0;
 }
 

@@ -37,15 +37,27 @@ def test_field_tables_match_oracle_ffc(dt, batch):
         assert err < (1e-13 if dt == "f64" else 1e-6)
 
 
-def test_profile_grad_matches_oracle(rng):
-    case("profile gradient 32x32x16 fp64 batch 3")
+@pytest.mark.parametrize("nk,rmax,dt", [
+    (12, 0.45, "f64"),
+    (64, 0.5, "f32"),    # the differentiation workload's knots and reach
+    (16, 0.95, "f64"),   # nine lattice images in reach of the hats
+    (96, 0.3, "f64"),    # more knots than one 64-wide output tile
+])
+def test_profile_grad_matches_oracle(rng, nk, rmax, dt):
+    case(f"profile gradient 32x32x16 {dt} batch 3, {nk} knots, r_max {rmax}")
     nx = ny = 32
-    m, nk, rmax = 16, 12, 0.45
+    m = 16
     gp = rng.standard_normal((3, m, ny, nx))
-    plan = se2.Plan([(nx, ny, m)], dtype="f64")
-    out = plan.profile_grad(0, _dev(gp, torch.float64), nk, rmax).cpu().numpy()
-    ref = OA.grad_profile(gp, nk, rmax)
-    assert np.max(np.abs(out - ref)) <= 1e-12 * np.max(np.abs(ref))
+    tdt = torch.float64 if dt == "f64" else torch.float32
+    plan = se2.Plan([(nx, ny, m)], dtype=dt)
+    out = plan.profile_grad(0, _dev(gp, tdt), nk, rmax).cpu().numpy()
+    ref = OA.grad_profile(gp.astype(np.float32).astype(np.float64) if dt == "f32" else gp, nk, rmax)
+    err = np.max(np.abs(out - ref)) / np.max(np.abs(ref))
+    print(f"  max rel err {err:.2e}", flush=True)
+    assert err <= 1e-12
+    # deterministic: a second call gives the same bits
+    again = plan.profile_grad(0, _dev(gp, tdt), nk, rmax).cpu().numpy()
+    assert np.array_equal(out, again)
 
 
 def _loss_parts(nx, ny, m, batch, nk, rmax, seed, rng):
