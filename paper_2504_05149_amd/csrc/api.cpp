@@ -505,10 +505,12 @@ int pencil_width(int ncols, int L, bool d, int want = 16) {
 }
 
 hipError_t run_slab(const se2conv_plan_s* p, SlabArgs a, bool d, hipStream_t st) {
-    // x rows of a prime length with register kernels (one direction, planes, no product):
-    // Rader's algorithm in registers, unless the plan asks for the generic kernels
-    if (!(p->flags & SE2CONV_PLAN_GENERIC) && !a.do_t && a.mul == 0 && a.in_mode == 1 && a.out_mode == 1 &&
-        !a.items && a.px.rader && rader_fast_supported(a.px.L, d) && a.fwd != a.inv) {
+    // x rows of a prime length with register kernels (planes; one direction, or forward,
+    // 1-D product and inverse): Rader's algorithm in registers, unless the plan asks for
+    // the generic kernels
+    if (!(p->flags & SE2CONV_PLAN_GENERIC) && !a.do_t && a.in_mode == 1 && a.out_mode == 1 && !a.items &&
+        a.px.rader && rader_fast_supported(a.px.L, d) &&
+        ((a.mul == 0 && a.fwd != a.inv) || (a.mul == 1 && a.fwd && a.inv))) {
         PencilArgs r{};
         r.in0 = a.in0;
         r.in1 = a.in1;
@@ -527,7 +529,11 @@ hipError_t run_slab(const se2conv_plan_s* p, SlabArgs a, bool d, hipStream_t st)
         r.ncols = a.ny;
         r.fwd = a.fwd;
         r.inv = a.inv;
-        r.mul = 0;
+        r.mul = a.mul;
+        r.ntab = a.mul ? a.ntab : 0;
+        for (int j = 0; j < r.ntab; ++j) r.tab1[j] = a.tx[j];
+        r.conj_tab = a.conj_tab;
+        r.scale = a.scale;
         r.p = a.px;
         r.cplx = a.cplx;
         hipError_t e = launch_rader_pencil(r, d, st);
@@ -550,7 +556,7 @@ hipError_t run_pencil(const se2conv_plan_s* p, PencilArgs a, bool d, hipStream_t
     // asks for the generic kernels
     if (!(p->flags & SE2CONV_PLAN_GENERIC) && a.p.rader && rader_fast_supported(a.p.L, d) && a.mode == 1 &&
         !a.items &&
-        ((a.fwd && a.inv && a.mul == 2) || (a.fwd != a.inv && a.mul == 0))) {
+        ((a.fwd && a.inv && (a.mul == 2 || a.mul == 1)) || (a.fwd != a.inv && a.mul == 0))) {
         hipError_t e = launch_rader_pencil(a, d, st);
         if (e != hipSuccess) return e;
         return after_pass(a.axis == 1 ? 1 : 2, st);
@@ -1335,10 +1341,109 @@ se2conv_status validate_io(se2conv_plan_s* p, int32_t shape_idx, const void* f, 
     return SE2CONV_OK;
 }
 
+// Separable chain on a grid with an odd side: fields packed in pairs (re/im planes, the
+// odd batch's last imaginary plane in the workspace), and the 3-D product regrouped into
+// 1-D circular convolutions as on even grids: x and theta in one slab pass when the slab
+// fits in LDS, else x rows then theta pencils, and y pencils; each pass forward, product
+// with its axis' factor, inverse.  Two or three passes over the batch instead of the
+// general path's three or five (forward, 3-D product along y, inverse).  The packing
+// holds because every 1-D factor of a separable table is the transform of a real kernel
+// along its axis.
+se2conv_status enqueue_sep_pairs(se2conv_plan_s* p, const se2conv_shape& s, const void* f, void* out, int batch,
+                                 const Chain& ch, bool conj, hipStream_t st) {
+    const bool d = dbl(p);
+    const long long n = (long long)s.nx * s.ny * s.m;
+    const size_t rb = real_bytes(p), cb = cplx_bytes(p);
+    const int pairs = (batch + 1) / 2;
+    const bool odd = (batch & 1) != 0;
+    const void* f1 = batch == 1 ? nullptr : (const char*)f + rb * n;
+    void* o1 = batch == 1 ? nullptr : (char*)out + rb * n;
+    void* lone = odd ? p->ws : nullptr;
+    const RadixPlan px = radix_plan_of(p, s.nx, d), py = radix_plan_of(p, s.ny, d), pt = radix_plan_of(p, s.m, d);
+    const bool fits = slab_fits(s, d);
+    SlabArgs a{};
+    a.in0 = f;
+    a.in1 = f1;
+    a.out0 = out;
+    a.out1 = o1;
+    a.lone_in1 = nullptr;  // the odd item's imaginary plane is zero on input
+    a.lone_out1 = lone;
+    a.item_stride_in = 2 * n;
+    a.item_stride_out = 2 * n;
+    a.nitems = pairs;
+    a.in_mode = 1;
+    a.out_mode = 1;
+    a.nx = s.nx;
+    a.ny = s.ny;
+    a.m = s.m;
+    a.nslab = s.ny;
+    a.pad = 0;
+    a.fwd = 1;
+    a.inv = 1;
+    a.mul = 1;
+    a.ntab = ch.ntab;
+    a.conj_tab = conj ? 1 : 0;
+    a.px = px;
+    a.pt = pt;
+    a.twx = stage_tw_of(p, px, d);
+    a.twt = stage_tw_of(p, pt, d);
+    for (int j = 0; j < ch.ntab; ++j) {
+        a.tx[j] = ch.ptr[j];
+        a.tt[j] = (const char*)ch.ptr[j] + cb * (s.nx + s.ny);
+    }
+    if (fits) {
+        a.rows_per_tile = s.m;
+        a.ntile_t = 1;
+        a.do_t = 1;
+        a.scale = 1.0 / ((double)s.nx * s.m);
+    } else {
+        a.rows_per_tile = rows_for_xpass(s, d, sched_of(p, s).xrow_points);
+        a.ntile_t = (s.m + a.rows_per_tile - 1) / a.rows_per_tile;
+        a.do_t = 0;
+        a.scale = 1.0 / (double)s.nx;
+    }
+    HIPCHK(run_slab(p, a, d, st));
+    auto pencil = [&](int axis) -> hipError_t {
+        const int L = axis == 1 ? s.ny : s.m;
+        PencilArgs b{};
+        b.in0 = out;
+        b.in1 = o1;
+        b.out0 = out;
+        b.out1 = o1;
+        b.lone_in1 = lone;
+        b.lone_out1 = lone;
+        b.item_stride_in = 2 * n;
+        b.item_stride_out = 2 * n;
+        b.nitems = pairs;
+        b.mode = 1;
+        b.axis = axis;
+        b.nx = s.nx;
+        b.ny = s.ny;
+        b.m = s.m;
+        b.ncols = s.nx;
+        b.W = pencil_width(b.ncols, L, d, sched_of(p, s).pencil_w);
+        b.pad = 0;
+        b.fwd = 1;
+        b.inv = 1;
+        b.mul = 1;
+        b.ntab = ch.ntab;
+        for (int j = 0; j < ch.ntab; ++j) b.tab1[j] = (const char*)ch.ptr[j] + cb * (axis == 1 ? s.nx : s.nx + s.ny);
+        b.conj_tab = conj ? 1 : 0;
+        b.scale = 1.0 / (double)L;
+        b.p = axis == 1 ? py : pt;
+        b.tw = stage_tw_of(p, b.p, d);
+        return run_pencil(p, b, d, st);
+    };
+    HIPCHK(pencil(1));
+    if (!fits) HIPCHK(pencil(2));
+    return SE2CONV_OK;
+}
+
 se2conv_status enqueue_problem(se2conv_plan_s* p, int shape_idx, const void* f, void* out, int batch,
                                const Chain& ch, bool all_sep, bool conj, hipStream_t st) {
     const se2conv_shape& s = p->shapes[shape_idx];
     if (all_sep && pair_layout(s)) return enqueue_sep(p, s, f, out, batch, ch, conj, st);
+    if (all_sep) return enqueue_sep_pairs(p, s, f, out, batch, ch, conj, st);
     return enqueue_full(p, s, f, out, batch, ch, conj, st);
 }
 

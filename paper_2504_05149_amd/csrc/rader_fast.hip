@@ -16,10 +16,12 @@
 // permuted order between its two transforms: no scatter or gather in between.
 //
 // MODE 0: forward DFT, product with the chain (x scale, conjugated for the adjoint),
-//         inverse DFT; MODE 1: forward only; MODE 2: inverse only.  Pencils on the planes
-// of field pairs (PencilArgs mode 1): W columns of x at one outer coordinate, lines along
-// y (axis 1) or theta (axis 2); or (axis 0, ROWS) W rows of x at one theta, lines along x
-// (one direction only).  Tiles are loaded into LDS whole, computed in registers,
+//         inverse DFT; MODE 1: forward only; MODE 2: inverse only.  The product of MODE 0
+// is the 3-D chain factor at the line's frequencies (PencilArgs mul 2: FULL, quarter or
+// separable tables) or a 1-D factor along the line (mul 1: one axis of separable tables,
+// a 1-D circular convolution).  Pencils on the planes of field pairs (PencilArgs mode 1):
+// W columns of x at one outer coordinate, lines along y (axis 1) or theta (axis 2); or
+// (axis 0, ROWS) W rows of x at one theta, lines along x.  Tiles are loaded into LDS whole, computed in registers,
 // scattered back to natural order through LDS and stored.
 #include "passes.hpp"
 #include "regfft.hpp"
@@ -136,10 +138,11 @@ __global__ void __launch_bounds__(kRaderW * RaderGeom<P>::R2) rader_pencil(Penci
     int* pin = reinterpret_cast<int*>(fl + P);            // g^q mod P
     int* pout = pin + N;                                  // g^-q mod P
     const int tid = threadIdx.x;
+    const bool one_d = MODE == 0 && a.mul == 1;  // 1-D factor along the line only
     bool sep = MODE == 0;
-    for (int j = 0; j < a.ntab; ++j) sep = sep && a.tab3[j] == nullptr;
+    for (int j = 0; j < a.ntab; ++j) sep = sep && (one_d || a.tab3[j] == nullptr);
     if (sep) {
-        const void* const* lt = a.axis == 1 ? a.sepy : a.sept;
+        const void* const* lt = one_d ? a.tab1 : (a.axis == 1 ? a.sepy : a.sept);
         for (int i = tid; i < P; i += NT) {
             C<T> v = mk<T>((T)1, (T)0);
             for (int j = 0; j < a.ntab; ++j) v = mul<T>(v, reinterpret_cast<const C<T>*>(lt[j])[i]);
@@ -213,10 +216,11 @@ __global__ void __launch_bounds__(kRaderW * RaderGeom<P>::R2) rader_pencil(Penci
             if constexpr (MODE == 0) {
                 const int kx = min(c0 + q, a.ncols - 1);  // columns past the edge compute, unstored
                 if (sep) {
-                    // scale x the factors of x and of the outer coordinate, then the line's from LDS
+                    // scale x the factors of x and of the outer coordinate (3-D product),
+                    // then the line's from LDS
                     C<T> c = mk<T>((T)a.scale, (T)0);
                     const void* const* ot = a.axis == 1 ? a.sept : a.sepy;
-                    for (int j = 0; j < a.ntab; ++j) {
+                    for (int j = 0; j < a.ntab && !one_d; ++j) {
                         c = mul<T>(c, reinterpret_cast<const C<T>*>(a.sepx[j])[kx]);
                         c = mul<T>(c, reinterpret_cast<const C<T>*>(ot[j])[other]);
                     }
@@ -296,7 +300,8 @@ static hipError_t launch_rader_t(const PencilArgs& a, hipStream_t s) {
 
 template <typename T, int P>
 static hipError_t launch_rader_p(const PencilArgs& a, int mode, hipStream_t s) {
-    if (a.axis == 0) {  // x rows: one direction at a time
+    if (a.axis == 0) {  // x rows
+        if (mode == 0) return launch_rader_t<T, P, 0, true>(a, s);
         if (mode == 1) return launch_rader_t<T, P, 1, true>(a, s);
         if (mode == 2) return launch_rader_t<T, P, 2, true>(a, s);
         return hipErrorInvalidValue;
@@ -334,11 +339,11 @@ static hipError_t launch_rader_typed(const PencilArgs& a, int mode, hipStream_t 
 
 hipError_t launch_rader_pencil(const PencilArgs& a, bool dbl, hipStream_t s) {
     int mode;
-    if (a.fwd && a.inv && a.mul == 2) mode = 0;
+    if (a.fwd && a.inv && (a.mul == 2 || a.mul == 1)) mode = 0;
     else if (a.fwd && !a.inv && a.mul == 0) mode = 1;
     else if (!a.fwd && a.inv && a.mul == 0) mode = 2;
     else return hipErrorInvalidValue;
-    if (a.mode != 1 || a.items) return hipErrorInvalidValue;
+    if (a.mode != 1 || a.items || (a.axis == 0 && a.mul == 2)) return hipErrorInvalidValue;
     return dbl ? launch_rader_typed<double>(a, mode, s) : launch_rader_typed<float>(a, mode, s);
 }
 
