@@ -286,6 +286,7 @@ struct se2conv_plan_s {
     hipEvent_t ev_fork = nullptr;
     std::vector<hipEvent_t> ev_join;
     std::mutex mu;
+    std::mutex fork_mu;  // one fork / join on the auxiliary streams at a time
     // pass timing (SE2CONV_TIMING)
     bool timing = false;
     std::vector<hipEvent_t> ev_pool;
@@ -1117,11 +1118,39 @@ se2conv_status enqueue_full(se2conv_plan_s* p, const se2conv_shape& s, const voi
     return SE2CONV_OK;
 }
 
+constexpr int kChainStreams = 4;
+
+// Auxiliary streams and events of the plan (created once, under the plan mutex).
+se2conv_status ensure_aux_streams(se2conv_plan_s* p) {
+    std::lock_guard<std::mutex> g(p->mu);
+    if (!p->aux.empty()) return SE2CONV_OK;
+    std::vector<hipStream_t> st(kChainStreams, nullptr);
+    std::vector<hipEvent_t> ev(kChainStreams, nullptr);
+    hipEvent_t fork = nullptr;
+    bool good = hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess;
+    for (int i = 0; good && i < kChainStreams; ++i)
+        good = hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) == hipSuccess;
+    if (!good) {
+        for (auto x : st)
+            if (x) (void)hipStreamDestroy(x);
+        for (auto x : ev)
+            if (x) (void)hipEventDestroy(x);
+        if (fork) (void)hipEventDestroy(fork);
+        return fail(SE2CONV_ERR_DEVICE, "could not create the chain streams");
+    }
+    p->aux = st;
+    p->ev_join = ev;
+    p->ev_fork = fork;
+    return SE2CONV_OK;
+}
+
+
 // Every shape class of a grouped item list in one launch per pass (the multi-class
 // register kernels), when every class has them; *done tells whether it ran.  Classes go
 // largest first, so that the last workgroups of the grid are the small ones.
 se2conv_status enqueue_multi(se2conv_plan_s* p, const SepItem* d_items, const std::vector<std::pair<int, int>>& groups,
-                             const std::vector<int>& counts, bool conj, hipStream_t st, bool* done) {
+                             const std::vector<int>& counts, bool conj, hipStream_t st, bool* done, bool fork_ok) {
     *done = false;
     static const bool enabled = [] {
         const char* e = std::getenv("SE2CONV_CHAIN_MULTI");
@@ -1157,6 +1186,33 @@ se2conv_status enqueue_multi(se2conv_plan_s* p, const SepItem* d_items, const st
         c.twx = reinterpret_cast<const float2*>(tw_of(p, s.nx, false));
         c.twy = reinterpret_cast<const float2*>(tw_of(p, s.ny, false));
         c.twt = reinterpret_cast<const float2*>(tw_of(p, s.m, false));
+    }
+    // Classes with NX = 3 * 2^k run their slab kernel at two waves per SIMD, the others at
+    // three: two kernels per pass.  With both kinds present they go to two streams (two
+    // branches of a captured graph), so that the kinds share the GPU instead of each
+    // running alone: 256 uneven problems in 15 classes, 0.396 ms per replay in one slab and one
+    // pencil launch, 0.376 ms with the kinds in turn on one stream, 0.349 ms on two.
+    MultiArgs part[2] = {m, m};
+    part[0].nclass = part[1].nclass = 0;
+    for (int k = 0; k < ng; ++k) {
+        MultiArgs& q = part[(m.c[k].nx & (m.c[k].nx - 1)) == 0 ? 0 : 1];
+        q.c[q.nclass++] = m.c[k];
+    }
+    if (fork_ok && part[0].nclass && part[1].nclass) {
+        se2conv_status r = ensure_aux_streams(p);
+        if (r != SE2CONV_OK) return r;
+        std::lock_guard<std::mutex> g(p->fork_mu);
+        hipStream_t side = p->aux[0];
+        HIPCHK(hipEventRecord(p->ev_fork, st));
+        HIPCHK(hipStreamWaitEvent(side, p->ev_fork, 0));
+        HIPCHK(launch_slab_multi(part[1], side));
+        HIPCHK(launch_pencil_multi(part[1], side));
+        HIPCHK(launch_slab_multi(part[0], st));
+        HIPCHK(launch_pencil_multi(part[0], st));
+        HIPCHK(hipEventRecord(p->ev_join[0], side));
+        HIPCHK(hipStreamWaitEvent(st, p->ev_join[0], 0));
+        *done = true;
+        return SE2CONV_OK;
     }
     HIPCHK(launch_slab_multi(m, st));
     HIPCHK(after_pass(0, st));
@@ -2742,36 +2798,6 @@ se2conv_status se2conv_backward(se2conv_plan_t p, int32_t shape_idx, const void*
     return ok();
 }
 
-namespace {
-
-constexpr int kChainStreams = 4;
-
-// Auxiliary streams and events of the plan (created once, under the plan mutex).
-se2conv_status ensure_aux_streams(se2conv_plan_s* p) {
-    std::lock_guard<std::mutex> g(p->mu);
-    if (!p->aux.empty()) return SE2CONV_OK;
-    std::vector<hipStream_t> st(kChainStreams, nullptr);
-    std::vector<hipEvent_t> ev(kChainStreams, nullptr);
-    hipEvent_t fork = nullptr;
-    bool good = hipEventCreateWithFlags(&fork, hipEventDisableTiming) == hipSuccess;
-    for (int i = 0; good && i < kChainStreams; ++i)
-        good = hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking) == hipSuccess &&
-               hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) == hipSuccess;
-    if (!good) {
-        for (auto x : st)
-            if (x) (void)hipStreamDestroy(x);
-        for (auto x : ev)
-            if (x) (void)hipEventDestroy(x);
-        if (fork) (void)hipEventDestroy(fork);
-        return fail(SE2CONV_ERR_DEVICE, "could not create the chain streams");
-    }
-    p->aux = st;
-    p->ev_join = ev;
-    p->ev_fork = fork;
-    return SE2CONV_OK;
-}
-
-}  // namespace
 
 se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int32_t n_probs, uint32_t flags,
                              hipStream_t stream) {
@@ -2906,6 +2932,7 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
                        (long long)sb.nx * sb.ny * sb.m * rec->group_counts[b];
             });
             const int nst = std::min(ngroups, chain_streams);
+            std::lock_guard<std::mutex> fg(p->fork_mu);
             HIPCHK(hipEventRecord(p->ev_fork, stream));
             for (int k = 0; k < nst; ++k) HIPCHK(hipStreamWaitEvent(p->aux[k], p->ev_fork, 0));
             for (int oi = 0; oi < ngroups; ++oi) {
@@ -2923,7 +2950,7 @@ se2conv_status se2conv_chain(se2conv_plan_t p, const se2conv_problem* probs, int
         } else {
             bool multi = false;
             se2conv_status r = enqueue_multi(p, reinterpret_cast<const SepItem*>(rec->d_items), rec->groups,
-                                             rec->group_counts, conj, stream, &multi);
+                                             rec->group_counts, conj, stream, &multi, !(flags & SE2CONV_TIMING));
             if (r != SE2CONV_OK) return r;
             for (int gi = 0; !multi && gi < ngroups; ++gi) {
                 const int sidx = rec->groups[gi].first;
@@ -3074,7 +3101,7 @@ se2conv_status se2conv_chain_noalloc(se2conv_plan_t p, const se2conv_problem* pr
         first += (int)kv.second.size();
     }
     bool multi = false;
-    se2conv_status mr = enqueue_multi(p, sp, groups, counts, conj, stream, &multi);
+    se2conv_status mr = enqueue_multi(p, sp, groups, counts, conj, stream, &multi, false);
     if (mr != SE2CONV_OK) return mr;
     for (size_t gi = 0; !multi && gi < groups.size(); ++gi) {
         se2conv_status r = enqueue_sep_items(p, p->shapes[groups[gi].first], sp + groups[gi].second, counts[gi], conj,

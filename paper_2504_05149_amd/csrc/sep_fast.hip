@@ -69,7 +69,11 @@ template <int NX, int M, int RCX = (M < 32 ? M : 32)> struct SlabGeom {
 // accessor (the multi-class launches); otherwise a.items may be null (then the launch's
 // fields are a.in / a.out with one chain in the argument block) and the chain's table
 // pointers are copied into a local array.
-template <int NX, int M, int RCX, bool ACC>
+// CLAMPED: every thread belongs to a slab that names a valid one (a slab past its class's
+// end repeats the class's last slab and writes the same values), so no load, LDS write
+// or store needs a predicate.  The predicates of the general form cost the multi-class
+// kernel about 90 VGPRs (244 against 156 for the 32 x 64 class alone).
+template <int NX, int M, int RCX, bool ACC, bool CLAMPED = false>
 __device__ __forceinline__ void slab_body(const FastSepArgs& a, int ny, int item, int s, bool active, int tid,
                                           unsigned char* smem) {
     using Gm = SlabGeom<NX, M, RCX>;
@@ -111,7 +115,7 @@ __device__ __forceinline__ void slab_body(const FastSepArgs& a, int ny, int item
                 tt[j] = a.tt[j];
             }
         }
-    } else if (active) {
+    } else if (CLAMPED || active) {
         fin = reinterpret_cast<const float*>(it->in);
         fout = reinterpret_cast<float*>(it->out);
     }
@@ -129,7 +133,7 @@ __device__ __forceinline__ void slab_body(const FastSepArgs& a, int ny, int item
         else
             return chain_factor(tt, ntab, i, sc, a.conj_tab);
     };
-    if (active) {
+    if (CLAMPED || active) {
         for (int i = tid; i < NX; i += NT) {
             const int k1 = i / R2, t = i - k1 * R2;
             const float2 w = a.tw[t * k1];
@@ -157,7 +161,7 @@ __device__ __forceinline__ void slab_body(const FastSepArgs& a, int ny, int item
 
     const int t = tid % R2, g = tid / R2;
     const bool xlane = XT == NT || tid < XT;   // takes part in the x phase (lanes from XT on idle)
-    const bool xw = xlane && active;           // ... and writes
+    const bool xw = xlane && (CLAMPED || active);  // ... and loads and writes LDS
     // uniform tile base; per-lane offsets stay 32-bit (Nx Ny M < 2^30 is checked on the host)
     const float* __restrict__ in0 = fin + (long long)(2 * s) * NX;
     const float* __restrict__ in1 = in0 + NX;
@@ -272,8 +276,10 @@ __device__ __forceinline__ void slab_body(const FastSepArgs& a, int ny, int item
         }
         RegDFT<MV, true, float>::run(v);
     }
-    // 5. store columns
-    if (!active) return;
+    // 5. store columns (CLAMPED: a repeated slab stores the same bits as the slab it
+    // repeats, in the same workgroup after the same barriers, so its stores need no
+    // predicate either; a predicated store phase cost the multi-class kernel spills)
+    if (!CLAMPED && !active) return;
     float* __restrict__ out0 = fout + (long long)(2 * s) * NX;
     float* __restrict__ out1 = out0 + NX;
     __builtin_amdgcn_s_setprio(2);
@@ -565,47 +571,73 @@ template <int NX, int M>
 __device__ __forceinline__ void slab_class(const MultiArgs& m, const MultiClass& c, int lb, unsigned char* smem) {
     using MS = MultiSlab<NX, M>;
     constexpr int NT = MS::Gm::NT, S = MS::S;
+    // NX a power of two: the S slabs of a workgroup cover its threads exactly
+    constexpr bool CLAMPED = S * NT == SE2C_MULTI_THREADS;
     const int sub_raw = threadIdx.x / NT;
     const int sub = sub_raw < S ? sub_raw : S - 1;   // lanes beyond S shadow the last slab
     const int tid = threadIdx.x - sub_raw * NT;
     const int nslab = c.ny / 2;
-    const int unit = lb * S + sub;
-    const bool active = sub_raw < S && unit < c.nitems * nslab;
-    const int item = active ? unit / nslab : 0;
+    const int nunits = c.nitems * nslab;
+    const int unit_raw = lb * S + sub;
+    const bool active = sub_raw < S && unit_raw < nunits;
+    const int unit = CLAMPED ? min(unit_raw, nunits - 1) : unit_raw;
+    const int item = (CLAMPED || active) ? unit / nslab : 0;
     FastSepArgs a{};
     a.items = m.items + c.item0;
     a.tw = c.tw;
     a.twt = c.twt;
     a.conj_tab = m.conj_tab;
-    slab_body<NX, M, MS::RC, true>(a, c.ny, item, unit - item * nslab, active, tid, smem + (size_t)sub * MS::REGION);
+    slab_body<NX, M, MS::RC, true, CLAMPED>(a, c.ny, item, unit - item * nslab, active, tid,
+                                             smem + (size_t)sub * MS::REGION);
 }
 
-#ifndef SE2C_MULTI_SLABS
-#define SE2C_MULTI_SLABS(X) \
-    X(32, 16) X(32, 32) X(32, 64) X(48, 16) X(48, 32) X(48, 64) X(64, 16) X(64, 32) X(64, 64) \
-    X(96, 16) X(96, 32) X(96, 64) X(128, 16) X(128, 32) X(128, 64) X(256, 16) X(256, 32)
-#endif
+// The classes in two launches by register budget: NX a power of two (no predicates, 153
+// VGPRs, three waves per SIMD) and NX = 3 * 2^k (lanes left over beside the slabs).
+#define SE2C_MULTI_SLABS_P2(X) \
+    X(32, 16) X(32, 32) X(32, 64) X(64, 16) X(64, 32) X(64, 64) X(128, 16) X(128, 32) X(128, 64) X(256, 16) X(256, 32)
+#define SE2C_MULTI_SLABS_P3(X) X(48, 16) X(48, 32) X(48, 64) X(96, 16) X(96, 32) X(96, 64)
+#define SE2C_MULTI_SLABS(X) SE2C_MULTI_SLABS_P2(X) SE2C_MULTI_SLABS_P3(X)
 
-__global__ void __launch_bounds__(SE2C_MULTI_THREADS) xt_slab_multi(MultiArgs m) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __builtin_amdgcn_s_setprio(2);
+__device__ __forceinline__ const MultiClass& multi_class_of(const MultiArgs& m, int* lb) {
     int ci = 0;
     for (int k = 1; k < m.nclass; ++k)
         if ((int)blockIdx.x >= m.c[k].first_block) ci = k;
-    const MultiClass& c = m.c[ci];
-    const int lb = blockIdx.x - c.first_block;
-    switch (c.code) {
+    *lb = blockIdx.x - m.c[ci].first_block;
+    return m.c[ci];
+}
+
 #define SE2C_X(NX_, M_) \
     case NX_ * 1024 + M_: slab_class<NX_, M_>(m, c, lb, smem_raw); break;
-        SE2C_MULTI_SLABS(SE2C_X)
-#undef SE2C_X
+
+__global__ void __launch_bounds__(SE2C_MULTI_THREADS) __attribute__((amdgpu_waves_per_eu(3)))
+xt_slab_multi(MultiArgs m) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __builtin_amdgcn_s_setprio(2);
+    int lb;
+    const MultiClass& c = multi_class_of(m, &lb);
+    switch (c.code) {
+        SE2C_MULTI_SLABS_P2(SE2C_X)
         default: break;
     }
 }
 
+__global__ void __launch_bounds__(SE2C_MULTI_THREADS) xt_slab_multi3(MultiArgs m) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __builtin_amdgcn_s_setprio(2);
+    int lb;
+    const MultiClass& c = multi_class_of(m, &lb);
+    switch (c.code) {
+        SE2C_MULTI_SLABS_P3(SE2C_X)
+        default: break;
+    }
+}
+#undef SE2C_X
+
 // One pencil tile (W adjacent x-pairs x L points along y at theta = o, columns from
 // ct * W) of field `item`, in place on the item's output, by threads tid < NT.
-template <int L, int WW>
+// CLAMPED: as for the slabs, an inactive tile repeats a valid one and every predicate
+// goes (108 VGPRs, four waves per SIMD, for lines of 2^k points; 153 before).
+template <int L, int WW, bool CLAMPED = false>
 __device__ __forceinline__ void pencil_tile(const FastSepArgs& a, int nx, int ny, int item, int o, int ct, bool active,
                                             int tid, unsigned char* smem) {
     using Gm = LineGeom<L, WW>;
@@ -617,7 +649,7 @@ __device__ __forceinline__ void pencil_tile(const FastSepArgs& a, int nx, int ny
     const int ncols = nx / 2;
     const int q = tid % W, t = tid / W;
     float2* base = nullptr;
-    if (active) {
+    if (CLAMPED || active) {
         const SepItem& it = a.items[item];
         base = reinterpret_cast<float2*>(it.out) + (long long)o * ncols * ny + ct * W;
         auto ty = [&](int j) { return reinterpret_cast<const float2*>(it.tab[j]) + nx; };
@@ -634,7 +666,7 @@ __device__ __forceinline__ void pencil_tile(const FastSepArgs& a, int nx, int ny
     float2 w[R1];
 #pragma unroll
     for (int r = 0; r < R1; ++r) w[r] = make_float2(0.f, 0.f);
-    if (active) {
+    if (CLAMPED || active) {
 #pragma unroll
         for (int r = 0; r < R1; ++r) w[r] = (base + r * rstride)[lane_off];
     }
@@ -643,7 +675,7 @@ __device__ __forceinline__ void pencil_tile(const FastSepArgs& a, int nx, int ny
     RegDFT<R1, false, float>::run(w);
 #pragma unroll
     for (int k1 = 1; k1 < R1; ++k1) w[k1] = mul<float>(w[k1], tw_f[k1 * R2 + t]);
-    if (active) {
+    if (CLAMPED || active) {
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1) buf[(k1 * R2 + t) * W + q] = w[k1];
     }
@@ -662,7 +694,7 @@ __device__ __forceinline__ void pencil_tile(const FastSepArgs& a, int nx, int ny
         for (int tt = 1; tt < R2; ++tt) u[j][tt] = mulc<float>(u[j][tt], tw_i[tt * R1 + k1]);
     }
     __syncthreads();
-    if (active) {
+    if (CLAMPED || active) {
 #pragma unroll
         for (int j = 0; j < CC; ++j) {
 #pragma unroll
@@ -673,7 +705,7 @@ __device__ __forceinline__ void pencil_tile(const FastSepArgs& a, int nx, int ny
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) w[k1] = buf[(k1 * R2 + t) * W + q];
     RegDFT<R1, true, float>::run(w);
-    if (!active) return;
+    if (!CLAMPED && !active) return;
     __builtin_amdgcn_s_setprio(2);
 #pragma unroll
     for (int r = 0; r < R1; ++r) (base + r * rstride)[lane_off] = w[r];
@@ -695,37 +727,58 @@ __device__ __forceinline__ void pencil_class(const MultiArgs& m, const MultiClas
     const int tid = threadIdx.x - sub_raw * NT;
     const int ctiles = (c.nx / 2) / WW;
     const int per_item = ctiles * c.m;
-    const int unit = lb * S + sub;
-    const bool active = sub_raw < S && unit < c.nitems * per_item;
-    const int item = active ? unit / per_item : 0;
+    // every class's tiles cover the workgroup's threads exactly (NT divides 256); a tile
+    // past the class's end repeats the class's last tile, in the same workgroup
+    constexpr bool CLAMPED = S * NT == SE2C_MULTI_THREADS;
+    const int nunits = c.nitems * per_item;
+    const int unit_raw = lb * S + sub;
+    const bool active = sub_raw < S && unit_raw < nunits;
+    const int unit = CLAMPED ? min(unit_raw, nunits - 1) : unit_raw;
+    const int item = (CLAMPED || active) ? unit / per_item : 0;
     const int rem = unit - item * per_item;
     const int o = rem / ctiles;
     FastSepArgs a{};
     a.items = m.items + c.item0;
     a.tw = c.tw;
     a.conj_tab = m.conj_tab;
-    pencil_tile<L, WW>(a, c.nx, c.ny, item, o, rem - o * ctiles, active, tid, smem + (size_t)sub * MP::REGION);
+    pencil_tile<L, WW, CLAMPED>(a, c.nx, c.ny, item, o, rem - o * ctiles, active, tid,
+                                smem + (size_t)sub * MP::REGION);
 }
 
-#define SE2C_MULTI_PENCILS(X) \
-    X(32, 16) X(32, 8) X(48, 16) X(48, 8) X(64, 16) X(64, 8) X(96, 16) X(96, 8) X(128, 16) X(128, 8) X(256, 16) X(256, 8)
+// Pencil classes in two launches as well: lines of 2^k points fit the 128 VGPRs of four
+// waves per SIMD, the 96-point lines (24 values per thread) do not; 48 goes with 96, so
+// that square problems of a class kind keep both passes in one kind.
+#define SE2C_MULTI_PENCILS_A(X) \
+    X(32, 16) X(32, 8) X(64, 16) X(64, 8) X(128, 16) X(128, 8) X(256, 16) X(256, 8)
+#define SE2C_MULTI_PENCILS_B(X) X(48, 16) X(48, 8) X(96, 16) X(96, 8)
+#define SE2C_MULTI_PENCILS(X) SE2C_MULTI_PENCILS_A(X) SE2C_MULTI_PENCILS_B(X)
 
-__global__ void __launch_bounds__(SE2C_MULTI_THREADS) y_pencil_multi(MultiArgs m) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    __builtin_amdgcn_s_setprio(2);
-    int ci = 0;
-    for (int k = 1; k < m.nclass; ++k)
-        if ((int)blockIdx.x >= m.c[k].first_block) ci = k;
-    const MultiClass& c = m.c[ci];
-    const int lb = blockIdx.x - c.first_block;
-    switch (c.code) {
 #define SE2C_X(L_, W_) \
     case L_ * 1024 + W_: pencil_class<L_, W_>(m, c, lb, smem_raw); break;
-        SE2C_MULTI_PENCILS(SE2C_X)
-#undef SE2C_X
+
+__global__ void __launch_bounds__(SE2C_MULTI_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+y_pencil_multi(MultiArgs m) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __builtin_amdgcn_s_setprio(2);
+    int lb;
+    const MultiClass& c = multi_class_of(m, &lb);
+    switch (c.code) {
+        SE2C_MULTI_PENCILS_A(SE2C_X)
         default: break;
     }
 }
+
+__global__ void __launch_bounds__(SE2C_MULTI_THREADS) y_pencil_multi3(MultiArgs m) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __builtin_amdgcn_s_setprio(2);
+    int lb;
+    const MultiClass& c = multi_class_of(m, &lb);
+    switch (c.code) {
+        SE2C_MULTI_PENCILS_B(SE2C_X)
+        default: break;
+    }
+}
+#undef SE2C_X
 
 // Host side of the multi-class launches: shape support, class codes, units per
 // workgroup and LDS.
@@ -809,21 +862,49 @@ static hipError_t plan_multi(MultiArgs& m, bool pencil, int* blocks, size_t* lds
 }
 
 hipError_t launch_slab_multi(MultiArgs m, hipStream_t s) {
-    int blocks = 0;
-    size_t lds = 0;
-    hipError_t e = plan_multi(m, false, &blocks, &lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(xt_slab_multi, dim3(blocks), dim3(SE2C_MULTI_THREADS), lds, s, m);
-    return hipGetLastError();
+    // power-of-two classes first (most of the points), then the 3 * 2^k classes; each
+    // launch keeps the classes' order (largest first)
+    MultiArgs part[2] = {m, m};
+    part[0].nclass = part[1].nclass = 0;
+    for (int k = 0; k < m.nclass; ++k) {
+        const int nx = m.c[k].nx;
+        MultiArgs& q = part[(nx & (nx - 1)) == 0 ? 0 : 1];
+        q.c[q.nclass++] = m.c[k];
+    }
+    for (int h = 0; h < 2; ++h) {
+        if (part[h].nclass == 0) continue;
+        int blocks = 0;
+        size_t lds = 0;
+        hipError_t e = plan_multi(part[h], false, &blocks, &lds);
+        if (e != hipSuccess) return e;
+        if (h == 0) hipLaunchKernelGGL(xt_slab_multi, dim3(blocks), dim3(SE2C_MULTI_THREADS), lds, s, part[h]);
+        else hipLaunchKernelGGL(xt_slab_multi3, dim3(blocks), dim3(SE2C_MULTI_THREADS), lds, s, part[h]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_pencil_multi(MultiArgs m, hipStream_t s) {
-    int blocks = 0;
-    size_t lds = 0;
-    hipError_t e = plan_multi(m, true, &blocks, &lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(y_pencil_multi, dim3(blocks), dim3(SE2C_MULTI_THREADS), lds, s, m);
-    return hipGetLastError();
+    MultiArgs part[2] = {m, m};
+    part[0].nclass = part[1].nclass = 0;
+    for (int k = 0; k < m.nclass; ++k) {
+        const int ny = m.c[k].ny;
+        MultiArgs& q = part[(ny & (ny - 1)) == 0 ? 0 : 1];
+        q.c[q.nclass++] = m.c[k];
+    }
+    for (int h = 0; h < 2; ++h) {
+        if (part[h].nclass == 0) continue;
+        int blocks = 0;
+        size_t lds = 0;
+        hipError_t e = plan_multi(part[h], true, &blocks, &lds);
+        if (e != hipSuccess) return e;
+        if (h == 0) hipLaunchKernelGGL(y_pencil_multi, dim3(blocks), dim3(SE2C_MULTI_THREADS), lds, s, part[h]);
+        else hipLaunchKernelGGL(y_pencil_multi3, dim3(blocks), dim3(SE2C_MULTI_THREADS), lds, s, part[h]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -953,7 +1034,13 @@ hipError_t prepare_fast_kernels() {
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(xt_slab_multi), hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
     if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(xt_slab_multi3), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+    if (e != hipSuccess) return e;
     e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_pencil_multi), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+    if (e != hipSuccess) return e;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(y_pencil_multi3), hipFuncAttributeMaxDynamicSharedMemorySize,
                             160 * 1024);
     if (e != hipSuccess) return e;
     SE2C_SLAB_ATTR(32, 16) SE2C_SLAB_ATTR(32, 32) SE2C_SLAB_ATTR(32, 64)
