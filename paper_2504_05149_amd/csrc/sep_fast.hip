@@ -552,17 +552,22 @@ __global__ void __launch_bounds__(RowGeom<NX>::NT) x_rows_fast(FastSepArgs a) {
 }
 
 // ------------------------------------------------- multi-class launches (uneven batches)
-// One launch per pass covers every shape class of a heterogeneous submission: a
-// workgroup of 256 threads takes S = 256 / NT slabs (or pencil tiles) of one class side
-// by side, each in its own LDS region; the classes are laid end to end over the grid, so
+// One launch per pass and class kind covers every shape class of a heterogeneous
+// submission: a workgroup takes S = (its threads) / NT slabs (or pencil tiles) of one class
+// side by side, each in its own LDS region; the classes are laid end to end over the grid, so
 // small classes no longer run alone.  The transpose chunk is 16 rows wherever the x
 // rounds need no more, which keeps every class within about 45 KB of LDS per workgroup.
+// NTH: threads per workgroup, 256 for classes of 2^k points and 192 for 3 x 2^k (48 and
+// 96 points: 48, 96 or 192 threads per slab), so that the slabs cover every workgroup.
+template <int NX> constexpr int multi_slab_threads() { return (NX & (NX - 1)) == 0 ? SE2C_MULTI_THREADS : 192; }
+
 template <int NX, int M> struct MultiSlab {
+    static constexpr int NTH = multi_slab_threads<NX>();
     static constexpr int NT0 = NX * (M == 64 ? 2 : 1);
     static constexpr int R20 = NX / ((NX % 3 == 0) ? NX / 4 : 16);
     static constexpr int RC = (M < 32 || NT0 / R20 <= 16) ? 16 : 32;
     using Gm = SlabGeom<NX, M, RC>;
-    static constexpr int S = SE2C_MULTI_THREADS / Gm::NT;
+    static constexpr int S = NTH / Gm::NT;
     static constexpr size_t REGION = (Gm::LDS + 15) / 16 * 16;
     static constexpr size_t LDS = REGION * S;
 };
@@ -571,8 +576,8 @@ template <int NX, int M>
 __device__ __forceinline__ void slab_class(const MultiArgs& m, const MultiClass& c, int lb, unsigned char* smem) {
     using MS = MultiSlab<NX, M>;
     constexpr int NT = MS::Gm::NT, S = MS::S;
-    // NX a power of two: the S slabs of a workgroup cover its threads exactly
-    constexpr bool CLAMPED = S * NT == SE2C_MULTI_THREADS;
+    // the S slabs of a workgroup cover its threads exactly
+    constexpr bool CLAMPED = S * NT == MS::NTH;
     const int sub_raw = threadIdx.x / NT;
     const int sub = sub_raw < S ? sub_raw : S - 1;   // lanes beyond S shadow the last slab
     const int tid = threadIdx.x - sub_raw * NT;
@@ -591,8 +596,9 @@ __device__ __forceinline__ void slab_class(const MultiArgs& m, const MultiClass&
                                              smem + (size_t)sub * MS::REGION);
 }
 
-// The classes in two launches by register budget: NX a power of two (no predicates, 153
-// VGPRs, three waves per SIMD) and NX = 3 * 2^k (lanes left over beside the slabs).
+// The classes in two launches by register budget: NX a power of two (153 VGPRs, three
+// waves per SIMD) and NX = 3 * 2^k (24 values per thread at 96 points, 192-thread
+// workgroups).
 #define SE2C_MULTI_SLABS_P2(X) \
     X(32, 16) X(32, 32) X(32, 64) X(64, 16) X(64, 32) X(64, 64) X(128, 16) X(128, 32) X(128, 64) X(256, 16) X(256, 32)
 #define SE2C_MULTI_SLABS_P3(X) X(48, 16) X(48, 32) X(48, 64) X(96, 16) X(96, 32) X(96, 64)
@@ -621,7 +627,7 @@ xt_slab_multi(MultiArgs m) {
     }
 }
 
-__global__ void __launch_bounds__(SE2C_MULTI_THREADS) xt_slab_multi3(MultiArgs m) {
+__global__ void __launch_bounds__(192) xt_slab_multi3(MultiArgs m) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __builtin_amdgcn_s_setprio(2);
     int lb;
@@ -878,7 +884,7 @@ hipError_t launch_slab_multi(MultiArgs m, hipStream_t s) {
         hipError_t e = plan_multi(part[h], false, &blocks, &lds);
         if (e != hipSuccess) return e;
         if (h == 0) hipLaunchKernelGGL(xt_slab_multi, dim3(blocks), dim3(SE2C_MULTI_THREADS), lds, s, part[h]);
-        else hipLaunchKernelGGL(xt_slab_multi3, dim3(blocks), dim3(SE2C_MULTI_THREADS), lds, s, part[h]);
+        else hipLaunchKernelGGL(xt_slab_multi3, dim3(blocks), dim3(192), lds, s, part[h]);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
