@@ -191,17 +191,41 @@ __global__ void __launch_bounds__(kRaderW * RaderGeom<P>::R2) rader_pencil(Penci
         if (in1) in1 += obase * es;
         const int ncols = min(W, a.ncols - c0);
         __syncthreads();  // the previous tile's stores have read the LDS tile
-        for (int i = tid; i < P * W; i += NT) {
-            // rows: consecutive threads along the points of a row (contiguous in memory)
-            const int c = ROWS ? i / P : i % W;
-            const int e = ROWS ? i - c * P : i / W;
-            C<T> v = mk<T>((T)0, (T)0);
-            if (c < ncols) {
-                const long long off = (e * astride + c * cstride) * es;
-                v.x = in0[off];
-                v.y = in1 ? in1[off] : (T)0;
+        // The tile's loads go out STG at a time before their LDS writes, so that STG HBM
+        // round trips overlap: element by element, every load waited for the one before
+        // (the write to LDS needs its value), eleven round trips in a row per thread at 101.
+        // The loads are unconditional (out-of-tile elements read a clamped address and are
+        // zeroed after the load): a load under a branch made the compiler wait for every
+        // earlier load first.  Rows: consecutive threads along the points of a row
+        // (contiguous in memory).  In-tile offsets are 32-bit (P * plane * 2 < 2^31 for
+        // every supported grid).
+        constexpr int LIT = (P * W + NT - 1) / NT;  // elements per thread
+        // (FP64 x rows keep one at a time: 48 -> 55 us at 101 with six, against 26.5 -> 23.8
+        // and 29.6 -> 28.1 us for the FP32 pencils and rows)
+        constexpr int STG = (sizeof(T) == 8 && ROWS) ? 1 : (LIT < 6 ? LIT : 6);
+        const int ast = (int)astride * es, cst = (int)cstride * es;
+        const bool has1 = in1 != nullptr;
+        const T* in1p = has1 ? in1 : in0;
+#pragma unroll 1
+        for (int k0 = 0; k0 < LIT; k0 += STG) {
+            C<T> lv[STG];
+#pragma unroll
+            for (int k = 0; k < STG; ++k) {
+                const int i = tid + (k0 + k) * NT;
+                const int c = ROWS ? i / P : i % W;
+                const int e = ROWS ? i - c * P : i / W;
+                const bool ok = k0 + k < LIT && i < P * W && c < ncols;
+                const int off = min(e, P - 1) * ast + min(c, ncols - 1) * cst;
+                const T vx = in0[off], vy = in1p[off];
+                lv[k] = mk<T>(ok ? vx : (T)0, (ok && has1) ? vy : (T)0);
             }
-            tile[e * WP + c] = v;
+#pragma unroll
+            for (int k = 0; k < STG; ++k) {
+                const int i = tid + (k0 + k) * NT;
+                const int c = ROWS ? i / P : i % W;
+                const int e = ROWS ? i - c * P : i / W;
+                if (k0 + k < LIT && i < P * W) tile[e * WP + c] = lv[k];
+            }
         }
         __syncthreads();
         C<T> x[R1];
