@@ -67,6 +67,27 @@ def test_general_size_separable_chain(nx, ny, m, batch, lc, dt):
     assert worst <= _tol(dt, nx * ny * m)
 
 
+@pytest.mark.parametrize("nx,ny,m,batch,dt", [(31, 31, 31, 3, "f32"), (45, 35, 49, 1, "f64"), (33, 24, 301, 2, "f32")])
+def test_general_size_separable_adjoint(nx, ny, m, batch, dt):
+    """The separable schedule on field pairs (odd Nx or Ny) with the conjugated factors: the
+    x-theta slab where it fits, x rows and theta pencils where it does not (M = 301)."""
+    case(f"general size {nx}x{ny}x{m} batch={batch} {dt}: separable chain of 2, adjoint")
+    ks = chain_kernel_params(6, 2)
+    chain = [(k.sigma, k.kappa, 0.5 + 0.4 * j) for j, k in enumerate(ks)]
+    f = sample_fields(6, batch, 8, nx, ny, m)
+    plan = se2.Plan([(nx, ny, m)], dtype=dt)
+    table = plan.coeffs(0, [se2.GaussVM(s, k, th) for s, k, th in chain])
+    out = plan.apply(0, _dev(f, _tdt(dt)), table, adjoint=True)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy().astype(np.float64)
+    ref_t = np.conj(oracle_table_gauss(nx, ny, m, chain))
+    for b in range(batch):
+        err = parity_err(out[b], oc.conv_with_coeffs(f[b], ref_t))
+        print(f"  field {b}: {err:.2e} (tol {_tol(dt, nx * ny * m):.1e})", flush=True)
+        assert err <= _tol(dt, nx * ny * m)
+    plan.close()
+
+
 @pytest.mark.parametrize("nx,ny,m,dt", [(33, 29, 25, "f64"), (45, 35, 21, "f32")])
 def test_general_size_tables_match_oracle_ffc(nx, ny, m, dt):
     case(f"tables on odd grid {nx}x{ny}x{m} {dt}: separable and full (samples x profile)")
