@@ -145,3 +145,48 @@ def test_c4_gradients_256x256x64_batch8():
         e_gf = parity_err(gf[b], oc.conv_with_coeffs(g[b], np.conj(table)))
         print(f"  grad_f field {b}: {e_gf:.2e}", flush=True)
         assert e_gf <= 1e-4
+
+
+def test_c4_finite_differences_fp64_at_full_size():
+    """Central differences of the C4 loss at its full size, on the FP64 GPU path: the loss is
+    quadratic in the field and in the profile (the output is linear in each), so the central
+    difference equals the derivative up to rounding, whatever h; a large h keeps the
+    rounding of the two loss sums (33.5 M terms each) small against 2h."""
+    case("C4 shape 256x256x64 batch 8, FP64: central differences on 6 field and 6 profile coordinates")
+    f, target, prof, nk, rmax = _c4_problem()
+    m, ny, nx = f.shape[1:]
+    plan = se2.Plan([(nx, ny, m)], dtype="f64")
+    fd0 = _dev(f, torch.float64)
+    pd0 = _dev(prof, torch.float64)
+    tgt = _dev(target, torch.float64)
+
+    def loss_of(fa, pa):
+        with torch.no_grad():
+            out = radial_profile_conv(fa, pa, plan, 0, rmax, True)
+            return float(((out - tgt) ** 2).sum().item())
+
+    fd = fd0.clone().requires_grad_(True)
+    pd = pd0.clone().requires_grad_(True)
+    out = radial_profile_conv(fd, pd, plan, 0, rmax, True)
+    ((out - tgt) ** 2).sum().backward()
+    rng = np.random.default_rng([2504_05149, 4, 7])
+    h = 0.1
+    for _ in range(6):
+        idx = tuple(int(rng.integers(0, s)) for s in f.shape)
+        fp, fm = fd0.clone(), fd0.clone()
+        fp[idx] += h
+        fm[idx] -= h
+        num = (loss_of(fp, pd0) - loss_of(fm, pd0)) / (2 * h)
+        ana = fd.grad[idx].item()
+        print(f"  d/df{idx}: {num:.9e} vs {ana:.9e}", flush=True)
+        assert abs(num - ana) <= 1e-5 * max(1.0, abs(ana)), (idx, num, ana)
+    for _ in range(6):
+        idx = (int(rng.integers(0, nk // 4)), int(rng.integers(0, m)))  # knots inside the kernel's reach
+        pp, pm = pd0.clone(), pd0.clone()
+        pp[idx] += h
+        pm[idx] -= h
+        num = (loss_of(fd0, pp) - loss_of(fd0, pm)) / (2 * h)
+        ana = pd.grad[idx].item()
+        print(f"  d/dprof{idx}: {num:.9e} vs {ana:.9e}", flush=True)
+        assert abs(num - ana) <= 1e-5 * max(1.0, abs(ana)), (idx, num, ana)
+    plan.close()
