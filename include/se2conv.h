@@ -416,10 +416,14 @@ typedef struct {
  * se2conv_chain: run n_probs problems (different shapes and kernel chains allowed),
  * ordered after earlier work on the stream; the call's work is complete when the stream
  * reaches the point after it.  Problems whose tables are all SEPARABLE are grouped by
- * shape into one launch per pass per shape class; the classes run one after another on
- * `stream` (the environment variable SE2CONV_CHAIN_STREAMS = 2..4 forks them over that
- * many of the plan's auxiliary streams, joined back into `stream`; not with
- * SE2CONV_TIMING).  Problems with FULL tables follow one at a time.  A problem's output
+ * shape.  On FP32 plans, when every class has the multi-class register kernels (N in 32,
+ * 48, 64, 96, 128, 256 with M 16, 32, 64), the classes of 2^k points take one launch per
+ * pass and those of 3 * 2^k another, the second kind on one of the plan's auxiliary
+ * streams (forked from and joined back into `stream`; on `stream` alone with
+ * SE2CONV_TIMING).  Otherwise each class takes one launch per pass, the classes one after
+ * another on `stream` (the environment variable SE2CONV_CHAIN_STREAMS = 2..4 forks them
+ * over that many auxiliary streams; not with SE2CONV_TIMING).  Problems with FULL tables
+ * follow one at a time.  A problem's output
  * must not overlap another problem's input or output.  With SE2CONV_GRAPH the
  * submission (forks included) is captured into a HIP graph on first use and replayed
  * on later calls with the same problem list (same pointers, sizes and table kinds).

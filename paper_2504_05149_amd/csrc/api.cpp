@@ -1146,9 +1146,11 @@ se2conv_status ensure_aux_streams(se2conv_plan_s* p) {
 }
 
 
-// Every shape class of a grouped item list in one launch per pass (the multi-class
-// register kernels), when every class has them; *done tells whether it ran.  Classes go
-// largest first, so that the last workgroups of the grid are the small ones.
+// Every shape class of a grouped item list in one launch per pass and class kind (the
+// multi-class register kernels), when every class has them; *done tells whether it ran.
+// Classes go largest first, so that the last workgroups of a grid are the small ones.
+// fork_ok: the second kind may run on an auxiliary stream (not under pass timing, not in
+// the allocation-free entry point).
 se2conv_status enqueue_multi(se2conv_plan_s* p, const SepItem* d_items, const std::vector<std::pair<int, int>>& groups,
                              const std::vector<int>& counts, bool conj, hipStream_t st, bool* done, bool fork_ok) {
     *done = false;
