@@ -12,7 +12,8 @@ dominant pass (measured live with HIP events on the launch stream) beside the
 whole path's, the relative L2 error against the FP64 oracle, the oracle's own CPU
 throughput, and a "secondary" object with the plain single-kernel convolution at
 the same shape, the uneven batch of 256 problems (one graph), the differentiated
-form (forward + gradients) and the chain-expanded rate.
+form (forward + gradients), a sum of SE(2)-shifted kernels, the FP64 path at
+512x512x128 and the prime length 101, and the chain-expanded rate.
 """
 from __future__ import annotations
 
@@ -768,8 +769,8 @@ def main():
 
 def secondary(steps, warmup, tune=True):
     """The plain single-kernel convolution at the headline shape, the uneven batch (C2), the
-    differentiated form (C4) and a sum of SE(2)-shifted kernels, measured in the same
-    invocation."""
+    differentiated form (C4), a sum of SE(2)-shifted kernels, the FP64 path at 512x512x128
+    (C3) and the prime length 101, measured in the same invocation."""
     out = {}
     r = run_gpu("headline_plain", steps, warmup, tune=tune)
     nx, ny, m = r["shape"]
@@ -792,6 +793,16 @@ def secondary(steps, warmup, tune=True):
     out["shifted_kernel_sum"] = {k: sh[k] for k in ("value", "unit", "ms_per_step", "replay_median_ms",
                                                     "pass_ms_total_per_step")}
     out["shifted_kernel_sum"]["workload"] = sh["config"]["workload"]
+    # the FP64 path (three register passes) and a prime grid length (Rader's algorithm)
+    for key, name in (("fp64_c3", "c3_f64"), ("prime_length_101", "odd101")):
+        r = run_gpu(name, steps, warmup, tune=tune)
+        rm = r["replay_median_ms"]
+        out[key] = {"workload": describe(name)["workload"], "dtype": WORKLOADS[name][6],
+                    "conv_per_s": round(r["batch"] * steps / r["elapsed"], 1),
+                    "ms_per_step": round(r["elapsed"] * 1e3 / steps, 4),
+                    "replay_median_ms": round(rm, 4),
+                    "conv_per_s_replay_median": round(r["batch"] / (rm * 1e-3), 1),
+                    "pass_ms": {k: round(v, 4) for k, v in r["avg_ms"].items()}}
     return out
 
 
